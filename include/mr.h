@@ -1,0 +1,182 @@
+/*
+ * mr.h -- C ABI of the MI355X (gfx950) library for the nonlinear multigrid solve of the
+ * mass-conservation (Monge-Ampere-type) equation used for initial-density reconstruction
+ * (Shi, Cautun & Li, "New method for initial density reconstruction").
+ *
+ * Equation (Sec. II, Eqs. 2-10 and 15): find the periodic displacement potential theta on an
+ * n^3 mesh (grid units, h = 1) such that, in every cell,
+ *
+ *     nabla^2 theta - (Sigma - <Sigma>) = 0,    Sigma = s* - 3,
+ *
+ * where s* is the largest real root of s^3 + p s + q = 0 with p = -(9/2) tr(Mbar^2),
+ * q = 9 tr(Mbar^3) - 27 (1 + delta), Mbar the traceless part of the second-order
+ * finite-difference Hessian (Eqs. 11-14). <Sigma> is the uniform shift that makes the periodic
+ * problem compatible (it vanishes for every exact discrete solution); it is reported as m_shift.
+ * The solution is normalised to <theta> = 0. The solver is the FAS V-cycle of Sec. II.A.3 with
+ * red-black Newton-Gauss-Seidel relaxation (Sec. II.A.2, Eq. 17).
+ *
+ * Conventions shared by every call:
+ *  - Arrays are contiguous C-order [n][n][n] (k fastest), periodic, in DEVICE memory owned by
+ *    the caller, unless the argument says "host".
+ *  - Work is enqueued on the HIP stream given at creation (NULL = default stream). Calls that
+ *    return a host scalar synchronise that stream before returning.
+ *  - Return codes: MR_OK (0); MR_NOT_CONVERGED (1: outputs are valid but the tolerance was not
+ *    reached); MR_EINVAL (-1: null pointer, unsupported size, bad option); MR_EDOMAIN (-2: a
+ *    non-finite delta or 1 + delta <= 0); MR_EDIVERGED (-3: non-finite or growing residual);
+ *    MR_EHIP (-4: a HIP runtime error); MR_ENOMEM (-5). mr_last_error() returns a
+ *    thread-local description of the last failure.
+ *  - Supported sizes: n even, n >= 4, and the coarsest mesh reached by halving while the
+ *    result stays even and >= 4 must be at most 16 cells wide (4^3 for powers of two,
+ *    6^3 for 96^3, 12^3 for 48 * 2^k ...).
+ */
+#ifndef MR_H
+#define MR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MR_OK = 0,
+  MR_NOT_CONVERGED = 1,
+  MR_EINVAL = -1,
+  MR_EDOMAIN = -2,
+  MR_EDIVERGED = -3,
+  MR_EHIP = -4,
+  MR_ENOMEM = -5
+};
+
+enum { MR_PREC_FP64 = 0, MR_PREC_MIXED = 1 };
+
+/* Solver options. tol is the relative residual ||r(theta)||_2 / ||r(0)||_2 on the finest mesh
+ * (the paper stops on the rms residual, Sec. II.A.2). npre/npost are red-black sweeps before and
+ * after the coarse correction, ncoarse the sweeps on the coarsest mesh (Sec. II.A.3).
+ * precision: MR_PREC_FP64, or MR_PREC_MIXED (FP32 relaxation and coarse grids on the linearised
+ * operator inside an FP64 defect-correction loop; the FP64 residual decides convergence).
+ * inner_cycles: FP32 V-cycles per outer step in mixed precision. warm_start: non-zero to start
+ * from the theta passed in instead of theta = 0. */
+typedef struct {
+  double tol;
+  int max_cycles;
+  int npre;
+  int npost;
+  int ncoarse;
+  int precision;
+  int inner_cycles;
+  int warm_start;
+  int reserved;
+} mr_opts;
+
+/* Per-solve report. history[c] is the relative residual after cycle c (history[0] = start). */
+typedef struct {
+  int status;
+  int cycles;
+  double rel_residual;
+  double r0_norm;
+  double m_shift;
+  double seconds;
+  double history[128];
+} mr_info;
+
+typedef struct mr_ctx mr_ctx;
+
+/* Fills *opts with the defaults: tol 1e-10, max_cycles 100, npre = npost = 2, ncoarse 20,
+ * FP64, inner_cycles 1, cold start. */
+void mr_default_opts(mr_opts* opts);
+
+/* Creates a solver context for an n^3 mesh: allocates the level hierarchy (about 1/7 of the
+ * finest arrays per field) plus one finest-level ping-pong buffer on the current HIP device.
+ * opts may be NULL (defaults). hip_stream is a hipStream_t (NULL = default stream).
+ * Returns MR_EINVAL for an unsupported n, MR_ENOMEM if allocation fails. */
+int mr_create(mr_ctx** out, int n, const mr_opts* opts, void* hip_stream);
+
+/* Releases the context and its device memory (NULL is ignored). */
+void mr_destroy(mr_ctx* ctx);
+
+/* Replaces the options of an existing context (same validation as mr_create). */
+int mr_set_opts(mr_ctx* ctx, const mr_opts* opts);
+
+/* Mesh size and level count of a context. */
+int mr_size(const mr_ctx* ctx);
+int mr_levels(const mr_ctx* ctx);
+
+/* Cloud-in-cell density assignment (the paper's footnote on density assignment, Sec. I).
+ * pos: device, np x 3 doubles (x, y, z) in cell units, any real value (wrapped periodically);
+ * mesh points sit at integer coordinates and a particle at x gives weight (1 - f) to floor(x)
+ * and f to floor(x) + 1 per axis, f = x - floor(x). delta_out: device n^3, receives
+ * rho / <rho> - 1 with <rho> = np * mass / n^3 (mass > 0). Accumulation is in unsigned 64-bit
+ * fixed point (each weight rounded to a multiple of 2^-40 of a particle's mass before the
+ * sum), so the result is bitwise reproducible. A cell can hold at most 2^24 particles' worth
+ * of weight; the total is checked after the deposit and an overflow returns MR_EINVAL. */
+int mr_deposit_cic(mr_ctx* ctx, const double* pos, int64_t np, double mass, double* delta_out);
+
+/* Residual of a given theta (Sec. II.A.1, Eq. 15 with the mean projection):
+ * r = nabla^2 theta - (Sigma - <Sigma>). r_out: device n^3 or NULL. rel_out: host, receives
+ * ||r||_2 / ||r(theta = 0)||_2 (NULL allowed). msum_out: host, receives <Sigma> (NULL allowed). */
+int mr_residual(mr_ctx* ctx, const double* delta, const double* theta, double* r_out,
+                double* rel_out, double* msum_out);
+
+/* FP64 or mixed-precision solve (per opts.precision) for theta given delta (Sec. II.A).
+ * theta: device n^3, input guess iff opts.warm_start, output the solution with <theta> = 0.
+ * delta is validated (finite, 1 + delta > 0). info: host, may be NULL. */
+int mr_solve(mr_ctx* ctx, const double* delta, double* theta, mr_info* info);
+
+/* Gradient of a loss through the solve. Given delta, the converged theta_star = solve(delta)
+ * and g = dLoss/dtheta (device n^3 each), writes grad_delta = dLoss/ddelta (device n^3):
+ * solves J_p^T lambda = g - <g> (J_p the Jacobian of the mean-projected operator, obtained by
+ * differentiating the physical root of the cubic of Sec. II, Eqs. 8-10) with a linear multigrid
+ * on the transposed operator, coefficients rebuilt per level from theta_star and delta, then
+ * grad = (dSigma/ddelta) * (lambda - <lambda>). tol/max_cycles/npre/npost from the context
+ * options. info may be NULL. */
+int mr_adjoint_solve(mr_ctx* ctx, const double* delta, const double* theta_star,
+                     const double* g, double* grad_delta, mr_info* info);
+
+/* Batched solve of nbox independent boxes (sizes n[b], device arrays delta[b], theta[b]) in
+ * mixed precision: every level phase of all boxes is one kernel launch over a work table,
+ * the outer iteration is captured once in a HIP graph and replayed until every box has reached
+ * opts.tol (converged boxes are masked out). Tile shapes per box size come from the tuner
+ * table (mr_tune_batched). infos: host array of nbox reports (may be NULL). */
+int mr_solve_batched(int nbox, const int* n, const double* const* delta, double* const* theta,
+                     const mr_opts* opts, mr_info* infos, void* hip_stream);
+
+/* ---- Building blocks of the cycle, exported so that each can be checked in isolation. ----
+ * All act on one mesh of size nl (any level of a hierarchy) with cell size h, on the context's
+ * stream, and write only their outputs. */
+
+/* One red-black Newton-Gauss-Seidel sweep (Sec. II.A.2, Eq. 17): red cells ((i+j+k) even)
+ * are updated from theta_in, then black cells from the red results and theta_in's black values:
+ *     theta_c <- (sum of 6 face neighbours - h^2 (Sigma_c + f_c - cshift)) / 6.
+ * f may be NULL (zero). theta_out must not alias theta_in. sum_out (host, may be NULL)
+ * receives sum over all cells of (Sigma_c + f_c) as evaluated during the sweep. */
+int mr_sweep(mr_ctx* ctx, int nl, double h, const double* delta, const double* f, double cshift,
+             const double* theta_in, double* theta_out, double* sum_out);
+
+/* Defect and restriction (Sec. II.A.3, Eq. 18 and the 8-son average R):
+ * d = nabla^2 theta - Sigma - f + cshift on the nl^3 mesh; writes theta_c = R theta and
+ * dr_c = R d on the (nl/2)^3 mesh. f may be NULL. */
+int mr_defect_restrict(mr_ctx* ctx, int nl, double h, const double* delta, const double* f,
+                       double cshift, const double* theta, double* theta_c, double* dr_c);
+
+/* Coarse right-hand side of the FAS equation (Sec. II.A.3, Eq. 19): on the nl^3 mesh with
+ * cell size h, f = nabla^2 theta_hat - Sigma(theta_hat) - rd (in place on rd_f allowed:
+ * pass the same pointer for rd and f_out). sum_out (host, may be NULL): sum of Sigma + f. */
+int mr_tau_rhs(mr_ctx* ctx, int nl, double h, const double* delta, const double* theta_hat,
+               const double* rd, double* f_out, double* sum_out);
+
+/* Correction (Sec. II.A.3, Eq. 20): theta += P(theta_c - theta_hat_c), P trilinear between
+ * cell centres (weights 3/4, 1/4 per axis); theta is the nl^3 mesh, the others (nl/2)^3. */
+int mr_prolong_correct(mr_ctx* ctx, int nl, const double* theta_c, const double* theta_hat_c,
+                       double* theta);
+
+/* 8-son average R from an nl^3 to an (nl/2)^3 mesh (Sec. II.A.3). */
+int mr_restrict(mr_ctx* ctx, int nl, const double* fine, double* coarse);
+
+const char* mr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MR_H */

@@ -1,0 +1,12 @@
+// Entry points of forms that are built in later stages.
+#include "mr.h"
+#include "mr_ctx.h"
+namespace mr {
+int Ctx::solve_mixed(const double*, double*, mr_info*) { return fail(MR_EINVAL, "mixed precision not available"); }
+void Ctx::release_extra() {}
+}
+extern "C" {
+int mr_deposit_cic(mr_ctx*, const double*, int64_t, double, double*) { return mr::fail(MR_EINVAL, "not available"); }
+int mr_adjoint_solve(mr_ctx*, const double*, const double*, const double*, double*, mr_info*) { return mr::fail(MR_EINVAL, "not available"); }
+int mr_solve_batched(int, const int*, const double* const*, double* const*, const mr_opts*, mr_info*, void*) { return mr::fail(MR_EINVAL, "not available"); }
+}

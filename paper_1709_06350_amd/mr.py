@@ -1,0 +1,281 @@
+"""Thin ctypes binding of libmr.so (include/mr.h). Argument marshalling only.
+
+Every computation runs in the HIP library; this module converts torch CUDA tensors (float64,
+contiguous, on the current device) to raw device pointers and passes the current torch stream.
+It never falls back to another implementation: if libmr.so is missing or a call fails, it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmr.so")
+
+MR_OK = 0
+MR_NOT_CONVERGED = 1
+MR_EINVAL = -1
+MR_EDOMAIN = -2
+MR_EDIVERGED = -3
+MR_EHIP = -4
+MR_ENOMEM = -5
+PREC_FP64 = 0
+PREC_MIXED = 1
+
+EXPORTED = [
+    "mr_default_opts", "mr_create", "mr_destroy", "mr_set_opts", "mr_size", "mr_levels",
+    "mr_deposit_cic", "mr_residual", "mr_solve", "mr_adjoint_solve", "mr_solve_batched",
+    "mr_sweep", "mr_defect_restrict", "mr_tau_rhs", "mr_prolong_correct", "mr_restrict",
+    "mr_last_error",
+]
+
+
+class mr_opts(ctypes.Structure):
+    _fields_ = [
+        ("tol", ctypes.c_double),
+        ("max_cycles", ctypes.c_int),
+        ("npre", ctypes.c_int),
+        ("npost", ctypes.c_int),
+        ("ncoarse", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("inner_cycles", ctypes.c_int),
+        ("warm_start", ctypes.c_int),
+        ("reserved", ctypes.c_int),
+    ]
+
+
+class mr_info(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int),
+        ("cycles", ctypes.c_int),
+        ("rel_residual", ctypes.c_double),
+        ("r0_norm", ctypes.c_double),
+        ("m_shift", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+        ("history", ctypes.c_double * 128),
+    ]
+
+
+class MRError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libmr error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: Optional[str] = None):
+    """Load libmr.so (built by paper_1709_06350_amd.build); raises if it is missing."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise ImportError(f"{p} not found: build it with `python -m paper_1709_06350_amd.build` "
+                          "(or __graft_entry__.build()); there is no fallback implementation")
+    lib = ctypes.CDLL(p)
+    vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
+    lib.mr_default_opts.argtypes = [ctypes.POINTER(mr_opts)]
+    lib.mr_default_opts.restype = None
+    lib.mr_create.argtypes = [ctypes.POINTER(vp), ip, ctypes.POINTER(mr_opts), vp]
+    lib.mr_destroy.argtypes = [vp]
+    lib.mr_destroy.restype = None
+    lib.mr_set_opts.argtypes = [vp, ctypes.POINTER(mr_opts)]
+    lib.mr_size.argtypes = [vp]
+    lib.mr_levels.argtypes = [vp]
+    lib.mr_deposit_cic.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, vp]
+    lib.mr_residual.argtypes = [vp, vp, vp, vp, dp, dp]
+    lib.mr_solve.argtypes = [vp, vp, vp, ctypes.POINTER(mr_info)]
+    lib.mr_adjoint_solve.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(mr_info)]
+    lib.mr_solve_batched.argtypes = [ip, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(vp),
+                                     ctypes.POINTER(vp), ctypes.POINTER(mr_opts),
+                                     ctypes.POINTER(mr_info), vp]
+    lib.mr_sweep.argtypes = [vp, ip, ctypes.c_double, vp, vp, ctypes.c_double, vp, vp, dp]
+    lib.mr_defect_restrict.argtypes = [vp, ip, ctypes.c_double, vp, vp, ctypes.c_double, vp, vp, vp]
+    lib.mr_tau_rhs.argtypes = [vp, ip, ctypes.c_double, vp, vp, vp, vp, dp]
+    lib.mr_prolong_correct.argtypes = [vp, ip, vp, vp, vp]
+    lib.mr_restrict.argtypes = [vp, ip, vp, vp]
+    lib.mr_last_error.argtypes = []
+    lib.mr_last_error.restype = ctypes.c_char_p
+    for name in EXPORTED:
+        if name not in ("mr_default_opts", "mr_destroy", "mr_last_error"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(code: int, allow=(MR_OK,)):
+    if code not in allow:
+        raise MRError(code, load().mr_last_error().decode())
+    return code
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def default_opts(**kw) -> mr_opts:
+    o = mr_opts()
+    load().mr_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+@dataclass
+class Info:
+    status: int
+    cycles: int
+    rel_residual: float
+    r0_norm: float
+    m_shift: float
+    seconds: float
+    history: List[float] = field(default_factory=list)
+
+    @staticmethod
+    def from_c(i: mr_info) -> "Info":
+        return Info(i.status, i.cycles, i.rel_residual, i.r0_norm, i.m_shift, i.seconds,
+                    list(i.history[: min(i.cycles, 127) + 1]))
+
+
+class Context:
+    """An mr_ctx for n^3 meshes bound to the current torch stream."""
+
+    def __init__(self, n: int, **opts):
+        self.lib = load()
+        self.n = n
+        self.opts = default_opts(**opts)
+        h = ctypes.c_void_p()
+        _check(self.lib.mr_create(ctypes.byref(h), n, ctypes.byref(self.opts), _stream()))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def levels(self) -> int:
+        return self.lib.mr_levels(self.h)
+
+    def set_opts(self, **kw):
+        for k, v in kw.items():
+            setattr(self.opts, k, v)
+        _check(self.lib.mr_set_opts(self.h, ctypes.byref(self.opts)))
+
+    def _empty(self, n=None):
+        n = self.n if n is None else n
+        return torch.empty((n, n, n), dtype=torch.float64, device="cuda")
+
+    # -- the four calls of the path ----------------------------------------------------------
+    def deposit_cic(self, pos: torch.Tensor, mass: float = 1.0, out: Optional[torch.Tensor] = None):
+        out = self._empty() if out is None else out
+        npart = pos.numel() // 3
+        _check(self.lib.mr_deposit_cic(self.h, _ptr(pos), npart, mass, _ptr(out)))
+        return out
+
+    def residual(self, delta: torch.Tensor, theta: torch.Tensor, want_r: bool = True):
+        r = self._empty() if want_r else None
+        rel = ctypes.c_double()
+        ms = ctypes.c_double()
+        _check(self.lib.mr_residual(self.h, _ptr(delta), _ptr(theta), _ptr(r), ctypes.byref(rel),
+                                    ctypes.byref(ms)))
+        return r, rel.value, ms.value
+
+    def solve(self, delta: torch.Tensor, theta: Optional[torch.Tensor] = None, check: bool = True):
+        theta = torch.zeros_like(delta) if theta is None else theta
+        info = mr_info()
+        code = self.lib.mr_solve(self.h, _ptr(delta), _ptr(theta), ctypes.byref(info))
+        if check:
+            _check(code)
+        return theta, Info.from_c(info)
+
+    def adjoint_solve(self, delta, theta_star, g, out=None, check: bool = True):
+        out = self._empty() if out is None else out
+        info = mr_info()
+        code = self.lib.mr_adjoint_solve(self.h, _ptr(delta), _ptr(theta_star), _ptr(g), _ptr(out),
+                                         ctypes.byref(info))
+        if check:
+            _check(code)
+        return out, Info.from_c(info)
+
+    # -- building blocks ---------------------------------------------------------------------
+    def sweep(self, delta, theta_in, h=1.0, f=None, cshift=0.0, out=None):
+        nl = theta_in.shape[0]
+        out = self._empty(nl) if out is None else out
+        s = ctypes.c_double()
+        _check(self.lib.mr_sweep(self.h, nl, h, _ptr(delta), _ptr(f), cshift, _ptr(theta_in), _ptr(out),
+                                 ctypes.byref(s)))
+        return out, s.value
+
+    def defect_restrict(self, delta, theta, h=1.0, f=None, cshift=0.0):
+        nl = theta.shape[0]
+        tc = self._empty(nl // 2)
+        dr = self._empty(nl // 2)
+        _check(self.lib.mr_defect_restrict(self.h, nl, h, _ptr(delta), _ptr(f), cshift, _ptr(theta),
+                                           _ptr(tc), _ptr(dr)))
+        return tc, dr
+
+    def tau_rhs(self, delta, theta_hat, rd, h):
+        nl = theta_hat.shape[0]
+        f = self._empty(nl)
+        s = ctypes.c_double()
+        _check(self.lib.mr_tau_rhs(self.h, nl, h, _ptr(delta), _ptr(theta_hat), _ptr(rd), _ptr(f),
+                                   ctypes.byref(s)))
+        return f, s.value
+
+    def prolong_correct(self, theta_c, theta_hat_c, theta):
+        nl = theta.shape[0]
+        _check(self.lib.mr_prolong_correct(self.h, nl, _ptr(theta_c), _ptr(theta_hat_c), _ptr(theta)))
+        return theta
+
+    def restrict(self, fine):
+        nl = fine.shape[0]
+        out = self._empty(nl // 2)
+        _check(self.lib.mr_restrict(self.h, nl, _ptr(fine), _ptr(out)))
+        return out
+
+
+def solve_batched(deltas: Sequence[torch.Tensor], thetas: Optional[Sequence[torch.Tensor]] = None,
+                  check: bool = True, **opts):
+    lib = load()
+    nbox = len(deltas)
+    thetas = [torch.zeros_like(d) for d in deltas] if thetas is None else list(thetas)
+    o = default_opts(**opts)
+    ns = (ctypes.c_int * nbox)(*[d.shape[0] for d in deltas])
+    dp = (ctypes.c_void_p * nbox)(*[d.data_ptr() for d in deltas])
+    tp = (ctypes.c_void_p * nbox)(*[t.data_ptr() for t in thetas])
+    for t in list(deltas) + thetas:
+        _ptr(t)
+    infos = (mr_info * nbox)()
+    code = lib.mr_solve_batched(nbox, ns, dp, tp, ctypes.byref(o), infos, _stream())
+    if check:
+        _check(code)
+    return thetas, [Info.from_c(i) for i in infos]

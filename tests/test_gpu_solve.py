@@ -1,0 +1,115 @@
+"""FP64 solve parity: the HIP solve against the oracle's fixed point and the closed forms.
+
+Binding check: the oracle-evaluated relative residual of the GPU theta is <= 1e-10. The
+difference from the oracle's own solution is also bounded (<= 1e-8 relative), and exact
+closed-form solutions are recovered to the same accuracy.
+"""
+import numpy as np
+import pytest
+
+import closed_forms as cf
+import inputs
+from gpu_util import announce, dev, host, require_gpu
+from oracle import multigrid as omg
+from oracle import operator as oop
+
+pytestmark = pytest.mark.gpu
+
+from paper_1709_06350_amd import mr  # noqa: E402
+
+
+def _gpu_solve(delta, **opts):
+    require_gpu()
+    n = delta.shape[0]
+    with mr.Context(n, **opts) as c:
+        theta, info = c.solve(dev(delta))
+    return host(theta), info
+
+
+def _rel_diff(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("n,sigma,rc,seed", [(32, 0.5, 4.0, 1000), (48, 0.7, 3.0, 11),
+                                             (40, 0.6, 3.0, 12), (64, 1.0, 2.0, 13)])
+def test_solve_matches_oracle(n, sigma, rc, seed):
+    announce(f"solve n={n} sigma={sigma}")
+    delta = inputs.lognormal(n, sigma, rc, seed)
+    theta, info = _gpu_solve(delta)
+    assert info.status == 0 and info.rel_residual <= 1e-10
+    assert oop.relative_residual(theta, delta) <= 1e-10
+    assert abs(theta.mean()) < 1e-13
+    ref, rinfo = omg.solve(delta, tol=1e-11)
+    assert _rel_diff(theta, ref) <= 1e-8
+    assert info.m_shift == pytest.approx(rinfo["m_shift"], abs=1e-10)
+
+
+def test_config0_cycles_and_history():
+    delta = inputs.config0_delta()
+    theta, info = _gpu_solve(delta)
+    assert info.cycles <= 16
+    hist = np.array(info.history)
+    assert np.all(np.diff(hist) < 0)
+
+
+def test_separable_closed_form_on_gpu():
+    delta, exact = cf.separable_case(32)
+    theta, info = _gpu_solve(delta, tol=1e-13, max_cycles=80)
+    assert np.max(np.abs(theta - exact)) <= 1e-10 * np.abs(exact).max()
+
+
+def test_manufactured_closed_form_on_gpu():
+    delta, exact = cf.manufactured_case(32)
+    theta, info = _gpu_solve(delta, tol=1e-13, max_cycles=80)
+    assert np.max(np.abs(theta - exact)) <= 1e-9 * np.abs(exact).max()
+    assert abs(info.m_shift) < 1e-11
+
+
+def test_uniform_density_and_poisson_limit():
+    theta, info = _gpu_solve(np.zeros((16, 16, 16)))
+    assert np.all(theta == 0.0) and info.cycles == 0
+    d1 = inputs.lognormal(32, 0.5, 2.0, 5)
+    lin = cf.poisson_fft(d1)
+    t, _ = _gpu_solve(1e-3 * d1, tol=1e-12)
+    assert np.abs(t / 1e-3 - lin).max() < 5e-3 * np.abs(lin).max()
+
+
+def test_solve_is_bitwise_deterministic():
+    delta = inputs.lognormal(32, 0.8, 3.0, 21)
+    a, _ = _gpu_solve(delta)
+    b, _ = _gpu_solve(delta)
+    assert np.array_equal(a, b)
+
+
+def test_warm_start_from_solution_needs_no_cycles():
+    require_gpu()
+    delta = inputs.lognormal(32, 0.6, 3.0, 22)
+    with mr.Context(32) as c:
+        theta, info = c.solve(dev(delta))
+        c.set_opts(warm_start=1)
+        t2, info2 = c.solve(dev(delta), theta=theta.clone())
+    assert info2.cycles == 0 and np.allclose(host(t2), host(theta), atol=1e-14)
+
+
+def test_error_paths():
+    require_gpu()
+    with pytest.raises(mr.MRError) as e:
+        mr.Context(30)  # coarsest 15^3 > 12^3
+    assert e.value.code == mr.MR_EINVAL
+    with pytest.raises(mr.MRError) as e:
+        mr.Context(17)
+    assert e.value.code == mr.MR_EINVAL
+    d = inputs.lognormal(16, 0.5, 2.0, 3)
+    bad = d.copy()
+    bad[3, 4, 5] = -1.5
+    with mr.Context(16) as c:
+        with pytest.raises(mr.MRError) as e:
+            c.solve(dev(bad))
+        assert e.value.code == mr.MR_EDOMAIN
+        bad[3, 4, 5] = np.nan
+        with pytest.raises(mr.MRError) as e:
+            c.solve(dev(bad))
+        assert e.value.code == mr.MR_EDOMAIN
+        c.set_opts(max_cycles=1, tol=1e-14)
+        theta, info = c.solve(dev(d), check=False)
+        assert info.status == mr.MR_NOT_CONVERGED and info.cycles == 1
