@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Benchmark of the reconstruction solve on one MI355X.
+
+Workload (one "step"): the whole hot path on a 512^3 periodic mesh with a seeded lognormal
+overdensity (sigma_g = 1.0, Gaussian-cut power-law spectrum with R_c = 2 cells, seed 1002),
+already resident in HBM: the FP64 FAS V-cycle solve to relative residual 1e-10 and, beside it
+on the same input, the mixed-precision solve to the same FP64 residual.
+
+Headline value: the finest-mesh FP64 red-black NGS sweep throughput (Gcell-updates/s), from HIP
+events recorded by the library around every finest-mesh sweep launch inside the timed region
+(the launches' own stream). The roofline entry prices that kernel at its algorithmic 24 bytes
+per cell update (theta read + write, delta read) against the 8 TB/s HBM peak.
+
+Prints ONE JSON line. --gpus N > 1 is refused: this path runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+SWEEP_BYTES_PER_UPDATE = 24.0  # theta read + theta write + delta read, FP64
+PROFILE_PMC = os.path.join(ROOT, "profiles", "sweep64_512_pmc.txt")
+KERNEL_SOURCES = ["paper_1709_06350_amd/csrc/sweep.hip", "paper_1709_06350_amd/csrc/mr_device.h"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per finest sweep launch from the committed PMC summary, if it matches the source."""
+    if not os.path.exists(PROFILE_PMC):
+        return None
+    txt = open(PROFILE_PMC).read()
+    m = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", txt)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not b or m.group(1) != kernel_hash():
+        return None
+    return float(b.group(1))
+
+
+def cpu_baseline(delta_np, seconds_target=15.0):
+    """The oracle's red-black sweep timed on host cores on a bounded 128^3 periodic sample."""
+    import numpy as np
+
+    from oracle import multigrid as omg
+
+    s = 128
+    d = np.ascontiguousarray(delta_np[:s, :s, :s])
+    th = np.zeros_like(d)
+    sweeps = 0
+    t0 = time.perf_counter()
+    while True:
+        th = omg.rb_sweep(th, d, None, 1.0)
+        sweeps += 1
+        if time.perf_counter() - t0 > seconds_target or sweeps >= 8:
+            break
+    dt = time.perf_counter() - t0
+    return {
+        "value": s ** 3 * sweeps / dt / 1e9,
+        "unit": "Gcell-updates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"{sweeps} red-black sweeps of the oracle on a 128^3 periodic sub-box of the "
+                  f"512^3 input ({dt:.1f} s, numpy, single thread)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is a design note only)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import inputs
+    from paper_1709_06350_amd import mr
+
+    torch.cuda.set_device(0)
+    n = args.n
+    delta_np = inputs.config2_delta(n)
+    delta = torch.from_numpy(delta_np).cuda()
+    theta = torch.zeros_like(delta)
+    theta_m = torch.zeros_like(delta)
+    ctx = mr.Context(n, tol=1e-10, max_cycles=100)
+    run_mixed = not args.no_mixed
+    ctxm = None
+    if run_mixed:
+        try:
+            ctxm = mr.Context(n, tol=1e-10, max_cycles=100, precision=mr.PREC_MIXED)
+            ctxm.solve(delta, theta_m)
+        except mr.MRError:
+            run_mixed = False
+            ctxm = None
+
+    def step():
+        _, i64 = ctx.solve(delta, theta)
+        im = None
+        if run_mixed:
+            _, im = ctxm.solve(delta, theta_m)
+        return i64, im
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing_enable(True)
+    t64 = tm = 0.0
+    info64 = infom = None
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        a = time.perf_counter()
+        _, info64 = ctx.solve(delta, theta)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        t64 += b - a
+        if run_mixed:
+            _, infom = ctxm.solve(delta, theta_m)
+            torch.cuda.synchronize()
+            tm += time.perf_counter() - b
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    tim = ctx.timing_read()
+    ctx.timing_enable(False)
+
+    avg_sweep_s = tim["sweep64_ms"] / max(1, tim["sweep64_launches"]) * 1e-3
+    cells = float(n) ** 3
+    gcups = cells / avg_sweep_s / 1e9
+    achieved = SWEEP_BYTES_PER_UPDATE * cells / avg_sweep_s / 1e9
+    traffic = measured_traffic()
+    out = {
+        "metric": "NGS smoother Gcell-updates/s (% HBM peak); 512^3 time-to-1e-10, mixed vs FP64",
+        "value": round(gcups, 3),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_total / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"lognormal delta on a periodic {n}^3 mesh (sigma_g=1.0, R_c=2 cells, seed 1002): "
+                        "FP64 FAS V-cycle solve to rel. residual 1e-10"
+                        + (" plus the mixed-precision solve on the same input" if run_mixed else ""),
+            "n": n,
+            "tol": 1e-10,
+            "npre": 2,
+            "npost": 2,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None if traffic is None else round(traffic / avg_sweep_s / 1e9, 1),
+            "kernel": "sweep_tile_kernel (finest-mesh FP64 red-black sweep)",
+            "avg_launch_us": round(avg_sweep_s * 1e6, 2),
+            "launches": tim["sweep64_launches"],
+        },
+        "time_to_solution_s": {
+            "fp64": round(t64 / args.steps, 4),
+            "mixed": round(tm / args.steps, 4) if run_mixed else None,
+            "ratio_mixed_over_fp64": round(tm / t64, 4) if run_mixed and t64 > 0 else None,
+        },
+        "cycles": {"fp64": info64.cycles if info64 else None,
+                   "mixed": infom.cycles if infom else None},
+        "rel_residual": {"fp64": info64.rel_residual if info64 else None,
+                         "mixed": infom.rel_residual if infom else None},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(delta_np)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

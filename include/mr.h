@@ -174,6 +174,21 @@ int mr_prolong_correct(mr_ctx* ctx, int nl, const double* theta_c, const double*
 /* 8-son average R from an nl^3 to an (nl/2)^3 mesh (Sec. II.A.3). */
 int mr_restrict(mr_ctx* ctx, int nl, const double* fine, double* coarse);
 
+/* Kernel timing with HIP events on the context's stream, for benchmarking. mr_timing_enable
+ * resets the counters and turns recording on (on != 0) or off. Recorded: every finest-mesh
+ * relaxation sweep launch (FP64 sweep, and the FP32 sweep of the mixed-precision form).
+ * mr_timing_read synchronises the stream and reports totals since the last enable. */
+typedef struct {
+  double sweep64_ms;          /* summed duration of finest-mesh FP64 sweep launches */
+  int64_t sweep64_launches;
+  double sweep32_ms;          /* summed duration of finest-mesh FP32 sweep launches */
+  int64_t sweep32_launches;
+  int64_t finest_cells;       /* cells of the finest mesh (cell updates per sweep) */
+} mr_timing;
+
+int mr_timing_enable(mr_ctx* ctx, int on);
+int mr_timing_read(mr_ctx* ctx, mr_timing* out);
+
 const char* mr_last_error(void);
 
 #ifdef __cplusplus

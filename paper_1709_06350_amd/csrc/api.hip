@@ -1,5 +1,6 @@
 // Host side of the library: context and level hierarchy, the FAS V-cycle driver (Sec. II.A.3)
-// and the C ABI declared in include/mr.h.
+// and the C ABI declared in include/mr.h. Inside the solver all fields are colour-split
+// (mr_device.h); the caller's arrays are in natural C order and are converted at the boundary.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -39,34 +40,78 @@ std::vector<int> level_sizes(int n) {
 
 int check_size(int n) {
   if (n < 4 || n % 2 != 0) return fail(MR_EINVAL, "n = %d: must be even and >= 4", n);
+  if (n > 1024) return fail(MR_EINVAL, "n = %d: larger than 1024", n);
   const auto s = level_sizes(n);
   if ((long)s.back() * s.back() * s.back() > kMaxCoarsest)
     return fail(MR_EINVAL, "n = %d: coarsest mesh %d^3 exceeds 12^3", n, s.back());
-  if (n > 2048) return fail(MR_EINVAL, "n = %d: too large", n);
+  if ((int)s.size() > kMaxLevels) return fail(MR_EINVAL, "n = %d: too many levels", n);
   return MR_OK;
 }
 
 int check_opts(const mr_opts& o) {
   if (!(o.tol >= 0.0) || o.max_cycles < 1 || o.max_cycles > 127 || o.npre < 0 || o.npost < 0 ||
-      o.ncoarse < 1 || (o.precision != MR_PREC_FP64 && o.precision != MR_PREC_MIXED) ||
-      o.inner_cycles < 1 || o.inner_cycles > 8)
+      o.npre + o.npost < 1 || o.ncoarse < 1 ||
+      (o.precision != MR_PREC_FP64 && o.precision != MR_PREC_MIXED) || o.inner_cycles < 1 ||
+      o.inner_cycles > 8)
     return fail(MR_EINVAL, "invalid options");
   return MR_OK;
 }
 
-TileCfg choose_tiles(int n, int max_lds) {
-  TileCfg t;
-  t.tk = 64;
-  while (t.tk > 4 && (n % t.tk != 0 || t.tk > n)) t.tk /= 2;
-  t.tj = 16;
-  while (t.tj > 2 && (n % t.tj != 0 || t.tj > n)) t.tj /= 2;
-  while (t.tj > 2 && sweep_lds_bytes(t.tj, t.tk) > (size_t)max_lds) t.tj /= 2;
-  t.tiles_j = n / t.tj;
-  t.tiles_k = n / t.tk;
-  const long tiles = (long)t.tiles_j * t.tiles_k;
+static int pow2_divisor(int v, int cap) {
+  int t = cap;
+  while (t > 1 && (v % t != 0 || t > v)) t /= 2;
+  return t;
+}
+
+static void pick_chunk(TileCfg& t, int n, bool even, int target_blocks, int min_ci) {
+  const long tiles = (long)t.tiles_j * t.tiles_m;
   t.ci = n;
-  while (t.ci % 2 == 0 && t.ci > 4 && tiles * (n / t.ci) < 2048) t.ci /= 2;
+  while (t.ci % 2 == 0 && t.ci / 2 >= min_ci && (!even || (t.ci / 2) % 2 == 0) &&
+         tiles * (n / t.ci) < target_blocks)
+    t.ci /= 2;
   while (tiles * (n / t.ci) > kMaxReduceBlocks && t.ci * 2 <= n && n % (t.ci * 2) == 0) t.ci *= 2;
+}
+
+// Half-sweep tile: the widest column count (power of two, <= 64) dividing n/2, then the first
+// compiled (tm, tj, cpt) shape whose rows divide n; chunks of >= 8 planes.
+struct TileChoice {
+  int tm, tj, cpt;
+};
+static const TileChoice kSweepPref[] = {{64, 8, 1}, {64, 4, 1}, {32, 16, 2}, {32, 8, 1}, {16, 32, 2},
+                                        {16, 16, 1}, {8, 16, 1},  {8, 8, 1},   {4, 8, 1},   {4, 16, 2},
+                                        {2, 4, 1},   {2, 8, 1}};
+
+TileCfg sweep_tiles(int n) {
+  TileCfg t;
+  const int nh = n / 2;
+  const int tm = pow2_divisor(nh, 64);
+  t.tm = 0;
+  for (const auto& c : kSweepPref) {
+    if (c.tm == tm && n % c.tj == 0 && c.tj <= n && half_sweep_tile_supported(c.tm, c.tj, c.cpt)) {
+      t.tm = c.tm;
+      t.tj = c.tj;
+      t.cpt = c.cpt;
+      break;
+    }
+  }
+  if (t.tm == 0) return t;  // unsupported: launch will fail with an invalid-value error
+  t.tiles_j = n / t.tj;
+  t.tiles_m = nh / t.tm;
+  pick_chunk(t, n, false, 1024, 8);
+  return t;
+}
+
+// Defect + restriction tile: even rows; a thread owns two rows, 256 threads.
+TileCfg defect_tiles(int n) {
+  TileCfg t;
+  const int nh = n / 2;
+  t.tm = pow2_divisor(nh, 64);
+  if (t.tm < 2) t.tm = 2;
+  t.tj = pow2_divisor(n, 512 / t.tm);
+  if (t.tj < 2) t.tj = 2;
+  t.tiles_j = n / t.tj;
+  t.tiles_m = nh / t.tm;
+  pick_chunk(t, n, true, 1024, 8);
   return t;
 }
 
@@ -99,37 +144,145 @@ int Ctx::write_scalar(int slot, double v) {
   return MR_OK;
 }
 
-// ---- one FP64 sweep / V-cycle on the level hierarchy ----------------------------------------
+// ---- event timing of finest-mesh sweeps ----------------------------------------------------
 
+int EventTimer::begin(hipStream_t s) {
+  if (!on) return -1;
+  if (next + 2 > pool.size()) {
+    if (pool.size() >= 8192) return -1;  // drop samples beyond the pool
+    for (int i = 0; i < 256; ++i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return -1;
+      pool.push_back(e);
+    }
+  }
+  const int idx = (int)next;
+  next += 2;
+  if (hipEventRecord(pool[idx], s) != hipSuccess) return -1;
+  return idx;
+}
+
+void EventTimer::end(int kind, int start, hipStream_t s) {
+  if (start < 0) return;
+  if (hipEventRecord(pool[start + 1], s) != hipSuccess) return;
+  pending[kind].push_back({start, start + 1});
+}
+
+int EventTimer::resolve() {
+  for (int k = 0; k < 2; ++k) {
+    for (auto& pr : pending[k]) {
+      if (hipEventSynchronize(pool[pr.second]) != hipSuccess) return MR_EHIP;
+      float t = 0.0f;
+      if (hipEventElapsedTime(&t, pool[pr.first], pool[pr.second]) != hipSuccess) return MR_EHIP;
+      ms[k] += t;
+      count[k] += 1;
+    }
+    pending[k].clear();
+  }
+  next = 0;
+  return MR_OK;
+}
+
+void EventTimer::reset() {
+  for (int k = 0; k < 2; ++k) {
+    pending[k].clear();
+    ms[k] = 0.0;
+    count[k] = 0;
+  }
+  next = 0;
+}
+
+void EventTimer::destroy() {
+  for (auto e : pool) (void)hipEventDestroy(e);
+  pool.clear();
+}
+
+// ---- FP64 sweep / V-cycle on the level hierarchy --------------------------------------------
+
+// One red-black sweep: red half-sweep from the current iterate, black half-sweep from the new
+// red values and the old black values; both use the shift of the previous sweep. The red sum goes
+// to the staging slot, the black sum to slot [1]; the black launch then moves staging to [0].
 int Ctx::sweep(int l) {
   Level& L = lv[l];
-  SweepArgs a{};
+  double* cs = lsum(l);
+  HalfSweepArgs a{};
   a.th_in = L.th[L.cur];
+  a.th_red_new = nullptr;
   a.th_out = L.th[L.cur ^ 1];
   a.delta = L.delta;
   a.f = (l == 0) ? nullptr : L.f;
   a.n = L.n;
+  a.colour = 0;
   a.h2 = L.h * L.h;
   a.ih2 = 1.0 / a.h2;
-  a.c_sum = scal + kSlotLevel + l;
+  a.c_sum = cs;
   a.c_scale = 1.0 / (double)L.cells;
   a.c_add = 0.0;
-  a.sum_out = scal + kSlotLevel + l;
+  a.sum_out = cs + 2;
+  a.copy_from = nullptr;
+  a.copy_to = nullptr;
   a.partials = partials;
   a.counter = counter;
-  a.tj = L.tile.tj;
-  a.tiles_j = L.tile.tiles_j;
-  a.tiles_k = L.tile.tiles_k;
-  a.ci = L.tile.ci;
-  hipError_t e = launch_sweep(a, L.tile.tk, stream);
-  if (e != hipSuccess) return hip_fail(e, "sweep");
+  const int ev = (l == 0) ? timer.begin(stream) : -1;
+  hipError_t e = launch_half_sweep(a, L.sw, stream);
+  if (e != hipSuccess) return hip_fail(e, "red half-sweep");
+  a.colour = 1;
+  a.th_red_new = L.th[L.cur ^ 1];
+  a.sum_out = cs + 1;
+  a.copy_from = cs + 2;
+  a.copy_to = cs + 0;
+  e = launch_half_sweep(a, L.sw, stream);
+  if (e != hipSuccess) return hip_fail(e, "black half-sweep");
+  timer.end(0, ev, stream);
   L.cur ^= 1;
+  return MR_OK;
+}
+
+// Pre-relaxation on level l, then the fused defect + restriction onto level l+1 (theta_c into
+// the coarse iterate and the saved copy, R d into the coarse f). norm_sums (device, 2 values)
+// receives sum d and sum d^2 of level l when given.
+int Ctx::down(int l, double* norm_sums) {
+  int rc;
+  for (int s = 0; s < opts.npre; ++s)
+    if ((rc = sweep(l)) != MR_OK) return rc;
+  Level& L = lv[l];
+  Level& Lc = lv[l + 1];
+  DefectArgs a{};
+  a.theta = L.th[L.cur];
+  a.delta = L.delta;
+  a.f = (l == 0) ? nullptr : L.f;
+  a.n = L.n;
+  a.ih2 = 1.0 / (L.h * L.h);
+  a.c_sum = lsum(l);
+  a.c_scale = 1.0 / (double)L.cells;
+  a.c_add = 0.0;
+  a.theta_c = Lc.th[Lc.cur];
+  a.theta_c2 = Lc.that;
+  a.dr = Lc.f;
+  a.sums_out = norm_sums ? norm_sums : scal + kSlotAux + 14;
+  a.partials = partials;
+  a.counter = counter;
+  hipError_t e = launch_defect_restrict_tiled(a, L.df, stream);
+  return e == hipSuccess ? MR_OK : hip_fail(e, "defect_restrict");
+}
+
+// Coarse-grid correction of level l from level l+1 and post-relaxation on level l.
+int Ctx::up(int l) {
+  Level& L = lv[l];
+  Level& Lc = lv[l + 1];
+  hipError_t e = launch_tau(Lc.that, Lc.delta, Lc.f, Lc.f, Lc.n, Lc.h, reducer(kSlotLevel + 3 * (l + 1)), stream);
+  if (e != hipSuccess) return hip_fail(e, "tau");
+  int rc;
+  if ((rc = vcycle(l + 1)) != MR_OK) return rc;
+  e = launch_prolong_correct(Lc.th[Lc.cur], Lc.that, L.th[L.cur], L.n, stream);
+  if (e != hipSuccess) return hip_fail(e, "prolong_correct");
+  for (int s = 0; s < opts.npost; ++s)
+    if ((rc = sweep(l)) != MR_OK) return rc;
   return MR_OK;
 }
 
 int Ctx::vcycle(int l) {
   Level& L = lv[l];
-  hipError_t e;
   if (l == nlev - 1) {
     CoarsestArgs a{};
     a.theta = L.th[L.cur];
@@ -139,37 +292,23 @@ int Ctx::vcycle(int l) {
     a.nsweeps = opts.ncoarse;
     a.h2 = L.h * L.h;
     a.ih2 = 1.0 / a.h2;
-    a.c_sum = scal + kSlotLevel + l;
+    a.c_sum = lsum(l);
     a.c_scale = 1.0 / (double)L.cells;
-    a.c_sum_out = scal + kSlotLevel + l;
-    e = launch_coarsest(a, stream);
+    a.c_sum_out = lsum(l);
+    hipError_t e = launch_coarsest(a, stream);
     return e == hipSuccess ? MR_OK : hip_fail(e, "coarsest");
   }
   int rc;
-  for (int s = 0; s < opts.npre; ++s)
-    if ((rc = sweep(l)) != MR_OK) return rc;
-  Level& Lc = lv[l + 1];
-  ShiftRef c{scal + kSlotLevel + l, 1.0 / (double)L.cells, 0.0};
-  e = launch_defect_restrict(L.th[L.cur], L.delta, (l == 0) ? nullptr : L.f, L.n, L.h, c,
-                             Lc.th[Lc.cur], Lc.that, Lc.f, stream);
-  if (e != hipSuccess) return hip_fail(e, "defect_restrict");
-  e = launch_tau(Lc.that, Lc.delta, Lc.f, Lc.f, Lc.n, Lc.h,
-                 Reduce{partials, counter, scal + kSlotLevel + l + 1}, kMaxReduceBlocks, stream);
-  if (e != hipSuccess) return hip_fail(e, "tau");
-  if ((rc = vcycle(l + 1)) != MR_OK) return rc;
-  e = launch_prolong_correct(Lc.th[Lc.cur], Lc.that, L.th[L.cur], L.n, stream);
-  if (e != hipSuccess) return hip_fail(e, "prolong_correct");
-  for (int s = 0; s < opts.npost; ++s)
-    if ((rc = sweep(l)) != MR_OK) return rc;
-  return MR_OK;
+  if ((rc = down(l, nullptr)) != MR_OK) return rc;
+  return up(l);
 }
 
-// Residual norm of the finest level: b = nabla^2 theta - Sigma + shift with the given shift;
+// Residual of the finest level with a given shift: b = nabla^2 theta - Sigma + shift;
 // ||r|| = sqrt(sum b^2 - (sum b)^2 / N^3) is the norm of the mean-projected residual and
-// <Sigma> = shift - <b>. shv is the host value of the shift.
-int Ctx::finest_norm(const double* theta, ShiftRef sh, double* nrm, double* msig) {
+// <Sigma> = shift - <b>.
+int Ctx::finest_norm(const double* theta_split, ShiftRef sh, double* nrm, double* msig) {
   Level& L = lv[0];
-  hipError_t e = launch_residual(theta, L.delta, L.n, 1.0, sh, nullptr, reducer(kSlotRes), kMaxReduceBlocks, stream);
+  hipError_t e = launch_residual(theta_split, L.delta, L.n, 1.0, sh, nullptr, reducer(kSlotRes), stream);
   if (e != hipSuccess) return hip_fail(e, "residual");
   double r[kSlotRes + 2];
   int rc = read_scalars(0, kSlotRes + 2, r);
@@ -177,25 +316,24 @@ int Ctx::finest_norm(const double* theta, ShiftRef sh, double* nrm, double* msig
   const double N3 = (double)L.cells;
   const double var = r[kSlotRes + 1] - r[kSlotRes] * r[kSlotRes] / N3;
   *nrm = std::sqrt(var > 0.0 ? var : 0.0);
-  const double shv = (sh.c_sum ? r[sh.c_sum - scal] * sh.c_scale : 0.0) + sh.c_add;
+  const double shv = (sh.c_sum ? (r[sh.c_sum - scal] + r[sh.c_sum - scal + 1]) * sh.c_scale : 0.0) + sh.c_add;
   *msig = shv - r[kSlotRes] / N3;
   return MR_OK;
 }
 
-int Ctx::prepare(const double* delta, double* theta) {
+// Validate delta, convert it to the colour-split layout and build its hierarchy.
+int Ctx::prepare(const double* delta) {
   Level& L0 = lv[0];
-  L0.delta = delta;
-  L0.th[0] = theta;
-  L0.th[1] = ws_theta0;
-  L0.cur = 0;
-  hipError_t e = launch_validate(delta, L0.cells, reducer(kSlotRes), kMaxReduceBlocks, stream);
+  hipError_t e = launch_validate(delta, L0.cells, reducer(kSlotRes), stream);
   if (e != hipSuccess) return hip_fail(e, "validate");
   double bad;
   int rc = read_scalars(kSlotRes, 1, &bad);
   if (rc != MR_OK) return rc;
   if (bad != 0.0) return fail(MR_EDOMAIN, "delta has %.0f cells with a non-finite value or 1 + delta <= 0", bad);
+  e = launch_to_split(delta, L0.delta, L0.n, stream);
+  if (e != hipSuccess) return hip_fail(e, "to_split");
   for (int l = 1; l < nlev; ++l) {
-    e = launch_restrict(lv[l - 1].delta, lv[l].delta_own, lv[l - 1].n, stream);
+    e = launch_restrict(lv[l - 1].delta, lv[l].delta, lv[l - 1].n, stream);
     if (e != hipSuccess) return hip_fail(e, "restrict delta");
   }
   return MR_OK;
@@ -203,25 +341,27 @@ int Ctx::prepare(const double* delta, double* theta) {
 
 int Ctx::solve_fp64(const double* delta, double* theta, mr_info* info) {
   auto t0 = std::chrono::steady_clock::now();
-  int rc = prepare(delta, theta);
+  int rc = prepare(delta);
   if (rc != MR_OK) return rc;
   Level& L0 = lv[0];
+  const double N3 = (double)L0.cells;
   hipError_t e;
-  if (!opts.warm_start) {
-    e = hipMemsetAsync(theta, 0, L0.cells * sizeof(double), stream);
-    if (e != hipSuccess) return hip_fail(e, "memset");
-  }
+  L0.cur = 0;
+  if (opts.warm_start) e = launch_to_split(theta, L0.th[0], L0.n, stream);
+  else e = hipMemsetAsync(L0.th[0], 0, L0.cells * sizeof(double), stream);
+  if (e != hipSuccess) return hip_fail(e, "initial theta");
   double r0, m0, nrm, msig;
   if ((rc = finest_norm(nullptr, ShiftRef{nullptr, 0.0, 0.0}, &r0, &m0)) != MR_OK) return rc;
-  if (r0 == 0.0) r0 = 1.0;
   if (opts.warm_start) {
-    if ((rc = finest_norm(theta, ShiftRef{nullptr, 0.0, 0.0}, &nrm, &msig)) != MR_OK) return rc;
+    if ((rc = finest_norm(L0.th[0], ShiftRef{nullptr, 0.0, 0.0}, &nrm, &msig)) != MR_OK) return rc;
   } else {
-    nrm = r0 == 1.0 ? 0.0 : r0;
+    nrm = r0;
     msig = m0;
   }
-  // Running sum of Sigma on the finest level, so that the first sweep uses the exact <Sigma>.
-  if ((rc = write_scalar(kSlotLevel + 0, msig * (double)L0.cells)) != MR_OK) return rc;
+  if (r0 == 0.0) r0 = 1.0;
+  // Running sums of the finest level, so that the first sweep uses the exact <Sigma>.
+  if ((rc = write_scalar(kSlotLevel + 0, msig * N3)) != MR_OK) return rc;
+  if ((rc = write_scalar(kSlotLevel + 1, 0.0)) != MR_OK) return rc;
   double rel = nrm / r0;
   mr_info loc{};
   loc.r0_norm = r0;
@@ -229,30 +369,35 @@ int Ctx::solve_fp64(const double* delta, double* theta, mr_info* info) {
   int cyc = 0;
   int status = MR_OK;
   double best = rel;
+  // Each cycle: pre-relaxation, then the defect pass, whose sums give the residual norm of the
+  // current iterate (convergence test); if not converged, coarse correction and post-relaxation.
   while (rel > opts.tol && cyc < opts.max_cycles) {
-    if ((rc = vcycle(0)) != MR_OK) return rc;
-    ++cyc;
-    if ((rc = finest_norm(L0.th[L0.cur], ShiftRef{scal + kSlotLevel + 0, 1.0 / (double)L0.cells, 0.0}, &nrm, &msig)) != MR_OK)
-      return rc;
+    if ((rc = down(0, scal + kSlotRes)) != MR_OK) return rc;
+    double r[kSlotRes + 2];
+    if ((rc = read_scalars(0, kSlotRes + 2, r)) != MR_OK) return rc;
+    const double var = r[kSlotRes + 1] - r[kSlotRes] * r[kSlotRes] / N3;
+    nrm = std::sqrt(var > 0.0 ? var : 0.0);
+    msig = (r[0] + r[1]) / N3 - r[kSlotRes] / N3;
     rel = nrm / r0;
+    ++cyc;
     if (cyc < 128) loc.history[cyc] = rel;
     if (!std::isfinite(rel) || rel > 1e6 * (best > 1.0 ? best : 1.0)) {
       status = fail(MR_EDIVERGED, "residual diverged at cycle %d (%g)", cyc, rel);
       break;
     }
     if (rel < best) best = rel;
+    if (rel <= opts.tol || cyc >= opts.max_cycles) break;
+    if ((rc = up(0)) != MR_OK) return rc;
   }
   if (status == MR_OK && rel > opts.tol) {
     status = MR_NOT_CONVERGED;
     fail(MR_NOT_CONVERGED, "not converged after %d cycles (rel residual %g)", cyc, rel);
   }
-  // Gauge <theta> = 0, result into the caller's buffer.
-  e = launch_sum(L0.th[L0.cur], L0.cells, reducer(kSlotGauge), kMaxReduceBlocks, stream);
-  if (e == hipSuccess)
-    e = launch_shift_copy(L0.th[L0.cur], theta, L0.cells, scal + kSlotGauge, 1.0 / (double)L0.cells, stream);
+  // Gauge <theta> = 0, result into the caller's buffer in natural order.
+  e = launch_sum(L0.th[L0.cur], L0.cells, reducer(kSlotGauge), stream);
+  if (e == hipSuccess) e = launch_from_split(L0.th[L0.cur], theta, L0.n, scal + kSlotGauge, 1.0 / N3, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return hip_fail(e, "gauge");
-  L0.cur = 0;
   loc.status = status;
   loc.cycles = cyc;
   loc.rel_residual = rel;
@@ -265,6 +410,28 @@ int Ctx::solve_fp64(const double* delta, double* theta, mr_info* info) {
 }  // namespace mr
 
 using namespace mr;
+
+namespace {
+
+// Device temporaries for the building-block entry points (freed on scope exit).
+struct Temps {
+  std::vector<void*> ptrs;
+  hipStream_t s;
+  explicit Temps(hipStream_t st) : s(st) {}
+  double* get(size_t count) {
+    void* p = nullptr;
+    if (hipMalloc(&p, count * sizeof(double)) != hipSuccess) return nullptr;
+    ptrs.push_back(p);
+    return (double*)p;
+  }
+  ~Temps() {
+    if (s) (void)hipStreamSynchronize(s);
+    else (void)hipDeviceSynchronize();
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+};
+
+}  // namespace
 
 extern "C" {
 
@@ -297,8 +464,6 @@ int mr_create(mr_ctx** out, int n, const mr_opts* opts, void* hip_stream) {
   c->opts = o;
   c->stream = (hipStream_t)hip_stream;
   (void)hipGetDevice(&c->device);
-  int max_lds = 65536;
-  c->max_lds = max_lds;
   const auto sizes = level_sizes(n);
   c->nlev = (int)sizes.size();
   c->lv.resize(sizes.size());
@@ -307,20 +472,22 @@ int mr_create(mr_ctx** out, int n, const mr_opts* opts, void* hip_stream) {
     L.n = sizes[l];
     L.cells = (size_t)L.n * L.n * L.n;
     L.h = std::ldexp(1.0, (int)l);
-    L.tile = choose_tiles(L.n, max_lds);
-    if (l == 0) continue;
-    if ((rc = c->dev_alloc(&L.th[0], L.cells)) != MR_OK ||
-        (rc = c->dev_alloc(&L.th[1], L.cells)) != MR_OK ||
-        (rc = c->dev_alloc(&L.that, L.cells)) != MR_OK ||
-        (rc = c->dev_alloc(&L.f, L.cells)) != MR_OK ||
-        (rc = c->dev_alloc(&L.delta_own, L.cells)) != MR_OK) {
+    if ((int)l < c->nlev - 1) {
+      L.sw = sweep_tiles(L.n);
+      L.df = defect_tiles(L.n);
+    }
+    if ((rc = c->dev_alloc(&L.th[0], L.cells)) != MR_OK || (rc = c->dev_alloc(&L.th[1], L.cells)) != MR_OK ||
+        (rc = c->dev_alloc(&L.delta, L.cells)) != MR_OK) {
       mr_destroy(reinterpret_cast<mr_ctx*>(c));
       return rc;
     }
-    L.delta = L.delta_own;
+    if (l == 0) continue;
+    if ((rc = c->dev_alloc(&L.that, L.cells)) != MR_OK || (rc = c->dev_alloc(&L.f, L.cells)) != MR_OK) {
+      mr_destroy(reinterpret_cast<mr_ctx*>(c));
+      return rc;
+    }
   }
-  if ((rc = c->dev_alloc(&c->ws_theta0, c->lv[0].cells)) != MR_OK ||
-      (rc = c->dev_alloc(&c->scal, kSlotCount)) != MR_OK ||
+  if ((rc = c->dev_alloc(&c->scal, kSlotCount)) != MR_OK ||
       (rc = c->dev_alloc(&c->partials, (size_t)kMaxReduceBlocks * kMaxNV)) != MR_OK) {
     mr_destroy(reinterpret_cast<mr_ctx*>(c));
     return rc;
@@ -344,9 +511,10 @@ void mr_destroy(mr_ctx* h) {
   Ctx* c = reinterpret_cast<Ctx*>(h);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
+  c->release_extra();
+  c->timer.destroy();
   for (void* p : c->owned) (void)hipFree(p);
   if (c->host) (void)hipHostFree(c->host);
-  c->release_extra();
   delete c;
 }
 
@@ -361,29 +529,52 @@ int mr_set_opts(mr_ctx* h, const mr_opts* opts) {
 int mr_size(const mr_ctx* h) { return h ? reinterpret_cast<const Ctx*>(h)->n : 0; }
 int mr_levels(const mr_ctx* h) { return h ? reinterpret_cast<const Ctx*>(h)->nlev : 0; }
 
+int mr_timing_enable(mr_ctx* h, int on) {
+  if (!h) return fail(MR_EINVAL, "mr_timing_enable: null context");
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  hipError_t e = c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "mr_timing_enable");
+  c->timer.reset();
+  c->timer.on = on != 0;
+  return MR_OK;
+}
+
+int mr_timing_read(mr_ctx* h, mr_timing* out) {
+  if (!h || !out) return fail(MR_EINVAL, "mr_timing_read: null argument");
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  hipError_t e = c->stream ? hipStreamSynchronize(c->stream) : hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "mr_timing_read");
+  if (c->timer.resolve() != MR_OK) return fail(MR_EHIP, "mr_timing_read: event query failed");
+  out->sweep64_ms = c->timer.ms[0];
+  out->sweep64_launches = c->timer.count[0];
+  out->sweep32_ms = c->timer.ms[1];
+  out->sweep32_launches = c->timer.count[1];
+  out->finest_cells = (int64_t)c->lv[0].cells;
+  return MR_OK;
+}
+
 int mr_residual(mr_ctx* h, const double* delta, const double* theta, double* r_out, double* rel_out,
                 double* msum_out) {
   if (!h || !delta || !theta) return fail(MR_EINVAL, "mr_residual: null argument");
   Ctx* c = reinterpret_cast<Ctx*>(h);
   Level& L0 = c->lv[0];
-  L0.delta = delta;
+  hipError_t e = launch_to_split(delta, L0.delta, L0.n, c->stream);
+  if (e == hipSuccess) e = launch_to_split(theta, L0.th[1], L0.n, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "mr_residual");
   int rc;
-  double r0, m0, n1, m1, n2, m2;
+  double r0, m0, n1, m1;
   if ((rc = c->finest_norm(nullptr, ShiftRef{nullptr, 0.0, 0.0}, &r0, &m0)) != MR_OK) return rc;
-  if ((rc = c->finest_norm(theta, ShiftRef{nullptr, 0.0, 0.0}, &n1, &m1)) != MR_OK) return rc;
-  // second pass with the exact mean of Sigma, writing r
-  hipError_t e = launch_residual(theta, delta, L0.n, 1.0, ShiftRef{nullptr, 0.0, m1}, r_out,
-                                 c->reducer(kSlotRes), kMaxReduceBlocks, c->stream);
+  if ((rc = c->finest_norm(L0.th[1], ShiftRef{nullptr, 0.0, 0.0}, &n1, &m1)) != MR_OK) return rc;
+  // second pass with the mean of Sigma, writing r in natural order
+  e = launch_residual(L0.th[1], L0.delta, L0.n, 1.0, ShiftRef{nullptr, 0.0, m1}, r_out, c->reducer(kSlotRes),
+                      c->stream);
   if (e != hipSuccess) return hip_fail(e, "residual");
   double r[2];
   if ((rc = c->read_scalars(kSlotRes, 2, r)) != MR_OK) return rc;
   const double var = r[1] - r[0] * r[0] / (double)L0.cells;
-  n2 = std::sqrt(var > 0 ? var : 0.0);
-  m2 = m1;
+  const double n2 = std::sqrt(var > 0 ? var : 0.0);
   if (rel_out) *rel_out = (r0 > 0.0) ? n2 / r0 : n2;
-  if (msum_out) *msum_out = m2;
-  (void)m0;
-  (void)n1;
+  if (msum_out) *msum_out = m1;
   return MR_OK;
 }
 
@@ -394,11 +585,11 @@ int mr_solve(mr_ctx* h, const double* delta, double* theta, mr_info* info) {
   return c->solve_fp64(delta, theta, info);
 }
 
-// ---- building blocks ----------------------------------------------------------------------
+// ---- building blocks (natural-order arguments; temporaries allocated per call) -------------
 
-static int check_level_size(Ctx* c, int nl) {
-  (void)c;
-  if (nl < 4 || nl % 4 != 0) return fail(MR_EINVAL, "level size %d: must be a multiple of 4", nl);
+static int check_level(int nl, bool coarsen) {
+  if (nl < 4 || nl % 2 != 0 || nl > 1024) return fail(MR_EINVAL, "level size %d not supported", nl);
+  if (coarsen && nl % 4 != 0) return fail(MR_EINVAL, "level size %d: must be a multiple of 4", nl);
   return MR_OK;
 }
 
@@ -406,76 +597,131 @@ int mr_sweep(mr_ctx* h, int nl, double hcell, const double* delta, const double*
              const double* theta_in, double* theta_out, double* sum_out) {
   if (!h || !delta || !theta_in || !theta_out || theta_in == theta_out)
     return fail(MR_EINVAL, "mr_sweep: bad pointers");
-  Ctx* c = reinterpret_cast<Ctx*>(h);
-  int rc = check_level_size(c, nl);
+  int rc = check_level(nl, true);
   if (rc != MR_OK) return rc;
-  TileCfg t = choose_tiles(nl, c->max_lds);
-  SweepArgs a{};
-  a.th_in = theta_in;
-  a.th_out = theta_out;
-  a.delta = delta;
-  a.f = f;
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  const size_t cells = (size_t)nl * nl * nl;
+  Temps tmp(c->stream);
+  double *ds = tmp.get(cells), *fs = f ? tmp.get(cells) : nullptr, *tin = tmp.get(cells), *tout = tmp.get(cells);
+  if (!ds || !tin || !tout || (f && !fs)) return fail(MR_ENOMEM, "mr_sweep: temporaries");
+  hipError_t e = launch_to_split(delta, ds, nl, c->stream);
+  if (e == hipSuccess && f) e = launch_to_split(f, fs, nl, c->stream);
+  if (e == hipSuccess) e = launch_to_split(theta_in, tin, nl, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "mr_sweep");
+  TileCfg t = sweep_tiles(nl);
+  HalfSweepArgs a{};
+  a.th_in = tin;
+  a.th_out = tout;
+  a.delta = ds;
+  a.f = fs;
   a.n = nl;
   a.h2 = hcell * hcell;
   a.ih2 = 1.0 / a.h2;
-  a.c_sum = nullptr;
-  a.c_scale = 0.0;
   a.c_add = cshift;
-  a.sum_out = c->scal + kSlotRes;
   a.partials = c->partials;
   a.counter = c->counter;
-  a.tj = t.tj;
-  a.tiles_j = t.tiles_j;
-  a.tiles_k = t.tiles_k;
-  a.ci = t.ci;
-  hipError_t e = launch_sweep(a, t.tk, c->stream);
-  if (e != hipSuccess) return hip_fail(e, "sweep");
-  double s;
-  if ((rc = c->read_scalars(kSlotRes, 1, &s)) != MR_OK) return rc;
-  if (sum_out) *sum_out = s;
+  a.colour = 0;
+  a.sum_out = c->scal + kSlotAux + 0;
+  e = launch_half_sweep(a, t, c->stream);
+  a.colour = 1;
+  a.th_red_new = tout;
+  a.sum_out = c->scal + kSlotAux + 1;
+  if (e == hipSuccess) e = launch_half_sweep(a, t, c->stream);
+  if (e == hipSuccess) e = launch_from_split(tout, theta_out, nl, nullptr, 0.0, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "mr_sweep");
+  double s[2];
+  if ((rc = c->read_scalars(kSlotAux, 2, s)) != MR_OK) return rc;
+  if (sum_out) *sum_out = s[0] + s[1];
   return MR_OK;
 }
 
 int mr_defect_restrict(mr_ctx* h, int nl, double hcell, const double* delta, const double* f,
                        double cshift, const double* theta, double* theta_c, double* dr_c) {
   if (!h || !delta || !theta || !theta_c || !dr_c) return fail(MR_EINVAL, "mr_defect_restrict: null argument");
+  int rc = check_level(nl, true);
+  if (rc != MR_OK) return rc;
   Ctx* c = reinterpret_cast<Ctx*>(h);
-  if (nl < 4 || nl % 2) return fail(MR_EINVAL, "bad level size");
-  hipError_t e = launch_defect_restrict(theta, delta, f, nl, hcell, ShiftRef{nullptr, 0.0, cshift},
-                                        theta_c, nullptr, dr_c, c->stream);
+  const size_t cells = (size_t)nl * nl * nl, cc = cells / 8;
+  Temps tmp(c->stream);
+  double *ds = tmp.get(cells), *fs = f ? tmp.get(cells) : nullptr, *ts = tmp.get(cells), *tcs = tmp.get(cc),
+         *drs = tmp.get(cc);
+  if (!ds || !ts || !tcs || !drs || (f && !fs)) return fail(MR_ENOMEM, "mr_defect_restrict: temporaries");
+  hipError_t e = launch_to_split(delta, ds, nl, c->stream);
+  if (e == hipSuccess && f) e = launch_to_split(f, fs, nl, c->stream);
+  if (e == hipSuccess) e = launch_to_split(theta, ts, nl, c->stream);
+  DefectArgs a{};
+  a.theta = ts;
+  a.delta = ds;
+  a.f = fs;
+  a.n = nl;
+  a.ih2 = 1.0 / (hcell * hcell);
+  a.c_add = cshift;
+  a.theta_c = tcs;
+  a.dr = drs;
+  a.sums_out = c->scal + kSlotAux;
+  a.partials = c->partials;
+  a.counter = c->counter;
+  if (e == hipSuccess) e = launch_defect_restrict_tiled(a, defect_tiles(nl), c->stream);
+  if (e == hipSuccess) e = launch_from_split(tcs, theta_c, nl / 2, nullptr, 0.0, c->stream);
+  if (e == hipSuccess) e = launch_from_split(drs, dr_c, nl / 2, nullptr, 0.0, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  return e == hipSuccess ? MR_OK : hip_fail(e, "defect_restrict");
+  return e == hipSuccess ? MR_OK : hip_fail(e, "mr_defect_restrict");
 }
 
 int mr_tau_rhs(mr_ctx* h, int nl, double hcell, const double* delta, const double* theta_hat,
                const double* rd, double* f_out, double* sum_out) {
   if (!h || !delta || !theta_hat || !rd || !f_out) return fail(MR_EINVAL, "mr_tau_rhs: null argument");
+  int rc = check_level(nl, false);
+  if (rc != MR_OK) return rc;
   Ctx* c = reinterpret_cast<Ctx*>(h);
-  if (nl < 2 || nl % 2) return fail(MR_EINVAL, "bad level size");
-  hipError_t e = launch_tau(theta_hat, delta, rd, f_out, nl, hcell, c->reducer(kSlotRes), kMaxReduceBlocks, c->stream);
-  if (e != hipSuccess) return hip_fail(e, "tau");
+  const size_t cells = (size_t)nl * nl * nl;
+  Temps tmp(c->stream);
+  double *ds = tmp.get(cells), *ts = tmp.get(cells), *rs = tmp.get(cells);
+  if (!ds || !ts || !rs) return fail(MR_ENOMEM, "mr_tau_rhs: temporaries");
+  hipError_t e = launch_to_split(delta, ds, nl, c->stream);
+  if (e == hipSuccess) e = launch_to_split(theta_hat, ts, nl, c->stream);
+  if (e == hipSuccess) e = launch_to_split(rd, rs, nl, c->stream);
+  if (e == hipSuccess) e = launch_tau(ts, ds, rs, rs, nl, hcell, c->reducer(kSlotAux), c->stream);
+  if (e == hipSuccess) e = launch_from_split(rs, f_out, nl, nullptr, 0.0, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "mr_tau_rhs");
   double s;
-  int rc = c->read_scalars(kSlotRes, 1, &s);
-  if (rc == MR_OK && sum_out) *sum_out = s;
-  return rc;
+  if ((rc = c->read_scalars(kSlotAux, 1, &s)) != MR_OK) return rc;
+  if (sum_out) *sum_out = s;
+  return MR_OK;
 }
 
 int mr_prolong_correct(mr_ctx* h, int nl, const double* theta_c, const double* theta_hat_c, double* theta) {
   if (!h || !theta_c || !theta_hat_c || !theta) return fail(MR_EINVAL, "mr_prolong_correct: null argument");
+  int rc = check_level(nl, true);
+  if (rc != MR_OK) return rc;
   Ctx* c = reinterpret_cast<Ctx*>(h);
-  if (nl < 4 || nl % 2) return fail(MR_EINVAL, "bad level size");
-  hipError_t e = launch_prolong_correct(theta_c, theta_hat_c, theta, nl, c->stream);
+  const size_t cells = (size_t)nl * nl * nl, cc = cells / 8;
+  Temps tmp(c->stream);
+  double *a = tmp.get(cc), *b = tmp.get(cc), *t = tmp.get(cells);
+  if (!a || !b || !t) return fail(MR_ENOMEM, "mr_prolong_correct: temporaries");
+  hipError_t e = launch_to_split(theta_c, a, nl / 2, c->stream);
+  if (e == hipSuccess) e = launch_to_split(theta_hat_c, b, nl / 2, c->stream);
+  if (e == hipSuccess) e = launch_to_split(theta, t, nl, c->stream);
+  if (e == hipSuccess) e = launch_prolong_correct(a, b, t, nl, c->stream);
+  if (e == hipSuccess) e = launch_from_split(t, theta, nl, nullptr, 0.0, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  return e == hipSuccess ? MR_OK : hip_fail(e, "prolong_correct");
+  return e == hipSuccess ? MR_OK : hip_fail(e, "mr_prolong_correct");
 }
 
 int mr_restrict(mr_ctx* h, int nl, const double* fine, double* coarse) {
   if (!h || !fine || !coarse) return fail(MR_EINVAL, "mr_restrict: null argument");
+  int rc = check_level(nl, true);
+  if (rc != MR_OK) return rc;
   Ctx* c = reinterpret_cast<Ctx*>(h);
-  if (nl < 2 || nl % 2) return fail(MR_EINVAL, "bad level size");
-  hipError_t e = launch_restrict(fine, coarse, nl, c->stream);
+  const size_t cells = (size_t)nl * nl * nl, cc = cells / 8;
+  Temps tmp(c->stream);
+  double *a = tmp.get(cells), *b = tmp.get(cc);
+  if (!a || !b) return fail(MR_ENOMEM, "mr_restrict: temporaries");
+  hipError_t e = launch_to_split(fine, a, nl, c->stream);
+  if (e == hipSuccess) e = launch_restrict(a, b, nl, c->stream);
+  if (e == hipSuccess) e = launch_from_split(b, coarse, nl / 2, nullptr, 0.0, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  return e == hipSuccess ? MR_OK : hip_fail(e, "restrict");
+  return e == hipSuccess ? MR_OK : hip_fail(e, "mr_restrict");
 }
 
 }  // extern "C"

@@ -12,29 +12,42 @@
 
 namespace mr {
 
-// Device scalar slots: running sums of (Sigma + f) per level, reduction results, gauge.
-constexpr int kSlotLevel = 0;    // 0..31
+// Device scalar slots: per level the running sums (red, black) of Sigma + f of the last sweep
+// and a staging slot; reduction results; gauge; scratch for the mixed / adjoint drivers.
+constexpr int kSlotLevel = 0;    // 3 per level: [0] red sum, [1] black sum, [2] staging
+constexpr int kMaxLevels = 10;
 constexpr int kSlotRes = 32;     // 4 values
 constexpr int kSlotGauge = 36;
-constexpr int kSlotAux = 40;     // 8 values for the mixed / adjoint drivers
+constexpr int kSlotAux = 40;     // 16 values
 constexpr int kSlotCount = 64;
 constexpr int kHostSlots = 80;
 
-struct TileCfg {
-  int tk = 64, tj = 8, ci = 32, tiles_j = 1, tiles_k = 1;
-};
-
+// One mesh of the hierarchy. All fields colour-split; th[0], th[1] are the ping-pong buffers
+// (both colours each), th[cur] the current iterate.
 struct Level {
   int n = 0;
   size_t cells = 0;
   double h = 1.0;
   double* th[2] = {nullptr, nullptr};
   int cur = 0;
-  double* that = nullptr;
-  const double* delta = nullptr;
-  double* delta_own = nullptr;
-  double* f = nullptr;
-  TileCfg tile;
+  double* that = nullptr;   // R theta_hat saved for the correction (levels >= 1)
+  double* delta = nullptr;
+  double* f = nullptr;      // FAS right-hand side (levels >= 1)
+  TileCfg sw, df;           // tiles of the half-sweep and of the defect + restriction
+};
+
+struct EventTimer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, int>> pending[2];   // [0] fp64 sweeps, [1] fp32 sweeps
+  double ms[2] = {0.0, 0.0};
+  int64_t count[2] = {0, 0};
+  size_t next = 0;
+  int begin(hipStream_t s);                      // returns event index or -1
+  void end(int kind, int start, hipStream_t s);
+  int resolve();
+  void reset();
+  void destroy();
 };
 
 struct MixedState;
@@ -45,12 +58,12 @@ struct Ctx {
   hipStream_t stream = nullptr;
   mr_opts opts{};
   std::vector<Level> lv;
-  double* ws_theta0 = nullptr;
   double* scal = nullptr;
   double* partials = nullptr;
   unsigned int* counter = nullptr;
   double* host = nullptr;
   std::vector<void*> owned;
+  EventTimer timer;
   MixedState* mixed = nullptr;
   AdjointState* adj = nullptr;
 
@@ -58,10 +71,13 @@ struct Ctx {
   Reduce reducer(int slot);
   int read_scalars(int slot, int count, double* out);
   int write_scalar(int slot, double v);
+  double* lsum(int l) { return scal + kSlotLevel + 3 * l; }
   int sweep(int l);
+  int down(int l, double* norm_sums);
+  int up(int l);
   int vcycle(int l);
-  int finest_norm(const double* theta, ShiftRef sh, double* nrm, double* msig);
-  int prepare(const double* delta, double* theta);
+  int finest_norm(const double* theta_split, ShiftRef sh, double* nrm, double* msig);
+  int prepare(const double* delta_natural);
   int solve_fp64(const double* delta, double* theta, mr_info* info);
   int solve_mixed(const double* delta, double* theta, mr_info* info);
   void release_extra();
@@ -70,6 +86,7 @@ struct Ctx {
 int fail(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* where);
 std::vector<int> level_sizes(int n);
-TileCfg choose_tiles(int n, int max_lds);
+TileCfg sweep_tiles(int n);
+TileCfg defect_tiles(int n);
 
 }  // namespace mr

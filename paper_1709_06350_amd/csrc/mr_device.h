@@ -73,6 +73,31 @@ __device__ __forceinline__ double sigma_cell(const Nb18& t, double opd, double i
   return largest_root(p, q) - 3.0;
 }
 
+// ---- colour-split layout --------------------------------------------------------------------
+// Inside the solver every n^3 field is stored colour-split: [c][i][j][m] with c = (i+j+k) & 1
+// (0 red, 1 black) and m = k >> 1, so that each half-sweep streams one contiguous colour.
+// In row (i, j) the cells of colour c sit at k = 2m + ((i + j + c) & 1).
+__device__ __forceinline__ unsigned split_idx(int n, int i, int j, int k) {
+  const unsigned half = (unsigned)n * (unsigned)n * (unsigned)(n >> 1);
+  return ((i + j + k) & 1) * half + ((unsigned)i * n + j) * (unsigned)(n >> 1) + (unsigned)(k >> 1);
+}
+
+// Gather the 18 neighbours of (i, j, k) from a colour-split periodic n^3 field.
+__device__ __forceinline__ void gather18_split(const double* __restrict__ a, int n, int i, int j, int k, Nb18& t) {
+  const int im = wrapi(i - 1, n), ip = wrapi(i + 1, n);
+  const int jm = wrapi(j - 1, n), jp = wrapi(j + 1, n);
+  const int km = wrapi(k - 1, n), kp = wrapi(k + 1, n);
+  t.xm = a[split_idx(n, im, j, k)]; t.xp = a[split_idx(n, ip, j, k)];
+  t.ym = a[split_idx(n, i, jm, k)]; t.yp = a[split_idx(n, i, jp, k)];
+  t.zm = a[split_idx(n, i, j, km)]; t.zp = a[split_idx(n, i, j, kp)];
+  t.xpyp = a[split_idx(n, ip, jp, k)]; t.xmym = a[split_idx(n, im, jm, k)];
+  t.xpym = a[split_idx(n, ip, jm, k)]; t.xmyp = a[split_idx(n, im, jp, k)];
+  t.xpzp = a[split_idx(n, ip, j, kp)]; t.xmzm = a[split_idx(n, im, j, km)];
+  t.xpzm = a[split_idx(n, ip, j, km)]; t.xmzp = a[split_idx(n, im, j, kp)];
+  t.ypzp = a[split_idx(n, i, jp, kp)]; t.ymzm = a[split_idx(n, i, jm, km)];
+  t.ypzm = a[split_idx(n, i, jp, km)]; t.ymzp = a[split_idx(n, i, jm, kp)];
+}
+
 // Gather the 18 neighbours of (i, j, k) from a periodic n^3 array in global memory.
 __device__ __forceinline__ void gather18(const double* __restrict__ a, int n, int i, int j, int k, Nb18& t) {
   const int im = wrapi(i - 1, n), ip = wrapi(i + 1, n);
@@ -126,7 +151,7 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double (*red)[NV], in
 // All threads of the block must call this. On return, thread 0 of the last block has written
 // result[0..NV-1]. nblocks is the number of blocks of the launch, bid this block's index.
 template <int NV>
-__device__ void grid_sum(double (&v)[NV], double* __restrict__ partials, unsigned int* counter,
+__device__ bool grid_sum(double (&v)[NV], double* __restrict__ partials, unsigned int* counter,
                          double* result, int nblocks, int bid) {
   __shared__ double red[16][NV];
   __shared__ int am_last;
@@ -140,7 +165,7 @@ __device__ void grid_sum(double (&v)[NV], double* __restrict__ partials, unsigne
     am_last = (prev == (unsigned)(nblocks - 1));
   }
   __syncthreads();
-  if (!am_last) return;
+  if (!am_last) return false;
   double w[NV];
 #pragma unroll
   for (int c = 0; c < NV; ++c) w[c] = 0.0;
@@ -155,6 +180,7 @@ __device__ void grid_sum(double (&v)[NV], double* __restrict__ partials, unsigne
     for (int c = 0; c < NV; ++c) result[c] = w[c];
     __hip_atomic_store(counter, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
+  return true;
 }
 
 // Map a launch-order block index to a logical tile index so that each of the 8 XCDs (which

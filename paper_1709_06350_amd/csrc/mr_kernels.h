@@ -8,31 +8,62 @@
 namespace mr {
 
 constexpr int kMaxCoarsest = 12 * 12 * 12;
-constexpr int kMaxReduceBlocks = 8192;   // partial-sum slots (blocks of a reducing launch)
+constexpr int kMaxReduceBlocks = 16384;  // partial-sum slots (blocks of a reducing launch)
 constexpr int kMaxNV = 4;                // values reduced per launch
 
+// Tile of the 2.5D kernels: tm columns (m = k >> 1) x tj rows (j), chunks of ci planes (i).
+struct TileCfg {
+  int tm = 64, tj = 4, ci = 32, tiles_j = 1, tiles_m = 1, cpt = 1;   // cpt: cells per thread per plane
+};
+
 // The uniform shift subtracted from the source in a relaxation or defect is
-// C = (c_sum ? *c_sum * c_scale : 0) + c_add: either a device-resident running sum of
-// (Sigma + f) from the previous pass, or an explicit value.
+// C = (c_sum ? (c_sum[0] + c_sum[1]) * c_scale : 0) + c_add: either device-resident running sums
+// of (Sigma + f) of the two colours from the previous sweep, or an explicit value.
 struct ShiftRef {
   const double* c_sum;
   double c_scale;
   double c_add;
 };
 
-struct SweepArgs {
+// One colour's half-sweep. th_in holds both colours of the snapshot; for the black half-sweep
+// th_red_new points at the new red values (colour 0 half of th_out). Writes colour `colour` of
+// th_out. sum_out receives sum over the colour of (Sigma + f); after that, the last block copies
+// *copy_from to *copy_to when copy_to is set.
+struct HalfSweepArgs {
   const double* th_in;
+  const double* th_red_new;
   double* th_out;
   const double* delta;
   const double* f;        // may be null
-  int n;
+  int n, colour;
   double h2, ih2;
   const double* c_sum;
   double c_scale, c_add;
-  double* sum_out;        // device: sum over cells of (Sigma + f)
+  double* sum_out;
+  const double* copy_from;
+  double* copy_to;
   double* partials;
   unsigned int* counter;
-  int tj, tiles_j, tiles_k, ci;
+  int tj, tiles_j, tiles_m, ci;
+};
+
+// Fused defect + restriction: theta_c (and theta_c2) = R theta, dr = R d with
+// d = nabla^2 theta - Sigma - f + C; sums_out[0..1] = sum d, sum d^2 over the fine mesh.
+struct DefectArgs {
+  const double* theta;
+  const double* delta;
+  const double* f;        // may be null
+  int n;
+  double ih2;
+  const double* c_sum;
+  double c_scale, c_add;
+  double* theta_c;
+  double* theta_c2;       // may be null
+  double* dr;
+  double* sums_out;
+  double* partials;
+  unsigned int* counter;
+  int tj, tiles_j, tiles_m, ci;
 };
 
 struct CoarsestArgs {
@@ -43,7 +74,7 @@ struct CoarsestArgs {
   double h2, ih2;
   const double* c_sum;
   double c_scale, c_add;
-  double* c_sum_out;      // may be null
+  double* c_sum_out;      // may be null; receives (sum, 0)
 };
 
 struct Reduce {
@@ -52,32 +83,31 @@ struct Reduce {
   double* result;         // device, up to 4 values
 };
 
-size_t sweep_lds_bytes(int tj, int tk);
-hipError_t launch_sweep(const SweepArgs& a, int tk, hipStream_t s);
+size_t tile_lds_bytes(int tj, int tm);
+hipError_t launch_half_sweep(const HalfSweepArgs& a, const TileCfg& t, hipStream_t s);
+bool half_sweep_tile_supported(int tm, int tj, int cpt);
+hipError_t launch_defect_restrict_tiled(const DefectArgs& a, const TileCfg& t, hipStream_t s);
 hipError_t launch_coarsest(const CoarsestArgs& a, hipStream_t s);
 
-// theta_c = R theta, dr = R (nabla^2 theta - Sigma - f + C) on the coarse mesh.
-hipError_t launch_defect_restrict(const double* theta, const double* delta, const double* f,
-                                  int n, double h, ShiftRef c, double* theta_c, double* theta_c2,
-                                  double* dr, hipStream_t s);
-// f = nabla^2 th - Sigma(th) - rd on an n^3 mesh (f may alias rd); result[0] = sum(Sigma + f).
+// All fields below are colour-split unless named "natural".
+// f = nabla^2 th - Sigma(th) - rd on an n^3 mesh (f may alias rd); result[0..1] = (sum(Sigma + f), 0).
 hipError_t launch_tau(const double* th, const double* delta, const double* rd, double* f, int n,
-                      double h, Reduce red, int max_blocks, hipStream_t s);
-// theta += P(tc - that) from the (n/2)^3 mesh onto the n^3 mesh.
-hipError_t launch_prolong_correct(const double* tc, const double* that, double* theta, int n,
-                                  hipStream_t s);
+                      double h, Reduce red, hipStream_t s);
+// theta += P(tc - that) from the (n/2)^3 mesh onto the n^3 mesh; that is overwritten with tc - that.
+hipError_t launch_prolong_correct(const double* tc, double* that, double* theta, int n, hipStream_t s);
 // coarse = 8-son mean of fine (fine n^3).
 hipError_t launch_restrict(const double* fine, double* coarse, int n, hipStream_t s);
-// b = nabla^2 theta - Sigma + shift on the n^3 mesh (theta == null means theta = 0);
-// result[0] = sum b, result[1] = sum b^2; r_out (may be null) receives b.
-hipError_t launch_residual(const double* theta, const double* delta, int n, double h,
-                           ShiftRef shift, double* r_out, Reduce red, int max_blocks, hipStream_t s);
-// result[0] = number of cells with a non-finite delta or 1 + delta <= 0.
-hipError_t launch_validate(const double* delta, size_t cells, Reduce red, int max_blocks, hipStream_t s);
+// b = nabla^2 theta - Sigma + shift (theta == null means theta = 0); result[0] = sum b,
+// result[1] = sum b^2; r_natural (may be null) receives b in natural order.
+hipError_t launch_residual(const double* theta, const double* delta, int n, double h, ShiftRef shift,
+                           double* r_natural, Reduce red, hipStream_t s);
+// natural -> colour-split and back; from_split subtracts (*sum) * scale when sum is given.
+hipError_t launch_to_split(const double* natural, double* split, int n, hipStream_t s);
+hipError_t launch_from_split(const double* split, double* natural, int n, const double* sum, double scale,
+                             hipStream_t s);
+// result[0] = number of entries with a non-finite value or 1 + value <= 0.
+hipError_t launch_validate(const double* delta, size_t cells, Reduce red, hipStream_t s);
 // result[0] = sum of a (size cells).
-hipError_t launch_sum(const double* a, size_t cells, Reduce red, int max_blocks, hipStream_t s);
-// out = in - (*sum) * scale (in and out may alias).
-hipError_t launch_shift_copy(const double* in, double* out, size_t cells, const double* sum,
-                             double scale, hipStream_t s);
+hipError_t launch_sum(const double* a, size_t cells, Reduce red, hipStream_t s);
 
 }  // namespace mr

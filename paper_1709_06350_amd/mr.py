@@ -30,7 +30,7 @@ EXPORTED = [
     "mr_default_opts", "mr_create", "mr_destroy", "mr_set_opts", "mr_size", "mr_levels",
     "mr_deposit_cic", "mr_residual", "mr_solve", "mr_adjoint_solve", "mr_solve_batched",
     "mr_sweep", "mr_defect_restrict", "mr_tau_rhs", "mr_prolong_correct", "mr_restrict",
-    "mr_last_error",
+    "mr_timing_enable", "mr_timing_read", "mr_last_error",
 ]
 
 
@@ -57,6 +57,16 @@ class mr_info(ctypes.Structure):
         ("m_shift", ctypes.c_double),
         ("seconds", ctypes.c_double),
         ("history", ctypes.c_double * 128),
+    ]
+
+
+class mr_timing(ctypes.Structure):
+    _fields_ = [
+        ("sweep64_ms", ctypes.c_double),
+        ("sweep64_launches", ctypes.c_int64),
+        ("sweep32_ms", ctypes.c_double),
+        ("sweep32_launches", ctypes.c_int64),
+        ("finest_cells", ctypes.c_int64),
     ]
 
 
@@ -100,6 +110,8 @@ def load(path: Optional[str] = None):
     lib.mr_tau_rhs.argtypes = [vp, ip, ctypes.c_double, vp, vp, vp, vp, dp]
     lib.mr_prolong_correct.argtypes = [vp, ip, vp, vp, vp]
     lib.mr_restrict.argtypes = [vp, ip, vp, vp]
+    lib.mr_timing_enable.argtypes = [vp, ip]
+    lib.mr_timing_read.argtypes = [vp, ctypes.POINTER(mr_timing)]
     lib.mr_last_error.argtypes = []
     lib.mr_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -225,6 +237,16 @@ class Context:
         if check:
             _check(code)
         return out, Info.from_c(info)
+
+    def timing_enable(self, on: bool = True):
+        _check(self.lib.mr_timing_enable(self.h, 1 if on else 0))
+
+    def timing_read(self) -> dict:
+        t = mr_timing()
+        _check(self.lib.mr_timing_read(self.h, ctypes.byref(t)))
+        return dict(sweep64_ms=t.sweep64_ms, sweep64_launches=t.sweep64_launches,
+                    sweep32_ms=t.sweep32_ms, sweep32_launches=t.sweep32_launches,
+                    finest_cells=t.finest_cells)
 
     # -- building blocks ---------------------------------------------------------------------
     def sweep(self, delta, theta_in, h=1.0, f=None, cshift=0.0, out=None):

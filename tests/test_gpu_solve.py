@@ -45,11 +45,13 @@ def test_solve_matches_oracle(n, sigma, rc, seed):
 
 
 def test_config0_cycles_and_history():
+    # history[0] is the start; history[c] is measured after the pre-relaxation of cycle c, so the
+    # first entry follows relaxation only (no coarse correction yet) and may exceed the start.
     delta = inputs.config0_delta()
     theta, info = _gpu_solve(delta)
     assert info.cycles <= 16
     hist = np.array(info.history)
-    assert np.all(np.diff(hist) < 0)
+    assert np.all(np.diff(hist[1:]) < 0) and hist[-1] <= 1e-10
 
 
 def test_separable_closed_form_on_gpu():
