@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
+#include <cmath>
 #include <cstdarg>
 #include <string>
 #include <vector>
@@ -19,7 +21,8 @@ constexpr int kMaxLevels = 10;
 constexpr int kSlotRes = 32;     // 4 values
 constexpr int kSlotGauge = 36;
 constexpr int kSlotAux = 40;     // 16 values
-constexpr int kSlotCount = 64;
+constexpr int kSlotLin = 64;     // 3 per level: running sums of the linear (FP32 / adjoint) smoother
+constexpr int kSlotCount = 128;
 constexpr int kHostSlots = 80;
 
 // One mesh of the hierarchy. All fields colour-split; th[0], th[1] are the ping-pong buffers
@@ -80,7 +83,11 @@ struct Ctx {
   int prepare(const double* delta_natural);
   int solve_fp64(const double* delta, double* theta, mr_info* info);
   int solve_mixed(const double* delta, double* theta, mr_info* info);
+  double* linsum(int l);
+  int lin_sweep(int l);
+  int lin_vcycle(int l);
   void release_extra();
+  void release_adjoint();
 };
 
 int fail(int code, const char* fmt, ...);

@@ -77,6 +77,27 @@ struct CoarsestArgs {
   double* c_sum_out;      // may be null; receives (sum, 0)
 };
 
+// FP32 half-sweep of the linearised operator (mixed precision): e colour `colour` from the
+// snapshot e_in (black half-sweep: red from e_red_new), base potential / root / rhs colour-split.
+struct LinSweepArgs {
+  const float* e_in;
+  const float* e_red_new;
+  float* e_out;
+  const float* base;
+  const float* sb;
+  const float* rhs;
+  int n, colour;
+  float h2, ih2;
+  const double* c_sum;
+  double c_scale, c_add;
+  double* sum_out;
+  const double* copy_from;
+  double* copy_to;
+  double* partials;
+  unsigned int* counter;
+  int tiles_j, tiles_m, ci;
+};
+
 struct Reduce {
   double* partials;
   unsigned int* counter;
@@ -109,5 +130,20 @@ hipError_t launch_from_split(const double* split, double* natural, int n, const 
 hipError_t launch_validate(const double* delta, size_t cells, Reduce red, hipStream_t s);
 // result[0] = sum of a (size cells).
 hipError_t launch_sum(const double* a, size_t cells, Reduce red, hipStream_t s);
+
+// ---- mixed precision (FP32 linearised multigrid) ----
+bool lin_tile_supported(int tm, int tj);
+hipError_t launch_lin_half_sweep(const LinSweepArgs& a, const TileCfg& t, hipStream_t s);
+hipError_t launch_mixed_resid64(const double* theta, const double* delta, int n, double C, float* rhs32, float* base32,
+                                float* sb32, Reduce red, hipStream_t s);
+hipError_t launch_base_root(const float* base32, const double* delta, int n, double h, float* sb32, hipStream_t s);
+hipError_t launch_restrict32(const float* fine, float* coarse, int n, hipStream_t s);
+hipError_t launch_lin_resid_restrict(const float* e, const float* base, const float* sb, const float* rhs, int n, double h,
+                                     ShiftRef c, float* rhs_c, Reduce red, hipStream_t s);
+hipError_t launch_prolong_add32(const float* ec, float* e, int n, hipStream_t s);
+hipError_t launch_lin_coarsest(float* e, const float* base, const float* sb, const float* rhs, int n, int nsweeps, double h,
+                               const double* c_sum, double c_scale, hipStream_t s);
+hipError_t launch_update64(double* theta, const float* e, size_t cells, hipStream_t s);
+hipError_t launch_fill32(float* a, float v, size_t cells, hipStream_t s);
 
 }  // namespace mr

@@ -2,8 +2,7 @@
 #include "mr.h"
 #include "mr_ctx.h"
 namespace mr {
-int Ctx::solve_mixed(const double*, double*, mr_info*) { return fail(MR_EINVAL, "mixed precision not available"); }
-void Ctx::release_extra() {}
+void Ctx::release_adjoint() {}
 }
 extern "C" {
 int mr_deposit_cic(mr_ctx*, const double*, int64_t, double, double*) { return mr::fail(MR_EINVAL, "not available"); }
