@@ -528,6 +528,10 @@ static int mixed_alloc(Ctx* c) {
 }
 
 void Ctx::release_extra() {
+  if (cic_grid) {
+    (void)hipFree(cic_grid);
+    cic_grid = nullptr;
+  }
   if (mixed) {
     for (void* p : mixed->owned) (void)hipFree(p);
     delete mixed;

@@ -67,6 +67,7 @@ struct Ctx {
   double* host = nullptr;
   std::vector<void*> owned;
   EventTimer timer;
+  unsigned long long* cic_grid = nullptr;   // fixed-point CIC accumulation grid (allocated on first use)
   MixedState* mixed = nullptr;
   AdjointState* adj = nullptr;
 
@@ -83,6 +84,7 @@ struct Ctx {
   int prepare(const double* delta_natural);
   int solve_fp64(const double* delta, double* theta, mr_info* info);
   int solve_mixed(const double* delta, double* theta, mr_info* info);
+  int deposit_cic(const double* pos, long long np, double mass, double* delta_out);
   double* linsum(int l);
   int lin_sweep(int l);
   int lin_vcycle(int l);

@@ -5,7 +5,6 @@ namespace mr {
 void Ctx::release_adjoint() {}
 }
 extern "C" {
-int mr_deposit_cic(mr_ctx*, const double*, int64_t, double, double*) { return mr::fail(MR_EINVAL, "not available"); }
 int mr_adjoint_solve(mr_ctx*, const double*, const double*, const double*, double*, mr_info*) { return mr::fail(MR_EINVAL, "not available"); }
 int mr_solve_batched(int, const int*, const double* const*, double* const*, const mr_opts*, mr_info*, void*) { return mr::fail(MR_EINVAL, "not available"); }
 }
