@@ -4,4 +4,5 @@ The computation lives in the HIP library libmr.so (C ABI in include/mr.h); ``mr`
 ctypes binding and ``autograd`` wraps the solve and its adjoint as a torch.autograd.Function.
 """
 from . import mr  # noqa: F401
+from . import autograd  # noqa: F401
 from .mr import Context, Info, MRError, solve_batched  # noqa: F401

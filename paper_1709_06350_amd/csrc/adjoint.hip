@@ -1,0 +1,436 @@
+// Adjoint of the solve: gradient of a loss L(theta(delta)) with respect to delta, FP64.
+//
+// With F(theta, delta) = nabla^2 theta - Sigma + <Sigma> (the mean-projected operator of Sec. II.A.1,
+// Eq. 15) and the gauge <theta> = 0, dL/d(delta) = D * (lambda - <lambda>) where
+// J_p^T lambda = g - <g>, g = dL/dtheta, J_p the Jacobian of F and D = dSigma/d(delta) =
+// 27 / (3 s^2 + p) (implicit differentiation of the physical root of the cubic, Sec. II,
+// Eqs. 8-10). For mean-free lambda, J_p^T lambda = J^T lambda with J the 19-point stencil
+//   (J e)_c = [sum_a A_a(c) S_a(e) - 6 e_c - sum_{a<b} W_ab(c) D_ab(e) / 2] / h^2,
+//   A_a = 1 - Wbar_aa, W = (9 s Mbar - 27 Mbar^2) / (3 s^2 + p),
+// so the transpose gathers each neighbour's coefficient times its lambda:
+//   (J^T l)_c = [sum_a (A_a l)(c +- e_a) - 6 l_c - sum_{a<b} D_ab(W_ab l)(c) / 2] / h^2.
+// It is solved by a linear multigrid (red-black Gauss-Seidel on J^T with the -6/h^2 diagonal,
+// 8-son restriction, trilinear prolongation) whose coefficients are rebuilt on every level from
+// the restricted theta_star and delta (no forward V-cycle state is stored). lambda is kept
+// mean-free after every sweep: each level's array is stored with a uniform offset mu (the mean of
+// the last sweep's output), which every read subtracts.
+#include <chrono>
+#include <cmath>
+
+#include "mr.h"
+#include "mr_ctx.h"
+#include "mr_device.h"
+#include "mr_kernels.h"
+
+namespace mr {
+
+struct AdjLevel {
+  double* lam[2] = {nullptr, nullptr};
+  int cur = 0;
+  double* rhs = nullptr;
+  double* coef = nullptr;   // 6 fields: A_x, A_y, A_z, W_xy, W_xz, W_yz (each colour-split n^3)
+};
+
+struct AdjointState {
+  std::vector<AdjLevel> lv;
+  double* D = nullptr;      // dSigma/d(delta) on the finest mesh (colour-split)
+  std::vector<void*> owned;
+};
+
+// ---- coefficient fields --------------------------------------------------------------------
+
+__global__ void __launch_bounds__(256) adj_coef_kernel(const double* __restrict__ theta, const double* __restrict__ delta,
+                                                       int n, double ih2, double* __restrict__ coef,
+                                                       double* __restrict__ Dout) {
+  const size_t cells = (size_t)n * n * n;
+  const int row = xcd_remap(blockIdx.x, gridDim.x);
+  const int i = row / n, j = row - i * n;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const unsigned e = split_idx(n, i, j, k);
+    Nb18 t;
+    gather18_split(theta, n, i, j, k, t);
+    double S;
+    const double sig = sigma_cell(t, 1.0 + delta[e], ih2, S);
+    const double s = sig + 3.0;
+    const double Sx = t.xm + t.xp, Sy = t.ym + t.yp, Sz = t.zm + t.zp;
+    const double s3 = (Sx + Sy + Sz) * (1.0 / 3.0);
+    const double mx = (Sx - s3) * ih2, my = (Sy - s3) * ih2, mz = (Sz - s3) * ih2;
+    const double mxy = 0.25 * ((t.xpyp + t.xmym) - (t.xpym + t.xmyp)) * ih2;
+    const double mxz = 0.25 * ((t.xpzp + t.xmzm) - (t.xpzm + t.xmzp)) * ih2;
+    const double myz = 0.25 * ((t.ypzp + t.ymzm) - (t.ypzm + t.ymzp)) * ih2;
+    const double xy2 = mxy * mxy, xz2 = mxz * mxz, yz2 = myz * myz;
+    const double T2 = mx * mx + my * my + mz * mz + 2.0 * (xy2 + xz2 + yz2);
+    const double den = 3.0 * s * s - 4.5 * T2;
+    const double inv = 1.0 / den;
+    const double s9 = 9.0 * s, q9 = 9.0 * T2;
+    coef[0 * cells + e] = 1.0 - (s9 * mx - 27.0 * (mx * mx + xy2 + xz2) + q9) * inv;
+    coef[1 * cells + e] = 1.0 - (s9 * my - 27.0 * (xy2 + my * my + yz2) + q9) * inv;
+    coef[2 * cells + e] = 1.0 - (s9 * mz - 27.0 * (xz2 + yz2 + mz * mz) + q9) * inv;
+    coef[3 * cells + e] = (s9 * mxy - 27.0 * (mx * mxy + mxy * my + mxz * myz)) * inv;
+    coef[4 * cells + e] = (s9 * mxz - 27.0 * (mx * mxz + mxy * myz + mxz * mz)) * inv;
+    coef[5 * cells + e] = (s9 * myz - 27.0 * (mxy * mxz + my * myz + myz * mz)) * inv;
+    if (Dout) Dout[e] = 27.0 * inv;
+  }
+}
+
+// Off-diagonal part of h^2 (J^T l)_c from neighbours' coefficients and (mean-adjusted) lambda.
+// lam(i,j,k) is supplied by the caller (it knows which colour carries which offset).
+template <class LamAt>
+__device__ __forceinline__ double adj_offdiag(const double* __restrict__ coef, size_t cells, int n, int i, int j, int k,
+                                              LamAt lam) {
+  const int im = wrapi(i - 1, n), ip = wrapi(i + 1, n);
+  const int jm = wrapi(j - 1, n), jp = wrapi(j + 1, n);
+  const int km = wrapi(k - 1, n), kp = wrapi(k + 1, n);
+  auto AL = [&](int f, int a, int b, int c) {
+    const unsigned g = split_idx(n, a, b, c);
+    return coef[f * cells + g] * lam(a, b, c, g);
+  };
+  double off = AL(0, im, j, k) + AL(0, ip, j, k) + AL(1, i, jm, k) + AL(1, i, jp, k) + AL(2, i, j, km) + AL(2, i, j, kp);
+  const double dxy = (AL(3, ip, jp, k) + AL(3, im, jm, k)) - (AL(3, ip, jm, k) + AL(3, im, jp, k));
+  const double dxz = (AL(4, ip, j, kp) + AL(4, im, j, km)) - (AL(4, ip, j, km) + AL(4, im, j, kp));
+  const double dyz = (AL(5, i, jp, kp) + AL(5, i, jm, km)) - (AL(5, i, jp, km) + AL(5, i, jm, kp));
+  return off - 0.5 * (dxy + dxz + dyz);
+}
+
+// One colour of a red-black Gauss-Seidel sweep on J^T l = rhs. Stored arrays carry the offset mu
+// (mean of the previous sweep's output): the red pass subtracts it from both colours, the black
+// pass from the old black values only (the new red values are read as written). Sums the new
+// values (the next offset).
+__global__ void __launch_bounds__(256) adj_half_sweep_kernel(const double* __restrict__ lam_in,
+    const double* __restrict__ red_new, double* __restrict__ out, const double* __restrict__ rhs,
+    const double* __restrict__ coef, int n, int colour, double h2, const double* mu_sum, double mu_scale,
+    double* sum_out, const double* copy_from, double* copy_to, Reduce red) {
+  const size_t cells = (size_t)n * n * n;
+  const unsigned half = (unsigned)(cells / 2);
+  const double mu = mu_sum ? (mu_sum[0] + mu_sum[1]) * mu_scale : 0.0;
+  double acc = 0.0;
+  const int nh = n >> 1;
+  const int rows = n * n;
+  const int rpb = (rows + gridDim.x - 1) / gridDim.x;
+  const int r0 = xcd_remap(blockIdx.x, gridDim.x) * rpb;
+  const int r1 = r0 + rpb < rows ? r0 + rpb : rows;
+  auto lam = [&](int, int, int, unsigned g) -> double {
+    if (red_new && g < half) return red_new[g];
+    return lam_in[g] - mu;
+  };
+  for (int row = r0; row < r1; ++row) {
+    const int i = row / n, j = row - i * n;
+    const int q = (i + j + colour) & 1;
+    for (int m = threadIdx.x; m < nh; m += blockDim.x) {
+      const int k = 2 * m + q;
+      const unsigned e = split_idx(n, i, j, k);
+      const double off = adj_offdiag(coef, cells, n, i, j, k, lam);
+      const double v = (off - h2 * rhs[e]) * (1.0 / 6.0);
+      out[e] = v;
+      acc += v;
+    }
+  }
+  double vv[1] = {acc};
+  const bool last = grid_sum<1>(vv, red.partials, red.counter, sum_out, gridDim.x, blockIdx.x);
+  if (last && threadIdx.x == 0 && copy_to) *copy_to = *copy_from;
+}
+
+// res = rhs - J^T l on the fine mesh and rhs_c = R res; sums res^2 (the level's residual norm).
+__global__ void __launch_bounds__(256) adj_resid_restrict_kernel(const double* __restrict__ lam_in,
+    const double* __restrict__ rhs, const double* __restrict__ coef, int n, double ih2, const double* mu_sum,
+    double mu_scale, double* __restrict__ rhs_c, Reduce red) {
+  const size_t cells = (size_t)n * n * n;
+  const double mu = mu_sum ? (mu_sum[0] + mu_sum[1]) * mu_scale : 0.0;
+  const int m = n >> 1;
+  double a2 = 0.0;
+  const int rows = m * m;
+  const int rpb = (rows + gridDim.x - 1) / gridDim.x;
+  const int r0 = xcd_remap(blockIdx.x, gridDim.x) * rpb;
+  const int r1 = r0 + rpb < rows ? r0 + rpb : rows;
+  auto lam = [&](int, int, int, unsigned g) -> double { return lam_in[g] - mu; };
+  for (int row = r0; row < r1; ++row) {
+    const int I = row / m, J = row - I * m;
+    for (int K = threadIdx.x; K < m; K += blockDim.x) {
+      double s = 0.0;
+#pragma unroll 1
+      for (int q = 0; q < 8; ++q) {
+        const int i = 2 * I + (q >> 2), j = 2 * J + ((q >> 1) & 1), k = 2 * K + (q & 1);
+        const unsigned g = split_idx(n, i, j, k);
+        const double off = adj_offdiag(coef, cells, n, i, j, k, lam);
+        const double r = rhs[g] - (off - 6.0 * (lam_in[g] - mu)) * ih2;
+        s += r;
+        a2 += r * r;
+      }
+      rhs_c[split_idx(m, I, J, K)] = 0.125 * s;
+    }
+  }
+  double vv[2] = {0.0, a2};
+  grid_sum<2>(vv, red.partials, red.counter, red.result, gridDim.x, blockIdx.x);
+}
+
+// l += P(lc - mu_c) (trilinear; cell pair per thread as in the forward prolongation).
+__global__ void __launch_bounds__(512) adj_prolong_kernel(const double* __restrict__ lc, const double* mu_sum,
+                                                          double mu_scale, double* __restrict__ lam, int n) {
+  const int nh = n >> 1;
+  const int row = xcd_remap(blockIdx.x, gridDim.x);
+  const int i = row / n, j = row - i * n;
+  const int m = threadIdx.x;
+  if (m >= nh) return;
+  const double mu = mu_sum ? (mu_sum[0] + mu_sum[1]) * mu_scale : 0.0;
+  const int nc = n >> 1;
+  const int I = i >> 1, J = j >> 1, K = m;
+  const int I2 = wrapi((i & 1) ? I + 1 : I - 1, nc);
+  const int J2 = wrapi((j & 1) ? J + 1 : J - 1, nc);
+  const int Km = wrapi(K - 1, nc), Kp = wrapi(K + 1, nc);
+  const double wI[2] = {0.75, 0.25};
+  double lo = 0.0, hi = 0.0;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int ii = (s & 2) ? I2 : I, jj = (s & 1) ? J2 : J;
+    const double w = wI[(s >> 1) & 1] * wI[s & 1];
+    const double ek = lc[split_idx(nc, ii, jj, K)] - mu;
+    lo += w * (0.75 * ek + 0.25 * (lc[split_idx(nc, ii, jj, Km)] - mu));
+    hi += w * (0.75 * ek + 0.25 * (lc[split_idx(nc, ii, jj, Kp)] - mu));
+  }
+  const unsigned half = (unsigned)n * (unsigned)n * (unsigned)nh;
+  const unsigned off = ((unsigned)i * n + j) * (unsigned)nh + m;
+  const int c0 = (i + j) & 1;
+  lam[c0 * half + off] += lo;
+  lam[(1 - c0) * half + off] += hi;
+}
+
+// Coarsest level: nsweeps projected red-black sweeps in one block (lambda and rhs in LDS,
+// coefficients from global memory). Writes the mean-free result and sets its offset to 0.
+__global__ void __launch_bounds__(256) adj_coarsest_kernel(double* __restrict__ lam, const double* __restrict__ rhs,
+    const double* __restrict__ coef, int n, int nsweeps, double h2, const double* mu_sum, double mu_scale,
+    double* mu_out) {
+  __shared__ double tl[kMaxCoarsest], tr[kMaxCoarsest], tn[kMaxCoarsest];
+  __shared__ double red[16][1];
+  __shared__ double mnew;
+  const int n3 = n * n * n, tid = threadIdx.x;
+  const size_t cells = (size_t)n3;
+  const double mu0 = mu_sum ? (mu_sum[0] + mu_sum[1]) * mu_scale : 0.0;
+  for (int x = tid; x < n3; x += blockDim.x) {
+    const unsigned g = split_idx(n, x / (n * n), (x / n) % n, x % n);
+    tl[x] = lam[g] - mu0;
+    tr[x] = rhs[g];
+  }
+  __syncthreads();
+  auto lamv = [&](int a, int b, int c, unsigned) -> double { return tl[(a * n + b) * n + c]; };
+  for (int sw = 0; sw < nsweeps; ++sw) {
+    for (int colour = 0; colour < 2; ++colour) {
+      for (int x = tid; x < n3; x += blockDim.x) {
+        const int i = x / (n * n), j = (x / n) % n, k = x % n;
+        if (((i + j + k) & 1) != colour) continue;
+        const double off = adj_offdiag(coef, cells, n, i, j, k, lamv);
+        tn[x] = (off - h2 * tr[x]) * (1.0 / 6.0);
+      }
+      __syncthreads();
+      for (int x = tid; x < n3; x += blockDim.x) {
+        const int i = x / (n * n), j = (x / n) % n, k = x % n;
+        if (((i + j + k) & 1) == colour) tl[x] = tn[x];
+      }
+      __syncthreads();
+    }
+    double acc = 0.0;
+    for (int x = tid; x < n3; x += blockDim.x) acc += tl[x];
+    double v[1] = {acc};
+    block_sum<1>(v, red, tid, blockDim.x);
+    if (tid == 0) mnew = v[0] / (double)n3;
+    __syncthreads();
+    for (int x = tid; x < n3; x += blockDim.x) tl[x] -= mnew;
+    __syncthreads();
+  }
+  for (int x = tid; x < n3; x += blockDim.x) lam[split_idx(n, x / (n * n), (x / n) % n, x % n)] = tl[x];
+  if (tid == 0 && mu_out) {
+    mu_out[0] = 0.0;
+    mu_out[1] = 0.0;
+  }
+}
+
+// grad = D * (lambda - mu), natural order.
+__global__ void __launch_bounds__(1024) adj_grad_kernel(const double* __restrict__ lam, const double* mu_sum,
+                                                        double mu_scale, const double* __restrict__ D,
+                                                        double* __restrict__ grad, int n) {
+  const int row = xcd_remap(blockIdx.x, gridDim.x);
+  const int i = row / n, j = row - i * n;
+  const int k = threadIdx.x;
+  if (k >= n) return;
+  const double mu = (mu_sum[0] + mu_sum[1]) * mu_scale;
+  const unsigned g = split_idx(n, i, j, k);
+  grad[((size_t)i * n + j) * n + k] = D[g] * (lam[g] - mu);
+}
+
+__global__ void __launch_bounds__(256) center_kernel(double* __restrict__ a, size_t cells, const double* sum, double scale) {
+  const double m = (*sum) * scale;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < cells; e += (size_t)gridDim.x * blockDim.x)
+    a[e] -= m;
+}
+
+// ---- driver -------------------------------------------------------------------------------
+
+static int rows_blocks_a(int n) { return n * n < 4096 ? n * n : 4096; }
+static int row_threads_a(int n) { return n < 64 ? 64 : (n < 256 ? n : 256); }
+static int lin_blocks_a(size_t cells) {
+  size_t b = (cells + 255) / 256;
+  return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+}
+
+static int adjoint_alloc(Ctx* c) {
+  if (c->adj) return MR_OK;
+  AdjointState* a = new AdjointState();
+  c->adj = a;
+  a->lv.resize(c->nlev);
+  auto get = [&](double** p, size_t count) -> int {
+    hipError_t e = hipMalloc((void**)p, count * sizeof(double));
+    if (e != hipSuccess) return fail(MR_ENOMEM, "adjoint buffers: %s", hipGetErrorString(e));
+    a->owned.push_back(*p);
+    return MR_OK;
+  };
+  int rc;
+  for (int l = 0; l < c->nlev; ++l) {
+    const size_t cells = c->lv[l].cells;
+    AdjLevel& L = a->lv[l];
+    if ((rc = get(&L.lam[0], cells)) != MR_OK || (rc = get(&L.lam[1], cells)) != MR_OK ||
+        (rc = get(&L.rhs, cells)) != MR_OK || (rc = get(&L.coef, 6 * cells)) != MR_OK)
+      return rc;
+  }
+  return get(&a->D, c->lv[0].cells);
+}
+
+void Ctx::release_adjoint() {
+  if (!adj) return;
+  for (void* p : adj->owned) (void)hipFree(p);
+  delete adj;
+  adj = nullptr;
+}
+
+int Ctx::adj_sweep(int l) {
+  AdjLevel& A = adj->lv[l];
+  Level& F = lv[l];
+  double* ms = linsum(l);
+  const double scale = 1.0 / (double)F.cells;
+  hipLaunchKernelGGL(adj_half_sweep_kernel, dim3(rows_blocks_a(F.n)), dim3(row_threads_a(F.n / 2)), 0, stream,
+                     A.lam[A.cur], (const double*)nullptr, A.lam[A.cur ^ 1], A.rhs, A.coef, F.n, 0, F.h * F.h, ms, scale,
+                     ms + 2, (const double*)nullptr, (double*)nullptr, reducer(kSlotAux));
+  hipLaunchKernelGGL(adj_half_sweep_kernel, dim3(rows_blocks_a(F.n)), dim3(row_threads_a(F.n / 2)), 0, stream,
+                     A.lam[A.cur], A.lam[A.cur ^ 1], A.lam[A.cur ^ 1], A.rhs, A.coef, F.n, 1, F.h * F.h, ms, scale,
+                     ms + 1, ms + 2, ms + 0, reducer(kSlotAux));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "adjoint sweep");
+  A.cur ^= 1;
+  return MR_OK;
+}
+
+int Ctx::adj_vcycle(int l, double* norm2) {
+  AdjLevel& A = adj->lv[l];
+  Level& F = lv[l];
+  const double scale = 1.0 / (double)F.cells;
+  hipError_t e;
+  if (l == nlev - 1) {
+    hipLaunchKernelGGL(adj_coarsest_kernel, dim3(1), dim3(256), 0, stream, A.lam[A.cur], A.rhs, A.coef, F.n, opts.ncoarse,
+                       F.h * F.h, linsum(l), scale, linsum(l));
+    e = hipGetLastError();
+    return e == hipSuccess ? MR_OK : hip_fail(e, "adjoint coarsest");
+  }
+  int rc;
+  for (int s = 0; s < opts.npre; ++s)
+    if ((rc = adj_sweep(l)) != MR_OK) return rc;
+  AdjLevel& Ac = adj->lv[l + 1];
+  Level& Fc = lv[l + 1];
+  const int m = F.n / 2;
+  hipLaunchKernelGGL(adj_resid_restrict_kernel, dim3(rows_blocks_a(m)), dim3(row_threads_a(m)), 0, stream, A.lam[A.cur],
+                     A.rhs, A.coef, F.n, 1.0 / (F.h * F.h), linsum(l), scale, Ac.rhs,
+                     Reduce{partials, counter, norm2 ? norm2 : scal + kSlotAux + 4});
+  Ac.cur = 0;
+  if ((e = hipMemsetAsync(Ac.lam[0], 0, Fc.cells * sizeof(double), stream)) != hipSuccess) return hip_fail(e, "zero");
+  if ((e = hipMemsetAsync(linsum(l + 1), 0, 2 * sizeof(double), stream)) != hipSuccess) return hip_fail(e, "zero");
+  if (norm2) {
+    // convergence test of the finest level before the coarse correction
+    double r[2];
+    if ((rc = read_scalars((int)(norm2 - scal), 2, r)) != MR_OK) return rc;
+    adj_last_norm = std::sqrt(r[1] > 0.0 ? r[1] : 0.0);
+    if (adj_last_norm <= adj_stop) return MR_OK;
+  }
+  if ((rc = adj_vcycle(l + 1, nullptr)) != MR_OK) return rc;
+  hipLaunchKernelGGL(adj_prolong_kernel, dim3((unsigned)F.n * F.n), dim3(F.n / 2), 0, stream, Ac.lam[Ac.cur], linsum(l + 1),
+                     1.0 / (double)Fc.cells, A.lam[A.cur], F.n);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "adjoint prolongation");
+  for (int s = 0; s < opts.npost; ++s)
+    if ((rc = adj_sweep(l)) != MR_OK) return rc;
+  return MR_OK;
+}
+
+int Ctx::adjoint_solve(const double* delta, const double* theta_star, const double* g, double* grad, mr_info* info) {
+  auto t0 = std::chrono::steady_clock::now();
+  if (nlev == 1) return fail(MR_EINVAL, "adjoint needs at least two levels (n >= 8)");
+  int rc = adjoint_alloc(this);
+  if (rc != MR_OK) return rc;
+  if ((rc = prepare(delta)) != MR_OK) return rc;
+  Level& L0 = lv[0];
+  AdjLevel& A0 = adj->lv[0];
+  const double N3 = (double)L0.cells;
+  // theta_star hierarchy (in the forward buffers) and per-level coefficients
+  hipError_t e = launch_to_split(theta_star, L0.th[0], L0.n, stream);
+  for (int l = 1; l < nlev && e == hipSuccess; ++l) e = launch_restrict(lv[l - 1].th[0], lv[l].th[0], lv[l - 1].n, stream);
+  for (int l = 0; l < nlev && e == hipSuccess; ++l) {
+    hipLaunchKernelGGL(adj_coef_kernel, dim3((unsigned)lv[l].n * lv[l].n), dim3(lv[l].n < 256 ? lv[l].n : 256), 0, stream,
+                       lv[l].th[0], lv[l].delta, lv[l].n, 1.0 / (lv[l].h * lv[l].h), adj->lv[l].coef,
+                       l == 0 ? adj->D : (double*)nullptr);
+    e = hipGetLastError();
+  }
+  // rhs = g - <g>, lambda = 0
+  if (e == hipSuccess) e = launch_to_split(g, A0.rhs, L0.n, stream);
+  if (e == hipSuccess) e = launch_sum(A0.rhs, L0.cells, reducer(kSlotGauge), stream);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(center_kernel, dim3(lin_blocks_a(L0.cells)), dim3(256), 0, stream, A0.rhs, L0.cells,
+                       (const double*)(scal + kSlotGauge), 1.0 / N3);
+    e = hipGetLastError();
+  }
+  A0.cur = 0;
+  if (e == hipSuccess) e = hipMemsetAsync(A0.lam[0], 0, L0.cells * sizeof(double), stream);
+  if (e == hipSuccess) e = hipMemsetAsync(linsum(0), 0, 3 * sizeof(double), stream);
+  if (e != hipSuccess) return hip_fail(e, "adjoint setup");
+  // ||rhs||: the residual pass at lambda = 0
+  hipLaunchKernelGGL(adj_resid_restrict_kernel, dim3(rows_blocks_a(L0.n / 2)), dim3(row_threads_a(L0.n / 2)), 0, stream,
+                     A0.lam[0], A0.rhs, A0.coef, L0.n, 1.0, linsum(0), 1.0 / N3, adj->lv[1].rhs,
+                     Reduce{partials, counter, scal + kSlotAux + 6});
+  double r[2];
+  if ((rc = read_scalars(kSlotAux + 6, 2, r)) != MR_OK) return rc;
+  double r0 = std::sqrt(r[1] > 0.0 ? r[1] : 0.0);
+  mr_info loc{};
+  loc.r0_norm = r0;
+  loc.history[0] = 1.0;
+  if (r0 == 0.0) r0 = 1.0;
+  adj_stop = opts.tol * r0;
+  int cyc = 0, status = MR_OK;
+  double rel = (loc.r0_norm == 0.0) ? 0.0 : 1.0;
+  while (rel > opts.tol && cyc < opts.max_cycles) {
+    if ((rc = adj_vcycle(0, scal + kSlotAux + 6)) != MR_OK) return rc;
+    ++cyc;
+    rel = adj_last_norm / r0;
+    if (cyc < 128) loc.history[cyc] = rel;
+    if (!std::isfinite(rel)) {
+      status = fail(MR_EDIVERGED, "adjoint diverged at cycle %d", cyc);
+      break;
+    }
+  }
+  if (status == MR_OK && rel > opts.tol) {
+    status = MR_NOT_CONVERGED;
+    fail(MR_NOT_CONVERGED, "adjoint not converged after %d cycles (rel residual %g)", cyc, rel);
+  }
+  hipLaunchKernelGGL(adj_grad_kernel, dim3((unsigned)L0.n * L0.n), dim3(L0.n), 0, stream, A0.lam[A0.cur],
+                     (const double*)linsum(0), 1.0 / N3, adj->D, grad, L0.n);
+  e = hipGetLastError();
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return hip_fail(e, "adjoint gradient");
+  loc.status = status;
+  loc.cycles = cyc;
+  loc.rel_residual = rel;
+  loc.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = loc;
+  return status;
+}
+
+}  // namespace mr
+
+extern "C" int mr_adjoint_solve(mr_ctx* h, const double* delta, const double* theta_star, const double* g,
+                                double* grad_delta, mr_info* info) {
+  if (!h || !delta || !theta_star || !g || !grad_delta) return mr::fail(MR_EINVAL, "mr_adjoint_solve: null argument");
+  return reinterpret_cast<mr::Ctx*>(h)->adjoint_solve(delta, theta_star, g, grad_delta, info);
+}
