@@ -57,7 +57,7 @@ enum { MR_PREC_FP64 = 0, MR_PREC_MIXED = 1 };
  * precision: MR_PREC_FP64, or MR_PREC_MIXED (FP32 relaxation and coarse grids on the linearised
  * operator inside an FP64 defect-correction loop; the FP64 residual decides convergence).
  * inner_cycles: FP32 V-cycles per outer step in mixed precision. warm_start: non-zero to start
- * from the theta passed in instead of theta = 0. */
+ * from the theta passed in instead of theta = 0. flags: MR_FLAG_* bits (0 by default). */
 typedef struct {
   double tol;
   int max_cycles;
@@ -67,8 +67,12 @@ typedef struct {
   int precision;
   int inner_cycles;
   int warm_start;
-  int reserved;
+  int flags;
 } mr_opts;
+
+/* mr_solve_batched only: launch every pass directly on the stream instead of replaying the
+ * captured graph (same kernels and arguments; for checking the graph against direct launches). */
+enum { MR_FLAG_EAGER = 1 };
 
 /* Per-solve report. history[c] is the relative residual after cycle c (history[0] = start). */
 typedef struct {
@@ -134,13 +138,28 @@ int mr_solve(mr_ctx* ctx, const double* delta, double* theta, mr_info* info);
 int mr_adjoint_solve(mr_ctx* ctx, const double* delta, const double* theta_star,
                      const double* g, double* grad_delta, mr_info* info);
 
-/* Batched solve of nbox independent boxes (sizes n[b], device arrays delta[b], theta[b]) in
- * mixed precision: every level phase of all boxes is one kernel launch over a work table,
- * the outer iteration is captured once in a HIP graph and replayed until every box has reached
- * opts.tol (converged boxes are masked out). Tile shapes per box size come from the tuner
- * table (mr_tune_batched). infos: host array of nbox reports (may be NULL). */
+/* Batched solve of nbox independent periodic boxes of possibly different sizes (the one-mesh
+ * solve applied box by box, Sec. II.A, in the mixed-precision form). n: host array of nbox box
+ * sizes (each even, 8..1024, coarsest level at most 12^3). delta, theta: host arrays of nbox
+ * device pointers, delta[b] and theta[b] of n[b]^3 doubles in natural order; theta[b] is
+ * written (zero mean), every box starts from theta = 0. opts: as for mr_create (NULL: the
+ * defaults); precision and warm_start are ignored. Each phase of an outer iteration is one
+ * launch per distinct box size covering all boxes of that size; one outer iteration is captured
+ * in a HIP graph and replayed until every box has reached opts->tol or used opts->max_cycles
+ * iterations (a box that has stops being updated). FP32 sweep tiles per size come from
+ * mr_tune_lin_tiles. infos: host array of nbox reports (may be NULL); history[k] is the relative
+ * residual before update k, rel_residual the one of the returned potential. Device memory is
+ * allocated for the call and freed before it returns; the call synchronizes hip_stream.
+ * Returns MR_OK, MR_NOT_CONVERGED or MR_EDIVERGED (the worst box), MR_EDOMAIN for an invalid
+ * delta, or an argument / HIP / memory error. */
 int mr_solve_batched(int nbox, const int* n, const double* const* delta, double* const* theta,
                      const mr_opts* opts, mr_info* infos, void* hip_stream);
+
+/* Tile tuner of the FP32 linear sweep used by mr_solve_batched: times every compiled tile shape
+ * and plane-chunk length on one synthetic n^3 box on the current device, and returns (and caches
+ * per device and n) the fastest: tm cells along z/2, tj rows, ci planes per block, ms the time of
+ * one red+black sweep. Any output pointer may be NULL. n: multiple of 4, 8..1024. */
+int mr_tune_lin_tiles(int n, void* hip_stream, int* tm, int* tj, int* ci, float* ms);
 
 /* ---- Building blocks of the cycle, exported so that each can be checked in isolation. ----
  * All act on one mesh of size nl (any level of a hierarchy) with cell size h, on the context's

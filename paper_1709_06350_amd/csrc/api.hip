@@ -52,7 +52,7 @@ int check_opts(const mr_opts& o) {
   if (!(o.tol >= 0.0) || o.max_cycles < 1 || o.max_cycles > 127 || o.npre < 0 || o.npost < 0 ||
       o.npre + o.npost < 1 || o.ncoarse < 1 ||
       (o.precision != MR_PREC_FP64 && o.precision != MR_PREC_MIXED) || o.inner_cycles < 1 ||
-      o.inner_cycles > 8)
+      o.inner_cycles > 8 || (o.flags & ~MR_FLAG_EAGER) != 0)
     return fail(MR_EINVAL, "invalid options");
   return MR_OK;
 }

@@ -99,6 +99,7 @@ struct Ctx {
 int fail(int code, const char* fmt, ...);
 int hip_fail(hipError_t e, const char* where);
 std::vector<int> level_sizes(int n);
+int check_opts(const mr_opts& o);
 TileCfg sweep_tiles(int n);
 TileCfg defect_tiles(int n);
 

@@ -134,7 +134,7 @@ hipError_t launch_sum(const double* a, size_t cells, Reduce red, hipStream_t s);
 // ---- mixed precision (FP32 linearised multigrid) ----
 bool lin_tile_supported(int tm, int tj);
 hipError_t launch_lin_half_sweep(const LinSweepArgs& a, const TileCfg& t, hipStream_t s);
-hipError_t launch_mixed_resid64(const double* theta, const double* delta, int n, double C, float* rhs32, float* base32,
+hipError_t launch_mixed_resid64(const double* theta, const double* delta, int n, ShiftRef C, float* rhs32, float* base32,
                                 float* sb32, Reduce red, hipStream_t s);
 hipError_t launch_base_root(const float* base32, const double* delta, int n, double h, float* sb32, hipStream_t s);
 hipError_t launch_restrict32(const float* fine, float* coarse, int n, hipStream_t s);

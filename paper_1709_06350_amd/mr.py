@@ -23,12 +23,14 @@ MR_EDOMAIN = -2
 MR_EDIVERGED = -3
 MR_EHIP = -4
 MR_ENOMEM = -5
+MR_FLAG_EAGER = 1
 PREC_FP64 = 0
 PREC_MIXED = 1
 
 EXPORTED = [
     "mr_default_opts", "mr_create", "mr_destroy", "mr_set_opts", "mr_size", "mr_levels",
     "mr_deposit_cic", "mr_residual", "mr_solve", "mr_adjoint_solve", "mr_solve_batched",
+    "mr_tune_lin_tiles",
     "mr_sweep", "mr_defect_restrict", "mr_tau_rhs", "mr_prolong_correct", "mr_restrict",
     "mr_timing_enable", "mr_timing_read", "mr_last_error",
 ]
@@ -44,7 +46,7 @@ class mr_opts(ctypes.Structure):
         ("precision", ctypes.c_int),
         ("inner_cycles", ctypes.c_int),
         ("warm_start", ctypes.c_int),
-        ("reserved", ctypes.c_int),
+        ("flags", ctypes.c_int),
     ]
 
 
@@ -105,6 +107,8 @@ def load(path: Optional[str] = None):
     lib.mr_solve_batched.argtypes = [ip, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(vp),
                                      ctypes.POINTER(vp), ctypes.POINTER(mr_opts),
                                      ctypes.POINTER(mr_info), vp]
+    lib.mr_tune_lin_tiles.argtypes = [ip, vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_float)]
     lib.mr_sweep.argtypes = [vp, ip, ctypes.c_double, vp, vp, ctypes.c_double, vp, vp, dp]
     lib.mr_defect_restrict.argtypes = [vp, ip, ctypes.c_double, vp, vp, ctypes.c_double, vp, vp, vp]
     lib.mr_tau_rhs.argtypes = [vp, ip, ctypes.c_double, vp, vp, vp, vp, dp]
@@ -286,18 +290,37 @@ class Context:
 
 
 def solve_batched(deltas: Sequence[torch.Tensor], thetas: Optional[Sequence[torch.Tensor]] = None,
-                  check: bool = True, **opts):
+                  check: bool = True, eager: bool = False, **opts):
+    """Solve independent periodic boxes of possibly different sizes in one batched call
+    (mr_solve_batched: mixed precision, one launch per phase and box size, graph replay).
+
+    deltas: contiguous float64 CUDA tensors of shapes (n_b, n_b, n_b). thetas: output tensors of
+    the same shapes (allocated when None). eager: launch every pass directly instead of replaying
+    the captured graph. Remaining keywords set mr_opts fields (tol, max_cycles, npre, ...).
+    Returns (thetas, infos)."""
     lib = load()
     nbox = len(deltas)
     thetas = [torch.zeros_like(d) for d in deltas] if thetas is None else list(thetas)
     o = default_opts(**opts)
+    if eager:
+        o.flags |= MR_FLAG_EAGER
+    for t in list(deltas) + thetas:
+        _ptr(t)
     ns = (ctypes.c_int * nbox)(*[d.shape[0] for d in deltas])
     dp = (ctypes.c_void_p * nbox)(*[d.data_ptr() for d in deltas])
     tp = (ctypes.c_void_p * nbox)(*[t.data_ptr() for t in thetas])
-    for t in list(deltas) + thetas:
-        _ptr(t)
     infos = (mr_info * nbox)()
     code = lib.mr_solve_batched(nbox, ns, dp, tp, ctypes.byref(o), infos, _stream())
     if check:
         _check(code)
     return thetas, [Info.from_c(i) for i in infos]
+
+
+def tune_lin_tiles(n: int):
+    """Tile tuner of the batched FP32 sweep (mr_tune_lin_tiles) on the current device:
+    returns (tm, tj, ci, ms) for an n^3 box; the choice is cached per device and n."""
+    lib = load()
+    tm, tj, ci = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    ms = ctypes.c_float()
+    _check(lib.mr_tune_lin_tiles(n, _stream(), ctypes.byref(tm), ctypes.byref(tj), ctypes.byref(ci), ctypes.byref(ms)))
+    return tm.value, tj.value, ci.value, ms.value

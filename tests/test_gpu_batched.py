@@ -1,0 +1,146 @@
+"""Batched form: many independent periodic boxes of uneven sizes in one call.
+
+Each box is the one-mesh problem of Sec. II.A solved in the mixed-precision form to a relative
+residual of 1e-8. Checks per box: the oracle-evaluated relative residual of the returned theta is
+<= 1e-8; the potential agrees with the oracle's own solve (tol 1e-12) within the error that a
+residual of 1e-8 allows. For the mean-free Laplacian-dominated operator on an n^3 periodic mesh
+with h = 1 the smallest non-zero eigenvalue is about (2 pi / n)^2, so an rms residual of
+1e-8 r0 admits an rms potential error of about 1e-8 r0 (n / 2 pi)^2; the tests allow ten times
+that in the max norm.
+
+The graph form is checked against direct launches of the same passes (bitwise), and a box solved
+alone against the same box solved inside a batch (bitwise: every box reduces into its own slots,
+and the tuned tiles are cached per mesh size).
+"""
+import numpy as np
+import pytest
+import torch
+
+import inputs
+from gpu_util import announce, dev, host, require_gpu
+from oracle import multigrid as omg
+from oracle import operator as oop
+
+pytestmark = pytest.mark.gpu
+
+from paper_1709_06350_amd import mr  # noqa: E402
+
+TOL = 1e-8
+SMALL = [(16, 0.6, 3.0, 2001), (24, 0.9, 3.0, 2002), (32, 1.0, 4.0, 2003), (16, 1.1, 2.0, 2004),
+         (32, 0.5, 4.0, 2005), (24, 0.7, 2.0, 2006)]
+
+
+def _fields(spec):
+    return [inputs.lognormal(n, s, rc, seed) for n, s, rc, seed in spec]
+
+
+def _theta_bound(n, r0):
+    return 10.0 * TOL * r0 * (n / (2.0 * np.pi)) ** 2
+
+
+def test_tuner_returns_a_compiled_shape():
+    require_gpu()
+    for n in (16, 24, 64):
+        announce(f"tune n={n}")
+        tm, tj, ci, ms = mr.tune_lin_tiles(n)
+        assert (n // 2) % tm == 0 and n % tj == 0 and n % ci == 0 and ms > 0.0
+        assert mr.tune_lin_tiles(n)[:3] == (tm, tj, ci)   # cached
+
+
+def test_batched_small_matches_oracle():
+    require_gpu()
+    announce("batched small, 6 boxes of 16/24/32")
+    deltas = _fields(SMALL)
+    thetas, infos = mr.solve_batched([dev(d) for d in deltas], tol=TOL)
+    for (n, s, rc, seed), d, t, inf in zip(SMALL, deltas, thetas, infos):
+        th = host(t)
+        assert inf.status == 0 and inf.rel_residual <= TOL
+        rel = oop.relative_residual(th, d)
+        ref, rinfo = omg.solve(d, tol=1e-12, max_cycles=80)
+        err = np.abs(th - ref).max()
+        print(f"n={n} sigma={s}: outer {inf.cycles}, rel {rel:.3e}, max|theta - oracle| {err:.3e}")
+        assert rel <= TOL * (1 + 1e-6)
+        assert abs(th.mean()) <= 1e-12
+        assert err <= _theta_bound(n, inf.r0_norm)
+        r0 = oop.residual_norm(oop.projected_operator(np.zeros_like(d), d, 1.0))
+        assert inf.r0_norm == pytest.approx(r0, rel=1e-10)
+        hist = inf.history[: inf.cycles + 1]
+        assert hist[0] == pytest.approx(1.0, rel=1e-12) and hist[-1] <= TOL
+
+
+def test_batched_graph_matches_direct_launches():
+    require_gpu()
+    announce("batched graph vs eager")
+    deltas = [dev(d) for d in _fields(SMALL)]
+    tg, ig = mr.solve_batched(deltas, tol=TOL)
+    te, ie = mr.solve_batched(deltas, tol=TOL, eager=True)
+    for a, b, x, y in zip(tg, te, ig, ie):
+        assert torch.equal(a, b)
+        assert x.cycles == y.cycles and x.history[: x.cycles + 1] == y.history[: y.cycles + 1]
+
+
+def test_box_alone_equals_box_in_batch():
+    require_gpu()
+    announce("batched isolation")
+    deltas = [dev(d) for d in _fields(SMALL)]
+    tb, ib = mr.solve_batched(deltas, tol=TOL)
+    for k in (1, 2):
+        ta, ia = mr.solve_batched([deltas[k]], tol=TOL)
+        assert torch.equal(ta[0], tb[k]) and ia[0].cycles == ib[k].cycles
+
+
+def test_batched_replays_stop_per_box():
+    require_gpu()
+    announce("batched max_cycles")
+    deltas = [dev(d) for d in _fields(SMALL[:3])]
+    thetas, infos = mr.solve_batched(deltas, tol=1e-30, max_cycles=3, check=False)
+    for inf in infos:
+        assert inf.status == mr.MR_NOT_CONVERGED and inf.cycles == 3
+        assert inf.rel_residual < 1e-2
+    # boxes that converge at different outer iterations: the loose tolerance stops early
+    thetas, infos = mr.solve_batched(deltas, tol=TOL)
+    loose, li = mr.solve_batched(deltas, tol=1e-4)
+    for a, b in zip(infos, li):
+        assert b.cycles < a.cycles and b.rel_residual <= 1e-4
+
+
+def test_batched_rejects_bad_input():
+    require_gpu()
+    d = dev(inputs.lognormal(16, 0.5, 3.0, 7))
+    with pytest.raises(mr.MRError):
+        mr.solve_batched([d, dev(np.zeros((10, 10, 10)))])
+    bad = inputs.lognormal(16, 0.5, 3.0, 8)
+    bad[3, 4, 5] = -1.5
+    with pytest.raises(mr.MRError) as ei:
+        mr.solve_batched([d, dev(bad)])
+    assert ei.value.code == mr.MR_EDOMAIN
+    with pytest.raises(mr.MRError):
+        mr.solve_batched([d], npre=0, npost=0)
+
+
+@pytest.mark.timeout(900)
+def test_batched_full_workload():
+    """64 boxes of {64, 96, 128}^3 (lognormal, sigma_g ~ U[0.5, 1.2]): every box converges and
+    the oracle-evaluated residual is <= 1e-8; the potential error against the FP64 solve
+    (tol 1e-11) is reported and bounded as above."""
+    require_gpu()
+    spec = inputs.batched_boxes()
+    announce(f"batched full workload: {len(spec)} boxes")
+    deltas = [inputs.lognormal(n, s, 4.0, seed) for n, s, seed in spec]
+    thetas, infos = mr.solve_batched([dev(d) for d in deltas], tol=TOL)
+    worst_rel, worst_err = 0.0, 0.0
+    for (n, s, seed), d, t, inf in zip(spec, deltas, thetas, infos):
+        th = host(t)
+        assert inf.status == 0
+        rel, _ = oop.relative_residual_slabs(th, d, slab=16, workers=8)
+        assert rel <= TOL * (1 + 1e-6), (n, s, seed, rel)
+        with mr.Context(n, tol=1e-11, max_cycles=80) as c:
+            ref, _ = c.solve(dev(d), check=False)
+        ref = host(ref)
+        err = np.abs(th - ref).max()
+        assert err <= _theta_bound(n, inf.r0_norm), (n, s, seed, err)
+        worst_rel = max(worst_rel, rel)
+        worst_err = max(worst_err, err / np.abs(ref).max())
+    cyc = [i.cycles for i in infos]
+    print(f"64 boxes: outer iterations {min(cyc)}..{max(cyc)}, worst oracle rel residual {worst_rel:.3e}, "
+          f"worst max|theta - theta_fp64| / max|theta_fp64| {worst_err:.3e}")
