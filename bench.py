@@ -7,9 +7,14 @@ already resident in HBM: the FP64 FAS V-cycle solve to relative residual 1e-10 a
 on the same input, the mixed-precision solve to the same FP64 residual.
 
 Headline value: the finest-mesh FP64 red-black NGS sweep throughput (Gcell-updates/s), from HIP
-events recorded by the library around every finest-mesh sweep launch inside the timed region
-(the launches' own stream). The roofline entry prices that kernel at its algorithmic 24 bytes
-per cell update (theta read + write, delta read) against the 8 TB/s HBM peak.
+events recorded by the library around every finest-mesh sweep (its red and black launches) inside
+the timed region, on the launches' own stream. The roofline entry prices that kernel at its
+algorithmic 24 bytes per cell update (theta read + write, delta read) against the 8 TB/s HBM
+peak; "traffic" is the HBM traffic per sweep measured with rocprofv3 counters (committed
+summary), over the same sweep time.
+
+Also reported: time to solution of both 512^3 solves, and the batched form on 64 boxes of
+{64, 96, 128}^3 (mixed precision to 1e-8), timed once after one untimed run.
 
 Prints ONE JSON line. --gpus N > 1 is refused: this path runs on one GPU.
 """
@@ -46,7 +51,7 @@ def measured_traffic():
         return None
     txt = open(PROFILE_PMC).read()
     m = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", txt)
-    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    b = re.search(r"hbm_bytes_per_sweep:\s*([0-9.eE+]+)", txt)
     if not m or not b or m.group(1) != kernel_hash():
         return None
     return float(b.group(1))
@@ -79,6 +84,47 @@ def cpu_baseline(delta_np, seconds_target=15.0):
     }
 
 
+def copy_calibration(nbytes: int, reps: int):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}), flush=True)
+
+
+def batched_run():
+    """64 boxes of {64, 96, 128}^3, mixed precision to 1e-8; one untimed run, one timed run."""
+    import torch
+
+    import inputs
+    from paper_1709_06350_amd import mr
+
+    spec = inputs.batched_boxes()
+    deltas = [torch.from_numpy(inputs.lognormal(n, s, 4.0, seed)).cuda() for n, s, seed in spec]
+    thetas = [torch.zeros_like(d) for d in deltas]
+    mr.solve_batched(deltas, thetas, tol=1e-8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, infos = mr.solve_batched(deltas, thetas, tol=1e-8)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    cells = sum(n ** 3 for n, _, _ in spec)
+    cyc = [i.cycles for i in infos]
+    return {
+        "boxes": len(spec),
+        "cells": cells,
+        "seconds": round(dt, 4),
+        "mcells_solved_per_s": round(cells / dt / 1e6, 2),
+        "outer_iterations": [min(cyc), max(cyc)],
+        "worst_rel_residual": max(i.rel_residual for i in infos),
+        "tol": 1e-8,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,19 +133,24 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a device copy of BYTES bytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this solver runs on one GPU; --gpus {args.gpus} is not supported "
               "(multi-GPU sharding is a design note only)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import inputs
     from paper_1709_06350_amd import mr
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration, 3)
+        return
     n = args.n
     delta_np = inputs.config2_delta(n)
     delta = torch.from_numpy(delta_np).cuda()
@@ -180,9 +231,11 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None if traffic is None else round(traffic / avg_sweep_s / 1e9, 1),
-            "kernel": "sweep_tile_kernel (finest-mesh FP64 red-black sweep)",
-            "avg_launch_us": round(avg_sweep_s * 1e6, 2),
-            "launches": tim["sweep64_launches"],
+            "kernel": "half_sweep_tiled (finest-mesh FP64 red-black sweep: red + black launch)",
+            "sweep_us": round(avg_sweep_s * 1e6, 2),
+            "algorithmic_bytes_per_sweep": SWEEP_BYTES_PER_UPDATE * cells,
+            "traffic_bytes_per_sweep": traffic,
+            "sweeps_timed": tim["sweep64_launches"],
         },
         "time_to_solution_s": {
             "fp64": round(t64 / args.steps, 4),
@@ -194,6 +247,8 @@ def main():
         "rel_residual": {"fp64": info64.rel_residual if info64 else None,
                          "mixed": infom.rel_residual if infom else None},
     }
+    if not args.no_batched:
+        out["batched"] = batched_run()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(delta_np)
     print(json.dumps(out), flush=True)
