@@ -70,9 +70,11 @@ typedef struct {
   int flags;
 } mr_opts;
 
-/* mr_solve_batched only: launch every pass directly on the stream instead of replaying the
- * captured graph (same kernels and arguments; for checking the graph against direct launches). */
-enum { MR_FLAG_EAGER = 1 };
+/* MR_FLAG_EAGER (mr_solve_batched only): launch every pass directly on the stream instead of
+ * replaying the captured graph (same kernels and arguments; for checking the graph against direct
+ * launches). MR_FLAG_TWO_PASS: relax with one launch per colour (red, then black from the new
+ * red values) instead of the fused red-black launch; both compute the same update. */
+enum { MR_FLAG_EAGER = 1, MR_FLAG_TWO_PASS = 2 };
 
 /* Per-solve report. history[c] is the relative residual after cycle c (history[0] = start). */
 typedef struct {
@@ -169,7 +171,9 @@ int mr_tune_lin_tiles(int n, void* hip_stream, int* tm, int* tj, int* ci, float*
  * are updated from theta_in, then black cells from the red results and theta_in's black values:
  *     theta_c <- (sum of 6 face neighbours - h^2 (Sigma_c + f_c - cshift)) / 6.
  * f may be NULL (zero). theta_out must not alias theta_in. sum_out (host, may be NULL)
- * receives sum over all cells of (Sigma_c + f_c) as evaluated during the sweep. */
+ * receives sum over all cells of (Sigma_c + f_c) as evaluated during the sweep. Runs the fused
+ * red-black kernel, or the two per-colour launches (the pipelined kernel where the tile allows
+ * it) when the context's opts.flags has MR_FLAG_TWO_PASS. */
 int mr_sweep(mr_ctx* ctx, int nl, double h, const double* delta, const double* f, double cshift,
              const double* theta_in, double* theta_out, double* sum_out);
 

@@ -52,7 +52,7 @@ int check_opts(const mr_opts& o) {
   if (!(o.tol >= 0.0) || o.max_cycles < 1 || o.max_cycles > 127 || o.npre < 0 || o.npost < 0 ||
       o.npre + o.npost < 1 || o.ncoarse < 1 ||
       (o.precision != MR_PREC_FP64 && o.precision != MR_PREC_MIXED) || o.inner_cycles < 1 ||
-      o.inner_cycles > 8 || (o.flags & ~MR_FLAG_EAGER) != 0)
+      o.inner_cycles > 8 || (o.flags & ~(MR_FLAG_EAGER | MR_FLAG_TWO_PASS)) != 0)
     return fail(MR_EINVAL, "invalid options");
   return MR_OK;
 }
@@ -205,6 +205,28 @@ void EventTimer::destroy() {
 int Ctx::sweep(int l) {
   Level& L = lv[l];
   double* cs = lsum(l);
+  if (L.has_fz && !(opts.flags & MR_FLAG_TWO_PASS)) {
+    FusedSweepArgs a{};
+    a.th_in = L.th[L.cur];
+    a.th_out = L.th[L.cur ^ 1];
+    a.delta = L.delta;
+    a.f = (l == 0) ? nullptr : L.f;
+    a.n = L.n;
+    a.h2 = L.h * L.h;
+    a.ih2 = 1.0 / a.h2;
+    a.c_sum = cs;
+    a.c_scale = 1.0 / (double)L.cells;
+    a.c_add = 0.0;
+    a.sum_out = cs;   // red sum, black sum: the shift of the next sweep
+    a.partials = partials;
+    a.counter = counter;
+    const int ev = (l == 0) ? timer.begin(stream) : -1;
+    hipError_t e = launch_sweep_fused(a, L.fz, stream);
+    if (e != hipSuccess) return hip_fail(e, "fused sweep");
+    timer.end(0, ev, stream);
+    L.cur ^= 1;
+    return MR_OK;
+  }
   HalfSweepArgs a{};
   a.th_in = L.th[L.cur];
   a.th_red_new = nullptr;
@@ -502,6 +524,26 @@ int mr_create(mr_ctx** out, int n, const mr_opts* opts, void* hip_stream) {
     mr_destroy(reinterpret_cast<mr_ctx*>(c));
     return rc;
   }
+  // Relaxation schedule per level: the fused red-black launch or the two per-colour launches,
+  // whichever is faster on this device (timed on the level's own buffers before any use).
+  if (!(o.flags & MR_FLAG_TWO_PASS)) {
+    for (int l = 0; l < c->nlev - 1; ++l) {
+      Level& L = c->lv[l];
+      rc = tune_sweep(L.n, L.th[0], L.th[1], L.delta, c->partials, c->counter, c->scal + kSlotAux, &L.sw, c->stream,
+                      &L.has_fz, &L.fz);
+      if (rc != MR_OK) {
+        mr_destroy(reinterpret_cast<mr_ctx*>(c));
+        return rc;
+      }
+    }
+    if ((e = hipMemsetAsync(c->scal, 0, kSlotCount * sizeof(double), c->stream)) == hipSuccess)
+      e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+      rc = hip_fail(e, "mr_create");
+      mr_destroy(reinterpret_cast<mr_ctx*>(c));
+      return rc;
+    }
+  }
   *out = reinterpret_cast<mr_ctx*>(c);
   return MR_OK;
 }
@@ -608,25 +650,43 @@ int mr_sweep(mr_ctx* h, int nl, double hcell, const double* delta, const double*
   if (e == hipSuccess && f) e = launch_to_split(f, fs, nl, c->stream);
   if (e == hipSuccess) e = launch_to_split(theta_in, tin, nl, c->stream);
   if (e != hipSuccess) return hip_fail(e, "mr_sweep");
-  TileCfg t = sweep_tiles(nl);
-  HalfSweepArgs a{};
-  a.th_in = tin;
-  a.th_out = tout;
-  a.delta = ds;
-  a.f = fs;
-  a.n = nl;
-  a.h2 = hcell * hcell;
-  a.ih2 = 1.0 / a.h2;
-  a.c_add = cshift;
-  a.partials = c->partials;
-  a.counter = c->counter;
-  a.colour = 0;
-  a.sum_out = c->scal + kSlotAux + 0;
-  e = launch_half_sweep(a, t, c->stream);
-  a.colour = 1;
-  a.th_red_new = tout;
-  a.sum_out = c->scal + kSlotAux + 1;
-  if (e == hipSuccess) e = launch_half_sweep(a, t, c->stream);
+  FusedCfg fz;
+  if (!(c->opts.flags & MR_FLAG_TWO_PASS) && (tuned_sweep(nl, &fz) || pick_fused(nl, fz))) {
+    FusedSweepArgs a{};
+    a.th_in = tin;
+    a.th_out = tout;
+    a.delta = ds;
+    a.f = fs;
+    a.n = nl;
+    a.h2 = hcell * hcell;
+    a.ih2 = 1.0 / a.h2;
+    a.c_add = cshift;
+    a.sum_out = c->scal + kSlotAux;
+    a.partials = c->partials;
+    a.counter = c->counter;
+    if (e == hipSuccess) e = launch_sweep_fused(a, fz, c->stream);
+  } else {
+    TileCfg t = sweep_tiles(nl);
+    t.pipe = t.cpt == 1 && t.ci % 4 == 0 && half_sweep_pipe_supported(t.tm, t.tj);
+    HalfSweepArgs a{};
+    a.th_in = tin;
+    a.th_out = tout;
+    a.delta = ds;
+    a.f = fs;
+    a.n = nl;
+    a.h2 = hcell * hcell;
+    a.ih2 = 1.0 / a.h2;
+    a.c_add = cshift;
+    a.partials = c->partials;
+    a.counter = c->counter;
+    a.colour = 0;
+    a.sum_out = c->scal + kSlotAux + 0;
+    if (e == hipSuccess) e = launch_half_sweep(a, t, c->stream);
+    a.colour = 1;
+    a.th_red_new = tout;
+    a.sum_out = c->scal + kSlotAux + 1;
+    if (e == hipSuccess) e = launch_half_sweep(a, t, c->stream);
+  }
   if (e == hipSuccess) e = launch_from_split(tout, theta_out, nl, nullptr, 0.0, c->stream);
   if (e != hipSuccess) return hip_fail(e, "mr_sweep");
   double s[2];

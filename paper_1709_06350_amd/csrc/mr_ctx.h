@@ -37,6 +37,8 @@ struct Level {
   double* delta = nullptr;
   double* f = nullptr;      // FAS right-hand side (levels >= 1)
   TileCfg sw, df;           // tiles of the half-sweep and of the defect + restriction
+  FusedCfg fz;              // tile of the fused red-black sweep (has_fz: one fits)
+  bool has_fz = false;
 };
 
 struct EventTimer {

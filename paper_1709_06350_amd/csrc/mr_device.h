@@ -27,33 +27,53 @@ __device__ __forceinline__ int wrapi(int x, int n) {
 // e^3 >= 0, and c + e >= sqrt(-p/3)), so the iteration starts on the convex, increasing branch
 // right of the root and decreases monotonically onto it. The seed is formed in FP32 with the
 // hardware log2/exp2/sqrt/rcp; each FP64 step uses the approximate hardware reciprocal, whose
-// error only scales the already-small step. The loop ends, uniformly across the wavefront,
-// once every lane's last step is below 1e-8 of the root: Newton's error is then below ~1e-15.
-__device__ __forceinline__ double largest_root(double p, double q) {
+// error only scales the already-small step. Each root stops changing after the first step that
+// is below 1e-8 of it (Newton's error is then below ~1e-15), so the result depends only on
+// (p, q), never on the other lanes of the wavefront; the loop runs until every root of every
+// lane has stopped. N independent roots are iterated together to overlap their latencies.
+__device__ __forceinline__ float root_seed(double p, double q) {
   const float pf = (float)p;
   const float mq = fmaxf(-(float)q, 0.0f);
   const float c = mq > 0.0f ? __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(mq) * (1.0f / 3.0f)) : 0.0f;
   const float b1 = __builtin_amdgcn_sqrtf(fmaxf(-pf, 0.0f)) + c;
   const float b2 = c > 0.0f ? c - pf * __builtin_amdgcn_rcpf(3.0f * c) : b1;
-  double s = (double)fminf(b1, b2);
-#pragma unroll 1
-  for (int it = 0; it < 16; ++it) {
-    const double s2 = s * s;
-    const double g = __builtin_fma(s, s2 + p, q);
-    const double gp = __builtin_fma(3.0, s2, p);
-    const double ds = g * __builtin_amdgcn_rcp(gp);
-    s -= ds;
-    if (__ballot(__builtin_fabs(ds) > 1e-8 * s) == 0) break;
-  }
-  return s;
+  return fminf(b1, b2);
 }
 
-// Sigma = s* - 3 of one cell and S = sum of the 6 face neighbours.
-// With u_a = S_a - S/3 (h^2 times the barred diagonal) and w_ab = D_ab/4 (h^2 times the barred
-// off-diagonal), h^4 T2 = sum u_a^2 + 2 sum w_ab^2 and h^6 T3 = 3 u_x u_y u_z
-// - 3 (u_z w_xy^2 + u_y w_xz^2 + u_x w_yz^2) + 6 w_xy w_xz w_yz (tr of the cube of a traceless
-// symmetric matrix); p = -(9/2) T2, q = 9 T3 - 27 (1 + delta) (Sec. II, Eq. 9; Appendix A).
-__device__ __forceinline__ double sigma_cell(const Nb18& t, double opd, double ih2, double& S) {
+template <int N>
+__device__ __forceinline__ void largest_roots(const double (&p)[N], const double (&q)[N], double (&s)[N]) {
+  bool done[N];
+#pragma unroll
+  for (int u = 0; u < N; ++u) {
+    s[u] = (double)root_seed(p[u], q[u]);
+    done[u] = false;
+  }
+#pragma unroll 1
+  for (int it = 0; it < 16; ++it) {
+    bool any = false;
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      const double s2 = s[u] * s[u];
+      const double g = __builtin_fma(s[u], s2 + p[u], q[u]);
+      const double gp = __builtin_fma(3.0, s2, p[u]);
+      const double ds = g * __builtin_amdgcn_rcp(gp);
+      const double sn = s[u] - ds;
+      s[u] = done[u] ? s[u] : sn;
+      done[u] = done[u] || !(__builtin_fabs(ds) > 1e-8 * sn);
+      any = any || !done[u];
+    }
+    if (__ballot(any) == 0) break;
+  }
+}
+
+__device__ __forceinline__ double largest_root(double p, double q) {
+  double pp[1] = {p}, qq[1] = {q}, s[1];
+  largest_roots<1>(pp, qq, s);
+  return s[0];
+}
+
+// Cubic coefficients p, q of one cell and S = sum of the 6 face neighbours (see sigma_cell).
+__device__ __forceinline__ void cell_pq(const Nb18& t, double opd, double ih2, double& S, double& p, double& q) {
   const double Sx = t.xm + t.xp;
   const double Sy = t.ym + t.yp;
   const double Sz = t.zm + t.zp;
@@ -68,8 +88,18 @@ __device__ __forceinline__ double sigma_cell(const Nb18& t, double opd, double i
   const double Q = 3.0 * (ux * uy * uz - (__builtin_fma(uz, wxy2, __builtin_fma(uy, wxz2, ux * wyz2))))
                    + 6.0 * wxy * wxz * wyz;
   const double ih4 = ih2 * ih2;
-  const double p = -4.5 * P * ih4;
-  const double q = __builtin_fma(9.0 * Q, ih4 * ih2, -27.0 * opd);
+  p = -4.5 * P * ih4;
+  q = __builtin_fma(9.0 * Q, ih4 * ih2, -27.0 * opd);
+}
+
+// Sigma = s* - 3 of one cell and S = sum of the 6 face neighbours.
+// With u_a = S_a - S/3 (h^2 times the barred diagonal) and w_ab = D_ab/4 (h^2 times the barred
+// off-diagonal), h^4 T2 = sum u_a^2 + 2 sum w_ab^2 and h^6 T3 = 3 u_x u_y u_z
+// - 3 (u_z w_xy^2 + u_y w_xz^2 + u_x w_yz^2) + 6 w_xy w_xz w_yz (tr of the cube of a traceless
+// symmetric matrix); p = -(9/2) T2, q = 9 T3 - 27 (1 + delta) (Sec. II, Eq. 9; Appendix A).
+__device__ __forceinline__ double sigma_cell(const Nb18& t, double opd, double ih2, double& S) {
+  double p, q;
+  cell_pq(t, opd, ih2, S, p, q);
   return largest_root(p, q) - 3.0;
 }
 

@@ -14,6 +14,7 @@ constexpr int kMaxNV = 4;                // values reduced per launch
 // Tile of the 2.5D kernels: tm columns (m = k >> 1) x tj rows (j), chunks of ci planes (i).
 struct TileCfg {
   int tm = 64, tj = 4, ci = 32, tiles_j = 1, tiles_m = 1, cpt = 1;   // cpt: cells per thread per plane
+  bool pipe = false;   // half-sweep only: the pipelined kernel (cpt 1, ci % 4 == 0)
 };
 
 // The uniform shift subtracted from the source in a relaxation or defect is
@@ -66,6 +67,30 @@ struct DefectArgs {
   int tj, tiles_j, tiles_m, ci;
 };
 
+// Fused red-black sweep (one launch): th_in holds both colours of the old iterate, th_out
+// receives both colours of the new one. sum_out[0] / sum_out[1] receive the sums of Sigma + f over
+// the red / black cells as evaluated during the sweep.
+struct FusedSweepArgs {
+  const double* th_in;
+  double* th_out;
+  const double* delta;
+  const double* f;        // may be null
+  int n;
+  double h2, ih2;
+  const double* c_sum;
+  double c_scale, c_add;
+  double* sum_out;
+  double* partials;
+  unsigned int* counter;
+  int tiles_j, tiles_m, nchunks;
+};
+
+// Tile of the fused sweep: tm x tj cells of (m, j) per block, the i axis split into nchunks
+// chunks of (nearly) equal length; blocks = tiles_j * tiles_m * nchunks.
+struct FusedCfg {
+  int tm = 0, tj = 0, tiles_j = 0, tiles_m = 0, nchunks = 0;
+};
+
 struct CoarsestArgs {
   double* theta;
   const double* delta;
@@ -107,8 +132,21 @@ struct Reduce {
 size_t tile_lds_bytes(int tj, int tm);
 hipError_t launch_half_sweep(const HalfSweepArgs& a, const TileCfg& t, hipStream_t s);
 bool half_sweep_tile_supported(int tm, int tj, int cpt);
+bool half_sweep_pipe_supported(int tm, int tj);
 hipError_t launch_defect_restrict_tiled(const DefectArgs& a, const TileCfg& t, hipStream_t s);
 hipError_t launch_coarsest(const CoarsestArgs& a, hipStream_t s);
+// Chooses a fused-sweep tile for an n^3 mesh on the current device by occupancy (false: no
+// compiled tile fits).
+bool pick_fused(int n, FusedCfg& cfg);
+// Times the fused candidates and the two-launch sweep (tiles *two, general and pipelined kernel)
+// on the given n^3 buffers, which it overwrites; *use_fused tells whether the fused launch is
+// fastest, *cfg its configuration, *two the faster two-launch variant. The result is cached per
+// device and n. Returns an MR_ status code.
+int tune_sweep(int n, double* th_a, double* th_b, double* delta, double* partials, unsigned* counter, double* sums,
+               TileCfg* two, hipStream_t s, bool* use_fused, FusedCfg* cfg);
+// The cached tuning result for n on the current device (false: not tuned or two launches won).
+bool tuned_sweep(int n, FusedCfg* cfg);
+hipError_t launch_sweep_fused(const FusedSweepArgs& a, const FusedCfg& cfg, hipStream_t s);
 
 // All fields below are colour-split unless named "natural".
 // f = nabla^2 th - Sigma(th) - rd on an n^3 mesh (f may alias rd); result[0..1] = (sum(Sigma + f), 0).

@@ -14,6 +14,15 @@
 // theta value is read from HBM about once per launch. Every thread updates exactly one cell per
 // plane (perfect balance); the block's tiles are mapped so that each XCD walks a contiguous
 // range of tiles and shares halos in its own L2.
+#include <algorithm>
+#include <type_traits>
+#include <map>
+#include <mutex>
+#include <utility>
+#include <vector>
+
+#include "mr.h"
+#include "mr_ctx.h"
 #include "mr_device.h"
 #include "mr_kernels.h"
 
@@ -227,6 +236,134 @@ __global__ void __launch_bounds__(TM * TJ / CPT) half_sweep_tiled(HalfSweepArgs 
   if (last && tid == 0 && a.copy_to) *a.copy_to = *a.copy_from;
 }
 
+// ---- pipelined half-sweep ------------------------------------------------------------------
+// The same decomposition and arithmetic as half_sweep_tiled with one cell per thread, for the
+// large tiles of the fine meshes. The colour and the presence of f are compile-time, and the plane
+// loop is unrolled by the ring length (4) with slots taken relative to the chunk, so every LDS
+// access is a per-thread base plus an immediate. Old planes are fetched into registers two steps
+// before they enter LDS and delta / f two steps before use (rotating register sets), and every
+// memory operation of the loop body is unconditional (clamped plane indices), so the loads of
+// later steps stay in flight across the barrier. Requires ci % 4 == 0.
+template <int TM, int TJ, int COL, bool HAS_F>
+__global__ void __launch_bounds__(TM * TJ) half_sweep_pipe(HalfSweepArgs a) {
+  constexpr int NT = TM * TJ;
+  constexpr int RW = TM + 2, RH = TJ + 2;
+  constexpr int SLOT = RH * RW;
+  constexpr int TOTAL = 2 * SLOT;
+  constexpr int NPF = (TOTAL + NT - 1) / NT;
+  constexpr int O = 1 - COL;
+  __shared__ double lds[2 * 4 * SLOT];
+  const int n = a.n, nh = n >> 1;
+  const int tid = threadIdx.x;
+  int j0, m0, i0;
+  tile_coords(gridDim.x, a.tiles_m, a.tiles_j, TJ, TM, a.ci, j0, m0, i0);
+  const int ci = a.ci;
+  const unsigned half = (unsigned)n * (unsigned)n * (unsigned)nh;
+  const unsigned plane = (unsigned)n * (unsigned)nh;
+  const double* __restrict__ src0 = COL == 1 ? a.th_red_new : a.th_in;   // colour 0 values
+  const double* __restrict__ src1 = a.th_in + half;                      // colour 1 values
+
+  unsigned goff[NPF];
+  int loff[NPF];
+  bool col1[NPF];
+#pragma unroll
+  for (int t = 0; t < NPF; ++t) {
+    int e = tid + t * NT;
+    e = e < TOTAL ? e : TOTAL - 1;
+    const int cc = e / SLOT;
+    const int rem = e - cc * SLOT;
+    const int r = rem / RW;
+    const int c = rem - r * RW;
+    goff[t] = (unsigned)wrapi(j0 - 1 + r, n) * nh + (unsigned)wrapi(m0 - 1 + c, nh);
+    loff[t] = cc * 4 * SLOT + rem;
+    col1[t] = cc != 0;
+  }
+  // plane i0 - 1 + rel sits in slot rel & 3
+  auto fetch = [&](int rel, double (&v)[NPF]) {
+    const unsigned base = (unsigned)wrapi(i0 - 1 + rel, n) * plane;
+#pragma unroll
+    for (int t = 0; t < NPF; ++t) v[t] = (col1[t] ? src1 : src0)[base + goff[t]];
+  };
+  auto store = [&](int slot, const double (&v)[NPF]) {
+#pragma unroll
+    for (int t = 0; t < NPF; ++t) lds[loff[t] + slot * SLOT] = v[t];
+  };
+
+  const int s = tid % TM, r = tid / TM;
+  const int j = j0 + r, m = m0 + s;
+  const unsigned own = (unsigned)j * nh + m;
+  const int ob = (r + 1) * RW + (s + 1);                 // own cell inside a slot
+  const int q0 = (i0 + j + COL) & 1;                     // z-parity at even t
+  const int oq0 = ob + q0, oq1 = ob + (q0 ^ 1);
+  const double C = (a.c_sum ? (a.c_sum[0] + a.c_sum[1]) * a.c_scale : 0.0) + a.c_add;
+  const double h2 = a.h2, ih2 = a.ih2;
+  const double* __restrict__ dl = a.delta + COL * half + own;
+  const double* __restrict__ ff = HAS_F ? a.f + COL * half + own : nullptr;
+  double* __restrict__ out = a.th_out + COL * half + own;
+  const int last_plane = n - 1;
+  double acc = 0.0;
+
+  double V0[NPF], V1[NPF];
+  double D[4], Fv[4];
+  {
+    double va[NPF], vb[NPF], vc[NPF];
+    fetch(0, va);
+    fetch(1, vb);
+    fetch(2, vc);
+    store(0, va);
+    store(1, vb);
+    store(2, vc);
+  }
+  fetch(3, V0);
+  D[0] = dl[(unsigned)i0 * plane];
+  D[1] = dl[(unsigned)min(i0 + 1, last_plane) * plane];
+  if (HAS_F) {
+    Fv[0] = ff[(unsigned)i0 * plane];
+    Fv[1] = ff[(unsigned)min(i0 + 1, last_plane) * plane];
+  }
+  __syncthreads();
+
+  // step t (K = t & 3): plane i = i0 + t (rel t + 1); LDS holds rel t, t+1, t+2
+  auto step = [&](auto kc, int t, double (&vst)[NPF], double (&vft)[NPF]) {
+    constexpr int K = decltype(kc)::value;
+    constexpr int SM = (K + 0) & 3, S0 = (K + 1) & 3, SP = (K + 2) & 3, SN = (K + 3) & 3;
+    fetch(t + 4, vft);
+    const unsigned pn = (unsigned)min(i0 + t + 2, last_plane) * plane;
+    D[(K + 2) & 3] = dl[pn];
+    if (HAS_F) Fv[(K + 2) & 3] = ff[pn];
+    const int oq = (K & 1) ? oq1 : oq0;
+    const double* __restrict__ lo = lds + O * 4 * SLOT;     // other colour
+    const double* __restrict__ lc = lds + COL * 4 * SLOT;   // own colour
+    Nb18 c;
+    c.xm = lo[SM * SLOT + ob];         c.xp = lo[SP * SLOT + ob];
+    c.ym = lo[S0 * SLOT + ob - RW];    c.yp = lo[S0 * SLOT + ob + RW];
+    c.zm = lo[S0 * SLOT + oq - 1];     c.zp = lo[S0 * SLOT + oq];
+    c.xpyp = lc[SP * SLOT + ob + RW];  c.xmym = lc[SM * SLOT + ob - RW];
+    c.xpym = lc[SP * SLOT + ob - RW];  c.xmyp = lc[SM * SLOT + ob + RW];
+    c.xpzp = lc[SP * SLOT + oq];       c.xmzm = lc[SM * SLOT + oq - 1];
+    c.xpzm = lc[SP * SLOT + oq - 1];   c.xmzp = lc[SM * SLOT + oq];
+    c.ypzp = lc[S0 * SLOT + oq + RW];  c.ymzm = lc[S0 * SLOT + oq - RW - 1];
+    c.ypzm = lc[S0 * SLOT + oq + RW - 1]; c.ymzp = lc[S0 * SLOT + oq - RW];
+    const double fc = HAS_F ? Fv[K] : 0.0;
+    double S;
+    const double sig = sigma_cell(c, 1.0 + D[K], ih2, S);
+    out[(unsigned)(i0 + t) * plane] = (S - h2 * (sig + fc - C)) * (1.0 / 6.0);
+    acc += sig + fc;
+    store(SN, vst);
+    __syncthreads();
+  };
+  for (int t = 0; t < ci; t += 4) {
+    step(std::integral_constant<int, 0>(), t, V0, V1);
+    step(std::integral_constant<int, 1>(), t + 1, V1, V0);
+    step(std::integral_constant<int, 2>(), t + 2, V0, V1);
+    step(std::integral_constant<int, 3>(), t + 3, V1, V0);
+  }
+
+  double vv[1] = {acc};
+  const bool last = grid_sum<1>(vv, a.partials, a.counter, a.sum_out, gridDim.x, blockIdx.x);
+  if (last && tid == 0 && a.copy_to) *a.copy_to = *a.copy_from;
+}
+
 // ---- fused defect + restriction -----------------------------------------------------------
 // d = nabla^2 theta - Sigma - f + C at every fine cell, then the 8-son averages of d and theta
 // (Eq. 18 and R). A thread owns fine rows 2J, 2J+1 and the cell pair k = 2m, 2m+1 (both colours
@@ -371,6 +508,316 @@ __global__ void __launch_bounds__(256) coarsest_kernel(CoarsestArgs a) {
   }
 }
 
+// ---- fused red-black sweep (one launch per sweep) -----------------------------------------
+// Both half-sweeps of Eq. 17 in one pass over the mesh. A cell's update reads only its 18
+// neighbours (never its own old value), so a block can compute the new red values of plane p on
+// its tile plus a one-cell halo (the halo cells are recomputed identically by the neighbouring
+// blocks), and the new black values of plane p - 2 on its tile from red values already in LDS.
+// Old theta of both colours (tile plus a two-cell halo) streams through LDS rings: red needs
+// planes p-1..p+1, black p-3..p+1 (faces of red at plane p, edges of black at p-3..p-1); the
+// new red values live in a 4-plane ring. One barrier per plane; every old value, delta and f is
+// read from HBM once (plus halos) and every new value written once: 24 B per cell update.
+// Latency: old planes are fetched into registers three plane steps before they enter LDS, and
+// the per-cell inputs (delta, f) two steps before use, from three rotating register sets (the
+// plane loop is unrolled by three so that each set is a fixed group of registers).
+// Sums of Sigma + f over the block's own cells of each colour go to sum_out[0] (red) and
+// sum_out[1] (black).
+template <int TM, int TJ>
+struct FusedTile {
+  static constexpr int NT = TM * TJ;
+  static constexpr int DW = TM + 4, DH = TJ + 4, DS = DW * DH;   // old values: tile + 2-cell halo
+  static constexpr int EW = TM + 2, EH = TJ + 2, ES = EW * EH;   // new red: tile + 1-cell halo
+  static constexpr int H = 2 * EW + 2 * TJ;                      // red halo cells per plane
+  static constexpr int LTOT = 2 * DS;                            // old values loaded per plane
+  static constexpr int NPF = (LTOT + NT - 1) / NT;
+  static constexpr int LDS = 4 * DS + 6 * DS + 4 * ES;           // doubles
+  static_assert(H <= NT, "tile too small for its halo");
+};
+
+__device__ __forceinline__ int slot6(int p) { return ((p % 6) + 6) % 6; }
+
+// Per-cell inputs of one plane step: delta and f of the own red cell, the red halo cell and the
+// own black cell.
+struct StepIn {
+  double dRo, dRh, dB, fRo, fRh, fB;
+};
+
+// The plane loop runs over steps t = 0, 1, ... (red plane p = i0 - 1 + t, black plane p - 2).
+// Ring slots are taken relative to the first old plane P0 = i0 - 2 (rel = plane - P0), and the
+// loop is unrolled by 12 (a multiple of both ring lengths), so that every slot and the parity of
+// every z-neighbour offset is a compile-time constant of the unrolled step: each LDS access is a
+// per-thread base address plus an immediate offset.
+template <int TM, int TJ, bool HAS_F>
+struct FusedSweep {
+  using F = FusedTile<TM, TJ>;
+  static constexpr int NT = F::NT, DW = F::DW, DS = F::DS, EW = F::EW, ES = F::ES, NPF = F::NPF;
+  static constexpr int OR0 = 0, OB0 = 4 * DS, NR0 = 10 * DS;   // ring bases (doubles)
+  static constexpr int s4(int rel) { return rel & 3; }
+  static constexpr int s6(int rel) { return rel % 6; }
+
+  double* lds;
+  const double* __restrict__ th;
+  const double* __restrict__ dl;
+  const double* __restrict__ ff;
+  double* __restrict__ out;
+  int n, P0, i0, i1, tlast;          // tlast: last step; planes P0 .. P0 + tlast + 2 are loaded
+  unsigned plane, half, own_off, halo_off;
+  bool has_halo;
+  double C, h2, ih2, accR, accB;
+  unsigned goff[NPF];
+  int soff_r[NPF], soff_b[NPF];
+  bool blk[NPF];
+  // per-thread LDS element offsets: own red cell (D coords), red halo cell (D coords), own black
+  // cell (E coords in the new-red ring, D coords in the old-black ring); *_q[k]: the same plus the
+  // z-parity of the cell when rel is even (k = 0) or odd (k = 1)
+  int pro, pro_q[2], prh, prh_q[2], pbE, pbE_q[2], pbD, pbD_q[2];
+  int wro, wrh;   // new red of the own and the halo cell (E coords, ring base)
+  double B0[NPF], B1[NPF], B2[NPF];
+  StepIn I0, I1, I2;
+
+  __device__ __forceinline__ void fetch(int rel, double (&v)[NPF]) const {
+    const unsigned base = (unsigned)wrapi(P0 + rel, n) * plane;
+#pragma unroll
+    for (int t = 0; t < NPF; ++t) v[t] = th[base + goff[t]];
+  }
+  template <int REL>
+  __device__ __forceinline__ void store(const double (&v)[NPF]) {
+#pragma unroll
+    for (int t = 0; t < NPF; ++t) lds[blk[t] ? soff_b[t] + s6(REL) * DS : soff_r[t] + s4(REL) * DS] = v[t];
+  }
+  __device__ __forceinline__ void store_rt(int rel, const double (&v)[NPF]) {
+    const int sr = (rel & 3) * DS, sb = (rel % 6) * DS;
+#pragma unroll
+    for (int t = 0; t < NPF; ++t) lds[blk[t] ? soff_b[t] + sb : soff_r[t] + sr] = v[t];
+  }
+  __device__ __forceinline__ double cell_in(const double* __restrict__ fld, int colour, int rel, unsigned off) const {
+    return fld[(unsigned)colour * half + (unsigned)wrapi(P0 + rel, n) * plane + off];
+  }
+  // inputs of step t: red plane rel t + 1 (if plane <= i1), black plane rel t - 1 (if in [i0, i1))
+  __device__ __forceinline__ StepIn load_in(int t) const {
+    double dRo = 0.0, dRh = 0.0, dB = 0.0, fRo = 0.0, fRh = 0.0, fB = 0.0;
+    if (P0 + t + 1 <= i1) {
+      dRo = cell_in(dl, 0, t + 1, own_off);
+      if (has_halo) dRh = cell_in(dl, 0, t + 1, halo_off);
+      if (HAS_F) {
+        fRo = cell_in(ff, 0, t + 1, own_off);
+        if (has_halo) fRh = cell_in(ff, 0, t + 1, halo_off);
+      }
+    }
+    const int pb = P0 + t - 1;
+    if (pb >= i0 && pb < i1) {
+      dB = cell_in(dl, 1, t - 1, own_off);
+      if (HAS_F) fB = cell_in(ff, 1, t - 1, own_off);
+    }
+    return StepIn{dRo, dRh, dB, fRo, fRh, fB};
+  }
+  // red cell of plane REL from the old rings; pc at the cell (D coords), pq = pc + q
+  template <int REL>
+  __device__ __forceinline__ void gather_red(int c0, int q0, Nb18& t) const {
+    const double* pc = lds + c0;
+    const double* pq = lds + q0;
+    constexpr int bm = OB0 + s6(REL + 5) * DS, b0 = OB0 + s6(REL) * DS, bp = OB0 + s6(REL + 1) * DS;
+    constexpr int rm = OR0 + s4(REL + 3) * DS, r0 = OR0 + s4(REL) * DS, rp = OR0 + s4(REL + 1) * DS;
+    t.xm = pc[bm]; t.xp = pc[bp];
+    t.ym = pc[b0 - DW]; t.yp = pc[b0 + DW];
+    t.zm = pq[b0 - 1];  t.zp = pq[b0];
+    t.xpyp = pc[rp + DW]; t.xmym = pc[rm - DW];
+    t.xpym = pc[rp - DW]; t.xmyp = pc[rm + DW];
+    t.xpzp = pq[rp];      t.xmzm = pq[rm - 1];
+    t.xpzm = pq[rp - 1];  t.xmzp = pq[rm];
+    t.ypzp = pq[r0 + DW]; t.ymzm = pq[r0 - DW - 1];
+    t.ypzm = pq[r0 + DW - 1]; t.ymzp = pq[r0 - DW];
+  }
+  // black own cell of plane REL: faces from the new-red ring (E coords), edges from old black
+  template <int REL>
+  __device__ __forceinline__ void gather_black(Nb18& t) const {
+    const double* eq = lds + pbE_q[REL & 1];
+    const double* dq = lds + pbD_q[REL & 1];
+    const double* pE = lds + pbE;
+    const double* pD = lds + pbD;
+    constexpr int nm = s4(REL + 3) * ES, n0 = s4(REL) * ES, np = s4(REL + 1) * ES;
+    constexpr int bm = s6(REL + 5) * DS, b0 = s6(REL) * DS, bp = s6(REL + 1) * DS;
+    t.xm = pE[nm]; t.xp = pE[np];
+    t.ym = pE[n0 - EW]; t.yp = pE[n0 + EW];
+    t.zm = eq[n0 - 1];   t.zp = eq[n0];
+    t.xpyp = pD[bp + DW]; t.xmym = pD[bm - DW];
+    t.xpym = pD[bp - DW]; t.xmyp = pD[bm + DW];
+    t.xpzp = dq[bp];       t.xmzm = dq[bm - 1];
+    t.xpzm = dq[bp - 1];   t.xmzp = dq[bm];
+    t.ypzp = dq[b0 + DW];  t.ymzm = dq[b0 - DW - 1];
+    t.ypzm = dq[b0 + DW - 1]; t.ymzp = dq[b0 - DW];
+  }
+
+  // Step t = 12 u + K: red plane rel t + 1, black plane rel t - 1; store old plane rel t + 3
+  // (fetched two steps earlier), fetch rel t + 5, load the inputs of step t + 2.
+  template <int K>
+  __device__ __forceinline__ void step(int t) {
+    if (t > tlast) return;
+    constexpr int kS = (K + 2) % 3, kF = (K + 1) % 3;          // store / fetch buffer
+    constexpr int kC = K % 3, kN = (K + 2) % 3;                // current / next inputs
+    double(&vs)[NPF] = kS == 0 ? B0 : (kS == 1 ? B1 : B2);
+    double(&vf)[NPF] = kF == 0 ? B0 : (kF == 1 ? B1 : B2);
+    const StepIn& cur = kC == 0 ? I0 : (kC == 1 ? I1 : I2);
+    StepIn& nxt = kN == 0 ? I0 : (kN == 1 ? I1 : I2);
+    if (t + 4 <= tlast) fetch(t + 5, vf);
+    if (t + 2 <= tlast) nxt = load_in(t + 2);
+    constexpr int REL = K + 1;            // red plane rel modulo 12 (t = 12 u + K)
+    constexpr int RELB = K + 11;          // black plane rel (t - 1) modulo 12, kept non-negative
+    const int pr = P0 + t + 1, pb = P0 + t - 1;
+    const bool do_red = pr <= i1;
+    const bool do_black = pb >= i0;
+    if (do_red && has_halo) {
+      Nb18 c;
+      gather_red<REL>(prh, prh_q[REL & 1], c);
+      double S, pp[1], qq[1], sr[1];
+      cell_pq(c, 1.0 + cur.dRh, ih2, S, pp[0], qq[0]);
+      largest_roots<1>(pp, qq, sr);
+      lds[wrh + s4(REL) * ES] = (S - h2 * (sr[0] - 3.0 + cur.fRh - C)) * (1.0 / 6.0);
+    }
+    if (do_red || do_black) {
+      Nb18 tr, tb;
+      double Sr = 0.0, Sb = 0.0, pp[2] = {0.0, 0.0}, qq[2] = {-27.0, -27.0}, sr[2];
+      if (do_red) {
+        gather_red<REL>(pro, pro_q[REL & 1], tr);
+        cell_pq(tr, 1.0 + cur.dRo, ih2, Sr, pp[0], qq[0]);
+      }
+      if (do_black) {
+        gather_black<RELB>(tb);
+        cell_pq(tb, 1.0 + cur.dB, ih2, Sb, pp[1], qq[1]);
+      }
+      largest_roots<2>(pp, qq, sr);
+      if (do_red) {
+        const double sig = sr[0] - 3.0;
+        const double nv = (Sr - h2 * (sig + cur.fRo - C)) * (1.0 / 6.0);
+        lds[wro + s4(REL) * ES] = nv;
+        if (pr >= i0 && pr < i1) {
+          out[(unsigned)pr * plane + own_off] = nv;
+          accR += sig + cur.fRo;
+        }
+      }
+      if (do_black) {
+        const double sig = sr[1] - 3.0;
+        out[half + (unsigned)pb * plane + own_off] = (Sb - h2 * (sig + cur.fB - C)) * (1.0 / 6.0);
+        accB += sig + cur.fB;
+      }
+    }
+    if (t + 2 <= tlast) store<K + 3>(vs);
+    __syncthreads();
+  }
+};
+
+template <int TM, int TJ, bool HAS_F>
+__global__ void __launch_bounds__(TM * TJ) sweep_fused(FusedSweepArgs a) {
+  using FS = FusedSweep<TM, TJ, HAS_F>;
+  using F = FusedTile<TM, TJ>;
+  constexpr int NT = F::NT, DW = F::DW, DS = F::DS, EW = F::EW, NPF = F::NPF;
+  __shared__ double lds[F::LDS];
+  FS st;
+  st.lds = lds;
+  const int n = a.n, nh = n >> 1;
+  const int tid = threadIdx.x;
+  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int ntile = a.tiles_m * a.tiles_j;
+  const int tile = logical % ntile, chunk = logical / ntile;
+  const int m0 = (tile % a.tiles_m) * TM, j0 = (tile / a.tiles_m) * TJ;
+  st.n = n;
+  st.i0 = (int)(((long)chunk * n) / a.nchunks);
+  st.i1 = (int)(((long)(chunk + 1) * n) / a.nchunks);
+  st.P0 = st.i0 - 2;
+  st.tlast = st.i1 + 1 - (st.i0 - 1);
+  st.plane = (unsigned)n * (unsigned)nh;
+  st.half = st.plane * (unsigned)n;
+  st.th = a.th_in;
+  st.dl = a.delta;
+  st.ff = a.f;
+  st.out = a.th_out;
+  st.C = (a.c_sum ? (a.c_sum[0] + a.c_sum[1]) * a.c_scale : 0.0) + a.c_add;
+  st.h2 = a.h2;
+  st.ih2 = a.ih2;
+  st.accR = 0.0;
+  st.accB = 0.0;
+#pragma unroll
+  for (int t = 0; t < NPF; ++t) {
+    int e = tid + t * NT;
+    e = e < F::LTOT ? e : F::LTOT - 1;
+    const int cc = e / DS;
+    const int rem = e - cc * DS;
+    const int r = rem / DW;
+    const int c = rem - r * DW;
+    st.goff[t] = (unsigned)cc * st.half + (unsigned)wrapi(j0 - 2 + r, n) * nh + (unsigned)wrapi(m0 - 2 + c, nh);
+    st.soff_r[t] = FS::OR0 + rem;
+    st.soff_b[t] = FS::OB0 + rem;
+    st.blk[t] = cc != 0;
+  }
+  const int s = tid % TM, r = tid / TM;
+  st.has_halo = tid < F::H;
+  int rh = 0, sh = 0;
+  if (tid < EW) {
+    rh = 0;
+    sh = tid;
+  } else if (tid < 2 * EW) {
+    rh = TJ + 1;
+    sh = tid - EW;
+  } else {
+    const int k = tid - 2 * EW;
+    rh = 1 + (k >> 1);
+    sh = (k & 1) ? TM + 1 : 0;
+  }
+  const int jm = j0 + r, mm = m0 + s;
+  const int jh = wrapi(j0 - 1 + rh, n), mh = wrapi(m0 - 1 + sh, nh);
+  st.own_off = (unsigned)jm * nh + mm;
+  st.halo_off = (unsigned)jh * nh + mh;
+  // z-parity of a colour-c cell of row j in plane P0 + rel: q = (P0 + rel + j + c) & 1
+  const int qro = (st.P0 + jm) & 1, qrh = (st.P0 + jh) & 1, qb = (st.P0 + jm + 1) & 1;
+  st.pro = (r + 2) * DW + (s + 2);
+  st.pro_q[0] = st.pro + qro;
+  st.pro_q[1] = st.pro + (qro ^ 1);
+  st.prh = (rh + 1) * DW + (sh + 1);
+  st.prh_q[0] = st.prh + qrh;
+  st.prh_q[1] = st.prh + (qrh ^ 1);
+  st.pbE = FS::NR0 + (r + 1) * EW + (s + 1);
+  st.pbE_q[0] = st.pbE + qb;
+  st.pbE_q[1] = st.pbE + (qb ^ 1);
+  st.pbD = FS::OB0 + (r + 2) * DW + (s + 2);
+  st.pbD_q[0] = st.pbD + qb;
+  st.pbD_q[1] = st.pbD + (qb ^ 1);
+  st.wro = FS::NR0 + (r + 1) * EW + (s + 1);
+  st.wrh = FS::NR0 + rh * EW + sh;
+
+  // prologue: old planes rel 0..2 into LDS, rel 3 and 4 in flight, inputs of steps 0 and 1
+  {
+    double va[NPF], vb[NPF], vc[NPF];
+    st.fetch(0, va);
+    st.fetch(1, vb);
+    st.fetch(2, vc);
+    st.store_rt(0, va);
+    st.store_rt(1, vb);
+    st.store_rt(2, vc);
+  }
+  st.fetch(3, st.B2);
+  if (st.tlast >= 3) st.fetch(4, st.B0);
+  st.I0 = st.load_in(0);
+  st.I1 = st.load_in(1);
+  st.I2 = StepIn{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  __syncthreads();
+  for (int t = 0; t <= st.tlast; t += 12) {
+    st.template step<0>(t);
+    st.template step<1>(t + 1);
+    st.template step<2>(t + 2);
+    st.template step<3>(t + 3);
+    st.template step<4>(t + 4);
+    st.template step<5>(t + 5);
+    st.template step<6>(t + 6);
+    st.template step<7>(t + 7);
+    st.template step<8>(t + 8);
+    st.template step<9>(t + 9);
+    st.template step<10>(t + 10);
+    st.template step<11>(t + 11);
+  }
+  double vv[2] = {st.accR, st.accB};
+  grid_sum<2>(vv, a.partials, a.counter, a.sum_out, gridDim.x, blockIdx.x);
+}
+
 // ---- launchers ----------------------------------------------------------------------------
 
 size_t tile_lds_bytes(int tj, int tm) { return sizeof(double) * 2 * 4 * (size_t)(tj + 2) * (tm + 2); }
@@ -394,6 +841,8 @@ static bool tile_ok(const TileCfg& t, int n, int threads) {
   X(64, 8, 2) X(64, 4, 1) X(64, 8, 1) X(64, 16, 4) X(32, 8, 1) X(32, 16, 2) X(16, 16, 1) \
   X(16, 32, 2) X(8, 16, 1) X(8, 8, 1) X(4, 8, 1) X(4, 16, 2) X(2, 4, 1) X(2, 8, 1)
 
+#define MR_HP_TILES(X) X(64, 8) X(64, 4) X(32, 8) X(32, 16) X(16, 16)
+
 bool half_sweep_tile_supported(int tm, int tj, int cpt) {
 #define MR_HS_MATCH(TM, TJ, CPT) if (tm == TM && tj == TJ && cpt == CPT) return true;
   MR_HS_TILES(MR_HS_MATCH)
@@ -412,6 +861,24 @@ hipError_t launch_half_sweep(const HalfSweepArgs& a, const TileCfg& t, hipStream
   b.tiles_m = t.tiles_m;
   b.ci = t.ci;
   const int blocks = (int)blocks_l;
+  if (t.pipe) {
+    if (t.ci % 4 != 0 || t.cpt != 1 || (a.colour == 1 && !a.th_red_new)) return hipErrorInvalidValue;
+#define MR_HP_LAUNCH(TM, TJ)                                                                            \
+    if (t.tm == TM && t.tj == TJ) {                                                                     \
+      if (a.colour == 0 && !a.f)                                                                        \
+        hipLaunchKernelGGL((half_sweep_pipe<TM, TJ, 0, false>), dim3(blocks), dim3(TM * TJ), 0, s, b);  \
+      else if (a.colour == 0)                                                                           \
+        hipLaunchKernelGGL((half_sweep_pipe<TM, TJ, 0, true>), dim3(blocks), dim3(TM * TJ), 0, s, b);   \
+      else if (!a.f)                                                                                    \
+        hipLaunchKernelGGL((half_sweep_pipe<TM, TJ, 1, false>), dim3(blocks), dim3(TM * TJ), 0, s, b);  \
+      else                                                                                              \
+        hipLaunchKernelGGL((half_sweep_pipe<TM, TJ, 1, true>), dim3(blocks), dim3(TM * TJ), 0, s, b);   \
+      return hipGetLastError();                                                                         \
+    }
+    MR_HP_TILES(MR_HP_LAUNCH)
+#undef MR_HP_LAUNCH
+    return hipErrorInvalidValue;
+  }
 #define MR_HS_LAUNCH(TM, TJ, CPT)                                                                  \
   if (t.tm == TM && t.tj == TJ && t.cpt == CPT) {                                                  \
     hipLaunchKernelGGL((half_sweep_tiled<TM, TJ, CPT>), dim3(blocks), dim3(TM * TJ / CPT), 0, s, b); \
@@ -420,6 +887,13 @@ hipError_t launch_half_sweep(const HalfSweepArgs& a, const TileCfg& t, hipStream
   MR_HS_TILES(MR_HS_LAUNCH)
 #undef MR_HS_LAUNCH
   return hipErrorInvalidValue;
+}
+
+bool half_sweep_pipe_supported(int tm, int tj) {
+#define MR_HP_MATCH(TM, TJ) if (tm == TM && tj == TJ) return true;
+  MR_HP_TILES(MR_HP_MATCH)
+#undef MR_HP_MATCH
+  return false;
 }
 
 hipError_t launch_defect_restrict_tiled(const DefectArgs& a, const TileCfg& t, hipStream_t s) {
@@ -448,6 +922,248 @@ hipError_t launch_coarsest(const CoarsestArgs& a, hipStream_t s) {
   if ((long)a.n * a.n * a.n > kMaxCoarsest) return hipErrorInvalidValue;
   hipLaunchKernelGGL(coarsest_kernel, dim3(1), dim3(256), 0, s, a);
   return hipGetLastError();
+}
+
+}  // namespace mr
+
+namespace mr {
+
+#define MR_FUSED_TILES(X) X(64, 8) X(32, 16) X(32, 8) X(16, 16) X(16, 8) X(8, 8) X(8, 4) X(4, 8)
+
+static const void* fused_kernel(int tm, int tj) {
+#define MR_FZ_PTR(TM, TJ) \
+  if (tm == TM && tj == TJ) return reinterpret_cast<const void*>(&sweep_fused<TM, TJ, true>);
+  MR_FUSED_TILES(MR_FZ_PTR)
+#undef MR_FZ_PTR
+  return nullptr;
+}
+
+// Candidate configurations for an n^3 mesh: every compiled tile that fits, each with the chunk
+// counts (chunks of at least 4 planes) whose fill * ci / (ci + 3) is within 15% of the best for
+// that tile, where fill is the fraction of the device's resident block slots the grid occupies
+// over its rounds and a chunk of ci planes takes ci + 3 plane steps. Ordered by that score.
+static std::vector<std::pair<double, FusedCfg>> fused_candidates(int n) {
+  std::vector<std::pair<double, FusedCfg>> out;
+  static const int pref[][2] = {{64, 8}, {32, 16}, {32, 8}, {16, 16}, {16, 8}, {8, 8}, {8, 4}, {4, 8}};
+  const int nh = n / 2;
+  int dev = 0, cus = 0;
+  if (n < 8 || hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    return out;
+  for (const auto& t : pref) {
+    const int tm = t[0], tj = t[1];
+    if (nh % tm != 0 || n % tj != 0) continue;
+    const void* k = fused_kernel(tm, tj);
+    int bpc = 0;
+    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, k, tm * tj, 0) != hipSuccess || bpc < 1) continue;
+    const long tiles = (long)(n / tj) * (nh / tm);
+    const long cap = (long)cus * bpc;
+    std::vector<std::pair<double, int>> ch;
+    for (int c = 1; c <= n; ++c) {
+      if (n / c < 4 && c > 1) break;
+      const long blocks = tiles * c;
+      if (blocks > kMaxReduceBlocks) break;
+      const long rounds = (blocks + cap - 1) / cap;
+      const double fill = (double)blocks / (double)(rounds * cap);
+      const double ci = (double)n / c;
+      ch.push_back({fill * ci / (ci + 3.0), c});
+    }
+    if (ch.empty()) continue;
+    std::sort(ch.begin(), ch.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    for (size_t i = 0; i < ch.size() && i < 3 && ch[i].first >= 0.85 * ch[0].first; ++i) {
+      FusedCfg c;
+      c.tm = tm;
+      c.tj = tj;
+      c.tiles_j = n / tj;
+      c.tiles_m = nh / tm;
+      c.nchunks = ch[i].second;
+      out.push_back({ch[i].first, c});
+    }
+  }
+  std::stable_sort(out.begin(), out.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+  return out;
+}
+
+bool pick_fused(int n, FusedCfg& cfg) {
+  const auto c = fused_candidates(n);
+  if (c.empty()) return false;
+  cfg = c.front().second;
+  return true;
+}
+
+// Synthetic state for timing, colour-split: a potential of three periodic plane waves of about
+// ten cells' wavelength whose Hessian is of order one (as in a converged solution of a strongly
+// non-linear field, so that the root iteration counts are representative), and a lognormal-like
+// density with the same contrast.
+__global__ void tune_fill_kernel(double* __restrict__ th, double* __restrict__ delta, int n) {
+  const int nh = n >> 1;
+  const size_t half = (size_t)n * n * nh, cells = 2 * half;
+  const double tw = 6.283185307179586 / n;
+  const double sc = n / 10.0;
+  const double k1[3] = {3.0 / 9.11, 5.0 / 9.11, 7.0 / 9.11}, k2[3] = {-4.0 / 6.71, 2.0 / 6.71, 5.0 / 6.71},
+               k3[3] = {6.0 / 7.0, -3.0 / 7.0, 2.0 / 7.0};
+  double w1[3], w2[3], w3[3];
+  for (int d = 0; d < 3; ++d) {
+    w1[d] = tw * fmax(1.0, rint(sc * k1[d] * (k1[d] < 0 ? -1.0 : 1.0))) * (k1[d] < 0 ? -1.0 : 1.0);
+    w2[d] = tw * fmax(1.0, rint(sc * k2[d] * (k2[d] < 0 ? -1.0 : 1.0))) * (k2[d] < 0 ? -1.0 : 1.0);
+    w3[d] = tw * fmax(1.0, rint(sc * k3[d] * (k3[d] < 0 ? -1.0 : 1.0))) * (k3[d] < 0 ? -1.0 : 1.0);
+  }
+  const double a1 = 0.8 / (w1[0] * w1[0] + w1[1] * w1[1] + w1[2] * w1[2]);
+  const double a2 = 0.8 / (w2[0] * w2[0] + w2[1] * w2[1] + w2[2] * w2[2]);
+  const double a3 = 0.8 / (w3[0] * w3[0] + w3[1] * w3[1] + w3[2] * w3[2]);
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < cells; e += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e / half);
+    const size_t rem = e - c * half;
+    const int i = (int)(rem / ((size_t)n * nh));
+    const int j = (int)((rem / nh) % n);
+    const int m = (int)(rem % nh);
+    const int k = 2 * m + ((i + j + c) & 1);
+    const double x = i, y = j, z = k;
+    th[e] = a1 * sin(w1[0] * x + w1[1] * y + w1[2] * z) + a2 * sin(w2[0] * x + w2[1] * y + w2[2] * z + 1.0) +
+            a3 * sin(w3[0] * x + w3[1] * y + w3[2] * z + 2.0);
+    delta[e] = exp(0.9 * sin(w2[0] * z - w1[1] * x + w3[2] * y + 0.5) - 0.405) - 1.0;
+  }
+}
+
+static std::mutex g_sweep_tune_mu;
+static std::map<std::pair<int, int>, std::pair<bool, FusedCfg>> g_sweep_tuned;   // (device, n)
+static std::map<std::pair<int, int>, TileCfg> g_half_tuned;                       // (device, n)
+
+bool tuned_sweep(int n, FusedCfg* cfg) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  std::lock_guard<std::mutex> lk(g_sweep_tune_mu);
+  auto it = g_sweep_tuned.find({dev, n});
+  if (it == g_sweep_tuned.end() || !it->second.first) return false;
+  *cfg = it->second.second;
+  return true;
+}
+
+int tune_sweep(int n, double* th_a, double* th_b, double* delta, double* partials, unsigned* counter, double* sums,
+               TileCfg* two, hipStream_t s, bool* use_fused, FusedCfg* cfg) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return hip_fail(hipErrorInvalidDevice, "sweep tuner");
+  {
+    std::lock_guard<std::mutex> lk(g_sweep_tune_mu);
+    auto it = g_sweep_tuned.find({dev, n});
+    if (it != g_sweep_tuned.end()) {
+      *use_fused = it->second.first;
+      *cfg = it->second.second;
+      auto jt = g_half_tuned.find({dev, n});
+      if (jt != g_half_tuned.end()) *two = jt->second;
+      return MR_OK;
+    }
+  }
+  const auto cand = fused_candidates(n);
+  const size_t cells = (size_t)n * n * n;
+  hipLaunchKernelGGL(tune_fill_kernel, dim3(1024), dim3(256), 0, s, th_a, delta, n);
+  hipError_t e = hipGetLastError();
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&ea);
+  if (e == hipSuccess) e = hipEventCreate(&eb);
+  const int reps = cells >= ((size_t)1 << 24) ? 2 : 4;
+  auto time_it = [&](auto&& run, float* ms) -> hipError_t {
+    hipError_t r = run();                                   // warm-up
+    if (r == hipSuccess) r = hipEventRecord(ea, s);
+    for (int k = 0; k < reps && r == hipSuccess; ++k) r = run();
+    if (r == hipSuccess) r = hipEventRecord(eb, s);
+    if (r == hipSuccess) r = hipEventSynchronize(eb);
+    if (r == hipSuccess) r = hipEventElapsedTime(ms, ea, eb);
+    *ms /= reps;
+    return r;
+  };
+  float best = 3.0e38f;
+  FusedCfg best_cfg;
+  bool best_fused = false;
+  // two launches per sweep: the general kernel, and the pipelined one where it applies
+  std::vector<TileCfg> twos{*two};
+  if (two->cpt == 1 && two->ci % 4 == 0 && half_sweep_pipe_supported(two->tm, two->tj)) {
+    TileCfg tp = *two;
+    tp.pipe = true;
+    twos.push_back(tp);
+  }
+  TileCfg best_two = *two;
+  for (const TileCfg& tw : twos) {
+    if (e != hipSuccess) break;
+    HalfSweepArgs a{};
+    a.th_in = th_a;
+    a.th_out = th_b;
+    a.delta = delta;
+    a.n = n;
+    a.h2 = 1.0;
+    a.ih2 = 1.0;
+    a.partials = partials;
+    a.counter = counter;
+    float ms = 0.0f;
+    e = time_it([&]() {
+      HalfSweepArgs r = a;
+      r.colour = 0;
+      r.sum_out = sums;
+      hipError_t x = launch_half_sweep(r, tw, s);
+      r.colour = 1;
+      r.th_red_new = th_b;
+      r.sum_out = sums + 1;
+      return x == hipSuccess ? launch_half_sweep(r, tw, s) : x;
+    }, &ms);
+    if (e == hipSuccess && ms < best) {
+      best = ms;
+      best_two = tw;
+    }
+  }
+  for (const auto& c : cand) {
+    if (e != hipSuccess) break;
+    FusedSweepArgs a{};
+    a.th_in = th_a;
+    a.th_out = th_b;
+    a.delta = delta;
+    a.n = n;
+    a.h2 = 1.0;
+    a.ih2 = 1.0;
+    a.sum_out = sums;
+    a.partials = partials;
+    a.counter = counter;
+    float ms = 0.0f;
+    e = time_it([&]() { return launch_sweep_fused(a, c.second, s); }, &ms);
+    if (e == hipSuccess && ms < best) {
+      best = ms;
+      best_cfg = c.second;
+      best_fused = true;
+    }
+  }
+  if (ea) (void)hipEventDestroy(ea);
+  if (eb) (void)hipEventDestroy(eb);
+  if (e != hipSuccess) return hip_fail(e, "sweep tuner");
+  {
+    std::lock_guard<std::mutex> lk(g_sweep_tune_mu);
+    g_sweep_tuned[{dev, n}] = {best_fused, best_cfg};
+    g_half_tuned[{dev, n}] = best_two;
+  }
+  *use_fused = best_fused;
+  *cfg = best_cfg;
+  *two = best_two;
+  return MR_OK;
+}
+
+hipError_t launch_sweep_fused(const FusedSweepArgs& a, const FusedCfg& cfg, hipStream_t s) {
+  const long blocks = (long)cfg.tiles_j * cfg.tiles_m * cfg.nchunks;
+  if (blocks < 1 || blocks > kMaxReduceBlocks || cfg.tj * cfg.tiles_j != a.n || cfg.tm * cfg.tiles_m != a.n / 2 ||
+      cfg.nchunks > a.n)
+    return hipErrorInvalidValue;
+  FusedSweepArgs b = a;
+  b.tiles_j = cfg.tiles_j;
+  b.tiles_m = cfg.tiles_m;
+  b.nchunks = cfg.nchunks;
+#define MR_FZ_LAUNCH(TM, TJ)                                                                           \
+  if (cfg.tm == TM && cfg.tj == TJ) {                                                                  \
+    if (b.f)                                                                                           \
+      hipLaunchKernelGGL((sweep_fused<TM, TJ, true>), dim3((unsigned)blocks), dim3(TM * TJ), 0, s, b);  \
+    else                                                                                               \
+      hipLaunchKernelGGL((sweep_fused<TM, TJ, false>), dim3((unsigned)blocks), dim3(TM * TJ), 0, s, b); \
+    return hipGetLastError();                                                                          \
+  }
+  MR_FUSED_TILES(MR_FZ_LAUNCH)
+#undef MR_FZ_LAUNCH
+  return hipErrorInvalidValue;
 }
 
 }  // namespace mr

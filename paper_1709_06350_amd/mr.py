@@ -24,6 +24,7 @@ MR_EDIVERGED = -3
 MR_EHIP = -4
 MR_ENOMEM = -5
 MR_FLAG_EAGER = 1
+MR_FLAG_TWO_PASS = 2
 PREC_FP64 = 0
 PREC_MIXED = 1
 

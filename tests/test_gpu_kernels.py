@@ -34,15 +34,26 @@ def ctx():
         yield c
 
 
+@pytest.fixture(scope="module")
+def ctx2():
+    """Context whose sweeps use one launch per colour instead of the fused red-black launch."""
+    require_gpu()
+    with mr.Context(64, flags=mr.MR_FLAG_TWO_PASS) as c:
+        yield c
+
+
 def _close(a, b, scale, tol=1e-12):
     err = np.max(np.abs(a - b))
     assert err <= tol * scale, f"max abs diff {err:.3e} > {tol:.0e} * {scale:.3e}"
 
 
+@pytest.mark.parametrize("two_pass", [False, True])
 @pytest.mark.parametrize("n,h,with_f", [(16, 1.0, False), (32, 1.0, False), (48, 1.0, False),
-                                        (32, 2.0, True), (64, 4.0, True), (8, 8.0, True)])
-def test_sweep_matches_oracle(ctx, n, h, with_f):
-    announce(f"sweep n={n} h={h} f={with_f}")
+                                        (32, 2.0, True), (64, 4.0, True), (8, 8.0, True), (128, 1.0, False)])
+def test_sweep_matches_oracle(ctx, ctx2, two_pass, n, h, with_f):
+    announce(f"sweep n={n} h={h} f={with_f} two_pass={two_pass}")
+    if two_pass:
+        ctx = ctx2
     delta, theta = _state(n, 100 + n)
     f = 0.05 * np.random.default_rng(n).standard_normal(theta.shape) if with_f else None
     C = 0.0123
@@ -64,6 +75,18 @@ def test_sweep_is_deterministic(ctx):
     a, s1 = ctx.sweep(dev(delta), dev(theta), cshift=0.01)
     b, s2 = ctx.sweep(dev(delta), dev(theta), cshift=0.01)
     assert np.array_equal(host(a), host(b)) and s1 == s2
+
+
+def test_fused_and_two_pass_sweeps_agree(ctx, ctx2):
+    """Same update, two schedules: the fused launch recomputes the halo red values of every tile in
+    the neighbouring blocks (the root iteration depends on the cell only), so both agree to
+    rounding (the compiler may contract a product into an FMA differently in the two kernels)."""
+    delta, theta = _state(64, 9)
+    a, s1 = ctx.sweep(dev(delta), dev(theta), cshift=0.004)
+    b, s2 = ctx2.sweep(dev(delta), dev(theta), cshift=0.004)
+    ha, hb = host(a), host(b)
+    _close(ha, hb, np.abs(hb).max(), tol=1e-14)
+    assert abs(s1 - s2) <= 1e-12 * (abs(s1) + 1.0)
 
 
 @pytest.mark.parametrize("n,h,with_f", [(16, 1.0, False), (48, 2.0, True)])
