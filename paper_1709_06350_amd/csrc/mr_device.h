@@ -27,10 +27,10 @@ __device__ __forceinline__ int wrapi(int x, int n) {
 // e^3 >= 0, and c + e >= sqrt(-p/3)), so the iteration starts on the convex, increasing branch
 // right of the root and decreases monotonically onto it. The seed is formed in FP32 with the
 // hardware log2/exp2/sqrt/rcp; each FP64 step uses the approximate hardware reciprocal, whose
-// error only scales the already-small step. Each root stops changing after the first step that
-// is below 1e-8 of it (Newton's error is then below ~1e-15), so the result depends only on
-// (p, q), never on the other lanes of the wavefront; the loop runs until every root of every
-// lane has stopped. N independent roots are iterated together to overlap their latencies.
+// error only scales the already-small step. Every root takes four steps; a root whose last step
+// is still above 1e-8 of it keeps stepping until one is below (Newton's error is then below
+// ~1e-15). The result depends only on (p, q), never on the other lanes of the wavefront.
+// N independent roots are iterated together to overlap their latencies.
 __device__ __forceinline__ float root_seed(double p, double q) {
   const float pf = (float)p;
   const float mq = fmaxf(-(float)q, 0.0f);
@@ -42,24 +42,43 @@ __device__ __forceinline__ float root_seed(double p, double q) {
 
 template <int N>
 __device__ __forceinline__ void largest_roots(const double (&p)[N], const double (&q)[N], double (&s)[N]) {
-  bool done[N];
+  double ds[N];
 #pragma unroll
-  for (int u = 0; u < N; ++u) {
-    s[u] = (double)root_seed(p[u], q[u]);
-    done[u] = false;
-  }
-#pragma unroll 1
-  for (int it = 0; it < 16; ++it) {
-    bool any = false;
+  for (int u = 0; u < N; ++u) s[u] = (double)root_seed(p[u], q[u]);
+  // Four steps for every root: from the upper-bound seed (typically ~1e-4 away) this reaches the
+  // stopping test for nearly every cell, with no per-lane control in the common path.
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
 #pragma unroll
     for (int u = 0; u < N; ++u) {
       const double s2 = s[u] * s[u];
       const double g = __builtin_fma(s[u], s2 + p[u], q[u]);
       const double gp = __builtin_fma(3.0, s2, p[u]);
-      const double ds = g * __builtin_amdgcn_rcp(gp);
-      const double sn = s[u] - ds;
+      ds[u] = g * __builtin_amdgcn_rcp(gp);
+      s[u] -= ds[u];
+    }
+  }
+  bool done[N];
+  bool any = false;
+#pragma unroll
+  for (int u = 0; u < N; ++u) {
+    done[u] = !(__builtin_fabs(ds[u]) > 1e-8 * s[u]);
+    any = any || !done[u];
+  }
+  if (__ballot(any) == 0) return;
+  // the few roots that still move (near a double root or from a poor seed) continue alone
+#pragma unroll 1
+  for (int it = 4; it < 24; ++it) {
+    any = false;
+#pragma unroll
+    for (int u = 0; u < N; ++u) {
+      const double s2 = s[u] * s[u];
+      const double g = __builtin_fma(s[u], s2 + p[u], q[u]);
+      const double gp = __builtin_fma(3.0, s2, p[u]);
+      const double d = g * __builtin_amdgcn_rcp(gp);
+      const double sn = s[u] - d;
       s[u] = done[u] ? s[u] : sn;
-      done[u] = done[u] || !(__builtin_fabs(ds) > 1e-8 * sn);
+      done[u] = done[u] || !(__builtin_fabs(d) > 1e-8 * sn);
       any = any || !done[u];
     }
     if (__ballot(any) == 0) break;
