@@ -231,7 +231,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None if traffic is None else round(traffic / avg_sweep_s / 1e9, 1),
-            "kernel": "half_sweep_tiled (finest-mesh FP64 red-black sweep: red + black launch)",
+            "kernel": "half_sweep_pipe (finest-mesh FP64 red-black sweep: red + black launch)",
             "sweep_us": round(avg_sweep_s * 1e6, 2),
             "algorithmic_bytes_per_sweep": SWEEP_BYTES_PER_UPDATE * cells,
             "traffic_bytes_per_sweep": traffic,

@@ -15,6 +15,7 @@
 // W is rebuilt on the fly in every sweep from an FP32 copy of the base potential (both colours in
 // LDS with e) and the FP32 base root s; coarse meshes use the restricted base potential and
 // their own root (rediscretisation).
+#include <algorithm>
 #include <type_traits>
 
 #include "mr_ctx.h"
@@ -23,6 +24,9 @@
 #include "mixed_device.h"
 
 namespace mr {
+
+// Compiled tile shapes (tm columns of m, tj rows) of the FP32 linear sweeps.
+#define MR_LIN_TILES(X) X(64, 8) X(64, 4) X(32, 16) X(32, 8) X(16, 16) X(8, 16) X(4, 8) X(2, 4)
 
 template <int TM, int TJ>
 __global__ void __launch_bounds__(TM * TJ) lin_half_sweep_tiled(LinSweepArgs a) {
@@ -79,8 +83,8 @@ __global__ void __launch_bounds__(TM * TJ) lin_sweep_pipe(LinSweepArgs a) {
   constexpr int NT = TM * TJ;
   constexpr int RW = TM + 2;
   constexpr int SLOT = LinTile<TM, TJ>::SLOT;
-  constexpr int TOTAL = 4 * SLOT;
-  constexpr int NPF = (TOTAL + NT - 1) / NT;
+  constexpr int PER = (SLOT + NT - 1) / NT;   // loads per field and thread
+  constexpr int NPF = 4 * PER;
   constexpr int O = 1 - COL;
   __shared__ float lds[LinTile<TM, TJ>::LDS];
   const int n = a.n, nh = n >> 1;
@@ -89,7 +93,7 @@ __global__ void __launch_bounds__(TM * TJ) lin_sweep_pipe(LinSweepArgs a) {
   const int tm_i = logical % a.tiles_m;
   const int tj_i = (logical / a.tiles_m) % a.tiles_j;
   const int chunk = logical / (a.tiles_m * a.tiles_j);
-  const int j0 = tj_i * TJ, m0 = tm_i * TM, i0 = chunk * a.ci;
+  const int j0 = tj_i * TJ, m0 = tm_i * TM, i0 = chunk * a.ci, ci = a.ci;
   const unsigned half = (unsigned)n * (unsigned)n * (unsigned)nh;
   const unsigned plane = (unsigned)n * (unsigned)nh;
   const float* __restrict__ f0 = COL == 1 ? a.e_red_new : a.e_in;   // e red
@@ -97,32 +101,34 @@ __global__ void __launch_bounds__(TM * TJ) lin_sweep_pipe(LinSweepArgs a) {
   const float* __restrict__ f2 = a.base;                             // base red
   const float* __restrict__ f3 = a.base + half;                      // base black
 
-  unsigned goff[NPF];
-  int loff[NPF];
-  int fld[NPF];
+  // loader: element k of field f is f * SLOT + (k % PER) * NT + tid (clamped inside the field), so
+  // that the source field of every load is a compile-time constant
+  unsigned goff[PER];
+  int loff[PER];
 #pragma unroll
-  for (int t = 0; t < NPF; ++t) {
-    int e = tid + t * NT;
-    e = e < TOTAL ? e : TOTAL - 1;
-    const int ff = e / SLOT;
-    const int rem = e - ff * SLOT;
-    const int r = rem / RW;
-    const int c = rem - r * RW;
-    goff[t] = (unsigned)wrapi(j0 - 1 + r, n) * nh + (unsigned)wrapi(m0 - 1 + c, nh);
-    loff[t] = ff * 4 * SLOT + rem;
-    fld[t] = ff;
+  for (int k = 0; k < PER; ++k) {
+    int e = tid + k * NT;
+    e = e < SLOT ? e : SLOT - 1;
+    const int r = e / RW;
+    const int c = e - r * RW;
+    goff[k] = (unsigned)wrapi(j0 - 1 + r, n) * nh + (unsigned)wrapi(m0 - 1 + c, nh);
+    loff[k] = e;
   }
   auto fetch = [&](int rel, float (&v)[NPF]) {
     const unsigned base = (unsigned)wrapi(i0 - 1 + rel, n) * plane;
 #pragma unroll
-    for (int t = 0; t < NPF; ++t) {
-      const float* src = fld[t] == 0 ? f0 : (fld[t] == 1 ? f1 : (fld[t] == 2 ? f2 : f3));
-      v[t] = src[base + goff[t]];
+    for (int k = 0; k < PER; ++k) {
+      v[0 * PER + k] = f0[base + goff[k]];
+      v[1 * PER + k] = f1[base + goff[k]];
+      v[2 * PER + k] = f2[base + goff[k]];
+      v[3 * PER + k] = f3[base + goff[k]];
     }
   };
   auto store = [&](int slot, const float (&v)[NPF]) {
 #pragma unroll
-    for (int t = 0; t < NPF; ++t) lds[loff[t] + slot * SLOT] = v[t];
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+      for (int k = 0; k < PER; ++k) lds[(f * 4 + slot) * SLOT + loff[k]] = v[f * PER + k];
   };
 
   const int s = tid % TM, r = tid / TM;
@@ -192,7 +198,7 @@ __global__ void __launch_bounds__(TM * TJ) lin_sweep_pipe(LinSweepArgs a) {
     store(SN, vst);
     __syncthreads();
   };
-  for (int t = 0; t < a.ci; t += 4) {
+  for (int t = 0; t < ci; t += 4) {
     step(std::integral_constant<int, 0>(), t, V0, V1);
     step(std::integral_constant<int, 1>(), t + 1, V1, V0);
     step(std::integral_constant<int, 2>(), t + 2, V0, V1);
@@ -228,8 +234,8 @@ __global__ void __launch_bounds__(TM * TJ / 2) lin_resid_restrict_tiled(LinRRArg
   constexpr int NT = TM * TJ / 2;
   constexpr int RW = TM + 2, RH = TJ + 2;
   constexpr int SLOT = RH * RW;
-  constexpr int TOTAL = 4 * SLOT;
-  constexpr int NPF = (TOTAL + NT - 1) / NT;
+  constexpr int PER = (SLOT + NT - 1) / NT;   // loads per field and thread
+  constexpr int NPF = 4 * PER;
   __shared__ float lds[4 * 4 * SLOT];
   const int n = a.n, nh = n >> 1, nc = n >> 1, nch = nc >> 1;
   const int tid = threadIdx.x;
@@ -248,32 +254,34 @@ __global__ void __launch_bounds__(TM * TJ / 2) lin_resid_restrict_tiled(LinRRArg
   const float* __restrict__ f2 = a.base;
   const float* __restrict__ f3 = a.base + half;
 
-  unsigned goff[NPF];
-  int loff[NPF];
-  int fld[NPF];
+  // loader: element k of field f is f * SLOT + (k % PER) * NT + tid (clamped inside the field), so
+  // that the source field of every load is a compile-time constant
+  unsigned goff[PER];
+  int loff[PER];
 #pragma unroll
-  for (int t = 0; t < NPF; ++t) {
-    int e = tid + t * NT;
-    e = e < TOTAL ? e : TOTAL - 1;
-    const int ff = e / SLOT;
-    const int rem = e - ff * SLOT;
-    const int r = rem / RW;
-    const int c = rem - r * RW;
-    goff[t] = (unsigned)wrapi(j0 - 1 + r, n) * nh + (unsigned)wrapi(m0 - 1 + c, nh);
-    loff[t] = ff * 4 * SLOT + rem;
-    fld[t] = ff;
+  for (int k = 0; k < PER; ++k) {
+    int e = tid + k * NT;
+    e = e < SLOT ? e : SLOT - 1;
+    const int r = e / RW;
+    const int c = e - r * RW;
+    goff[k] = (unsigned)wrapi(j0 - 1 + r, n) * nh + (unsigned)wrapi(m0 - 1 + c, nh);
+    loff[k] = e;
   }
   auto fetch = [&](int rel, float (&v)[NPF]) {
     const unsigned base = (unsigned)wrapi(i0 - 1 + rel, n) * plane;
 #pragma unroll
-    for (int t = 0; t < NPF; ++t) {
-      const float* src = fld[t] == 0 ? f0 : (fld[t] == 1 ? f1 : (fld[t] == 2 ? f2 : f3));
-      v[t] = src[base + goff[t]];
+    for (int k = 0; k < PER; ++k) {
+      v[0 * PER + k] = f0[base + goff[k]];
+      v[1 * PER + k] = f1[base + goff[k]];
+      v[2 * PER + k] = f2[base + goff[k]];
+      v[3 * PER + k] = f3[base + goff[k]];
     }
   };
   auto store = [&](int slot, const float (&v)[NPF]) {
 #pragma unroll
-    for (int t = 0; t < NPF; ++t) lds[loff[t] + slot * SLOT] = v[t];
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+      for (int k = 0; k < PER; ++k) lds[(f * 4 + slot) * SLOT + loff[k]] = v[f * PER + k];
   };
 
   const int s = tid % TM, rr = tid / TM;            // coarse row within the tile
@@ -534,9 +542,10 @@ static const void* resid_tiled_kernel(int tm, int tj) {
 // threads = tm * tj / per) that divides the mesh, the plane axis split in units of 4 planes so
 // that the grid fills whole waves of the device's resident block slots as well as possible.
 // Returns false when no tile applies.
-template <typename Get>
-static bool tiled_cfg(int n, Get get, int per, int& tm, int& tj, int& nchunks) {
-  static const int pref[][2] = {{64, 8}, {32, 8}, {16, 8}, {8, 8}, {4, 8}};
+static const int kPref8[][2] = {{64, 8}, {32, 8}, {16, 8}, {8, 8}, {4, 8}};
+
+template <typename Get, size_t NP>
+static bool tiled_cfg(int n, Get get, int per, int& tm, int& tj, int& nchunks, const int (&pref)[NP][2]) {
   if (n % 8 != 0) return false;
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -573,7 +582,7 @@ static bool tiled_cfg(int n, Get get, int per, int& tm, int& tj, int& nchunks) {
 }
 
 static bool resid_tiled_cfg(int n, int& tm, int& tj, int& nchunks) {
-  return tiled_cfg(n, resid_tiled_kernel, 1, tm, tj, nchunks);
+  return tiled_cfg(n, resid_tiled_kernel, 1, tm, tj, nchunks, kPref8);
 }
 
 // Inner shift of level 0 from the outer residual sums: (sum of rhs, 0) = (-sum b, 0).
@@ -593,7 +602,6 @@ static int lin_blocks(size_t cells) {
 static int rows_blocks(int n) { return n * n < 4096 ? n * n : 4096; }
 static int row_threads(int n) { return n < 64 ? 64 : (n < 256 ? n : 256); }
 
-#define MR_LIN_TILES(X) X(64, 4) X(32, 8) X(16, 16) X(8, 16) X(4, 8) X(2, 4)
 
 bool lin_tile_supported(int tm, int tj) {
 #define MR_LIN_MATCH(TM, TJ) if (tm == TM && tj == TJ) return true;
@@ -603,9 +611,9 @@ bool lin_tile_supported(int tm, int tj) {
 }
 
 hipError_t launch_lin_half_sweep(const LinSweepArgs& a, const TileCfg& t, hipStream_t s) {
-  const long blocks_l = (long)t.tiles_j * t.tiles_m * (a.n / t.ci);
+  const long blocks_l = (long)t.tiles_j * t.tiles_m * (a.n / std::max(t.ci, 1));
   if (blocks_l < 1 || blocks_l > kMaxReduceBlocks || t.tj * t.tiles_j != a.n || t.tm * t.tiles_m != a.n / 2 ||
-      a.n % t.ci != 0)
+      t.ci < 1 || a.n % t.ci != 0)
     return hipErrorInvalidValue;
   LinSweepArgs b = a;
   b.tiles_j = t.tiles_j;
@@ -613,7 +621,7 @@ hipError_t launch_lin_half_sweep(const LinSweepArgs& a, const TileCfg& t, hipStr
   b.ci = t.ci;
   const int blocks = (int)blocks_l;
   if (t.pipe) {
-    if (t.ci % 4 != 0 || (a.colour == 1 && !a.e_red_new)) return hipErrorInvalidValue;
+    if (b.ci % 4 != 0 || (a.colour == 1 && !a.e_red_new)) return hipErrorInvalidValue;
 #define MR_LP_LAUNCH(TM, TJ)                                                                          \
     if (t.tm == TM && t.tj == TJ) {                                                                   \
       if (a.colour == 0)                                                                              \
@@ -670,7 +678,7 @@ hipError_t launch_restrict32(const float* fine, float* coarse, int n, hipStream_
 hipError_t launch_lin_resid_restrict(const float* e, const float* base, const float* sb, const float* rhs, int n, double h,
                                      ShiftRef c, float* rhs_c, Reduce red, hipStream_t s) {
   int tm = 0, tj = 0, nch = 0;
-  if (tiled_cfg(n, rr_tiled_kernel, 2, tm, tj, nch)) {
+  if (tiled_cfg(n, rr_tiled_kernel, 2, tm, tj, nch, kPref8)) {
     LinRRArgs a{e, base, sb, rhs, n, (float)(1.0 / (h * h)), c, rhs_c, red, n / tj, n / 2 / tm, nch};
     const unsigned blocks = (unsigned)(a.tiles_j * a.tiles_m * nch);
 #define MR_RR_LAUNCH(TM, TJ)                                                                           \

@@ -42,7 +42,8 @@ __device__ __forceinline__ float lin_source(const Nb18f& b, float s, float ih2, 
   const float myz = 0.25f * ((b.ypzp + b.ymzm) - (b.ypzm + b.ymzp)) * ih2;
   const float xy2 = mxy * mxy, xz2 = mxz * mxz, yz2 = myz * myz;
   const float T2 = mx * mx + my * my + mz * mz + 2.0f * (xy2 + xz2 + yz2);
-  const float inv = 1.0f / (3.0f * s * s - 4.5f * T2);
+  // hardware reciprocal: the linearised operator only steers the defect correction
+  const float inv = __builtin_amdgcn_rcpf(3.0f * s * s - 4.5f * T2);
   const float s9 = 9.0f * s;
   const float q9 = 9.0f * T2;
   const float Wxx = (s9 * mx - 27.0f * (mx * mx + xy2 + xz2) + q9) * inv;

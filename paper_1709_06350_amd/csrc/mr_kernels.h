@@ -14,7 +14,7 @@ constexpr int kMaxNV = 4;                // values reduced per launch
 // Tile of the 2.5D kernels: tm columns (m = k >> 1) x tj rows (j), chunks of ci planes (i).
 struct TileCfg {
   int tm = 64, tj = 4, ci = 32, tiles_j = 1, tiles_m = 1, cpt = 1;   // cpt: cells per thread per plane
-  bool pipe = false;   // half-sweep only: the pipelined kernel (cpt 1, ci % 4 == 0)
+  bool pipe = false;   // one-colour sweeps: the pipelined kernel (cpt 1, ci % 4 == 0)
 };
 
 // The uniform shift subtracted from the source in a relaxation or defect is
