@@ -63,6 +63,25 @@ __device__ __forceinline__ bool box_of(const BBox* boxes, const int* cls, int bp
   return boxes[b].st->active != 0;
 }
 
+// Convergence bookkeeping of one box after its residual reduction (last block, one thread).
+__device__ void box_check(const BBox& x, double N3) {
+  BStat& st = *x.st;
+  const double var = x.res[3] - x.res[2] * x.res[2] / N3;
+  const double rel = sqrt(var > 0.0 ? var : 0.0) / st.r0;
+  if (st.iters < 128) st.hist[st.iters] = rel;
+  st.rel = rel;
+  if (!__builtin_isfinite(rel) || rel > 1e6 * (st.best < 1.0 ? 1.0 : st.best)) {
+    st.status = MR_EDIVERGED;
+    st.active = 0;
+  } else {
+    if (rel < st.best) st.best = rel;
+    if (rel <= st.tol || st.iters >= st.maxit)
+      st.active = 0;
+    else
+      st.iters += 1;
+  }
+}
+
 __global__ void __launch_bounds__(256) b_resid64_kernel(const BBox* boxes, const int* cls, int bpb, int n) {
   int b, t;
   if (!box_of(boxes, cls, bpb, b, t)) return;
@@ -70,23 +89,22 @@ __global__ void __launch_bounds__(256) b_resid64_kernel(const BBox* boxes, const
   const double N3 = (double)n * n * n;
   const bool last = mixed_resid64_body(x.theta, x.lv[0].delta, n, ShiftRef{x.res, 1.0 / N3, 0.0}, x.lv[0].rhs,
                                        x.lv[0].base, x.lv[0].sb, Reduce{x.partials, x.counter, x.res}, t, bpb);
-  if (last && threadIdx.x == 0) {
-    BStat& st = *x.st;
-    const double var = x.res[3] - x.res[2] * x.res[2] / N3;
-    const double rel = sqrt(var > 0.0 ? var : 0.0) / st.r0;
-    if (st.iters < 128) st.hist[st.iters] = rel;
-    st.rel = rel;
-    if (!__builtin_isfinite(rel) || rel > 1e6 * (st.best < 1.0 ? 1.0 : st.best)) {
-      st.status = MR_EDIVERGED;
-      st.active = 0;
-    } else {
-      if (rel < st.best) st.best = rel;
-      if (rel <= st.tol || st.iters >= st.maxit)
-        st.active = 0;
-      else
-        st.iters += 1;
-    }
-  }
+  if (last && threadIdx.x == 0) box_check(x, N3);
+}
+
+// Tiled FP64 residual of every box of a size class: bpb = tiles_j * tiles_m * nchunks blocks per box.
+template <int TM, int TJ>
+__global__ void __launch_bounds__(TM * TJ) b_resid64_tiled_kernel(const BBox* boxes, const int* cls, int bpb, int n,
+                                                                  int tiles_j, int tiles_m, int nchunks) {
+  __shared__ double lds[2 * 4 * (TJ + 2) * (TM + 2)];
+  int b, t;
+  if (!box_of(boxes, cls, bpb, b, t)) return;
+  const BBox& x = boxes[b];
+  const double N3 = (double)n * n * n;
+  ResidTiledArgs a{x.theta, x.lv[0].delta, n, ShiftRef{x.res, 1.0 / N3, 0.0}, x.lv[0].rhs, x.lv[0].base, x.lv[0].sb,
+                   Reduce{x.partials, x.counter, x.res}, tiles_j, tiles_m, nchunks};
+  const bool last = mixed_resid64_tiled_body<TM, TJ>(a, t, t, bpb, lds);
+  if (last && threadIdx.x == 0) box_check(x, N3);
 }
 
 __global__ void __launch_bounds__(512) b_base_kernel(const BBox* boxes, const int* cls, int bpb, int l, int nf, double ihc2) {
@@ -119,9 +137,9 @@ __global__ void b_inner_shift_kernel(const BBox* boxes, const int* cls, int nb) 
   x.lv[0].lsum[1] = 0.0;
 }
 
-template <int TM, int TJ>
-__global__ void __launch_bounds__(TM * TJ) b_lin_sweep_kernel(const BBox* boxes, const int* cls, int bpb, int l, int colour,
-                                                              int cur, int n, float h2, float ih2, int tiles_j, int tiles_m,
+template <int TM, int TJ, int COL>
+__global__ void __launch_bounds__(TM * TJ) b_lin_sweep_kernel(const BBox* boxes, const int* cls, int bpb, int l, int cur,
+                                                              int n, float h2, float ih2, int tiles_j, int tiles_m,
                                                               int ci) {
   __shared__ float lds[LinTile<TM, TJ>::LDS];
   int b, t;
@@ -130,26 +148,26 @@ __global__ void __launch_bounds__(TM * TJ) b_lin_sweep_kernel(const BBox* boxes,
   const BLevel& L = x.lv[l];
   LinSweepArgs a{};
   a.e_in = L.e[cur];
-  a.e_red_new = colour ? L.e[cur ^ 1] : nullptr;
+  a.e_red_new = COL ? L.e[cur ^ 1] : nullptr;
   a.e_out = L.e[cur ^ 1];
   a.base = L.base;
   a.sb = L.sb;
   a.rhs = L.rhs;
   a.n = n;
-  a.colour = colour;
+  a.colour = COL;
   a.h2 = h2;
   a.ih2 = ih2;
   a.c_sum = L.lsum;
   a.c_scale = 1.0 / ((double)n * n * n);
-  a.sum_out = colour ? L.lsum + 1 : L.lsum + 2;
-  a.copy_from = colour ? L.lsum + 2 : nullptr;
-  a.copy_to = colour ? L.lsum : nullptr;
+  a.sum_out = COL ? L.lsum + 1 : L.lsum + 2;
+  a.copy_from = COL ? L.lsum + 2 : nullptr;
+  a.copy_to = COL ? L.lsum : nullptr;
   a.partials = x.partials;
   a.counter = x.counter;
   a.tiles_j = tiles_j;
   a.tiles_m = tiles_m;
   a.ci = ci;
-  lin_sweep_body<TM, TJ>(a, t, t, bpb, lds);
+  lin_sweep_pipe_body<TM, TJ, COL>(a, t, t, bpb, lds);
 }
 
 __global__ void __launch_bounds__(256) b_resid_restrict_kernel(const BBox* boxes, const int* cls, int bpb, int l, int cur,
@@ -160,6 +178,19 @@ __global__ void __launch_bounds__(256) b_resid_restrict_kernel(const BBox* boxes
   const BLevel& L = x.lv[l];
   lin_resid_restrict_body(L.e[cur], L.base, L.sb, L.rhs, n, ih2, ShiftRef{L.lsum, 1.0 / ((double)n * n * n), 0.0},
                           x.lv[l + 1].rhs, Reduce{x.partials, x.counter, x.lv[l + 1].lsum}, t, bpb);
+}
+
+template <int TM, int TJ>
+__global__ void __launch_bounds__(TM * TJ / 2) b_resid_restrict_tiled_kernel(const BBox* boxes, const int* cls, int bpb,
+    int l, int cur, int n, float ih2, int tiles_j, int tiles_m, int nchunks) {
+  __shared__ float lds[4 * 4 * (TJ + 2) * (TM + 2)];
+  int b, t;
+  if (!box_of(boxes, cls, bpb, b, t)) return;
+  const BBox& x = boxes[b];
+  const BLevel& L = x.lv[l];
+  LinRRArgs a{L.e[cur], L.base, L.sb, L.rhs, n, ih2, ShiftRef{L.lsum, 1.0 / ((double)n * n * n), 0.0}, x.lv[l + 1].rhs,
+              Reduce{x.partials, x.counter, x.lv[l + 1].lsum}, tiles_j, tiles_m, nchunks};
+  lin_resid_restrict_tiled_body<TM, TJ>(a, t, t, bpb, lds);
 }
 
 __global__ void __launch_bounds__(512) b_prolong_kernel(const BBox* boxes, const int* cls, int bpb, int l, int cur_c,
@@ -189,15 +220,21 @@ __global__ void __launch_bounds__(256) b_update_kernel(const BBox* boxes, const 
 // ---- FP32 sweep tile tuner ----------------------------------------------------------------
 
 #define MR_BLIN_TILES(X) X(64, 4) X(32, 8) X(16, 16) X(8, 16) X(4, 8) X(2, 4)
+#define MR_BRT_TILES(X) X(64, 8) X(32, 8) X(16, 8) X(8, 8) X(4, 8)
 
 static hipError_t launch_b_lin_sweep(const BBox* boxes, const int* cls, int nb, const TileCfg& t, int l, int colour, int cur,
                                      int n, double h, hipStream_t s) {
   const int bpb = t.tiles_j * t.tiles_m * (n / t.ci);
+  if (t.ci % 4 != 0) return hipErrorInvalidValue;
   const float h2 = (float)(h * h), ih2 = (float)(1.0 / (h * h));
 #define MR_BLIN_LAUNCH(TM, TJ)                                                                                   \
   if (t.tm == TM && t.tj == TJ) {                                                                                \
-    hipLaunchKernelGGL((b_lin_sweep_kernel<TM, TJ>), dim3(nb * bpb), dim3(TM * TJ), 0, s, boxes, cls, bpb, l, colour, \
-                       cur, n, h2, ih2, t.tiles_j, t.tiles_m, t.ci);                                             \
+    if (colour == 0)                                                                                             \
+      hipLaunchKernelGGL((b_lin_sweep_kernel<TM, TJ, 0>), dim3(nb * bpb), dim3(TM * TJ), 0, s, boxes, cls, bpb, l, \
+                         cur, n, h2, ih2, t.tiles_j, t.tiles_m, t.ci);                                           \
+    else                                                                                                         \
+      hipLaunchKernelGGL((b_lin_sweep_kernel<TM, TJ, 1>), dim3(nb * bpb), dim3(TM * TJ), 0, s, boxes, cls, bpb, l, \
+                         cur, n, h2, ih2, t.tiles_j, t.tiles_m, t.ci);                                           \
     return hipGetLastError();                                                                                    \
   }
   MR_BLIN_TILES(MR_BLIN_LAUNCH)
@@ -333,6 +370,13 @@ int tune_lin_tiles(int n, hipStream_t s, TileCfg* out, float* ms_out) {
 
 namespace {
 
+// Tile of a 2.5D residual kernel for one size class (tm x tj of (m, j), nch chunks of planes).
+struct BTile {
+  bool ok = false;
+  int tm = 0, tj = 0, tiles_j = 0, tiles_m = 0, nch = 0;
+  int bpb() const { return tiles_j * tiles_m * nch; }
+};
+
 struct SizeClass {
   int n = 0, nlev = 0;
   std::vector<int> boxes;   // global box indices
@@ -340,7 +384,34 @@ struct SizeClass {
   std::vector<int> ns;
   std::vector<double> hs;
   std::vector<TileCfg> tiles;
+  BTile resid;              // FP64 outer residual (finest level)
+  std::vector<BTile> rr;    // linear residual + restriction per level
 };
+
+// The largest compiled tile that divides an n^3 mesh (n a multiple of 8), and a chunk count (in
+// units of 4 planes, chunks of at least 8 planes) that gives each box about 64 blocks. It depends on
+// n only, so a box is reduced in the same order whatever else is in the batch.
+BTile pick_btile(int n) {
+  static const int pref[][2] = {{64, 8}, {32, 8}, {16, 8}, {8, 8}, {4, 8}};
+  BTile t;
+  if (n % 8 != 0) return t;
+  for (const auto& p : pref) {
+    if ((n / 2) % p[0] != 0 || n % p[1] != 0) continue;
+    t.tm = p[0];
+    t.tj = p[1];
+    t.tiles_j = n / p[1];
+    t.tiles_m = n / 2 / p[0];
+    const long tiles = (long)t.tiles_j * t.tiles_m;
+    long nch = (64 + tiles - 1) / tiles;
+    nch = std::max(1L, std::min(nch, (long)(n / 8)));
+    while (nch > 1 && tiles * nch > kBoxPartials) --nch;
+    if (tiles * nch > kBoxPartials) return BTile{};
+    t.nch = (int)nch;
+    t.ok = true;
+    return t;
+  }
+  return t;
+}
 
 struct BatchMem {
   std::vector<void*> ptrs;
@@ -369,9 +440,20 @@ static int record_iteration(std::vector<SizeClass>& cls, BBox* dboxes, const mr_
   // 1. FP64 residual of every box (also the base state of level 0)
   for (auto& c : cls) {
     const int nb = (int)c.boxes.size();
-    const int bpb = rows_grid_b(c.n * c.n / 8 > 0 ? c.n * c.n / 8 : 1);
-    hipLaunchKernelGGL(b_resid64_kernel, dim3(nb * bpb), dim3(c.n < 256 ? (c.n < 64 ? 64 : c.n) : 256), 0, s, dboxes,
-                       c.d_boxes, bpb, c.n);
+    if (c.resid.ok) {
+      const BTile& t = c.resid;
+      const int bpb = t.bpb();
+#define MR_BRT_LAUNCH(TM, TJ)                                                                                     \
+      if (t.tm == TM && t.tj == TJ)                                                                               \
+        hipLaunchKernelGGL((b_resid64_tiled_kernel<TM, TJ>), dim3(nb * bpb), dim3(TM * TJ), 0, s, dboxes, c.d_boxes, \
+                           bpb, c.n, t.tiles_j, t.tiles_m, t.nch);
+      MR_BRT_TILES(MR_BRT_LAUNCH)
+#undef MR_BRT_LAUNCH
+    } else {
+      const int bpb = rows_grid_b(c.n * c.n / 8 > 0 ? c.n * c.n / 8 : 1);
+      hipLaunchKernelGGL(b_resid64_kernel, dim3(nb * bpb), dim3(c.n < 256 ? (c.n < 64 ? 64 : c.n) : 256), 0, s, dboxes,
+                         c.d_boxes, bpb, c.n);
+    }
     if (!ok()) return hip_fail(e, "batched residual");
   }
   // 2. base hierarchy
@@ -417,9 +499,21 @@ static int record_iteration(std::vector<SizeClass>& cls, BBox* dboxes, const mr_
           cur[ci][l] ^= 1;
         }
         const int m = n / 2;
-        const int bpb = rows_grid_b(m * m / 4 > 0 ? m * m / 4 : 1);
-        hipLaunchKernelGGL(b_resid_restrict_kernel, dim3(nb * bpb), dim3(m < 256 ? (m < 64 ? 64 : m) : 256), 0, s, dboxes,
-                           c.d_boxes, bpb, l, cur[ci][l], n, (float)(1.0 / (h * h)));
+        if (c.rr[l].ok) {
+          const BTile& t = c.rr[l];
+          const int bpb = t.bpb();
+#define MR_BRR_LAUNCH(TM, TJ)                                                                                  \
+          if (t.tm == TM && t.tj == TJ)                                                                        \
+            hipLaunchKernelGGL((b_resid_restrict_tiled_kernel<TM, TJ>), dim3(nb * bpb), dim3(TM * TJ / 2), 0, s, \
+                               dboxes, c.d_boxes, bpb, l, cur[ci][l], n, (float)(1.0 / (h * h)), t.tiles_j,      \
+                               t.tiles_m, t.nch);
+          MR_BRT_TILES(MR_BRR_LAUNCH)
+#undef MR_BRR_LAUNCH
+        } else {
+          const int bpb = rows_grid_b(m * m / 4 > 0 ? m * m / 4 : 1);
+          hipLaunchKernelGGL(b_resid_restrict_kernel, dim3(nb * bpb), dim3(m < 256 ? (m < 64 ? 64 : m) : 256), 0, s,
+                             dboxes, c.d_boxes, bpb, l, cur[ci][l], n, (float)(1.0 / (h * h)));
+        }
         cur[ci][l + 1] = 0;
         const size_t cc = (size_t)m * m * m;
         hipLaunchKernelGGL(b_fill_kernel, dim3(nb * 64), dim3(256), 0, s, dboxes, c.d_boxes, 64, l + 1, 0, cc);
@@ -486,6 +580,11 @@ int solve_batched(int nbox, const int* n, const double* const* delta, double* co
       cls.push_back(c);
     }
     cls[cls_of_n[n[b]]].boxes.push_back(b);
+  }
+  for (auto& c : cls) {
+    c.resid = pick_btile(c.n);
+    c.rr.assign(c.nlev, BTile{});
+    for (int l = 0; l + 1 < c.nlev; ++l) c.rr[l] = pick_btile(c.ns[l]);
   }
   // per-box memory and descriptors
   BStat* dstat = mem.get<BStat>(nbox);

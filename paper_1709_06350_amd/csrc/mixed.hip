@@ -74,298 +74,22 @@ __global__ void __launch_bounds__(256) fill32_kernel(float* __restrict__ a, floa
   fill32_body(a, v, cells, blockIdx.x, gridDim.x);
 }
 
-// ---- pipelined FP32 linear half-sweep --------------------------------------------------------
-// lin_sweep_body's decomposition and arithmetic with the colour compile-time and the plane loop
-// unrolled by the ring length (compile-time LDS slots); planes are fetched two steps before they
-// enter LDS and the base root / right-hand side two steps before use. Requires ci % 4 == 0.
 template <int TM, int TJ, int COL>
 __global__ void __launch_bounds__(TM * TJ) lin_sweep_pipe(LinSweepArgs a) {
-  constexpr int NT = TM * TJ;
-  constexpr int RW = TM + 2;
-  constexpr int SLOT = LinTile<TM, TJ>::SLOT;
-  constexpr int PER = (SLOT + NT - 1) / NT;   // loads per field and thread
-  constexpr int NPF = 4 * PER;
-  constexpr int O = 1 - COL;
   __shared__ float lds[LinTile<TM, TJ>::LDS];
-  const int n = a.n, nh = n >> 1;
-  const int tid = threadIdx.x;
-  const int logical = xcd_remap(blockIdx.x, gridDim.x);
-  const int tm_i = logical % a.tiles_m;
-  const int tj_i = (logical / a.tiles_m) % a.tiles_j;
-  const int chunk = logical / (a.tiles_m * a.tiles_j);
-  const int j0 = tj_i * TJ, m0 = tm_i * TM, i0 = chunk * a.ci, ci = a.ci;
-  const unsigned half = (unsigned)n * (unsigned)n * (unsigned)nh;
-  const unsigned plane = (unsigned)n * (unsigned)nh;
-  const float* __restrict__ f0 = COL == 1 ? a.e_red_new : a.e_in;   // e red
-  const float* __restrict__ f1 = a.e_in + half;                      // e black
-  const float* __restrict__ f2 = a.base;                             // base red
-  const float* __restrict__ f3 = a.base + half;                      // base black
-
-  // loader: element k of field f is f * SLOT + (k % PER) * NT + tid (clamped inside the field), so
-  // that the source field of every load is a compile-time constant
-  unsigned goff[PER];
-  int loff[PER];
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    int e = tid + k * NT;
-    e = e < SLOT ? e : SLOT - 1;
-    const int r = e / RW;
-    const int c = e - r * RW;
-    goff[k] = (unsigned)wrapi(j0 - 1 + r, n) * nh + (unsigned)wrapi(m0 - 1 + c, nh);
-    loff[k] = e;
-  }
-  auto fetch = [&](int rel, float (&v)[NPF]) {
-    const unsigned base = (unsigned)wrapi(i0 - 1 + rel, n) * plane;
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      v[0 * PER + k] = f0[base + goff[k]];
-      v[1 * PER + k] = f1[base + goff[k]];
-      v[2 * PER + k] = f2[base + goff[k]];
-      v[3 * PER + k] = f3[base + goff[k]];
-    }
-  };
-  auto store = [&](int slot, const float (&v)[NPF]) {
-#pragma unroll
-    for (int f = 0; f < 4; ++f)
-#pragma unroll
-      for (int k = 0; k < PER; ++k) lds[(f * 4 + slot) * SLOT + loff[k]] = v[f * PER + k];
-  };
-
-  const int s = tid % TM, r = tid / TM;
-  const int j = j0 + r, m = m0 + s;
-  const unsigned own = (unsigned)j * nh + m;
-  const int ob = (r + 1) * RW + (s + 1);
-  const int q0 = (i0 + j + COL) & 1;
-  const int oq0 = ob + q0, oq1 = ob + (q0 ^ 1);
-  const double Cd = (a.c_sum ? (a.c_sum[0] + a.c_sum[1]) * a.c_scale : 0.0) + a.c_add;
-  const float C = (float)Cd;
-  const float h2 = a.h2, ih2 = a.ih2;
-  const float* __restrict__ sbc = a.sb + COL * half + own;
-  const float* __restrict__ rc = a.rhs + COL * half + own;
-  float* __restrict__ out = a.e_out + COL * half + own;
-  const int last_plane = n - 1;
-  double acc = 0.0;
-
-  float V0[NPF], V1[NPF];
-  float SB[4], RH[4];
-  {
-    float va[NPF], vb[NPF], vc[NPF];
-    fetch(0, va);
-    fetch(1, vb);
-    fetch(2, vc);
-    store(0, va);
-    store(1, vb);
-    store(2, vc);
-  }
-  fetch(3, V0);
-  SB[0] = sbc[(unsigned)i0 * plane];
-  RH[0] = rc[(unsigned)i0 * plane];
-  SB[1] = sbc[(unsigned)min(i0 + 1, last_plane) * plane];
-  RH[1] = rc[(unsigned)min(i0 + 1, last_plane) * plane];
-  __syncthreads();
-
-  auto step = [&](auto kc, int t, float (&vst)[NPF], float (&vft)[NPF]) {
-    constexpr int K = decltype(kc)::value;
-    constexpr int SM = K & 3, S0 = (K + 1) & 3, SP = (K + 2) & 3, SN = (K + 3) & 3;
-    fetch(t + 4, vft);
-    const unsigned pn = (unsigned)min(i0 + t + 2, last_plane) * plane;
-    SB[(K + 2) & 3] = sbc[pn];
-    RH[(K + 2) & 3] = rc[pn];
-    const int oq = (K & 1) ? oq1 : oq0;
-    Nb18f te, tb;
-#define MR_LP_GATHER(T, LO, LC)                                                        \
-    {                                                                                  \
-      const float* lo = lds + (LO) * 4 * SLOT;                                          \
-      const float* lc = lds + (LC) * 4 * SLOT;                                          \
-      T.xm = lo[SM * SLOT + ob];         T.xp = lo[SP * SLOT + ob];                     \
-      T.ym = lo[S0 * SLOT + ob - RW];    T.yp = lo[S0 * SLOT + ob + RW];                \
-      T.zm = lo[S0 * SLOT + oq - 1];     T.zp = lo[S0 * SLOT + oq];                     \
-      T.xpyp = lc[SP * SLOT + ob + RW];  T.xmym = lc[SM * SLOT + ob - RW];              \
-      T.xpym = lc[SP * SLOT + ob - RW];  T.xmyp = lc[SM * SLOT + ob + RW];              \
-      T.xpzp = lc[SP * SLOT + oq];       T.xmzm = lc[SM * SLOT + oq - 1];               \
-      T.xpzm = lc[SP * SLOT + oq - 1];   T.xmzp = lc[SM * SLOT + oq];                   \
-      T.ypzp = lc[S0 * SLOT + oq + RW];  T.ymzm = lc[S0 * SLOT + oq - RW - 1];          \
-      T.ypzm = lc[S0 * SLOT + oq + RW - 1]; T.ymzp = lc[S0 * SLOT + oq - RW];           \
-    }
-    MR_LP_GATHER(te, O, COL)
-    MR_LP_GATHER(tb, 2 + O, 2 + COL)
-#undef MR_LP_GATHER
-    float Se;
-    const float g = lin_source(tb, SB[K], ih2, te, Se) * ih2;
-    const float rhs = RH[K];
-    out[(unsigned)(i0 + t) * plane] = (Se - h2 * (g + rhs - C)) * (1.0f / 6.0f);
-    acc += (double)(g + rhs);
-    store(SN, vst);
-    __syncthreads();
-  };
-  for (int t = 0; t < ci; t += 4) {
-    step(std::integral_constant<int, 0>(), t, V0, V1);
-    step(std::integral_constant<int, 1>(), t + 1, V1, V0);
-    step(std::integral_constant<int, 2>(), t + 2, V0, V1);
-    step(std::integral_constant<int, 3>(), t + 3, V1, V0);
-  }
-  double vv[1] = {acc};
-  const bool last = grid_sum<1>(vv, a.partials, a.counter, a.sum_out, gridDim.x, blockIdx.x);
-  if (last && tid == 0 && a.copy_to) *a.copy_to = *a.copy_from;
+  lin_sweep_pipe_body<TM, TJ, COL>(a, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x, gridDim.x, lds);
 }
-
-// ---- tiled linear residual + restriction ---------------------------------------------------
-// lin_resid_restrict_body's outputs on a 2.5D tile: e and the base potential (both colours) of
-// planes i-1..i+1 in a 4-slot LDS ring; a thread owns fine rows 2J, 2J+1 and the cell pair
-// k = 2m, 2m+1 (both colours of column m), so over planes 2I, 2I+1 it holds the 8 sons of coarse
-// cell (I, J, m) and writes their mean residual after the odd plane. Chunks are multiples of 4
-// planes; the plane loop is unrolled by the ring length (compile-time slots) with planes fetched
-// two steps ahead.
-struct LinRRArgs {
-  const float* e;
-  const float* base;
-  const float* sb;
-  const float* rhs;
-  int n;
-  float ih2;
-  ShiftRef cref;
-  float* rhs_c;
-  Reduce red;
-  int tiles_j, tiles_m, nchunks;
-};
 
 template <int TM, int TJ>
 __global__ void __launch_bounds__(TM * TJ / 2) lin_resid_restrict_tiled(LinRRArgs a) {
-  constexpr int NT = TM * TJ / 2;
-  constexpr int RW = TM + 2, RH = TJ + 2;
-  constexpr int SLOT = RH * RW;
-  constexpr int PER = (SLOT + NT - 1) / NT;   // loads per field and thread
-  constexpr int NPF = 4 * PER;
-  __shared__ float lds[4 * 4 * SLOT];
-  const int n = a.n, nh = n >> 1, nc = n >> 1, nch = nc >> 1;
-  const int tid = threadIdx.x;
-  const int logical = xcd_remap(blockIdx.x, gridDim.x);
-  const int ntile = a.tiles_m * a.tiles_j;
-  const int tile = logical % ntile, chunk = logical / ntile;
-  const int m0 = (tile % a.tiles_m) * TM, j0 = (tile / a.tiles_m) * TJ;
-  const int q4 = n / 4;
-  const int i0 = 4 * (int)(((long)chunk * q4) / a.nchunks);
-  const int i1 = 4 * (int)(((long)(chunk + 1) * q4) / a.nchunks);
-  const unsigned half = (unsigned)n * (unsigned)n * (unsigned)nh;
-  const unsigned plane = (unsigned)n * (unsigned)nh;
-  const unsigned halfc = (unsigned)nc * (unsigned)nc * (unsigned)nch;
-  const float* __restrict__ f0 = a.e;
-  const float* __restrict__ f1 = a.e + half;
-  const float* __restrict__ f2 = a.base;
-  const float* __restrict__ f3 = a.base + half;
+  __shared__ float lds[4 * 4 * (TJ + 2) * (TM + 2)];
+  lin_resid_restrict_tiled_body<TM, TJ>(a, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x, gridDim.x, lds);
+}
 
-  // loader: element k of field f is f * SLOT + (k % PER) * NT + tid (clamped inside the field), so
-  // that the source field of every load is a compile-time constant
-  unsigned goff[PER];
-  int loff[PER];
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    int e = tid + k * NT;
-    e = e < SLOT ? e : SLOT - 1;
-    const int r = e / RW;
-    const int c = e - r * RW;
-    goff[k] = (unsigned)wrapi(j0 - 1 + r, n) * nh + (unsigned)wrapi(m0 - 1 + c, nh);
-    loff[k] = e;
-  }
-  auto fetch = [&](int rel, float (&v)[NPF]) {
-    const unsigned base = (unsigned)wrapi(i0 - 1 + rel, n) * plane;
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      v[0 * PER + k] = f0[base + goff[k]];
-      v[1 * PER + k] = f1[base + goff[k]];
-      v[2 * PER + k] = f2[base + goff[k]];
-      v[3 * PER + k] = f3[base + goff[k]];
-    }
-  };
-  auto store = [&](int slot, const float (&v)[NPF]) {
-#pragma unroll
-    for (int f = 0; f < 4; ++f)
-#pragma unroll
-      for (int k = 0; k < PER; ++k) lds[(f * 4 + slot) * SLOT + loff[k]] = v[f * PER + k];
-  };
-
-  const int s = tid % TM, rr = tid / TM;            // coarse row within the tile
-  const int m = m0 + s;
-  const double Cd = (a.cref.c_sum ? (a.cref.c_sum[0] + a.cref.c_sum[1]) * a.cref.c_scale : 0.0) + a.cref.c_add;
-  const float C = (float)Cd;
-  const float ih2 = a.ih2;
-  double acc = 0.0;
-  float sres = 0.0f;
-
-  float V0[NPF], V1[NPF];
-  {
-    float va[NPF], vb[NPF], vc[NPF];
-    fetch(0, va);
-    fetch(1, vb);
-    fetch(2, vc);
-    store(0, va);
-    store(1, vb);
-    store(2, vc);
-  }
-  fetch(3, V0);
-  __syncthreads();
-
-  auto step = [&](auto kc, int t, float (&vst)[NPF], float (&vft)[NPF]) {
-    constexpr int K = decltype(kc)::value;
-    constexpr int SM = K & 3, S0 = (K + 1) & 3, SP = (K + 2) & 3, SN = (K + 3) & 3;
-    fetch(t + 4, vft);
-    const int i = i0 + t;
-#pragma unroll 1
-    for (int cell = 0; cell < 4; ++cell) {
-      const int dr = cell >> 1, c = cell & 1;
-      const int r = 2 * rr + dr;
-      const int j = j0 + r;
-      const int ob = (r + 1) * RW + (s + 1);
-      const unsigned o = (unsigned)c * half + (unsigned)i * plane + (unsigned)j * nh + m;
-      const float sbv = a.sb[o], rhv = a.rhs[o];
-      {
-        const int q = (i + j + c) & 1;
-        const int oq = ob + q;
-        const int O = 1 - c;
-        Nb18f te, tb;
-#define MR_RR_GATHER(T, LO, LC)                                                        \
-        {                                                                              \
-          const float* lo = lds + (LO) * 4 * SLOT;                                      \
-          const float* lc = lds + (LC) * 4 * SLOT;                                      \
-          T.xm = lo[SM * SLOT + ob];         T.xp = lo[SP * SLOT + ob];                 \
-          T.ym = lo[S0 * SLOT + ob - RW];    T.yp = lo[S0 * SLOT + ob + RW];            \
-          T.zm = lo[S0 * SLOT + oq - 1];     T.zp = lo[S0 * SLOT + oq];                 \
-          T.xpyp = lc[SP * SLOT + ob + RW];  T.xmym = lc[SM * SLOT + ob - RW];          \
-          T.xpym = lc[SP * SLOT + ob - RW];  T.xmyp = lc[SM * SLOT + ob + RW];          \
-          T.xpzp = lc[SP * SLOT + oq];       T.xmzm = lc[SM * SLOT + oq - 1];           \
-          T.xpzm = lc[SP * SLOT + oq - 1];   T.xmzp = lc[SM * SLOT + oq];               \
-          T.ypzp = lc[S0 * SLOT + oq + RW];  T.ymzm = lc[S0 * SLOT + oq - RW - 1];      \
-          T.ypzm = lc[S0 * SLOT + oq + RW - 1]; T.ymzp = lc[S0 * SLOT + oq - RW];       \
-        }
-        MR_RR_GATHER(te, O, c)
-        MR_RR_GATHER(tb, 2 + O, 2 + c)
-#undef MR_RR_GATHER
-        float Se;
-        const float src = lin_source(tb, sbv, ih2, te, Se) * ih2;
-        const float ec = lds[(c * 4 + S0) * SLOT + ob];
-        const float lap = (Se - 6.0f * ec) * ih2;
-        sres += rhv + src - lap - C;
-      }
-    }
-    if (K & 1) {   // odd plane (chunks start at even planes): the coarse cell is complete
-      const int I = i >> 1, J = (j0 >> 1) + rr, Kc = m;
-      const unsigned ec = ((I + J + Kc) & 1) * halfc + ((unsigned)I * nc + J) * (unsigned)nch + (unsigned)(Kc >> 1);
-      const float v = 0.125f * sres;
-      a.rhs_c[ec] = v;
-      acc += v;
-      sres = 0.0f;
-    }
-    store(SN, vst);
-    __syncthreads();
-  };
-  for (int t = 0; t < i1 - i0; t += 4) {
-    step(std::integral_constant<int, 0>(), t, V0, V1);
-    step(std::integral_constant<int, 1>(), t + 1, V1, V0);
-    step(std::integral_constant<int, 2>(), t + 2, V0, V1);
-    step(std::integral_constant<int, 3>(), t + 3, V1, V0);
-  }
-  double vv[2] = {acc, 0.0};
-  grid_sum<2>(vv, a.red.partials, a.red.counter, a.red.result, gridDim.x, blockIdx.x);
+template <int TM, int TJ>
+__global__ void __launch_bounds__(TM * TJ) mixed_resid64_tiled(ResidTiledArgs a) {
+  __shared__ double lds[2 * 4 * (TJ + 2) * (TM + 2)];
+  mixed_resid64_tiled_body<TM, TJ>(a, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x, gridDim.x, lds);
 }
 
 #define MR_RR_TILES(X) X(64, 8) X(32, 8) X(16, 8) X(8, 8) X(4, 8)
@@ -376,156 +100,6 @@ static const void* rr_tiled_kernel(int tm, int tj) {
   MR_RR_TILES(MR_RR_PTR)
 #undef MR_RR_PTR
   return nullptr;
-}
-
-// ---- tiled FP64 outer residual ------------------------------------------------------------
-// The same outputs as mixed_resid64_body, on the 2.5D decomposition of the sweeps: a block owns a
-// TM x TJ tile of (m, j) and a chunk of planes [i0, i1) (a multiple of 4 long); both colours of
-// theta for planes i-1..i+1 sit in a 4-slot LDS ring. Per plane step a thread evaluates the two
-// cells of its (j, m) column (one per colour), so that two independent roots overlap. The plane
-// loop is unrolled by the ring length (compile-time slots), planes are fetched two steps before
-// they enter LDS and delta two steps before use.
-struct ResidTiledArgs {
-  const double* theta;
-  const double* delta;
-  int n;
-  ShiftRef cref;
-  float* rhs32;
-  float* base32;
-  float* sb32;
-  Reduce red;
-  int tiles_j, tiles_m, nchunks;
-};
-
-template <int TM, int TJ>
-__global__ void __launch_bounds__(TM * TJ) mixed_resid64_tiled(ResidTiledArgs a) {
-  constexpr int NT = TM * TJ;
-  constexpr int RW = TM + 2, RH = TJ + 2;
-  constexpr int SLOT = RH * RW;
-  constexpr int TOTAL = 2 * SLOT;
-  constexpr int NPF = (TOTAL + NT - 1) / NT;
-  __shared__ double lds[2 * 4 * SLOT];
-  const int n = a.n, nh = n >> 1;
-  const int tid = threadIdx.x;
-  const int logical = xcd_remap(blockIdx.x, gridDim.x);
-  const int ntile = a.tiles_m * a.tiles_j;
-  const int tile = logical % ntile, chunk = logical / ntile;
-  const int m0 = (tile % a.tiles_m) * TM, j0 = (tile / a.tiles_m) * TJ;
-  const int q4 = n / 4;
-  const int i0 = 4 * (int)(((long)chunk * q4) / a.nchunks);
-  const int i1 = 4 * (int)(((long)(chunk + 1) * q4) / a.nchunks);
-  const unsigned half = (unsigned)n * (unsigned)n * (unsigned)nh;
-  const unsigned plane = (unsigned)n * (unsigned)nh;
-  const double* __restrict__ th = a.theta;
-
-  unsigned goff[NPF];
-  int loff[NPF];
-#pragma unroll
-  for (int t = 0; t < NPF; ++t) {
-    int e = tid + t * NT;
-    e = e < TOTAL ? e : TOTAL - 1;
-    const int cc = e / SLOT;
-    const int rem = e - cc * SLOT;
-    const int r = rem / RW;
-    const int c = rem - r * RW;
-    goff[t] = (unsigned)cc * half + (unsigned)wrapi(j0 - 1 + r, n) * nh + (unsigned)wrapi(m0 - 1 + c, nh);
-    loff[t] = cc * 4 * SLOT + rem;
-  }
-  auto fetch = [&](int rel, double (&v)[NPF]) {
-    const unsigned base = (unsigned)wrapi(i0 - 1 + rel, n) * plane;
-#pragma unroll
-    for (int t = 0; t < NPF; ++t) v[t] = th[base + goff[t]];
-  };
-  auto store = [&](int slot, const double (&v)[NPF]) {
-#pragma unroll
-    for (int t = 0; t < NPF; ++t) lds[loff[t] + slot * SLOT] = v[t];
-  };
-
-  const int s = tid % TM, r = tid / TM;
-  const int j = j0 + r, m = m0 + s;
-  const unsigned own = (unsigned)j * nh + m;
-  const int ob = (r + 1) * RW + (s + 1);
-  // z-parity of the colour-c cell of this column at plane i0 + t: (i0 + j + c + t) & 1
-  const int qa = (i0 + j) & 1;
-  const int oq00 = ob + qa, oq01 = ob + (qa ^ 1);          // colour 0 at even / odd t
-  const double C = (a.cref.c_sum ? (a.cref.c_sum[0] + a.cref.c_sum[1]) * a.cref.c_scale : 0.0) + a.cref.c_add;
-  const double* __restrict__ dl = a.delta + own;
-  const int last_plane = n - 1;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-
-  double V0[NPF], V1[NPF];
-  double D[4][2];
-  {
-    double va[NPF], vb[NPF], vc[NPF];
-    fetch(0, va);
-    fetch(1, vb);
-    fetch(2, vc);
-    store(0, va);
-    store(1, vb);
-    store(2, vc);
-  }
-  fetch(3, V0);
-  D[0][0] = dl[(unsigned)i0 * plane];
-  D[0][1] = dl[half + (unsigned)i0 * plane];
-  D[1][0] = dl[(unsigned)min(i0 + 1, last_plane) * plane];
-  D[1][1] = dl[half + (unsigned)min(i0 + 1, last_plane) * plane];
-  __syncthreads();
-
-  auto gather = [&](const double* lo, const double* lc, int SM, int S0, int SP, int oq, Nb18& c) {
-    c.xm = lo[SM * SLOT + ob];         c.xp = lo[SP * SLOT + ob];
-    c.ym = lo[S0 * SLOT + ob - RW];    c.yp = lo[S0 * SLOT + ob + RW];
-    c.zm = lo[S0 * SLOT + oq - 1];     c.zp = lo[S0 * SLOT + oq];
-    c.xpyp = lc[SP * SLOT + ob + RW];  c.xmym = lc[SM * SLOT + ob - RW];
-    c.xpym = lc[SP * SLOT + ob - RW];  c.xmyp = lc[SM * SLOT + ob + RW];
-    c.xpzp = lc[SP * SLOT + oq];       c.xmzm = lc[SM * SLOT + oq - 1];
-    c.xpzm = lc[SP * SLOT + oq - 1];   c.xmzp = lc[SM * SLOT + oq];
-    c.ypzp = lc[S0 * SLOT + oq + RW];  c.ymzm = lc[S0 * SLOT + oq - RW - 1];
-    c.ypzm = lc[S0 * SLOT + oq + RW - 1]; c.ymzp = lc[S0 * SLOT + oq - RW];
-  };
-  auto step = [&](auto kc, int t, double (&vst)[NPF], double (&vft)[NPF]) {
-    constexpr int K = decltype(kc)::value;
-    constexpr int SM = K & 3, S0 = (K + 1) & 3, SP = (K + 2) & 3, SN = (K + 3) & 3;
-    fetch(t + 4, vft);
-    const unsigned pn = (unsigned)min(i0 + t + 2, last_plane) * plane;
-    D[(K + 2) & 3][0] = dl[pn];
-    D[(K + 2) & 3][1] = dl[half + pn];
-    const double* l0 = lds;              // colour 0
-    const double* l1 = lds + 4 * SLOT;   // colour 1
-    // colour 0 cell: parity q = (i + j) & 1; colour 1 cell: the opposite parity
-    const int oqc0 = (K & 1) ? oq01 : oq00;
-    const int oqc1 = (K & 1) ? oq00 : oq01;
-    Nb18 c0, c1;
-    gather(l1, l0, SM, S0, SP, oqc0, c0);
-    gather(l0, l1, SM, S0, SP, oqc1, c1);
-    double S[2], pp[2], qq[2], sr[2];
-    cell_pq(c0, 1.0 + D[K][0], 1.0, S[0], pp[0], qq[0]);
-    cell_pq(c1, 1.0 + D[K][1], 1.0, S[1], pp[1], qq[1]);
-    largest_roots<2>(pp, qq, sr);
-    const unsigned e0 = (unsigned)(i0 + t) * plane + own;
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const double thc = (c == 0 ? l0 : l1)[S0 * SLOT + ob];
-      const double sig = sr[c] - 3.0;
-      const double b = (S[c] - 6.0 * thc) - sig + C;
-      const unsigned e = (unsigned)c * half + e0;
-      a.rhs32[e] = (float)(-b);
-      a.base32[e] = (float)thc;
-      a.sb32[e] = (float)sr[c];
-      a0 += b;
-      a1 += b * b;
-      a2 += sig;
-    }
-    store(SN, vst);
-    __syncthreads();
-  };
-  for (int t = 0; t < i1 - i0; t += 4) {
-    step(std::integral_constant<int, 0>(), t, V0, V1);
-    step(std::integral_constant<int, 1>(), t + 1, V1, V0);
-    step(std::integral_constant<int, 2>(), t + 2, V0, V1);
-    step(std::integral_constant<int, 3>(), t + 3, V1, V0);
-  }
-  double v[4] = {a2, 0.0, a0, a1};
-  grid_sum<4>(v, a.red.partials, a.red.counter, a.red.result, gridDim.x, blockIdx.x);
 }
 
 #define MR_RT_TILES(X) X(64, 8) X(32, 8) X(16, 8) X(8, 8) X(4, 8)

@@ -49,7 +49,8 @@ def _close(a, b, scale, tol=1e-12):
 
 @pytest.mark.parametrize("two_pass", [False, True])
 @pytest.mark.parametrize("n,h,with_f", [(16, 1.0, False), (32, 1.0, False), (48, 1.0, False),
-                                        (32, 2.0, True), (64, 4.0, True), (8, 8.0, True), (128, 1.0, False)])
+                                        (32, 2.0, True), (64, 4.0, True), (8, 8.0, True), (128, 1.0, False),
+                                        (128, 2.0, True)])
 def test_sweep_matches_oracle(ctx, ctx2, two_pass, n, h, with_f):
     announce(f"sweep n={n} h={h} f={with_f} two_pass={two_pass}")
     if two_pass:
