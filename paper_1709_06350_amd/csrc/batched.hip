@@ -413,17 +413,31 @@ BTile pick_btile(int n) {
   return t;
 }
 
+// Device memory of one batched call: a single allocation carved into 256-byte aligned pieces. The
+// carving runs twice: once to measure (reserve), once on the allocation (get).
 struct BatchMem {
-  std::vector<void*> ptrs;
+  char* base = nullptr;
+  size_t size = 0, used = 0;
+  bool measuring = true;
   ~BatchMem() {
-    for (void* p : ptrs) (void)hipFree(p);
+    if (base) (void)hipFree(base);
   }
   template <typename T>
   T* get(size_t count) {
-    void* p = nullptr;
-    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) return nullptr;
-    ptrs.push_back(p);
-    return (T*)p;
+    const size_t bytes = (count * sizeof(T) + 255) & ~(size_t)255;
+    if (measuring) {
+      size += bytes;
+      return reinterpret_cast<T*>(static_cast<uintptr_t>(256));   // placeholder, never dereferenced
+    }
+    if (!base || used + bytes > size) return nullptr;
+    T* p = reinterpret_cast<T*>(base + used);
+    used += bytes;
+    return p;
+  }
+  bool allocate() {
+    measuring = false;
+    used = 0;
+    return hipMalloc((void**)&base, size) == hipSuccess;
   }
 };
 
@@ -586,15 +600,24 @@ int solve_batched(int nbox, const int* n, const double* const* delta, double* co
     c.rr.assign(c.nlev, BTile{});
     for (int l = 0; l + 1 < c.nlev; ++l) c.rr[l] = pick_btile(c.ns[l]);
   }
-  // per-box memory and descriptors
-  BStat* dstat = mem.get<BStat>(nbox);
-  if (!dstat) return fail(MR_ENOMEM, "batched: status array");
+  // per-box memory and descriptors, carved from one allocation (measured first)
+  BStat* dstat = nullptr;
+  BBox* dboxes = nullptr;
+  double* scratch = nullptr;
+  unsigned* scounter = nullptr;
+  double* resall = nullptr;   // 8 doubles per box: the residual sums of its outer iteration
+  double* rbuf = nullptr;     // 8 doubles per box: results of the set-up and final reductions
+  auto carve = [&]() -> int {
+  dstat = mem.get<BStat>(nbox);
+  resall = mem.get<double>(8 * (size_t)nbox);
+  rbuf = mem.get<double>(8 * (size_t)nbox);
+  if (!dstat || !resall || !rbuf) return fail(MR_ENOMEM, "batched: status array");
   for (int b = 0; b < nbox; ++b) {
     const SizeClass& c = cls[cls_of_n[n[b]]];
     BBox& x = hb[b];
     x = BBox{};
     x.theta = mem.get<double>((size_t)c.n * c.n * c.n);
-    x.res = mem.get<double>(8);
+    x.res = resall + 8 * (size_t)b;
     x.partials = mem.get<double>((size_t)kBoxPartials * kMaxNV);
     x.counter = mem.get<unsigned>(16);
     x.st = dstat + b;
@@ -613,45 +636,61 @@ int solve_batched(int nbox, const int* n, const double* const* delta, double* co
       if (!L.e[0] || !L.e[1] || !L.rhs || !L.base || !L.sb || !d || !L.lsum) return fail(MR_ENOMEM, "batched: level buffers");
     }
   }
-  BBox* dboxes = mem.get<BBox>(nbox);
+  dboxes = mem.get<BBox>(nbox);
   if (!dboxes) return fail(MR_ENOMEM, "batched: descriptors");
   for (auto& c : cls) {
     c.d_boxes = mem.get<int>(c.boxes.size());
     if (!c.d_boxes) return fail(MR_ENOMEM, "batched: work table");
   }
-  double* scratch = mem.get<double>((size_t)kMaxReduceBlocks * kMaxNV + 64);
-  unsigned* scounter = mem.get<unsigned>(16);
+  scratch = mem.get<double>((size_t)kMaxReduceBlocks * kMaxNV + 64);
+  scounter = mem.get<unsigned>(16);
   if (!scratch || !scounter) return fail(MR_ENOMEM, "batched: scratch");
+  return MR_OK;
+  };
+  int crc = carve();
+  if (crc != MR_OK) return crc;
+  if (!mem.allocate()) return fail(MR_ENOMEM, "batched: %.1f MiB of device memory", mem.size / 1048576.0);
+  if ((crc = carve()) != MR_OK) return crc;
   hipError_t e = hipSuccess;
   for (auto& c : cls)
     if (e == hipSuccess) e = hipMemcpy(c.d_boxes, c.boxes.data(), c.boxes.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemsetAsync(scounter, 0, 16 * sizeof(unsigned), s);
-  Reduce red{scratch + 64, scounter, scratch};
   // Inputs: validate, convert, delta hierarchy, theta = 0. The residual at theta = 0 gives the
   // normalisation r0 and the running sum of Sigma that sets the shift of the first outer residual.
-  std::vector<BStat> hs(nbox);
+  // Every box reduces into its own result slots, so each phase needs one synchronisation.
+  std::vector<double> rh(8 * (size_t)nbox, 0.0);
+  for (int b = 0; b < nbox && e == hipSuccess; ++b) {
+    const size_t cells = (size_t)n[b] * n[b] * n[b];
+    e = launch_validate(delta[b], cells, Reduce{scratch + 64, scounter, rbuf + 8 * (size_t)b}, s);
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(rh.data(), rbuf, rh.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "batched setup");
+  for (int b = 0; b < nbox; ++b)
+    if (rh[8 * (size_t)b] != 0.0) return fail(MR_EDOMAIN, "batched: box %d has a non-finite value or 1 + delta <= 0", b);
   for (int b = 0; b < nbox && e == hipSuccess; ++b) {
     const SizeClass& c = cls[cls_of_n[n[b]]];
     const size_t cells = (size_t)c.n * c.n * c.n;
     BBox& x = hb[b];
-    e = launch_validate(delta[b], cells, red, s);
-    double bad = 0.0;
-    if (e == hipSuccess) e = hipMemcpyAsync(&bad, scratch, sizeof bad, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e == hipSuccess && bad != 0.0)
-      return fail(MR_EDOMAIN, "batched: box %d has a non-finite value or 1 + delta <= 0", b);
-    if (e == hipSuccess) e = launch_to_split(delta[b], const_cast<double*>(x.lv[0].delta), c.n, s);
+    e = launch_to_split(delta[b], const_cast<double*>(x.lv[0].delta), c.n, s);
     for (int l = 1; l < c.nlev && e == hipSuccess; ++l)
       e = launch_restrict(x.lv[l - 1].delta, const_cast<double*>(x.lv[l].delta), c.ns[l - 1], s);
     if (e == hipSuccess) e = hipMemsetAsync(x.theta, 0, cells * sizeof(double), s);
     for (int l = 0; l < c.nlev && e == hipSuccess; ++l) e = hipMemsetAsync(x.lv[l].lsum, 0, 4 * sizeof(double), s);
     if (e == hipSuccess) e = hipMemsetAsync(x.counter, 0, 16 * sizeof(unsigned), s);
-    if (e == hipSuccess) e = launch_residual(nullptr, x.lv[0].delta, c.n, 1.0, ShiftRef{nullptr, 0.0, 0.0}, nullptr, red, s);
-    double rr[2] = {0.0, 0.0};
-    if (e == hipSuccess) e = hipMemcpyAsync(rr, scratch, sizeof rr, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) break;
-    const double var = rr[1] - rr[0] * rr[0] / (double)cells;
+    if (e == hipSuccess)
+      e = launch_residual(nullptr, x.lv[0].delta, c.n, 1.0, ShiftRef{nullptr, 0.0, 0.0}, nullptr,
+                          Reduce{scratch + 64, scounter, rbuf + 8 * (size_t)b}, s);
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(rh.data(), rbuf, rh.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "batched setup");
+  std::vector<BStat> hs(nbox);
+  std::vector<double> resinit(8 * (size_t)nbox, 0.0);
+  for (int b = 0; b < nbox; ++b) {
+    const double cells = (double)n[b] * n[b] * n[b];
+    const double s0 = rh[8 * (size_t)b], s1 = rh[8 * (size_t)b + 1];
+    const double var = s1 - s0 * s0 / cells;
     BStat& st = hs[b];
     st = BStat{};
     st.active = 1;
@@ -662,9 +701,9 @@ int solve_batched(int nbox, const int* n, const double* const* delta, double* co
     st.tol = o.tol;
     st.rel = 1.0;
     st.best = 1e300;
-    const double init[4] = {-rr[0], 0.0, 0.0, 0.0};   // b = -Sigma at theta = 0
-    e = hipMemcpy(x.res, init, sizeof init, hipMemcpyHostToDevice);
+    resinit[8 * (size_t)b] = -s0;   // b = -Sigma at theta = 0: running sum of Sigma
   }
+  e = hipMemcpy(resall, resinit.data(), resinit.size() * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(dboxes, hb.data(), nbox * sizeof(BBox), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(dstat, hs.data(), nbox * sizeof(BStat), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "batched setup");
@@ -712,21 +751,25 @@ int solve_batched(int nbox, const int* n, const double* const* delta, double* co
   if (graph) (void)hipGraphDestroy(graph);
   if (cs) (void)hipStreamDestroy(cs);
   if (rc != MR_OK) return rc;
-  // final residual of the returned potentials, gauge, output
-  int status = MR_OK;
-  for (int b = 0; b < nbox; ++b) {
+  // final residual of the returned potentials, gauge, output (one synchronisation)
+  for (int b = 0; b < nbox && e == hipSuccess; ++b) {
     const SizeClass& c = cls[cls_of_n[n[b]]];
     const size_t cells = (size_t)c.n * c.n * c.n;
-    const double N3 = (double)cells;
     BBox& x = hb[b];
-    e = launch_residual(x.theta, x.lv[0].delta, c.n, 1.0, ShiftRef{nullptr, 0.0, 0.0}, nullptr, red, s);
-    double rr[2] = {0.0, 0.0};
-    if (e == hipSuccess) e = hipMemcpyAsync(rr, scratch, sizeof rr, hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = launch_sum(x.theta, cells, Reduce{scratch + 64, scounter, scratch + 8}, s);
-    if (e == hipSuccess) e = launch_from_split(x.theta, theta[b], c.n, scratch + 8, 1.0 / N3, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "batched output");
-    const double var = rr[1] - rr[0] * rr[0] / N3;
+    double* r = rbuf + 8 * (size_t)b;
+    e = launch_residual(x.theta, x.lv[0].delta, c.n, 1.0, ShiftRef{nullptr, 0.0, 0.0}, nullptr,
+                        Reduce{scratch + 64, scounter, r}, s);
+    if (e == hipSuccess) e = launch_sum(x.theta, cells, Reduce{scratch + 64, scounter, r + 2}, s);
+    if (e == hipSuccess) e = launch_from_split(x.theta, theta[b], c.n, r + 2, 1.0 / (double)cells, s);
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(rh.data(), rbuf, rh.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "batched output");
+  int status = MR_OK;
+  for (int b = 0; b < nbox; ++b) {
+    const double N3 = (double)n[b] * n[b] * n[b];
+    const double s0 = rh[8 * (size_t)b], s1 = rh[8 * (size_t)b + 1];
+    const double var = s1 - s0 * s0 / N3;
     const double relf = std::sqrt(var > 0.0 ? var : 0.0) / hs[b].r0;
     int st = hs[b].status;
     if (st == MR_OK && !std::isfinite(relf)) st = MR_EDIVERGED;
@@ -739,7 +782,7 @@ int solve_batched(int nbox, const int* n, const double* const* delta, double* co
       inf.cycles = hs[b].iters;
       inf.rel_residual = relf;
       inf.r0_norm = hs[b].r0;
-      inf.m_shift = -rr[0] / N3;
+      inf.m_shift = -s0 / N3;
       const int nh = std::min(hs[b].iters + 1, 128);
       for (int k = 0; k < nh; ++k) inf.history[k] = hs[b].hist[k];
       inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
