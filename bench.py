@@ -13,8 +13,9 @@ algorithmic 24 bytes per cell update (theta read + write, delta read) against th
 peak; "traffic" is the HBM traffic per sweep measured with rocprofv3 counters (committed
 summary), over the same sweep time.
 
-Also reported: time to solution of both 512^3 solves, and the batched form on 64 boxes of
-{64, 96, 128}^3 (mixed precision to 1e-8), timed once after one untimed run.
+Also reported: time to solution of both 512^3 solves; one adjoint solve at 512^3; the CIC
+deposit of 256^3 particles onto a 256^3 mesh; and the batched form on 64 boxes of
+{64, 96, 128}^3 (mixed precision to 1e-8), each timed after an untimed run.
 
 Prints ONE JSON line. --gpus N > 1 is refused: this path runs on one GPU.
 """
@@ -125,6 +126,46 @@ def batched_run():
     }
 
 
+def cic_run():
+    """CIC deposit of 256^3 Zel'dovich-displaced particles onto a 256^3 mesh (particles resident)."""
+    import torch
+
+    import inputs
+    from paper_1709_06350_amd import mr
+
+    n = 256
+    pos = torch.from_numpy(inputs.zeldovich_particles(n, 4.0, 1001)).cuda()
+    with mr.Context(n) as c:
+        out = c.deposit_cic(pos)
+        torch.cuda.synchronize()
+        reps = 5
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            c.deposit_cic(pos, out=out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+    npart = pos.shape[0]
+    return {"particles": npart, "mesh": n, "seconds": round(dt, 5),
+            "gparticles_per_s": round(npart / dt / 1e9, 3)}
+
+
+def adjoint_run(ctx, delta, theta):
+    """One adjoint solve (gradient of a loss through the solve) at the bench mesh, after the solve."""
+    import torch
+
+    g = theta - theta.mean()
+    ctx.set_opts(tol=1e-8)
+    out, info = ctx.adjoint_solve(delta, theta, g, check=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out, info = ctx.adjoint_solve(delta, theta, g, out=out, check=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.set_opts(tol=1e-10)
+    return {"seconds": round(dt, 4), "cycles": info.cycles, "rel_residual": info.rel_residual, "tol": 1e-8,
+            "status": info.status, "g": "theta - <theta> (dL/dtheta of L = |theta|^2 / 2)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -134,6 +175,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the CIC and adjoint timings")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a device copy of BYTES bytes (counter calibration)")
     args = ap.parse_args()
@@ -247,6 +289,9 @@ def main():
         "rel_residual": {"fp64": info64.rel_residual if info64 else None,
                          "mixed": infom.rel_residual if infom else None},
     }
+    if not args.no_extra:
+        out["adjoint"] = adjoint_run(ctx, delta, theta)
+        out["cic"] = cic_run()
     if not args.no_batched:
         out["batched"] = batched_run()
     if not args.no_cpu_baseline:

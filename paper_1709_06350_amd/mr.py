@@ -234,6 +234,14 @@ class Context:
             _check(code)
         return theta, Info.from_c(info)
 
+    def set_opts(self, **kw):
+        """Change solver options of this context (mr_set_opts); keywords are mr_opts fields."""
+        for k, v in kw.items():
+            if not hasattr(self.opts, k):
+                raise KeyError(k)
+            setattr(self.opts, k, v)
+        _check(self.lib.mr_set_opts(self.h, ctypes.byref(self.opts)))
+
     def adjoint_solve(self, delta, theta_star, g, out=None, check: bool = True):
         out = self._empty() if out is None else out
         info = mr_info()
