@@ -443,6 +443,170 @@ __global__ void __launch_bounds__(256) defect_restrict_kernel(DefectArgs a) {
   grid_sum<2>(vv, a.partials, a.counter, a.sums_out, gridDim.x, blockIdx.x);
 }
 
+// ---- pipelined defect + restriction ------------------------------------------------------------
+// The outputs of defect_restrict_kernel on the decomposition of the pipelined sweep: a thread owns
+// column (j, m) and evaluates both colours (two independent roots) per plane; it accumulates the
+// defect and theta over the plane pair 2I, 2I+1, and after the odd plane the thread of the even row
+// adds its neighbour's partial sums from LDS to complete the 8 sons of coarse cell (I, j/2, m).
+// Chunks are multiples of 4 planes (uneven lengths), the plane loop is unrolled by the ring length
+// (compile-time slots), planes are fetched two steps ahead and delta / f two steps before use.
+template <int TM, int TJ, bool HAS_F>
+__global__ void __launch_bounds__(TM * TJ) defect_restrict_pipe(DefectArgs a, int nchunks) {
+  constexpr int NT = TM * TJ;
+  constexpr int RW = TM + 2, RH = TJ + 2;
+  constexpr int SLOT = RH * RW;
+  constexpr int TOTAL = 2 * SLOT;
+  constexpr int NPF = (TOTAL + NT - 1) / NT;
+  static_assert(TJ % 2 == 0, "row pairs");
+  __shared__ double lds[2 * 4 * SLOT];
+  __shared__ double xb[NT][2];
+  const int n = a.n, nh = n >> 1, nc = n >> 1, nch = nc >> 1;
+  const int tid = threadIdx.x;
+  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int ntile = a.tiles_m * a.tiles_j;
+  const int tile = logical % ntile, chunk = logical / ntile;
+  const int m0 = (tile % a.tiles_m) * TM, j0 = (tile / a.tiles_m) * TJ;
+  const int q4 = n / 4;
+  const int i0 = 4 * (int)(((long)chunk * q4) / nchunks);
+  const int i1 = 4 * (int)(((long)(chunk + 1) * q4) / nchunks);
+  const unsigned half = (unsigned)n * (unsigned)n * (unsigned)nh;
+  const unsigned plane = (unsigned)n * (unsigned)nh;
+  const unsigned halfc = (unsigned)nc * (unsigned)nc * (unsigned)nch;
+  const double* __restrict__ th = a.theta;
+
+  unsigned goff[NPF];
+  int loff[NPF];
+#pragma unroll
+  for (int t = 0; t < NPF; ++t) {
+    int e = tid + t * NT;
+    e = e < TOTAL ? e : TOTAL - 1;
+    const int cc = e / SLOT;
+    const int rem = e - cc * SLOT;
+    const int r = rem / RW;
+    const int c = rem - r * RW;
+    goff[t] = (unsigned)cc * half + (unsigned)wrapi(j0 - 1 + r, n) * nh + (unsigned)wrapi(m0 - 1 + c, nh);
+    loff[t] = cc * 4 * SLOT + rem;
+  }
+  auto fetch = [&](int rel, double (&v)[NPF]) {
+    const unsigned base = (unsigned)wrapi(i0 - 1 + rel, n) * plane;
+#pragma unroll
+    for (int t = 0; t < NPF; ++t) v[t] = th[base + goff[t]];
+  };
+  auto store = [&](int slot, const double (&v)[NPF]) {
+#pragma unroll
+    for (int t = 0; t < NPF; ++t) lds[loff[t] + slot * SLOT] = v[t];
+  };
+
+  const int s = tid % TM, r = tid / TM;
+  const int j = j0 + r, m = m0 + s;
+  const unsigned own = (unsigned)j * nh + m;
+  const int ob = (r + 1) * RW + (s + 1);
+  const int qa = (i0 + j) & 1;
+  const int oq00 = ob + qa, oq01 = ob + (qa ^ 1);
+  const double C = (a.c_sum ? (a.c_sum[0] + a.c_sum[1]) * a.c_scale : 0.0) + a.c_add;
+  const double ih2 = a.ih2;
+  const double* __restrict__ dl = a.delta + own;
+  const double* __restrict__ ff = HAS_F ? a.f + own : nullptr;
+  const int last_plane = n - 1;
+  double n1 = 0.0, n2 = 0.0, sd = 0.0, st = 0.0;
+
+  double V0[NPF], V1[NPF];
+  double D[4][2], Fv[4][2];
+  {
+    double va[NPF], vb[NPF], vc[NPF];
+    fetch(0, va);
+    fetch(1, vb);
+    fetch(2, vc);
+    store(0, va);
+    store(1, vb);
+    store(2, vc);
+  }
+  fetch(3, V0);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const unsigned pk = (unsigned)min(i0 + k, last_plane) * plane;
+    D[k][0] = dl[pk];
+    D[k][1] = dl[half + pk];
+    if (HAS_F) {
+      Fv[k][0] = ff[pk];
+      Fv[k][1] = ff[half + pk];
+    }
+  }
+  __syncthreads();
+
+  auto gather = [&](const double* lo, const double* lc, int SM, int S0, int SP, int oq, Nb18& c) {
+    c.xm = lo[SM * SLOT + ob];         c.xp = lo[SP * SLOT + ob];
+    c.ym = lo[S0 * SLOT + ob - RW];    c.yp = lo[S0 * SLOT + ob + RW];
+    c.zm = lo[S0 * SLOT + oq - 1];     c.zp = lo[S0 * SLOT + oq];
+    c.xpyp = lc[SP * SLOT + ob + RW];  c.xmym = lc[SM * SLOT + ob - RW];
+    c.xpym = lc[SP * SLOT + ob - RW];  c.xmyp = lc[SM * SLOT + ob + RW];
+    c.xpzp = lc[SP * SLOT + oq];       c.xmzm = lc[SM * SLOT + oq - 1];
+    c.xpzm = lc[SP * SLOT + oq - 1];   c.xmzp = lc[SM * SLOT + oq];
+    c.ypzp = lc[S0 * SLOT + oq + RW];  c.ymzm = lc[S0 * SLOT + oq - RW - 1];
+    c.ypzm = lc[S0 * SLOT + oq + RW - 1]; c.ymzp = lc[S0 * SLOT + oq - RW];
+  };
+  auto step = [&](auto kc, int t, double (&vst)[NPF], double (&vft)[NPF]) {
+    constexpr int K = decltype(kc)::value;
+    constexpr int SM = K & 3, S0 = (K + 1) & 3, SP = (K + 2) & 3, SN = (K + 3) & 3;
+    fetch(t + 4, vft);
+    const unsigned pn = (unsigned)min(i0 + t + 2, last_plane) * plane;
+    D[(K + 2) & 3][0] = dl[pn];
+    D[(K + 2) & 3][1] = dl[half + pn];
+    if (HAS_F) {
+      Fv[(K + 2) & 3][0] = ff[pn];
+      Fv[(K + 2) & 3][1] = ff[half + pn];
+    }
+    const double* l0 = lds;
+    const double* l1 = lds + 4 * SLOT;
+    const int oqc0 = (K & 1) ? oq01 : oq00;
+    const int oqc1 = (K & 1) ? oq00 : oq01;
+    Nb18 c0, c1;
+    gather(l1, l0, SM, S0, SP, oqc0, c0);
+    gather(l0, l1, SM, S0, SP, oqc1, c1);
+    double S[2], pp[2], qq[2], sr[2];
+    cell_pq(c0, 1.0 + D[K][0], ih2, S[0], pp[0], qq[0]);
+    cell_pq(c1, 1.0 + D[K][1], ih2, S[1], pp[1], qq[1]);
+    largest_roots<2>(pp, qq, sr);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const double tc = (c == 0 ? l0 : l1)[S0 * SLOT + ob];
+      const double d = (S[c] - 6.0 * tc) * ih2 - (sr[c] - 3.0) - (HAS_F ? Fv[K][c] : 0.0) + C;
+      n1 += d;
+      n2 += d * d;
+      sd += d;
+      st += tc;
+    }
+    if (K & 1) {   // odd plane: partial sums of the plane pair to LDS
+      xb[tid][0] = sd;
+      xb[tid][1] = st;
+    }
+    store(SN, vst);
+    __syncthreads();
+    if (K & 1) {
+      if ((r & 1) == 0) {
+        const double sdt = sd + xb[tid + TM][0];
+        const double stt = st + xb[tid + TM][1];
+        const int i = i0 + t;
+        const int I = i >> 1, J = j >> 1, Kc = m;
+        const unsigned ec = ((I + J + Kc) & 1) * halfc + ((unsigned)I * nc + J) * (unsigned)nch + (unsigned)(Kc >> 1);
+        a.theta_c[ec] = 0.125 * stt;
+        if (a.theta_c2) a.theta_c2[ec] = 0.125 * stt;
+        a.dr[ec] = 0.125 * sdt;
+      }
+      sd = 0.0;
+      st = 0.0;
+    }
+  };
+  for (int t = 0; t < i1 - i0; t += 4) {
+    step(std::integral_constant<int, 0>(), t, V0, V1);
+    step(std::integral_constant<int, 1>(), t + 1, V1, V0);
+    step(std::integral_constant<int, 2>(), t + 2, V0, V1);
+    step(std::integral_constant<int, 3>(), t + 3, V1, V0);
+  }
+  double vv[2] = {n1, n2};
+  grid_sum<2>(vv, a.partials, a.counter, a.sums_out, gridDim.x, blockIdx.x);
+}
+
 // Coarsest mesh (at most 12^3 cells): nsweeps red-black sweeps by one block with the whole
 // mesh in LDS (natural order inside the block). Same update and snapshot semantics as the tiled
 // half-sweeps; the uniform shift is lagged by one sweep and refreshed in-block after every sweep.
@@ -896,7 +1060,64 @@ bool half_sweep_pipe_supported(int tm, int tj) {
   return false;
 }
 
+#define MR_DR_TILES(X) X(64, 8) X(32, 8) X(16, 8) X(8, 8) X(4, 8)
+
+// Tile and chunk count of the pipelined defect + restriction: the largest compiled tile dividing
+// the mesh, and the largest number of chunks (multiples of 4 planes) whose grid still fits in one
+// round of the device's resident block slots.
+static bool defect_pipe_cfg(int n, bool has_f, int& tm, int& tj, int& nchunks) {
+  static const int pref[][2] = {{64, 8}, {32, 8}, {16, 8}, {8, 8}, {4, 8}};
+  if (n % 8 != 0) return false;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    return false;
+  for (const auto& p : pref) {
+    if ((n / 2) % p[0] != 0 || n % p[1] != 0) continue;
+    const void* k = nullptr;
+#define MR_DR_PTR(TM, TJ)                                                                                  \
+    if (p[0] == TM && p[1] == TJ)                                                                          \
+      k = has_f ? reinterpret_cast<const void*>(&defect_restrict_pipe<TM, TJ, true>)                        \
+                : reinterpret_cast<const void*>(&defect_restrict_pipe<TM, TJ, false>);
+    MR_DR_TILES(MR_DR_PTR)
+#undef MR_DR_PTR
+    int bpc = 0;
+    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, k, p[0] * p[1], 0) != hipSuccess || bpc < 1) continue;
+    const long tiles = (long)(n / p[1]) * (n / 2 / p[0]);
+    const long cap = (long)cus * bpc;
+    long ch = cap / tiles;
+    ch = std::max(1L, std::min(ch, (long)(n / 8)));
+    while (ch > 1 && tiles * ch > kMaxReduceBlocks) --ch;
+    if (tiles * ch > kMaxReduceBlocks) return false;
+    tm = p[0];
+    tj = p[1];
+    nchunks = (int)ch;
+    return true;
+  }
+  return false;
+}
+
 hipError_t launch_defect_restrict_tiled(const DefectArgs& a, const TileCfg& t, hipStream_t s) {
+  {
+    int tm = 0, tj = 0, nch = 0;
+    if (defect_pipe_cfg(a.n, a.f != nullptr, tm, tj, nch)) {
+      DefectArgs b = a;
+      b.tj = tj;
+      b.tiles_j = a.n / tj;
+      b.tiles_m = a.n / 2 / tm;
+      const unsigned blocks = (unsigned)(b.tiles_j * b.tiles_m * nch);
+#define MR_DR_LAUNCH(TM, TJ)                                                                                 \
+      if (tm == TM && tj == TJ) {                                                                            \
+        if (a.f)                                                                                             \
+          hipLaunchKernelGGL((defect_restrict_pipe<TM, TJ, true>), dim3(blocks), dim3(TM * TJ), 0, s, b, nch);  \
+        else                                                                                                 \
+          hipLaunchKernelGGL((defect_restrict_pipe<TM, TJ, false>), dim3(blocks), dim3(TM * TJ), 0, s, b, nch); \
+        return hipGetLastError();                                                                            \
+      }
+      MR_DR_TILES(MR_DR_LAUNCH)
+#undef MR_DR_LAUNCH
+    }
+  }
   const int threads = tile_threads(t, t.tm * (t.tj / 2));
   if (!tile_ok(t, a.n, threads) || t.tj % 2 != 0 || t.ci % 2 != 0) return hipErrorInvalidValue;
   DefectArgs b = a;

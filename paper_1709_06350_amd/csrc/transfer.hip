@@ -85,13 +85,10 @@ __global__ void __launch_bounds__(256) coarse_diff_kernel(const double* __restri
 // cell pair k = 2m, 2m+1 of row (i, j), which share coarse column K = m; k = 2m takes its
 // k-neighbour at K - 1, k = 2m + 1 at K + 1. The two cells lie in the two colour halves at the
 // same offset.
-__global__ void __launch_bounds__(512) prolong_correct_kernel(const double* __restrict__ ec,
-    double* __restrict__ theta, int n) {
+__device__ __forceinline__ void prolong_correct_row(const double* __restrict__ ec, double* __restrict__ theta, int n,
+                                                    int row, int m) {
   const int nh = n >> 1;
-  const int row = xcd_remap(blockIdx.x, gridDim.x);
   const int i = row / n, j = row - i * n;
-  const int m = threadIdx.x;
-  if (m >= nh) return;
   const int nc = n >> 1;
   const int I = i >> 1, J = j >> 1, K = m;
   const int I2 = wrapi((i & 1) ? I + 1 : I - 1, nc);
@@ -113,6 +110,17 @@ __global__ void __launch_bounds__(512) prolong_correct_kernel(const double* __re
   const int c0 = (i + j) & 1;
   theta[c0 * half + off] += lo;
   theta[(1 - c0) * half + off] += hi;
+}
+
+// Each block handles a contiguous range of rows (blocks are mapped XCD-aware), a thread one
+// column m of every row in it.
+__global__ void __launch_bounds__(512) prolong_correct_kernel(const double* __restrict__ ec,
+    double* __restrict__ theta, int n, int rows_per_block) {
+  const int nh = n >> 1;
+  const int r0 = xcd_remap(blockIdx.x, gridDim.x) * rows_per_block;
+  const int r1 = min(r0 + rows_per_block, n * n);
+  for (int row = r0; row < r1; ++row)
+    for (int m = threadIdx.x; m < nh; m += blockDim.x) prolong_correct_row(ec, theta, n, row, m);
 }
 
 __global__ void __launch_bounds__(512) restrict_kernel(const double* __restrict__ fine,
@@ -187,7 +195,10 @@ hipError_t launch_tau(const double* th, const double* delta, const double* rd, d
 hipError_t launch_prolong_correct(const double* tc, double* that, double* theta, int n, hipStream_t s) {
   const size_t cc = (size_t)(n / 2) * (n / 2) * (n / 2);
   hipLaunchKernelGGL(coarse_diff_kernel, dim3(lin_grid(cc)), dim3(256), 0, s, tc, that, cc);
-  hipLaunchKernelGGL(prolong_correct_kernel, rows_of(n), dim3(n / 2), 0, s, that, theta, n);
+  const int rows = n * n;
+  const int rpb = rows > 16384 ? (rows + 8191) / 8192 : 1;
+  const int blocks = (rows + rpb - 1) / rpb;
+  hipLaunchKernelGGL(prolong_correct_kernel, dim3(blocks), dim3(n / 2 < 512 ? n / 2 : 512), 0, s, that, theta, n, rpb);
   return hipGetLastError();
 }
 

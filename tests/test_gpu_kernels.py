@@ -90,7 +90,7 @@ def test_fused_and_two_pass_sweeps_agree(ctx, ctx2):
     assert abs(s1 - s2) <= 1e-12 * (abs(s1) + 1.0)
 
 
-@pytest.mark.parametrize("n,h,with_f", [(16, 1.0, False), (48, 2.0, True)])
+@pytest.mark.parametrize("n,h,with_f", [(16, 1.0, False), (48, 2.0, True), (128, 1.0, False), (64, 2.0, True)])
 def test_defect_restrict_matches_oracle(ctx, n, h, with_f):
     announce(f"defect_restrict n={n}")
     delta, theta = _state(n, 200 + n)
