@@ -270,7 +270,9 @@ hipError_t launch_lin_resid_restrict(const float* e, const float* base, const fl
 }
 
 hipError_t launch_prolong_add32(const float* ec, float* e, int n, hipStream_t s) {
-  hipLaunchKernelGGL(prolong_add32_kernel, dim3((unsigned)n * n), dim3(n / 2), 0, s, ec, e, n);
+  const unsigned rows = (unsigned)n * n;
+  hipLaunchKernelGGL(prolong_add32_kernel, dim3(rows < 8192u ? rows : 8192u), dim3(n / 2 < 512 ? n / 2 : 512), 0, s, ec,
+                     e, n);
   return hipGetLastError();
 }
 

@@ -152,6 +152,9 @@ hipError_t launch_sweep_fused(const FusedSweepArgs& a, const FusedCfg& cfg, hipS
 // f = nabla^2 th - Sigma(th) - rd on an n^3 mesh (f may alias rd); result[0..1] = (sum(Sigma + f), 0).
 hipError_t launch_tau(const double* th, const double* delta, const double* rd, double* f, int n,
                       double h, Reduce red, hipStream_t s);
+// The tiled kernel for launch_tau where a tile fits n (*done false: nothing launched).
+hipError_t launch_tau_pipe(const double* th, const double* delta, const double* rd, double* f, int n, double h,
+                           Reduce red, hipStream_t s, bool* done);
 // theta += P(tc - that) from the (n/2)^3 mesh onto the n^3 mesh; that is overwritten with tc - that.
 hipError_t launch_prolong_correct(const double* tc, double* that, double* theta, int n, hipStream_t s);
 // coarse = 8-son mean of fine (fine n^3).

@@ -607,6 +607,187 @@ __global__ void __launch_bounds__(TM * TJ) defect_restrict_pipe(DefectArgs a, in
   grid_sum<2>(vv, a.partials, a.counter, a.sums_out, gridDim.x, blockIdx.x);
 }
 
+// ---- pipelined FAS right-hand side ---------------------------------------------------------------
+// tau_kernel's outputs (Eq. 19: f = nabla^2 th - Sigma(th) - rd, in place over rd allowed; sums of
+// Sigma + f) on the decomposition of the pipelined sweep: a thread owns column (j, m) and both
+// colours per plane (two roots per step); chunks are multiples of 4 planes.
+template <int TM, int TJ>
+__global__ void __launch_bounds__(TM * TJ) tau_pipe(const double* __restrict__ th, const double* __restrict__ delta,
+                                                    const double* rd, double* f, int n, double ih2, Reduce red,
+                                                    int tiles_j, int tiles_m, int nchunks) {
+  constexpr int NT = TM * TJ;
+  constexpr int RW = TM + 2, RH = TJ + 2;
+  constexpr int SLOT = RH * RW;
+  constexpr int TOTAL = 2 * SLOT;
+  constexpr int NPF = (TOTAL + NT - 1) / NT;
+  __shared__ double lds[2 * 4 * SLOT];
+  const int nh = n >> 1;
+  const int tid = threadIdx.x;
+  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int ntile = tiles_m * tiles_j;
+  const int tile = logical % ntile, chunk = logical / ntile;
+  const int m0 = (tile % tiles_m) * TM, j0 = (tile / tiles_m) * TJ;
+  const int q4 = n / 4;
+  const int i0 = 4 * (int)(((long)chunk * q4) / nchunks);
+  const int i1 = 4 * (int)(((long)(chunk + 1) * q4) / nchunks);
+  const unsigned half = (unsigned)n * (unsigned)n * (unsigned)nh;
+  const unsigned plane = (unsigned)n * (unsigned)nh;
+
+  unsigned goff[NPF];
+  int loff[NPF];
+#pragma unroll
+  for (int t = 0; t < NPF; ++t) {
+    int e = tid + t * NT;
+    e = e < TOTAL ? e : TOTAL - 1;
+    const int cc = e / SLOT;
+    const int rem = e - cc * SLOT;
+    const int r = rem / RW;
+    const int c = rem - r * RW;
+    goff[t] = (unsigned)cc * half + (unsigned)wrapi(j0 - 1 + r, n) * nh + (unsigned)wrapi(m0 - 1 + c, nh);
+    loff[t] = cc * 4 * SLOT + rem;
+  }
+  auto fetch = [&](int rel, double (&v)[NPF]) {
+    const unsigned base = (unsigned)wrapi(i0 - 1 + rel, n) * plane;
+#pragma unroll
+    for (int t = 0; t < NPF; ++t) v[t] = th[base + goff[t]];
+  };
+  auto store = [&](int slot, const double (&v)[NPF]) {
+#pragma unroll
+    for (int t = 0; t < NPF; ++t) lds[loff[t] + slot * SLOT] = v[t];
+  };
+
+  const int s = tid % TM, r = tid / TM;
+  const int j = j0 + r, m = m0 + s;
+  const unsigned own = (unsigned)j * nh + m;
+  const int ob = (r + 1) * RW + (s + 1);
+  const int qa = (i0 + j) & 1;
+  const int oq00 = ob + qa, oq01 = ob + (qa ^ 1);
+  const double* __restrict__ dl = delta + own;
+  const int last_plane = n - 1;
+  double acc = 0.0;
+
+  double V0[NPF], V1[NPF];
+  double D[4][2];
+  {
+    double va[NPF], vb[NPF], vc[NPF];
+    fetch(0, va);
+    fetch(1, vb);
+    fetch(2, vc);
+    store(0, va);
+    store(1, vb);
+    store(2, vc);
+  }
+  fetch(3, V0);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const unsigned pk = (unsigned)min(i0 + k, last_plane) * plane;
+    D[k][0] = dl[pk];
+    D[k][1] = dl[half + pk];
+  }
+  __syncthreads();
+
+  auto gather = [&](const double* lo, const double* lc, int SM, int S0, int SP, int oq, Nb18& c) {
+    c.xm = lo[SM * SLOT + ob];         c.xp = lo[SP * SLOT + ob];
+    c.ym = lo[S0 * SLOT + ob - RW];    c.yp = lo[S0 * SLOT + ob + RW];
+    c.zm = lo[S0 * SLOT + oq - 1];     c.zp = lo[S0 * SLOT + oq];
+    c.xpyp = lc[SP * SLOT + ob + RW];  c.xmym = lc[SM * SLOT + ob - RW];
+    c.xpym = lc[SP * SLOT + ob - RW];  c.xmyp = lc[SM * SLOT + ob + RW];
+    c.xpzp = lc[SP * SLOT + oq];       c.xmzm = lc[SM * SLOT + oq - 1];
+    c.xpzm = lc[SP * SLOT + oq - 1];   c.xmzp = lc[SM * SLOT + oq];
+    c.ypzp = lc[S0 * SLOT + oq + RW];  c.ymzm = lc[S0 * SLOT + oq - RW - 1];
+    c.ypzm = lc[S0 * SLOT + oq + RW - 1]; c.ymzp = lc[S0 * SLOT + oq - RW];
+  };
+  auto step = [&](auto kc, int t, double (&vst)[NPF], double (&vft)[NPF]) {
+    constexpr int K = decltype(kc)::value;
+    constexpr int SM = K & 3, S0 = (K + 1) & 3, SP = (K + 2) & 3, SN = (K + 3) & 3;
+    fetch(t + 4, vft);
+    const unsigned pn = (unsigned)min(i0 + t + 2, last_plane) * plane;
+    D[(K + 2) & 3][0] = dl[pn];
+    D[(K + 2) & 3][1] = dl[half + pn];
+    const double* l0 = lds;
+    const double* l1 = lds + 4 * SLOT;
+    const int oqc0 = (K & 1) ? oq01 : oq00;
+    const int oqc1 = (K & 1) ? oq00 : oq01;
+    Nb18 c0, c1;
+    gather(l1, l0, SM, S0, SP, oqc0, c0);
+    gather(l0, l1, SM, S0, SP, oqc1, c1);
+    double S[2], pp[2], qq[2], sr[2];
+    cell_pq(c0, 1.0 + D[K][0], ih2, S[0], pp[0], qq[0]);
+    cell_pq(c1, 1.0 + D[K][1], ih2, S[1], pp[1], qq[1]);
+    largest_roots<2>(pp, qq, sr);
+    const unsigned e0 = (unsigned)(i0 + t) * plane + own;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const double tc = (c == 0 ? l0 : l1)[S0 * SLOT + ob];
+      const double sig = sr[c] - 3.0;
+      const unsigned e = (unsigned)c * half + e0;
+      const double fv = (S[c] - 6.0 * tc) * ih2 - sig - rd[e];
+      f[e] = fv;
+      acc += sig + fv;
+    }
+    store(SN, vst);
+    __syncthreads();
+  };
+  for (int t = 0; t < i1 - i0; t += 4) {
+    step(std::integral_constant<int, 0>(), t, V0, V1);
+    step(std::integral_constant<int, 1>(), t + 1, V1, V0);
+    step(std::integral_constant<int, 2>(), t + 2, V0, V1);
+    step(std::integral_constant<int, 3>(), t + 3, V1, V0);
+  }
+  double vv[2] = {acc, 0.0};
+  grid_sum<2>(vv, red.partials, red.counter, red.result, gridDim.x, blockIdx.x);
+}
+
+// Tile and chunk count of the pipelined FAS right-hand side (as for the defect + restriction).
+bool tau_pipe_cfg(int n, int& tm, int& tj, int& nchunks) {
+  static const int pref[][2] = {{64, 8}, {32, 8}, {16, 8}, {8, 8}, {4, 8}};
+  if (n % 8 != 0) return false;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    return false;
+  for (const auto& p : pref) {
+    if ((n / 2) % p[0] != 0 || n % p[1] != 0) continue;
+    const void* k = nullptr;
+#define MR_TP_PTR(TM, TJ) \
+    if (p[0] == TM && p[1] == TJ) k = reinterpret_cast<const void*>(&tau_pipe<TM, TJ>);
+    MR_TP_PTR(64, 8) MR_TP_PTR(32, 8) MR_TP_PTR(16, 8) MR_TP_PTR(8, 8) MR_TP_PTR(4, 8)
+#undef MR_TP_PTR
+    int bpc = 0;
+    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, k, p[0] * p[1], 0) != hipSuccess || bpc < 1) continue;
+    const long tiles = (long)(n / p[1]) * (n / 2 / p[0]);
+    long ch = ((long)cus * bpc) / tiles;
+    ch = std::max(1L, std::min(ch, (long)(n / 8)));
+    while (ch > 1 && tiles * ch > kMaxReduceBlocks) --ch;
+    if (tiles * ch > kMaxReduceBlocks) return false;
+    tm = p[0];
+    tj = p[1];
+    nchunks = (int)ch;
+    return true;
+  }
+  return false;
+}
+
+hipError_t launch_tau_pipe(const double* th, const double* delta, const double* rd, double* f, int n, double h,
+                           Reduce red, hipStream_t s, bool* done) {
+  int tm = 0, tj = 0, nch = 0;
+  *done = false;
+  if (!tau_pipe_cfg(n, tm, tj, nch)) return hipSuccess;
+  const int tiles_j = n / tj, tiles_m = n / 2 / tm;
+  const unsigned blocks = (unsigned)(tiles_j * tiles_m * nch);
+  const double ih2 = 1.0 / (h * h);
+#define MR_TP_LAUNCH(TM, TJ)                                                                                   \
+  if (tm == TM && tj == TJ) {                                                                                  \
+    hipLaunchKernelGGL((tau_pipe<TM, TJ>), dim3(blocks), dim3(TM * TJ), 0, s, th, delta, rd, f, n, ih2, red,      \
+                       tiles_j, tiles_m, nch);                                                                 \
+    *done = true;                                                                                              \
+    return hipGetLastError();                                                                                  \
+  }
+  MR_TP_LAUNCH(64, 8) MR_TP_LAUNCH(32, 8) MR_TP_LAUNCH(16, 8) MR_TP_LAUNCH(8, 8) MR_TP_LAUNCH(4, 8)
+#undef MR_TP_LAUNCH
+  return hipSuccess;
+}
+
 // Coarsest mesh (at most 12^3 cells): nsweeps red-black sweeps by one block with the whole
 // mesh in LDS (natural order inside the block). Same update and snapshot semantics as the tiled
 // half-sweeps; the uniform shift is lagged by one sweep and refreshed in-block after every sweep.

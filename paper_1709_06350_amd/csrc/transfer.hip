@@ -187,6 +187,9 @@ static int row_threads(int n) { return n < 64 ? 64 : (n < 256 ? n : 256); }
 
 hipError_t launch_tau(const double* th, const double* delta, const double* rd, double* f, int n,
                       double h, Reduce red, hipStream_t s) {
+  bool done = false;
+  hipError_t e = launch_tau_pipe(th, delta, rd, f, n, h, red, s, &done);
+  if (e != hipSuccess || done) return e;
   hipLaunchKernelGGL(tau_kernel, dim3(rows_grid(n)), dim3(row_threads(n)), 0, s, th, delta, rd, f, n,
                      1.0 / (h * h), red);
   return hipGetLastError();

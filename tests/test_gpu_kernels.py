@@ -103,7 +103,7 @@ def test_defect_restrict_matches_oracle(ctx, n, h, with_f):
     _close(host(tc), omg.restrict(theta), np.abs(theta).max())
 
 
-@pytest.mark.parametrize("n,h", [(8, 2.0), (24, 4.0)])
+@pytest.mark.parametrize("n,h", [(8, 2.0), (24, 4.0), (64, 2.0), (128, 2.0)])
 def test_tau_rhs_matches_oracle(ctx, n, h):
     announce(f"tau n={n}")
     delta, theta = _state(n, 300 + n)
