@@ -73,8 +73,12 @@ typedef struct {
 /* MR_FLAG_EAGER (mr_solve_batched only): launch every pass directly on the stream instead of
  * replaying the captured graph (same kernels and arguments; for checking the graph against direct
  * launches). MR_FLAG_TWO_PASS: relax with one launch per colour (red, then black from the new
- * red values) instead of the fused red-black launch; both compute the same update. */
-enum { MR_FLAG_EAGER = 1, MR_FLAG_TWO_PASS = 2 };
+ * red values) instead of the fused red-black launch; both compute the same update.
+ * MR_FLAG_ADJ_ROWS / MR_FLAG_ADJ_TILED (mr_adjoint_solve): relax the adjoint with the untiled
+ * row kernel on every level, or with the tiled plane-marching kernel on every level a compiled
+ * tile fits, instead of the per-level timed choice; all compute the same update up to rounding
+ * order. Setting both is an error. */
+enum { MR_FLAG_EAGER = 1, MR_FLAG_TWO_PASS = 2, MR_FLAG_ADJ_ROWS = 4, MR_FLAG_ADJ_TILED = 8 };
 
 /* Per-solve report. history[c] is the relative residual after cycle c (history[0] = start). */
 typedef struct {

@@ -16,6 +16,11 @@
 // the last sweep's output), which every read subtracts.
 #include <chrono>
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <type_traits>
+#include <utility>
+#include <vector>
 
 #include "mr.h"
 #include "mr_ctx.h"
@@ -29,6 +34,8 @@ struct AdjLevel {
   int cur = 0;
   double* rhs = nullptr;
   double* coef = nullptr;   // 6 fields: A_x, A_y, A_z, W_xy, W_xz, W_yz (each colour-split n^3)
+  int tm = 0, tj = 0, ci = 0;   // half-sweep tile and chunk; tm == 0: the row kernel
+  bool pfc = false;             // coefficient prefetch of the tiled half-sweep
 };
 
 struct AdjointState {
@@ -128,6 +135,233 @@ __global__ void __launch_bounds__(256) adj_half_sweep_kernel(const double* __res
   double vv[1] = {acc};
   const bool last = grid_sum<1>(vv, red.partials, red.counter, sum_out, gridDim.x, blockIdx.x);
   if (last && threadIdx.x == 0 && copy_to) *copy_to = *copy_from;
+}
+
+// ---- pipelined half-sweep (fine meshes) ----------------------------------------------------
+// The same update as adj_half_sweep_kernel on a TJ x TM tile of (j, m) marching along i over a
+// chunk of ci planes (ci % 4 == 0). lambda of both colours (mean offset already removed) sits in a
+// 4-slot LDS plane ring filled two planes ahead, as in the forward pipelined half-sweep. The
+// coefficients are read from global memory one step ahead into registers; they are used exactly
+// once per cell, so staging them in LDS would buy nothing. The x-direction part of the transpose
+// stencil splits by plane: a plane p contributes X(p) = (A_x l)(p) and
+// E(p) = [(W_xy l)(j+1) - (W_xy l)(j-1)] + [(W_xz l)(k+1) - (W_xz l)(k-1)] to both cells that sit
+// on top of and below it with opposite signs of E, so each is computed once and reused two planes
+// later. Order of the sums differs from adj_offdiag (rounding only).
+struct AdjSweepArgs {
+  const double* lam_in;     // old lambda, both colours, stored with offset mu
+  const double* red_new;    // black pass: the new red values (no offset); red pass: unused
+  double* out;              // receives the new values of the swept colour
+  const double* rhs;
+  const double* coef;
+  int n;
+  double h2;
+  const double* mu_sum;     // mu = (mu_sum[0] + mu_sum[1]) * mu_scale
+  double mu_scale;
+  double* sum_out;          // sum of the new values
+  const double* copy_from;  // last block copies *copy_from to *copy_to (if copy_to)
+  double* copy_to;
+  Reduce red;
+};
+
+// PFC: coefficients of step t + 1 are loaded at the end of step t (in flight across the barrier),
+// else at the start of their own step (fewer registers, higher occupancy).
+template <int TM, int TJ, int COL, bool PFC>
+__global__ void __launch_bounds__(TM * TJ) adj_half_sweep_pipe(AdjSweepArgs a, int tiles_m, int tiles_j, int ci) {
+  constexpr int NT = TM * TJ;
+  constexpr int RW = TM + 2, RH = TJ + 2;
+  constexpr int SLOT = RH * RW;
+  constexpr int NPC = (SLOT + NT - 1) / NT;   // loader elements per thread and colour
+  constexpr int O = 1 - COL;
+  __shared__ double lds[2 * 4 * SLOT];
+  const int n = a.n, nh = n >> 1;
+  const double h2 = a.h2;
+  const int tid = threadIdx.x;
+  const int logical = xcd_remap(blockIdx.x, gridDim.x);
+  const int m0 = (logical % tiles_m) * TM;
+  const int j0 = ((logical / tiles_m) % tiles_j) * TJ;
+  const int i0 = (logical / (tiles_m * tiles_j)) * ci;
+  const size_t plane = (size_t)n * nh;
+  const size_t half = plane * n;
+  const double mu = a.mu_sum ? (a.mu_sum[0] + a.mu_sum[1]) * a.mu_scale : 0.0;
+  // colour-0 values: the new red values in the black pass (no offset), else the old ones
+  const double* __restrict__ src0 = COL == 1 ? a.red_new : a.lam_in;
+  const double* __restrict__ src1 = a.lam_in + half;
+  const double mu0 = COL == 1 ? 0.0 : mu;
+
+  // loader: element e of a slot is halo-tile row e / RW, column e % RW (same for both colours);
+  // byte offsets inside a plane, out-of-range elements clamped onto the last one
+  unsigned gb[NPC];
+  int le[NPC];
+#pragma unroll
+  for (int t = 0; t < NPC; ++t) {
+    int e = tid + t * NT;
+    e = e < SLOT ? e : SLOT - 1;
+    const int r = e / RW;
+    const int c = e - r * RW;
+    gb[t] = ((unsigned)wrapi(j0 - 1 + r, n) * nh + (unsigned)wrapi(m0 - 1 + c, nh)) * 8u;
+    le[t] = e;
+  }
+  // every global access goes through a buffer resource of one plane (uniform) and a per-lane
+  // byte offset inside it
+  const unsigned pbytes = (unsigned)plane * 8u;
+  auto prs = [&](const double* arr, int p) { return plane_rsrc(arr + (size_t)p * plane, pbytes); };
+  auto fetch = [&](int rel, double (&v)[2][NPC]) {
+    const int p = wrapi(i0 - 1 + rel, n);
+    const auto b0 = prs(src0, p), b1 = prs(src1, p);
+#pragma unroll
+    for (int t = 0; t < NPC; ++t) {
+      v[0][t] = ld_rs(b0, gb[t]);
+      v[1][t] = ld_rs(b1, gb[t]);
+    }
+  };
+  auto store = [&](int slot, const double (&v)[2][NPC]) {
+#pragma unroll
+    for (int t = 0; t < NPC; ++t) {
+      lds[le[t] + slot * SLOT] = v[0][t] - mu0;
+      lds[le[t] + (4 + slot) * SLOT] = v[1][t] - mu;
+    }
+  };
+
+  const int s = tid % TM, r = tid / TM;
+  const int j = j0 + r, m = m0 + s;
+  const unsigned rc = (unsigned)j * nh, rm = (unsigned)wrapi(j - 1, n) * nh, rp = (unsigned)wrapi(j + 1, n) * nh;
+  const int q0 = (i0 + j + COL) & 1;   // z-parity of the own cell at even steps
+  // byte offsets inside a plane: own cell, rows j -+ 1, and the k +- 1 columns at even (index 0)
+  // and odd (index 1) steps
+  const unsigned zp[2] = {(unsigned)wrapi(m + q0, nh), (unsigned)wrapi(m + (q0 ^ 1), nh)};
+  const unsigned zm[2] = {(unsigned)wrapi(m + q0 - 1, nh), (unsigned)wrapi(m + (q0 ^ 1) - 1, nh)};
+  const unsigned o_c = (rc + m) * 8u, o_ym = (rm + m) * 8u, o_yp = (rp + m) * 8u;
+  unsigned o_zp[2], o_zm[2], o_pp[2], o_mm[2], o_pm[2], o_mp[2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    o_zp[b] = (rc + zp[b]) * 8u;
+    o_zm[b] = (rc + zm[b]) * 8u;
+    o_pp[b] = (rp + zp[b]) * 8u;
+    o_mm[b] = (rm + zm[b]) * 8u;
+    o_pm[b] = (rp + zm[b]) * 8u;
+    o_mp[b] = (rm + zp[b]) * 8u;
+  }
+  const int ob = (r + 1) * RW + (s + 1);
+  const int oq0 = ob + q0, oq1 = ob + (q0 ^ 1);
+  const size_t cells = half * 2;
+  const double* __restrict__ cAx = a.coef + 0 * cells + O * half;
+  const double* __restrict__ cAy = a.coef + 1 * cells + O * half;
+  const double* __restrict__ cAz = a.coef + 2 * cells + O * half;
+  const double* __restrict__ cWxy = a.coef + 3 * cells + COL * half;
+  const double* __restrict__ cWxz = a.coef + 4 * cells + COL * half;
+  const double* __restrict__ cWyz = a.coef + 5 * cells + COL * half;
+  const double* __restrict__ rh = a.rhs + COL * half;
+  double* __restrict__ out = a.out + COL * half;
+  const int last_plane = n - 1;
+  const double* __restrict__ lo_all = lds + O * 4 * SLOT;
+  const double* __restrict__ lc_all = lds + COL * 4 * SLOT;
+
+  // coefficients of one step: x-part on plane i+1, in-plane part on plane i
+  struct Coef {
+    double ax, wxyp, wxym, wxzp, wxzm;
+    double aym, ayp, azm, azp, wpp, wmm, wpm, wmp;
+  };
+  auto load_x = [&](Coef& c, int p, int b) {
+    const auto rx = prs(cAx, p), rxy = prs(cWxy, p), rxz = prs(cWxz, p);
+    c.ax = ld_rs(rx, o_c);
+    c.wxyp = ld_rs(rxy, o_yp);
+    c.wxym = ld_rs(rxy, o_ym);
+    c.wxzp = ld_rs(rxz, o_zp[b]);
+    c.wxzm = ld_rs(rxz, o_zm[b]);
+  };
+  auto load_in = [&](Coef& c, int p, int b) {
+    const auto ry = prs(cAy, p), rz = prs(cAz, p), ryz = prs(cWyz, p);
+    c.aym = ld_rs(ry, o_ym);
+    c.ayp = ld_rs(ry, o_yp);
+    c.azm = ld_rs(rz, o_zm[b]);
+    c.azp = ld_rs(rz, o_zp[b]);
+    c.wpp = ld_rs(ryz, o_pp[b]);
+    c.wmm = ld_rs(ryz, o_mm[b]);
+    c.wpm = ld_rs(ryz, o_pm[b]);
+    c.wmp = ld_rs(ryz, o_mp[b]);
+  };
+  auto wrapp = [&](int p) { return p >= n ? p - n : (p < 0 ? p + n : p); };
+  // X and E of the plane held in LDS slot sl, for cells whose z-parity index is b
+  auto xe = [&](const Coef& c, int sl, int b, double& X, double& E) {
+    const int oq = b ? oq1 : oq0;
+    const double* __restrict__ lo = lo_all + sl * SLOT;
+    const double* __restrict__ lc = lc_all + sl * SLOT;
+    X = c.ax * lo[ob];
+    E = (c.wxyp * lc[ob + RW] - c.wxym * lc[ob - RW]) + (c.wxzp * lc[oq] - c.wxzm * lc[oq - 1]);
+  };
+
+  double V0[2][NPC], V1[2][NPC];
+  double Rv[4];
+  double Xr[2], Er[2];
+  Coef cf;
+  {
+    double va[2][NPC], vb[2][NPC], vc[2][NPC];
+    fetch(0, va);
+    fetch(1, vb);
+    fetch(2, vc);
+    store(0, va);
+    store(1, vb);
+    store(2, vc);
+  }
+  fetch(3, V0);
+  Rv[0] = ld_rs(prs(rh, i0), o_c);
+  Rv[1] = ld_rs(prs(rh, min(i0 + 1, last_plane)), o_c);
+  {
+    Coef pa, pb;
+    load_x(pa, wrapp(i0 - 1), 0);
+    load_x(pb, i0, 1);
+    if (PFC) {
+      load_x(cf, wrapp(i0 + 1), 0);
+      load_in(cf, i0, 0);
+    }
+    __syncthreads();
+    xe(pa, 0, 0, Xr[0], Er[0]);
+    xe(pb, 1, 1, Xr[1], Er[1]);
+  }
+  double acc = 0.0;
+
+  // step t (K = t & 3): plane i = i0 + t sits in slot (K + 1) & 3, plane i + 1 in (K + 2) & 3
+  auto step = [&](auto kc, int t, double (&vst)[2][NPC], double (&vft)[2][NPC]) {
+    constexpr int K = decltype(kc)::value;
+    constexpr int S0 = (K + 1) & 3, SP = (K + 2) & 3, SN = (K + 3) & 3;
+    constexpr int B = K & 1;
+    fetch(t + 4, vft);
+    Rv[(K + 2) & 3] = ld_rs(prs(rh, min(i0 + t + 2, last_plane)), o_c);
+    if (!PFC) {
+      load_x(cf, wrapp(i0 + t + 1), B);
+      load_in(cf, i0 + t, B);
+    }
+    double Xp, Ep;
+    xe(cf, SP, B, Xp, Ep);
+    const int oq = B ? oq1 : oq0;
+    const double* __restrict__ lo = lo_all + S0 * SLOT;
+    const double* __restrict__ lc = lc_all + S0 * SLOT;
+    const double P = (cf.aym * lo[ob - RW] + cf.ayp * lo[ob + RW]) + (cf.azm * lo[oq - 1] + cf.azp * lo[oq]);
+    const double dyz = (cf.wpp * lc[oq + RW] + cf.wmm * lc[oq - RW - 1]) - (cf.wpm * lc[oq + RW - 1] + cf.wmp * lc[oq - RW]);
+    const double off = (Xr[B] + Xp) + P - 0.5 * ((Ep - Er[B]) + dyz);
+    Xr[B] = Xp;
+    Er[B] = Ep;
+    const double v = (off - h2 * Rv[K]) * (1.0 / 6.0);
+    st_rs(prs(out, i0 + t), o_c, v);
+    acc += v;
+    if (PFC) {
+      const int ip = i0 + t + 1;
+      load_x(cf, wrapp(ip + 1), B ^ 1);
+      load_in(cf, min(ip, last_plane), B ^ 1);
+    }
+    store(SN, vst);
+    __syncthreads();
+  };
+  for (int t = 0; t < ci; t += 4) {
+    step(std::integral_constant<int, 0>(), t, V0, V1);
+    step(std::integral_constant<int, 1>(), t + 1, V1, V0);
+    step(std::integral_constant<int, 2>(), t + 2, V0, V1);
+    step(std::integral_constant<int, 3>(), t + 3, V1, V0);
+  }
+
+  double vv[1] = {acc};
+  const bool last = grid_sum<1>(vv, a.red.partials, a.red.counter, a.sum_out, gridDim.x, blockIdx.x);
+  if (last && tid == 0 && a.copy_to) *a.copy_to = *a.copy_from;
 }
 
 // res = rhs - J^T l on the fine mesh and rhs_c = R res; sums res^2 (the level's residual norm).
@@ -271,6 +505,141 @@ static int lin_blocks_a(size_t cells) {
   return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
 }
 
+// ---- half-sweep launch and tile choice ----------------------------------------------------
+
+#define MR_AP_TILES(X) X(64, 4) X(64, 8) X(32, 8) X(16, 16) X(8, 16) X(8, 8) X(4, 8)
+
+struct AdjCfg {
+  int tm = 0, tj = 0, ci = 0;   // tm == 0: the row kernel
+  bool pfc = false;
+};
+
+static hipError_t launch_adj_half(const AdjSweepArgs& a, int colour, const AdjCfg& c, hipStream_t s) {
+  if (colour == 1 && !a.red_new) return hipErrorInvalidValue;
+  if (c.tm == 0) {
+    hipLaunchKernelGGL(adj_half_sweep_kernel, dim3(rows_blocks_a(a.n)), dim3(row_threads_a(a.n / 2)), 0, s, a.lam_in,
+                       colour == 1 ? a.red_new : (const double*)nullptr, a.out, a.rhs, a.coef, a.n, colour, a.h2,
+                       a.mu_sum, a.mu_scale, a.sum_out, a.copy_from, a.copy_to, a.red);
+    return hipGetLastError();
+  }
+  const int nh = a.n / 2;
+  if (c.tj > a.n || nh % c.tm != 0 || a.n % c.tj != 0 || c.ci % 4 != 0 || a.n % c.ci != 0) return hipErrorInvalidValue;
+  const int tiles_m = nh / c.tm, tiles_j = a.n / c.tj;
+  const long blocks = (long)tiles_m * tiles_j * (a.n / c.ci);
+  if (blocks < 1 || blocks > kMaxReduceBlocks) return hipErrorInvalidValue;
+#define MR_AP_GO(TM, TJ, COL, PFC) \
+  hipLaunchKernelGGL((adj_half_sweep_pipe<TM, TJ, COL, PFC>), dim3(blocks), dim3(TM * TJ), 0, s, a, tiles_m, tiles_j, c.ci)
+#define MR_AP_LAUNCH(TM, TJ)                         \
+  if (c.tm == TM && c.tj == TJ) {                    \
+    if (colour == 0 && c.pfc)                        \
+      MR_AP_GO(TM, TJ, 0, true);                     \
+    else if (colour == 0)                            \
+      MR_AP_GO(TM, TJ, 0, false);                    \
+    else if (c.pfc)                                  \
+      MR_AP_GO(TM, TJ, 1, true);                     \
+    else                                             \
+      MR_AP_GO(TM, TJ, 1, false);                    \
+    return hipGetLastError();                        \
+  }
+  MR_AP_TILES(MR_AP_LAUNCH)
+#undef MR_AP_LAUNCH
+#undef MR_AP_GO
+  return hipErrorInvalidValue;
+}
+
+// The tiled schedule without timing: the first compiled tile that fits, chunks of 8 planes (4 on
+// meshes that 8 does not divide), the coefficient prefetch on even levels (so one solve runs both
+// load schedules). tm == 0 if none fits.
+static AdjCfg fixed_tiled_cfg(int n, int level) {
+  const int nh = n / 2;
+  AdjCfg c;
+  c.pfc = level % 2 == 0;
+  auto take = [&](int tm, int tj) {
+    if (c.tm != 0 || nh % tm != 0 || n % tj != 0 || tj > n) return;
+    const int ci = n % 8 == 0 ? 8 : 4;
+    if (n % ci != 0 || (long)(nh / tm) * (n / tj) * (n / ci) > kMaxReduceBlocks) return;
+    c.tm = tm;
+    c.tj = tj;
+    c.ci = ci;
+  };
+#define MR_AP_TAKE(TM, TJ) take(TM, TJ);
+  MR_AP_TILES(MR_AP_TAKE)
+#undef MR_AP_TAKE
+  return c;
+}
+
+static std::mutex g_adj_tune_mu;
+static std::map<std::pair<int, int>, AdjCfg> g_adj_tuned;   // (device, n)
+
+// Times both colours of a sweep for the row kernel and every compiled tile with chunks of 8 to
+// 256 planes (with and without the coefficient prefetch), on the level's own (zeroed) buffers, and keeps the fastest. Cached per (device, n).
+static int tune_adj_sweep(const AdjSweepArgs& base, hipStream_t s, AdjCfg* out) {
+  const int n = base.n, nh = n / 2;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return hip_fail(hipErrorInvalidDevice, "adjoint tuner");
+  {
+    std::lock_guard<std::mutex> lk(g_adj_tune_mu);
+    auto it = g_adj_tuned.find({dev, n});
+    if (it != g_adj_tuned.end()) {
+      *out = it->second;
+      return MR_OK;
+    }
+  }
+  std::vector<AdjCfg> cand{AdjCfg{}};
+  auto add = [&](int tm, int tj) {
+    if (nh % tm != 0 || n % tj != 0 || tj > n) return;
+    const long tiles = (long)(nh / tm) * (n / tj);
+    for (int ci = 8; ci <= 256 && ci <= n; ci *= 2) {
+      if (n % ci != 0 || tiles * (n / ci) > kMaxReduceBlocks) continue;
+      for (int pf = 0; pf < 2; ++pf) {
+        AdjCfg c;
+        c.tm = tm;
+        c.tj = tj;
+        c.ci = ci;
+        c.pfc = pf != 0;
+        cand.push_back(c);
+      }
+    }
+  };
+#define MR_AP_ADD(TM, TJ) add(TM, TJ);
+  MR_AP_TILES(MR_AP_ADD)
+#undef MR_AP_ADD
+  hipEvent_t ea = nullptr, eb = nullptr;
+  hipError_t e = hipEventCreate(&ea);
+  if (e == hipSuccess) e = hipEventCreate(&eb);
+  const size_t cells = (size_t)n * n * n;
+  const int reps = cells >= ((size_t)1 << 24) ? 2 : 4;
+  auto run = [&](const AdjCfg& c) {
+    hipError_t r = launch_adj_half(base, 0, c, s);
+    return r == hipSuccess ? launch_adj_half(base, 1, c, s) : r;
+  };
+  float best = 3.0e38f;
+  AdjCfg best_c;
+  for (const AdjCfg& c : cand) {
+    if (e != hipSuccess) break;
+    e = run(c);   // warm-up
+    if (e == hipSuccess) e = hipEventRecord(ea, s);
+    for (int k = 0; k < reps && e == hipSuccess; ++k) e = run(c);
+    if (e == hipSuccess) e = hipEventRecord(eb, s);
+    if (e == hipSuccess) e = hipEventSynchronize(eb);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ea, eb);
+    if (e == hipSuccess && ms < best) {
+      best = ms;
+      best_c = c;
+    }
+  }
+  if (ea) (void)hipEventDestroy(ea);
+  if (eb) (void)hipEventDestroy(eb);
+  if (e != hipSuccess) return hip_fail(e, "adjoint tuner");
+  {
+    std::lock_guard<std::mutex> lk(g_adj_tune_mu);
+    g_adj_tuned[{dev, n}] = best_c;
+  }
+  *out = best_c;
+  return MR_OK;
+}
+
 static int adjoint_alloc(Ctx* c) {
   if (c->adj) return MR_OK;
   AdjointState* a = new AdjointState();
@@ -290,7 +659,34 @@ static int adjoint_alloc(Ctx* c) {
         (rc = get(&L.rhs, cells)) != MR_OK || (rc = get(&L.coef, 6 * cells)) != MR_OK)
       return rc;
   }
-  return get(&a->D, c->lv[0].cells);
+  if ((rc = get(&a->D, c->lv[0].cells)) != MR_OK) return rc;
+  // half-sweep schedule per level, timed on the level's zeroed buffers
+  for (int l = 0; l + 1 < c->nlev; ++l) {
+    AdjLevel& L = a->lv[l];
+    const size_t cells = c->lv[l].cells;
+    hipError_t e = hipMemsetAsync(L.lam[0], 0, cells * sizeof(double), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(L.lam[1], 0, cells * sizeof(double), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(L.rhs, 0, cells * sizeof(double), c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(L.coef, 0, 6 * cells * sizeof(double), c->stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint tuner");
+    AdjSweepArgs t{};
+    t.lam_in = L.lam[0];
+    t.red_new = L.lam[1];
+    t.out = L.lam[1];
+    t.rhs = L.rhs;
+    t.coef = L.coef;
+    t.n = c->lv[l].n;
+    t.h2 = 1.0;
+    t.sum_out = c->scal + kSlotAux;
+    t.red = c->reducer(kSlotAux);
+    AdjCfg cfg;
+    if ((rc = tune_adj_sweep(t, c->stream, &cfg)) != MR_OK) return rc;
+    L.tm = cfg.tm;
+    L.tj = cfg.tj;
+    L.ci = cfg.ci;
+    L.pfc = cfg.pfc;
+  }
+  return MR_OK;
 }
 
 void Ctx::release_adjoint() {
@@ -305,13 +701,32 @@ int Ctx::adj_sweep(int l) {
   Level& F = lv[l];
   double* ms = linsum(l);
   const double scale = 1.0 / (double)F.cells;
-  hipLaunchKernelGGL(adj_half_sweep_kernel, dim3(rows_blocks_a(F.n)), dim3(row_threads_a(F.n / 2)), 0, stream,
-                     A.lam[A.cur], (const double*)nullptr, A.lam[A.cur ^ 1], A.rhs, A.coef, F.n, 0, F.h * F.h, ms, scale,
-                     ms + 2, (const double*)nullptr, (double*)nullptr, reducer(kSlotAux));
-  hipLaunchKernelGGL(adj_half_sweep_kernel, dim3(rows_blocks_a(F.n)), dim3(row_threads_a(F.n / 2)), 0, stream,
-                     A.lam[A.cur], A.lam[A.cur ^ 1], A.lam[A.cur ^ 1], A.rhs, A.coef, F.n, 1, F.h * F.h, ms, scale,
-                     ms + 1, ms + 2, ms + 0, reducer(kSlotAux));
-  hipError_t e = hipGetLastError();
+  AdjCfg cfg;
+  if (opts.flags & MR_FLAG_ADJ_TILED) {
+    cfg = fixed_tiled_cfg(F.n, l);
+  } else if (!(opts.flags & MR_FLAG_ADJ_ROWS)) {
+    cfg.tm = A.tm;
+    cfg.tj = A.tj;
+    cfg.ci = A.ci;
+    cfg.pfc = A.pfc;
+  }
+  AdjSweepArgs a{};
+  a.lam_in = A.lam[A.cur];
+  a.red_new = A.lam[A.cur ^ 1];
+  a.out = A.lam[A.cur ^ 1];
+  a.rhs = A.rhs;
+  a.coef = A.coef;
+  a.n = F.n;
+  a.h2 = F.h * F.h;
+  a.mu_sum = ms;
+  a.mu_scale = scale;
+  a.red = reducer(kSlotAux);
+  a.sum_out = ms + 2;   // red: its sum parks in the third slot
+  hipError_t e = launch_adj_half(a, 0, cfg, stream);
+  a.sum_out = ms + 1;   // black: then the red sum moves to the first slot
+  a.copy_from = ms + 2;
+  a.copy_to = ms + 0;
+  if (e == hipSuccess) e = launch_adj_half(a, 1, cfg, stream);
   if (e != hipSuccess) return hip_fail(e, "adjoint sweep");
   A.cur ^= 1;
   return MR_OK;

@@ -52,7 +52,8 @@ int check_opts(const mr_opts& o) {
   if (!(o.tol >= 0.0) || o.max_cycles < 1 || o.max_cycles > 127 || o.npre < 0 || o.npost < 0 ||
       o.npre + o.npost < 1 || o.ncoarse < 1 ||
       (o.precision != MR_PREC_FP64 && o.precision != MR_PREC_MIXED) || o.inner_cycles < 1 ||
-      o.inner_cycles > 8 || (o.flags & ~(MR_FLAG_EAGER | MR_FLAG_TWO_PASS)) != 0)
+      o.inner_cycles > 8 || (o.flags & ~(MR_FLAG_EAGER | MR_FLAG_TWO_PASS | MR_FLAG_ADJ_ROWS | MR_FLAG_ADJ_TILED)) != 0 ||
+      (o.flags & MR_FLAG_ADJ_ROWS && o.flags & MR_FLAG_ADJ_TILED))
     return fail(MR_EINVAL, "invalid options");
   return MR_OK;
 }

@@ -234,6 +234,21 @@ __device__ bool grid_sum(double (&v)[NV], double* __restrict__ partials, unsigne
 
 // Map a launch-order block index to a logical tile index so that each of the 8 XCDs (which
 // receive blocks round-robin) works on one contiguous range of tiles and shares halos in its L2.
+// Raw buffer access to one plane: a resource built from a wave-uniform base pointer (scalar
+// registers) and a per-lane 32-bit byte offset. This keeps per-lane address arithmetic at 32 bits
+// where the loop optimiser would otherwise materialise 64-bit addresses per load. Offsets at or
+// beyond `bytes` read 0 and drop stores (the hardware range check), never fault.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const double* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ double ld_rs(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, 0));
+}
+__device__ __forceinline__ void st_rs(__amdgpu_buffer_rsrc_t r, unsigned byte_off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v),
+                                       r, (int)byte_off, 0, 0);
+}
+
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
   if ((nb & 7) != 0) return b;
   return (b & 7) * (nb >> 3) + (b >> 3);

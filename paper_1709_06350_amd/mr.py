@@ -25,6 +25,8 @@ MR_EHIP = -4
 MR_ENOMEM = -5
 MR_FLAG_EAGER = 1
 MR_FLAG_TWO_PASS = 2
+MR_FLAG_ADJ_ROWS = 4
+MR_FLAG_ADJ_TILED = 8
 PREC_FP64 = 0
 PREC_MIXED = 1
 
@@ -201,11 +203,6 @@ class Context:
     @property
     def levels(self) -> int:
         return self.lib.mr_levels(self.h)
-
-    def set_opts(self, **kw):
-        for k, v in kw.items():
-            setattr(self.opts, k, v)
-        _check(self.lib.mr_set_opts(self.h, ctypes.byref(self.opts)))
 
     def _empty(self, n=None):
         n = self.n if n is None else n

@@ -5,6 +5,8 @@ Tolerances: <= 1e-8 relative L2 against the oracle adjoint (both solve the same 
 to ~1e-12); <= 1e-4 relative per cell against central differences (truncation O(eps^2) plus the
 forward solves' residual floor).
 """
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -29,20 +31,54 @@ def spectral_loss_torch(theta, theta_t, cells=4.0):
     return (W * (d.real ** 2 + d.imag ** 2)).sum()
 
 
-@pytest.mark.parametrize("n", [8, 16])
-def test_adjoint_matches_oracle_direct(n):
-    require_gpu()
-    announce(f"adjoint vs oracle n={n}")
+@functools.lru_cache(maxsize=None)
+def _oracle_case(n):
     delta = inputs.lognormal(n, 0.7, 2.0, 40 + n)
     theta = omg.solve(delta, tol=1e-14, max_cycles=100)[0]
     g = np.random.default_rng(n).standard_normal(delta.shape)
     ref, _ = olin.adjoint_gradient(theta, delta, g)
-    with mr.Context(n, tol=1e-13) as c:
+    return delta, theta, g, ref
+
+
+# flags 0: the per-level timed kernel choice; ADJ_TILED: the tiled plane-marching kernel wherever a
+# tile fits (both coefficient load schedules, alternating by level); ADJ_ROWS: the row kernel.
+# 24^3 has a 4 x 8 tile on its finest level and a row-kernel coarse level (12^3).
+@pytest.mark.parametrize("n,flags", [(8, 0), (16, 0), (16, mr.MR_FLAG_ADJ_TILED), (16, mr.MR_FLAG_ADJ_ROWS),
+                                     (24, mr.MR_FLAG_ADJ_TILED)])
+def test_adjoint_matches_oracle_direct(n, flags):
+    require_gpu()
+    announce(f"adjoint vs oracle n={n} flags={flags}")
+    delta, theta, g, ref = _oracle_case(n)
+    with mr.Context(n, tol=1e-13, flags=flags) as c:
         got, info = c.adjoint_solve(dev(delta), dev(theta), dev(g))
     got = host(got)
     err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
-    print(f"adjoint n={n}: cycles={info.cycles} rel L2 err={err:.3e}")
+    print(f"adjoint n={n} flags={flags}: cycles={info.cycles} rel L2 err={err:.3e}")
     assert info.status == 0 and err <= 1e-8
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_adjoint_tiled_matches_rows(n):
+    """The tiled and the row half-sweeps on meshes with several tiles and chunks per level: both
+    solve J^T l = g - <g> to 1e-12, so the gradients agree to that level (rounding order differs)."""
+    require_gpu()
+    announce(f"adjoint tiled vs rows n={n}")
+    delta = dev(inputs.lognormal(n, 0.8, 3.0, 70 + n))
+    with mr.Context(n, tol=1e-12) as c:
+        theta = torch.zeros_like(delta)
+        c.solve(delta, theta)
+        g = torch.randn(delta.shape, dtype=torch.float64, generator=torch.Generator().manual_seed(n)).to(delta.device)
+        out = {}
+        for flags in (mr.MR_FLAG_ADJ_ROWS, mr.MR_FLAG_ADJ_TILED, 0):
+            c.set_opts(flags=flags)
+            got, info = c.adjoint_solve(delta, theta, g)
+            assert info.status == 0, flags
+            out[flags] = host(got)
+    ref = out[mr.MR_FLAG_ADJ_ROWS]
+    for flags in (mr.MR_FLAG_ADJ_TILED, 0):
+        err = np.linalg.norm(out[flags] - ref) / np.linalg.norm(ref)
+        print(f"n={n} flags={flags}: rel L2 vs rows {err:.3e}")
+        assert err <= 1e-9, flags
 
 
 def test_autograd_matches_oracle_gradient():

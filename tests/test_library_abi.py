@@ -89,3 +89,15 @@ def test_struct_layouts_match_the_header(tmp_path):
     assert so == ctypes.sizeof(mr.mr_opts) and of == mr.mr_opts.flags.offset
     assert si == ctypes.sizeof(mr.mr_info) and oh == mr.mr_info.history.offset
     assert st == ctypes.sizeof(mr.mr_timing) and ofc == mr.mr_timing.finest_cells.offset
+
+
+def test_binding_constants_match_the_header_enums():
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    enums = {}
+    for body in re.findall(r"enum\s*\{(.*?)\}", text, flags=re.S):
+        for name, val in re.findall(r"(MR_\w+)\s*=\s*(-?\d+)", body):
+            enums[name] = int(val)
+    assert enums, "no enum constants found in the header"
+    for name, val in enums.items():
+        py = name if hasattr(mr, name) else name[len("MR_"):]
+        assert getattr(mr, py) == val, name
