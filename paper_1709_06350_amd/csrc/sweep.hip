@@ -258,48 +258,73 @@ __global__ void __launch_bounds__(TM * TJ) half_sweep_pipe(HalfSweepArgs a) {
   int j0, m0, i0;
   tile_coords(gridDim.x, a.tiles_m, a.tiles_j, TJ, TM, a.ci, j0, m0, i0);
   const int ci = a.ci;
-  const unsigned half = (unsigned)n * (unsigned)n * (unsigned)nh;
-  const unsigned plane = (unsigned)n * (unsigned)nh;
+  const size_t plane = (size_t)n * nh;
+  const size_t half = plane * n;
+  const unsigned pbytes = (unsigned)plane * 8u;
   const double* __restrict__ src0 = COL == 1 ? a.th_red_new : a.th_in;   // colour 0 values
   const double* __restrict__ src1 = a.th_in + half;                      // colour 1 values
+  // every global access goes through a buffer resource of one plane (uniform) and a per-lane
+  // byte offset inside it
+  auto prs = [&](const double* arr, int p) { return plane_rsrc(arr + (size_t)p * plane, pbytes); };
 
-  unsigned goff[NPF];
-  int loff[NPF];
+  // loader. SPLIT (when it costs no extra elements): elements 0 .. NPC-1 of a thread cover colour 0,
+  // NPC .. 2 NPC-1 colour 1, each over the slot's SLOT cells. Otherwise element t covers
+  // e = tid + t NT of the two slots together (colour e / SLOT), whose colour is per lane only
+  // where the block's range of t straddles the colour boundary. Out-of-range elements are clamped
+  // onto the last one (duplicate stores of the same value).
+  constexpr int NPC = (SLOT + NT - 1) / NT;
+  constexpr bool SPLIT = 2 * NPC == NPF;
+  unsigned gb[NPF];
+  int le[NPF];
   bool col1[NPF];
 #pragma unroll
   for (int t = 0; t < NPF; ++t) {
-    int e = tid + t * NT;
-    e = e < TOTAL ? e : TOTAL - 1;
-    const int cc = e / SLOT;
-    const int rem = e - cc * SLOT;
+    int cc, rem;
+    if (SPLIT) {
+      cc = t / NPC;
+      const int e = tid + (t - cc * NPC) * NT;
+      rem = e < SLOT ? e : SLOT - 1;
+    } else {
+      int e = tid + t * NT;
+      e = e < TOTAL ? e : TOTAL - 1;
+      cc = e / SLOT;
+      rem = e - cc * SLOT;
+    }
     const int r = rem / RW;
     const int c = rem - r * RW;
-    goff[t] = (unsigned)wrapi(j0 - 1 + r, n) * nh + (unsigned)wrapi(m0 - 1 + c, nh);
-    loff[t] = cc * 4 * SLOT + rem;
+    gb[t] = ((unsigned)wrapi(j0 - 1 + r, n) * nh + (unsigned)wrapi(m0 - 1 + c, nh)) * 8u;
+    le[t] = cc * 4 * SLOT + rem;
     col1[t] = cc != 0;
   }
   // plane i0 - 1 + rel sits in slot rel & 3
   auto fetch = [&](int rel, double (&v)[NPF]) {
-    const unsigned base = (unsigned)wrapi(i0 - 1 + rel, n) * plane;
+    const int p = wrapi(i0 - 1 + rel, n);
+    const auto b0 = prs(src0, p), b1 = prs(src1, p);
 #pragma unroll
-    for (int t = 0; t < NPF; ++t) v[t] = (col1[t] ? src1 : src0)[base + goff[t]];
+    for (int t = 0; t < NPF; ++t) {
+      if (SPLIT) v[t] = ld_rs(t < NPC ? b0 : b1, gb[t]);
+      else if ((t + 1) * NT <= SLOT) v[t] = ld_rs(b0, gb[t]);
+      else if (t * NT >= SLOT) v[t] = ld_rs(b1, gb[t]);
+      else if (col1[t]) v[t] = ld_rs(b1, gb[t]);
+      else v[t] = ld_rs(b0, gb[t]);
+    }
   };
   auto store = [&](int slot, const double (&v)[NPF]) {
 #pragma unroll
-    for (int t = 0; t < NPF; ++t) lds[loff[t] + slot * SLOT] = v[t];
+    for (int t = 0; t < NPF; ++t) lds[le[t] + slot * SLOT] = v[t];
   };
 
   const int s = tid % TM, r = tid / TM;
   const int j = j0 + r, m = m0 + s;
-  const unsigned own = (unsigned)j * nh + m;
+  const unsigned o_c = ((unsigned)j * nh + m) * 8u;      // own cell inside a plane (bytes)
   const int ob = (r + 1) * RW + (s + 1);                 // own cell inside a slot
   const int q0 = (i0 + j + COL) & 1;                     // z-parity at even t
   const int oq0 = ob + q0, oq1 = ob + (q0 ^ 1);
   const double C = (a.c_sum ? (a.c_sum[0] + a.c_sum[1]) * a.c_scale : 0.0) + a.c_add;
   const double h2 = a.h2, ih2 = a.ih2;
-  const double* __restrict__ dl = a.delta + COL * half + own;
-  const double* __restrict__ ff = HAS_F ? a.f + COL * half + own : nullptr;
-  double* __restrict__ out = a.th_out + COL * half + own;
+  const double* __restrict__ dl = a.delta + COL * half;
+  const double* __restrict__ ff = HAS_F ? a.f + COL * half : nullptr;
+  double* __restrict__ out = a.th_out + COL * half;
   const int last_plane = n - 1;
   double acc = 0.0;
 
@@ -315,11 +340,11 @@ __global__ void __launch_bounds__(TM * TJ) half_sweep_pipe(HalfSweepArgs a) {
     store(2, vc);
   }
   fetch(3, V0);
-  D[0] = dl[(unsigned)i0 * plane];
-  D[1] = dl[(unsigned)min(i0 + 1, last_plane) * plane];
+  D[0] = ld_rs(prs(dl, i0), o_c);
+  D[1] = ld_rs(prs(dl, min(i0 + 1, last_plane)), o_c);
   if (HAS_F) {
-    Fv[0] = ff[(unsigned)i0 * plane];
-    Fv[1] = ff[(unsigned)min(i0 + 1, last_plane) * plane];
+    Fv[0] = ld_rs(prs(ff, i0), o_c);
+    Fv[1] = ld_rs(prs(ff, min(i0 + 1, last_plane)), o_c);
   }
   __syncthreads();
 
@@ -328,9 +353,9 @@ __global__ void __launch_bounds__(TM * TJ) half_sweep_pipe(HalfSweepArgs a) {
     constexpr int K = decltype(kc)::value;
     constexpr int SM = (K + 0) & 3, S0 = (K + 1) & 3, SP = (K + 2) & 3, SN = (K + 3) & 3;
     fetch(t + 4, vft);
-    const unsigned pn = (unsigned)min(i0 + t + 2, last_plane) * plane;
-    D[(K + 2) & 3] = dl[pn];
-    if (HAS_F) Fv[(K + 2) & 3] = ff[pn];
+    const int pn = min(i0 + t + 2, last_plane);
+    D[(K + 2) & 3] = ld_rs(prs(dl, pn), o_c);
+    if (HAS_F) Fv[(K + 2) & 3] = ld_rs(prs(ff, pn), o_c);
     const int oq = (K & 1) ? oq1 : oq0;
     const double* __restrict__ lo = lds + O * 4 * SLOT;     // other colour
     const double* __restrict__ lc = lds + COL * 4 * SLOT;   // own colour
@@ -347,7 +372,7 @@ __global__ void __launch_bounds__(TM * TJ) half_sweep_pipe(HalfSweepArgs a) {
     const double fc = HAS_F ? Fv[K] : 0.0;
     double S;
     const double sig = sigma_cell(c, 1.0 + D[K], ih2, S);
-    out[(unsigned)(i0 + t) * plane] = (S - h2 * (sig + fc - C)) * (1.0 / 6.0);
+    st_rs(prs(out, i0 + t), o_c, (S - h2 * (sig + fc - C)) * (1.0 / 6.0));
     acc += sig + fc;
     store(SN, vst);
     __syncthreads();
@@ -1477,13 +1502,27 @@ int tune_sweep(int n, double* th_a, double* th_b, double* delta, double* partial
   float best = 3.0e38f;
   FusedCfg best_cfg;
   bool best_fused = false;
-  // two launches per sweep: the general kernel, and the pipelined one where it applies
+  // two launches per sweep: the general kernel, and the pipelined one on every compiled tile that
+  // fits, with chunks of 16 to 256 planes
   std::vector<TileCfg> twos{*two};
-  if (two->cpt == 1 && two->ci % 4 == 0 && half_sweep_pipe_supported(two->tm, two->tj)) {
-    TileCfg tp = *two;
-    tp.pipe = true;
-    twos.push_back(tp);
-  }
+  auto add_pipe = [&](int tm, int tj) {
+    if ((n / 2) % tm != 0 || n % tj != 0 || tj > n) return;
+    for (int ci = 16; ci <= 256 && ci <= n; ci *= 2) {
+      TileCfg tp;
+      tp.tm = tm;
+      tp.tj = tj;
+      tp.cpt = 1;
+      tp.ci = ci;
+      tp.tiles_j = n / tj;
+      tp.tiles_m = (n / 2) / tm;
+      tp.pipe = true;
+      const long blocks = (long)tp.tiles_j * tp.tiles_m * (n / ci);
+      if (n % ci == 0 && blocks <= kMaxReduceBlocks) twos.push_back(tp);
+    }
+  };
+#define MR_HP_ADD(TM, TJ) add_pipe(TM, TJ);
+  MR_HP_TILES(MR_HP_ADD)
+#undef MR_HP_ADD
   TileCfg best_two = *two;
   for (const TileCfg& tw : twos) {
     if (e != hipSuccess) break;
