@@ -397,37 +397,6 @@ __global__ void __launch_bounds__(256) adj_resid_restrict_kernel(const double* _
   grid_sum<2>(vv, red.partials, red.counter, red.result, gridDim.x, blockIdx.x);
 }
 
-// l += P(lc - mu_c) (trilinear; cell pair per thread as in the forward prolongation).
-__global__ void __launch_bounds__(512) adj_prolong_kernel(const double* __restrict__ lc, const double* mu_sum,
-                                                          double mu_scale, double* __restrict__ lam, int n) {
-  const int nh = n >> 1;
-  const int row = xcd_remap(blockIdx.x, gridDim.x);
-  const int i = row / n, j = row - i * n;
-  const int m = threadIdx.x;
-  if (m >= nh) return;
-  const double mu = mu_sum ? (mu_sum[0] + mu_sum[1]) * mu_scale : 0.0;
-  const int nc = n >> 1;
-  const int I = i >> 1, J = j >> 1, K = m;
-  const int I2 = wrapi((i & 1) ? I + 1 : I - 1, nc);
-  const int J2 = wrapi((j & 1) ? J + 1 : J - 1, nc);
-  const int Km = wrapi(K - 1, nc), Kp = wrapi(K + 1, nc);
-  const double wI[2] = {0.75, 0.25};
-  double lo = 0.0, hi = 0.0;
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int ii = (s & 2) ? I2 : I, jj = (s & 1) ? J2 : J;
-    const double w = wI[(s >> 1) & 1] * wI[s & 1];
-    const double ek = lc[split_idx(nc, ii, jj, K)] - mu;
-    lo += w * (0.75 * ek + 0.25 * (lc[split_idx(nc, ii, jj, Km)] - mu));
-    hi += w * (0.75 * ek + 0.25 * (lc[split_idx(nc, ii, jj, Kp)] - mu));
-  }
-  const unsigned half = (unsigned)n * (unsigned)n * (unsigned)nh;
-  const unsigned off = ((unsigned)i * n + j) * (unsigned)nh + m;
-  const int c0 = (i + j) & 1;
-  lam[c0 * half + off] += lo;
-  lam[(1 - c0) * half + off] += hi;
-}
-
 // Coarsest level: nsweeps projected red-black sweeps in one block (lambda and rhs in LDS,
 // coefficients from global memory). Writes the mean-free result and sets its offset to 0.
 __global__ void __launch_bounds__(256) adj_coarsest_kernel(double* __restrict__ lam, const double* __restrict__ rhs,
@@ -763,9 +732,10 @@ int Ctx::adj_vcycle(int l, double* norm2) {
     if (adj_last_norm <= adj_stop) return MR_OK;
   }
   if ((rc = adj_vcycle(l + 1, nullptr)) != MR_OK) return rc;
-  hipLaunchKernelGGL(adj_prolong_kernel, dim3((unsigned)F.n * F.n), dim3(F.n / 2), 0, stream, Ac.lam[Ac.cur], linsum(l + 1),
-                     1.0 / (double)Fc.cells, A.lam[A.cur], F.n);
-  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "adjoint prolongation");
+  // l += P(lc - mu_c)
+  if ((e = launch_prolong_add(Ac.lam[Ac.cur], linsum(l + 1), 1.0 / (double)Fc.cells, A.lam[A.cur], F.n, stream)) !=
+      hipSuccess)
+    return hip_fail(e, "adjoint prolongation");
   for (int s = 0; s < opts.npost; ++s)
     if ((rc = adj_sweep(l)) != MR_OK) return rc;
   return MR_OK;

@@ -280,7 +280,8 @@ inline __device__ void lin_resid_restrict_body(const float* __restrict__ e, cons
   double vv[2] = {acc, 0.0};
   grid_sum<2>(vv, red.partials, red.counter, red.result, nblocks, bid);
 }
-// e += P(ec) (trilinear, cell pair per thread; see prolong_correct_kernel).
+// e += P(ec) (trilinear: 3/4 of the coarse parent and 1/4 of the neighbour towards the fine cell in
+// each direction; a thread per fine cell pair k = 2m, 2m + 1).
 inline __device__ void prolong_add32_row(const float* __restrict__ ec, float* __restrict__ e, int n, int row, int m) {
   const int nh = n >> 1;
   const int i = row / n, j = row - i * n;

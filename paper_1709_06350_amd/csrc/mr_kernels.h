@@ -157,6 +157,9 @@ hipError_t launch_tau_pipe(const double* th, const double* delta, const double* 
                            Reduce red, hipStream_t s, bool* done);
 // theta += P(tc - that) from the (n/2)^3 mesh onto the n^3 mesh; that is overwritten with tc - that.
 hipError_t launch_prolong_correct(const double* tc, double* that, double* theta, int n, hipStream_t s);
+// theta += P(ec - mu) on the fine mesh n (mu = (mu_sum[0] + mu_sum[1]) * mu_scale, 0 if mu_sum is null)
+hipError_t launch_prolong_add(const double* ec, const double* mu_sum, double mu_scale, double* theta, int n,
+                              hipStream_t s);
 // coarse = 8-son mean of fine (fine n^3).
 hipError_t launch_restrict(const double* fine, double* coarse, int n, hipStream_t s);
 // b = nabla^2 theta - Sigma + shift (theta == null means theta = 0); result[0] = sum b,

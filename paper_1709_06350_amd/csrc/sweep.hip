@@ -1211,7 +1211,7 @@ static bool tile_ok(const TileCfg& t, int n, int threads) {
   X(64, 8, 2) X(64, 4, 1) X(64, 8, 1) X(64, 16, 4) X(32, 8, 1) X(32, 16, 2) X(16, 16, 1) \
   X(16, 32, 2) X(8, 16, 1) X(8, 8, 1) X(4, 8, 1) X(4, 16, 2) X(2, 4, 1) X(2, 8, 1)
 
-#define MR_HP_TILES(X) X(64, 8) X(64, 4) X(32, 8) X(32, 16) X(16, 16)
+#define MR_HP_TILES(X) X(64, 8) X(64, 4) X(64, 16) X(32, 8) X(32, 16) X(16, 16)
 
 bool half_sweep_tile_supported(int tm, int tj, int cpt) {
 #define MR_HS_MATCH(TM, TJ, CPT) if (tm == TM && tj == TJ && cpt == CPT) return true;

@@ -80,47 +80,78 @@ __global__ void __launch_bounds__(256) coarse_diff_kernel(const double* __restri
     that[e] = tc[e] - that[e];
 }
 
-// theta += P(ec) with ec = tc - that: trilinear between cell centres, 3/4 on the own coarse cell
-// and 1/4 on the neighbour on the side of the fine cell, per axis (Eq. 20). A thread owns the
-// cell pair k = 2m, 2m+1 of row (i, j), which share coarse column K = m; k = 2m takes its
-// k-neighbour at K - 1, k = 2m + 1 at K + 1. The two cells lie in the two colour halves at the
-// same offset.
-__device__ __forceinline__ void prolong_correct_row(const double* __restrict__ ec, double* __restrict__ theta, int n,
-                                                    int row, int m) {
-  const int nh = n >> 1;
-  const int i = row / n, j = row - i * n;
-  const int nc = n >> 1;
-  const int I = i >> 1, J = j >> 1, K = m;
-  const int I2 = wrapi((i & 1) ? I + 1 : I - 1, nc);
-  const int J2 = wrapi((j & 1) ? J + 1 : J - 1, nc);
-  const int Km = wrapi(K - 1, nc), Kp = wrapi(K + 1, nc);
-  const double wI[2] = {0.75, 0.25};
-  double lo = 0.0, hi = 0.0;   // cells k = 2m (neighbour K - 1) and k = 2m + 1 (neighbour K + 1)
+// Trilinear prolongation with correction, t += P(ec - mu) (mu = 0 unless SHIFT), a thread per
+// coarse cell (I, J, K): it loads the 3 x 3 x 3 coarse neighbourhood once and updates the 8 fine
+// sons, fine rows i = 2I + a, j = 2J + b and the cell pair k = 2K, 2K + 1 (both colours at column
+// K), issuing all 8 fine loads before any store. A fine cell takes 3/4 of its own coarse parent
+// and 1/4 of the neighbour towards it in each direction, the weights multiplied across x, y, z
+// (Eq. 20).
+template <bool SHIFT>
+__global__ void __launch_bounds__(256) prolong_quad_kernel(const double* __restrict__ ec, const double* mu_sum,
+                                                          double mu_scale, double* __restrict__ theta, int n) {
+  const int nc = n >> 1, nh = nc;
+  const long total = (long)nc * nc * nc;
+  const long gid = (long)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (gid >= total) return;
+  const int K = (int)(gid % nc);
+  const long rest = gid / nc;
+  const int J = (int)(rest % nc), I = (int)(rest / nc);
+  const double mu = SHIFT && mu_sum ? (mu_sum[0] + mu_sum[1]) * mu_scale : 0.0;
+  // e[a][b][c]: coarse cell (I - 1 + a, J - 1 + b, K - 1 + c)
+  double e[3][3][3];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int ii = (s & 2) ? I2 : I, jj = (s & 1) ? J2 : J;
-    const double w = wI[(s >> 1) & 1] * wI[s & 1];
-    const double ek = ec[split_idx(nc, ii, jj, K)];
-    lo += w * (0.75 * ek + 0.25 * ec[split_idx(nc, ii, jj, Km)]);
-    hi += w * (0.75 * ek + 0.25 * ec[split_idx(nc, ii, jj, Kp)]);
-  }
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double v = ec[split_idx(nc, wrapi(I - 1 + a, nc), wrapi(J - 1 + b, nc), wrapi(K - 1 + c, nc))];
+        e[a][b][c] = SHIFT ? v - mu : v;
+      }
   const unsigned half = (unsigned)n * (unsigned)n * (unsigned)nh;
-  const unsigned off = ((unsigned)i * n + j) * (unsigned)nh + m;
-  // cell k = 2m has colour (i + j) & 1, cell k = 2m + 1 the other one
-  const int c0 = (i + j) & 1;
-  theta[c0 * half + off] += lo;
-  theta[(1 - c0) * half + off] += hi;
+  unsigned off[2][2];
+  int c0[2][2];
+  double t[2][2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int i = 2 * I + a, j = 2 * J + b;
+      off[a][b] = ((unsigned)i * n + j) * (unsigned)nh + K;
+      c0[a][b] = (i + j) & 1;
+      t[a][b][0] = theta[c0[a][b] * half + off[a][b]];
+      t[a][b][1] = theta[(1 - c0[a][b]) * half + off[a][b]];
+    }
+  const double wI[2] = {0.75, 0.25};
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      // neighbour plane / row of the fine cell: I - 1 for even i, I + 1 for odd (index 0 or 2)
+      const int a2 = a ? 2 : 0, b2 = b ? 2 : 0;
+      double lo = 0.0, hi = 0.0;   // cells k = 2K (neighbour K - 1) and k = 2K + 1 (neighbour K + 1)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ia = (q & 2) ? a2 : 1, jb = (q & 1) ? b2 : 1;
+        const double w = wI[(q >> 1) & 1] * wI[q & 1];
+        const double ek = e[ia][jb][1];
+        lo += w * (0.75 * ek + 0.25 * e[ia][jb][0]);
+        hi += w * (0.75 * ek + 0.25 * e[ia][jb][2]);
+      }
+      theta[c0[a][b] * half + off[a][b]] = t[a][b][0] + lo;
+      theta[(1 - c0[a][b]) * half + off[a][b]] = t[a][b][1] + hi;
+    }
 }
 
-// Each block handles a contiguous range of rows (blocks are mapped XCD-aware), a thread one
-// column m of every row in it.
-__global__ void __launch_bounds__(512) prolong_correct_kernel(const double* __restrict__ ec,
-    double* __restrict__ theta, int n, int rows_per_block) {
-  const int nh = n >> 1;
-  const int r0 = xcd_remap(blockIdx.x, gridDim.x) * rows_per_block;
-  const int r1 = min(r0 + rows_per_block, n * n);
-  for (int row = r0; row < r1; ++row)
-    for (int m = threadIdx.x; m < nh; m += blockDim.x) prolong_correct_row(ec, theta, n, row, m);
+hipError_t launch_prolong_add(const double* ec, const double* mu_sum, double mu_scale, double* theta, int n,
+                              hipStream_t s) {
+  const long total = (long)(n / 2) * (n / 2) * (n / 2);
+  const unsigned blocks = (unsigned)((total + 255) / 256);
+  if (mu_sum)
+    hipLaunchKernelGGL((prolong_quad_kernel<true>), dim3(blocks), dim3(256), 0, s, ec, mu_sum, mu_scale, theta, n);
+  else
+    hipLaunchKernelGGL((prolong_quad_kernel<false>), dim3(blocks), dim3(256), 0, s, ec, mu_sum, mu_scale, theta, n);
+  return hipGetLastError();
 }
 
 __global__ void __launch_bounds__(512) restrict_kernel(const double* __restrict__ fine,
@@ -198,11 +229,8 @@ hipError_t launch_tau(const double* th, const double* delta, const double* rd, d
 hipError_t launch_prolong_correct(const double* tc, double* that, double* theta, int n, hipStream_t s) {
   const size_t cc = (size_t)(n / 2) * (n / 2) * (n / 2);
   hipLaunchKernelGGL(coarse_diff_kernel, dim3(lin_grid(cc)), dim3(256), 0, s, tc, that, cc);
-  const int rows = n * n;
-  const int rpb = rows > 16384 ? (rows + 8191) / 8192 : 1;
-  const int blocks = (rows + rpb - 1) / rpb;
-  hipLaunchKernelGGL(prolong_correct_kernel, dim3(blocks), dim3(n / 2 < 512 ? n / 2 : 512), 0, s, that, theta, n, rpb);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? launch_prolong_add(that, nullptr, 0.0, theta, n, s) : e;
 }
 
 hipError_t launch_restrict(const double* fine, double* coarse, int n, hipStream_t s) {
