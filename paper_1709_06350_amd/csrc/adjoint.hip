@@ -160,12 +160,15 @@ struct AdjSweepArgs {
   double* sum_out;          // sum of the new values
   const double* copy_from;  // last block copies *copy_from to *copy_to (if copy_to)
   double* copy_to;
+  const double* add_from;   // last block adds *add_from to *sum_out (if set)
   Reduce red;
 };
 
 // PFC: coefficients of step t + 1 are loaded at the end of step t (in flight across the barrier),
 // else at the start of their own step (fewer registers, higher occupancy).
-template <int TM, int TJ, int COL, bool PFC>
+// RES: instead of the update, the residual r = rhs - (J^T l) of the colour's cells (both colours
+// read from lam_in with the offset removed), its sum of squares into sum_out.
+template <int TM, int TJ, int COL, bool PFC, bool RES = false>
 __global__ void __launch_bounds__(TM * TJ) adj_half_sweep_pipe(AdjSweepArgs a, int tiles_m, int tiles_j, int ci) {
   constexpr int NT = TM * TJ;
   constexpr int RW = TM + 2, RH = TJ + 2;
@@ -174,7 +177,7 @@ __global__ void __launch_bounds__(TM * TJ) adj_half_sweep_pipe(AdjSweepArgs a, i
   constexpr int O = 1 - COL;
   __shared__ double lds[2 * 4 * SLOT];
   const int n = a.n, nh = n >> 1;
-  const double h2 = a.h2;
+  const double h2 = a.h2, ih2 = 1.0 / a.h2;
   const int tid = threadIdx.x;
   const int logical = xcd_remap(blockIdx.x, gridDim.x);
   const int m0 = (logical % tiles_m) * TM;
@@ -184,9 +187,9 @@ __global__ void __launch_bounds__(TM * TJ) adj_half_sweep_pipe(AdjSweepArgs a, i
   const size_t half = plane * n;
   const double mu = a.mu_sum ? (a.mu_sum[0] + a.mu_sum[1]) * a.mu_scale : 0.0;
   // colour-0 values: the new red values in the black pass (no offset), else the old ones
-  const double* __restrict__ src0 = COL == 1 ? a.red_new : a.lam_in;
+  const double* __restrict__ src0 = COL == 1 && !RES ? a.red_new : a.lam_in;
   const double* __restrict__ src1 = a.lam_in + half;
-  const double mu0 = COL == 1 ? 0.0 : mu;
+  const double mu0 = COL == 1 && !RES ? 0.0 : mu;
 
   // loader: element e of a slot is halo-tile row e / RW, column e % RW (same for both colours);
   // byte offsets inside a plane, out-of-range elements clamped onto the last one
@@ -341,9 +344,15 @@ __global__ void __launch_bounds__(TM * TJ) adj_half_sweep_pipe(AdjSweepArgs a, i
     const double off = (Xr[B] + Xp) + P - 0.5 * ((Ep - Er[B]) + dyz);
     Xr[B] = Xp;
     Er[B] = Ep;
-    const double v = (off - h2 * Rv[K]) * (1.0 / 6.0);
-    st_rs(prs(out, i0 + t), o_c, v);
-    acc += v;
+    if (RES) {
+      const double v = Rv[K] - (off - 6.0 * lc[ob]) * ih2;
+      st_rs(prs(out, i0 + t), o_c, v);
+      acc += v * v;
+    } else {
+      const double v = (off - h2 * Rv[K]) * (1.0 / 6.0);
+      st_rs(prs(out, i0 + t), o_c, v);
+      acc += v;
+    }
     if (PFC) {
       const int ip = i0 + t + 1;
       load_x(cf, wrapp(ip + 1), B ^ 1);
@@ -362,6 +371,7 @@ __global__ void __launch_bounds__(TM * TJ) adj_half_sweep_pipe(AdjSweepArgs a, i
   double vv[1] = {acc};
   const bool last = grid_sum<1>(vv, a.red.partials, a.red.counter, a.sum_out, gridDim.x, blockIdx.x);
   if (last && tid == 0 && a.copy_to) *a.copy_to = *a.copy_from;
+  if (last && tid == 0 && a.add_from) *a.sum_out += *a.add_from;
 }
 
 // res = rhs - J^T l on the fine mesh and rhs_c = R res; sums res^2 (the level's residual norm).
@@ -483,8 +493,11 @@ struct AdjCfg {
   bool pfc = false;
 };
 
-static hipError_t launch_adj_half(const AdjSweepArgs& a, int colour, const AdjCfg& c, hipStream_t s) {
-  if (colour == 1 && !a.red_new) return hipErrorInvalidValue;
+// One colour of a sweep (res = false), or of the residual r = rhs - J^T l (res = true: tiled
+// configurations only, the offset removed from both colours of lam_in).
+static hipError_t launch_adj_half(const AdjSweepArgs& a, int colour, const AdjCfg& c, hipStream_t s, bool res = false) {
+  if (colour == 1 && !a.red_new && !res) return hipErrorInvalidValue;
+  if (res && c.tm == 0) return hipErrorInvalidValue;
   if (c.tm == 0) {
     hipLaunchKernelGGL(adj_half_sweep_kernel, dim3(rows_blocks_a(a.n)), dim3(row_threads_a(a.n / 2)), 0, s, a.lam_in,
                        colour == 1 ? a.red_new : (const double*)nullptr, a.out, a.rhs, a.coef, a.n, colour, a.h2,
@@ -496,18 +509,23 @@ static hipError_t launch_adj_half(const AdjSweepArgs& a, int colour, const AdjCf
   const int tiles_m = nh / c.tm, tiles_j = a.n / c.tj;
   const long blocks = (long)tiles_m * tiles_j * (a.n / c.ci);
   if (blocks < 1 || blocks > kMaxReduceBlocks) return hipErrorInvalidValue;
-#define MR_AP_GO(TM, TJ, COL, PFC) \
-  hipLaunchKernelGGL((adj_half_sweep_pipe<TM, TJ, COL, PFC>), dim3(blocks), dim3(TM * TJ), 0, s, a, tiles_m, tiles_j, c.ci)
+#define MR_AP_GO(TM, TJ, COL, PFC, RES)                                                                     \
+  hipLaunchKernelGGL((adj_half_sweep_pipe<TM, TJ, COL, PFC, RES>), dim3(blocks), dim3(TM * TJ), 0, s, a, tiles_m, \
+                     tiles_j, c.ci)
 #define MR_AP_LAUNCH(TM, TJ)                         \
   if (c.tm == TM && c.tj == TJ) {                    \
-    if (colour == 0 && c.pfc)                        \
-      MR_AP_GO(TM, TJ, 0, true);                     \
+    if (res && colour == 0)                          \
+      MR_AP_GO(TM, TJ, 0, true, true);               \
+    else if (res)                                    \
+      MR_AP_GO(TM, TJ, 1, true, true);               \
+    else if (colour == 0 && c.pfc)                   \
+      MR_AP_GO(TM, TJ, 0, true, false);              \
     else if (colour == 0)                            \
-      MR_AP_GO(TM, TJ, 0, false);                    \
+      MR_AP_GO(TM, TJ, 0, false, false);             \
     else if (c.pfc)                                  \
-      MR_AP_GO(TM, TJ, 1, true);                     \
+      MR_AP_GO(TM, TJ, 1, true, false);              \
     else                                             \
-      MR_AP_GO(TM, TJ, 1, false);                    \
+      MR_AP_GO(TM, TJ, 1, false, false);             \
     return hipGetLastError();                        \
   }
   MR_AP_TILES(MR_AP_LAUNCH)
@@ -665,20 +683,26 @@ void Ctx::release_adjoint() {
   adj = nullptr;
 }
 
-int Ctx::adj_sweep(int l) {
-  AdjLevel& A = adj->lv[l];
-  Level& F = lv[l];
-  double* ms = linsum(l);
-  const double scale = 1.0 / (double)F.cells;
+// The level's half-sweep schedule: the timed choice, or the one a flag forces.
+static AdjCfg adj_level_cfg(const AdjLevel& A, int n, int l, int flags) {
   AdjCfg cfg;
-  if (opts.flags & MR_FLAG_ADJ_TILED) {
-    cfg = fixed_tiled_cfg(F.n, l);
-  } else if (!(opts.flags & MR_FLAG_ADJ_ROWS)) {
+  if (flags & MR_FLAG_ADJ_TILED) {
+    cfg = fixed_tiled_cfg(n, l);
+  } else if (!(flags & MR_FLAG_ADJ_ROWS)) {
     cfg.tm = A.tm;
     cfg.tj = A.tj;
     cfg.ci = A.ci;
     cfg.pfc = A.pfc;
   }
+  return cfg;
+}
+
+int Ctx::adj_sweep(int l) {
+  AdjLevel& A = adj->lv[l];
+  Level& F = lv[l];
+  double* ms = linsum(l);
+  const double scale = 1.0 / (double)F.cells;
+  const AdjCfg cfg = adj_level_cfg(adj->lv[l], lv[l].n, l, opts.flags);
   AdjSweepArgs a{};
   a.lam_in = A.lam[A.cur];
   a.red_new = A.lam[A.cur ^ 1];
@@ -718,9 +742,33 @@ int Ctx::adj_vcycle(int l, double* norm2) {
   AdjLevel& Ac = adj->lv[l + 1];
   Level& Fc = lv[l + 1];
   const int m = F.n / 2;
-  hipLaunchKernelGGL(adj_resid_restrict_kernel, dim3(rows_blocks_a(m)), dim3(row_threads_a(m)), 0, stream, A.lam[A.cur],
-                     A.rhs, A.coef, F.n, 1.0 / (F.h * F.h), linsum(l), scale, Ac.rhs,
-                     Reduce{partials, counter, norm2 ? norm2 : scal + kSlotAux + 4});
+  double* nrm = norm2 ? norm2 : scal + kSlotAux + 4;
+  const AdjCfg cfg = adj_level_cfg(adj->lv[l], lv[l].n, l, opts.flags);
+  if (cfg.tm != 0) {
+    // tiled: r of each colour into the free lambda buffer (sum of squares red -> aux slot, black
+    // plus red -> nrm[1]), then its 8-son average
+    AdjSweepArgs a{};
+    a.lam_in = A.lam[A.cur];
+    a.out = A.lam[A.cur ^ 1];
+    a.rhs = A.rhs;
+    a.coef = A.coef;
+    a.n = F.n;
+    a.h2 = F.h * F.h;
+    a.mu_sum = linsum(l);
+    a.mu_scale = scale;
+    a.red = reducer(kSlotAux);
+    a.sum_out = scal + kSlotAux + 10;
+    e = launch_adj_half(a, 0, cfg, stream, true);
+    a.sum_out = nrm + 1;
+    a.add_from = scal + kSlotAux + 10;
+    if (e == hipSuccess) e = launch_adj_half(a, 1, cfg, stream, true);
+    if (e == hipSuccess) e = launch_restrict(A.lam[A.cur ^ 1], Ac.rhs, F.n, stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint residual");
+  } else {
+    hipLaunchKernelGGL(adj_resid_restrict_kernel, dim3(rows_blocks_a(m)), dim3(row_threads_a(m)), 0, stream,
+                       A.lam[A.cur], A.rhs, A.coef, F.n, 1.0 / (F.h * F.h), linsum(l), scale, Ac.rhs,
+                       Reduce{partials, counter, nrm});
+  }
   Ac.cur = 0;
   if ((e = hipMemsetAsync(Ac.lam[0], 0, Fc.cells * sizeof(double), stream)) != hipSuccess) return hip_fail(e, "zero");
   if ((e = hipMemsetAsync(linsum(l + 1), 0, 2 * sizeof(double), stream)) != hipSuccess) return hip_fail(e, "zero");

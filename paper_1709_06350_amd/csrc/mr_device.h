@@ -232,8 +232,6 @@ __device__ bool grid_sum(double (&v)[NV], double* __restrict__ partials, unsigne
   return true;
 }
 
-// Map a launch-order block index to a logical tile index so that each of the 8 XCDs (which
-// receive blocks round-robin) works on one contiguous range of tiles and shares halos in its L2.
 // Raw buffer access to one plane: a resource built from a wave-uniform base pointer (scalar
 // registers) and a per-lane 32-bit byte offset. This keeps per-lane address arithmetic at 32 bits
 // where the loop optimiser would otherwise materialise 64-bit addresses per load. Offsets at or
@@ -249,6 +247,8 @@ __device__ __forceinline__ void st_rs(__amdgpu_buffer_rsrc_t r, unsigned byte_of
                                        r, (int)byte_off, 0, 0);
 }
 
+// Map a launch-order block index to a logical tile index so that each of the 8 XCDs (which
+// receive blocks round-robin) works on one contiguous range of tiles and shares halos in its L2.
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
   if ((nb & 7) != 0) return b;
   return (b & 7) * (nb >> 3) + (b >> 3);
