@@ -68,3 +68,57 @@ def test_lognormal_512_fp64_and_mixed():
     print(f"512^3: fp64 cycles={i64.cycles} oracle_rel={r64:.3e}; mixed outer={im.cycles} oracle_rel={rm:.3e}; "
           f"mixed vs fp64 rel L2 {err:.3e}")
     assert r64 <= 1e-10 and rm <= 1e-10 and err <= 1e-8
+
+
+@pytest.mark.timeout(900)
+def test_largest_mesh_1024_tiled_periodic_field():
+    """The largest supported mesh, 1024^3, on a 256^3 lognormal field tiled 4 x 4 x 4. The field has
+    period 256, and so must the solution: every cell's update depends only on its neighbourhood
+    and the mesh-wide sums are shared. Checked: the oracle's relative residual of one 256^3 tile on
+    its own periodic mesh (the same quantity as on the whole mesh) for the FP64 and the mixed solve;
+    the other tiles equal the first; the 1024^3 adjoint of a tiled dL/dtheta equals, tile by tile, the
+    256^3 adjoint (also on the GPU, whose parity is pinned by the oracle and finite-difference tests)."""
+    require_gpu()
+    n, t = 1024, 256
+    announce("largest mesh 1024^3: input")
+    d256 = inputs.lognormal(t, 1.0, 2.0, 1010)
+    delta = np.tile(d256, (4, 4, 4))
+    d = dev(delta)
+    del delta
+    g256 = np.random.default_rng(1011).standard_normal((t, t, t))
+    g256 -= g256.mean()
+    with mr.Context(n, tol=1e-10) as c:
+        announce("largest mesh 1024^3: FP64 solve")
+        th, i64 = c.solve(d)
+        assert i64.status == 0 and i64.rel_residual <= 1e-10
+        announce("largest mesh 1024^3: adjoint")
+        c.set_opts(tol=1e-8)
+        gd = dev(np.tile(g256, (4, 4, 4)))
+        grad, ia = c.adjoint_solve(d, th, gd)
+        assert ia.status == 0
+        del gd
+        tiles = [(0, 0, 0), (1, 2, 3), (3, 3, 3)]
+        th_t = [host(th[a * t:(a + 1) * t, b * t:(b + 1) * t, e * t:(e + 1) * t]) for a, b, e in tiles]
+        gr_t = [host(grad[a * t:(a + 1) * t, b * t:(b + 1) * t, e * t:(e + 1) * t]) for a, b, e in tiles]
+        announce("largest mesh 1024^3: mixed solve")
+        c.set_opts(tol=1e-10, precision=mr.PREC_MIXED)
+        thm, im = c.solve(d)
+        assert im.status == 0 and im.rel_residual <= 1e-10
+        thm_t = host(thm[:t, :t, :t])
+        del th, grad, thm
+    announce("largest mesh: 256^3 adjoint reference")
+    with mr.Context(t, tol=1e-10) as c:
+        th256, _ = c.solve(dev(d256))
+        c.set_opts(tol=1e-8)
+        ref_grad, _ = c.adjoint_solve(dev(d256), th256, dev(g256))
+        ref_grad = host(ref_grad)
+    for k in range(1, len(tiles)):
+        np.testing.assert_allclose(th_t[k], th_t[0], rtol=0, atol=1e-12 * np.abs(th_t[0]).max())
+        np.testing.assert_allclose(gr_t[k], gr_t[0], rtol=0, atol=1e-12 * np.abs(gr_t[0]).max())
+    announce("largest mesh: oracle residual of a tile")
+    r64, _ = oop.relative_residual_slabs(th_t[0], d256, slab=16, workers=WORKERS)
+    rm, _ = oop.relative_residual_slabs(thm_t, d256, slab=16, workers=WORKERS)
+    gerr = np.linalg.norm(gr_t[0] - ref_grad) / np.linalg.norm(ref_grad)
+    print(f"1024^3 tiled: fp64 cycles={i64.cycles} oracle_rel={r64:.3e}; mixed outer={im.cycles} oracle_rel={rm:.3e}; "
+          f"adjoint cycles={ia.cycles} vs 256^3 adjoint rel L2 {gerr:.3e}")
+    assert r64 <= 1e-10 and rm <= 1e-10 and gerr <= 1e-6
