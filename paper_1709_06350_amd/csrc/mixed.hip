@@ -16,7 +16,11 @@
 // LDS with e) and the FP32 base root s; coarse meshes use the restricted base potential and
 // their own root (rediscretisation).
 #include <algorithm>
+#include <map>
+#include <mutex>
 #include <type_traits>
+#include <utility>
+#include <vector>
 
 #include "mr_ctx.h"
 #include "mr_device.h"
@@ -26,7 +30,7 @@
 namespace mr {
 
 // Compiled tile shapes (tm columns of m, tj rows) of the FP32 linear sweeps.
-#define MR_LIN_TILES(X) X(64, 8) X(64, 4) X(32, 16) X(32, 8) X(16, 16) X(8, 16) X(4, 8) X(2, 4)
+#define MR_LIN_TILES(X) X(64, 8) X(64, 4) X(64, 16) X(32, 16) X(32, 8) X(16, 16) X(8, 16) X(4, 8) X(2, 4)
 
 template <int TM, int TJ>
 __global__ void __launch_bounds__(TM * TJ) lin_half_sweep_tiled(LinSweepArgs a) {
@@ -55,7 +59,7 @@ __global__ void __launch_bounds__(256) lin_resid_restrict_kernel(const float* __
   lin_resid_restrict_body(e, base, sb, rhs, n, ih2, cref, rhs_c, red, blockIdx.x, gridDim.x);
 }
 
-__global__ void __launch_bounds__(512) prolong_add32_kernel(const float* __restrict__ ec, float* __restrict__ e, int n) {
+__global__ void __launch_bounds__(256) prolong_add32_kernel(const float* __restrict__ ec, float* __restrict__ e, int n) {
   prolong_add32_body(ec, e, n, blockIdx.x, gridDim.x);
 }
 
@@ -270,9 +274,8 @@ hipError_t launch_lin_resid_restrict(const float* e, const float* base, const fl
 }
 
 hipError_t launch_prolong_add32(const float* ec, float* e, int n, hipStream_t s) {
-  const unsigned rows = (unsigned)n * n;
-  hipLaunchKernelGGL(prolong_add32_kernel, dim3(rows < 8192u ? rows : 8192u), dim3(n / 2 < 512 ? n / 2 : 512), 0, s, ec,
-                     e, n);
+  const long cc = (long)(n / 2) * (n / 2) * (n / 2);   // one thread per coarse cell
+  hipLaunchKernelGGL(prolong_add32_kernel, dim3((unsigned)((cc + 255) / 256)), dim3(256), 0, s, ec, e, n);
   return hipGetLastError();
 }
 
@@ -335,6 +338,99 @@ static TileCfg lin_tiles(int n) {
   return t;
 }
 
+static std::mutex g_lin_tune_mu;
+static std::map<std::pair<int, int>, TileCfg> g_lin_tuned;   // (device, n)
+
+// Times both colours of a linear sweep for the default tile and for the pipelined kernel on every
+// compiled tile with chunks of 16 to 256 planes, on the level's (zeroed) buffers, and keeps the
+// fastest. Cached per (device, n).
+static int tune_lin_sweep(Ctx* c, int l, TileCfg* out) {
+  const int n = c->lv[l].n, nh = n / 2;
+  LinLevel& L = c->mixed->lv[l];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return hip_fail(hipErrorInvalidDevice, "linear sweep tuner");
+  {
+    std::lock_guard<std::mutex> lk(g_lin_tune_mu);
+    auto it = g_lin_tuned.find({dev, n});
+    if (it != g_lin_tuned.end()) {
+      *out = it->second;
+      return MR_OK;
+    }
+  }
+  std::vector<TileCfg> cand{lin_tiles(n)};
+  auto add = [&](int tm, int tj) {
+    if (nh % tm != 0 || n % tj != 0 || tj > n || tm > nh) return;
+    for (int ci = 16; ci <= 256 && ci <= n; ci *= 2) {
+      TileCfg t;
+      t.tm = tm;
+      t.tj = tj;
+      t.cpt = 1;
+      t.ci = ci;
+      t.tiles_j = n / tj;
+      t.tiles_m = nh / tm;
+      t.pipe = true;
+      if (n % ci == 0 && (long)t.tiles_j * t.tiles_m * (n / ci) <= kMaxReduceBlocks) cand.push_back(t);
+    }
+  };
+#define MR_LIN_ADD(TM, TJ) add(TM, TJ);
+  MR_LIN_TILES(MR_LIN_ADD)
+#undef MR_LIN_ADD
+  const size_t cells = c->lv[l].cells;
+  hipError_t e = hipSuccess;
+  for (float* b : {L.e[0], L.e[1], L.base, L.sb, L.rhs})
+    if (e == hipSuccess) e = hipMemsetAsync(b, 0, cells * sizeof(float), c->stream);
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (e == hipSuccess) e = hipEventCreate(&ea);
+  if (e == hipSuccess) e = hipEventCreate(&eb);
+  LinSweepArgs a{};
+  a.e_in = L.e[0];
+  a.e_out = L.e[1];
+  a.base = L.base;
+  a.sb = L.sb;
+  a.rhs = L.rhs;
+  a.n = n;
+  a.h2 = 1.0f;
+  a.ih2 = 1.0f;
+  a.partials = c->partials;
+  a.counter = c->counter;
+  a.sum_out = c->scal + kSlotAux;
+  auto run = [&](const TileCfg& t) {
+    LinSweepArgs r = a;
+    r.colour = 0;
+    hipError_t x = launch_lin_half_sweep(r, t, c->stream);
+    r.colour = 1;
+    r.e_red_new = L.e[1];
+    return x == hipSuccess ? launch_lin_half_sweep(r, t, c->stream) : x;
+  };
+  const int reps = cells >= ((size_t)1 << 24) ? 2 : 4;
+  float best = 3.0e38f;
+  TileCfg best_t = cand[0];
+  for (const TileCfg& t : cand) {
+    if (e != hipSuccess) break;
+    if (t.tm == 0) continue;
+    e = run(t);   // warm-up
+    if (e == hipSuccess) e = hipEventRecord(ea, c->stream);
+    for (int k = 0; k < reps && e == hipSuccess; ++k) e = run(t);
+    if (e == hipSuccess) e = hipEventRecord(eb, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(eb);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ea, eb);
+    if (e == hipSuccess && ms < best) {
+      best = ms;
+      best_t = t;
+    }
+  }
+  if (ea) (void)hipEventDestroy(ea);
+  if (eb) (void)hipEventDestroy(eb);
+  if (e != hipSuccess) return hip_fail(e, "linear sweep tuner");
+  {
+    std::lock_guard<std::mutex> lk(g_lin_tune_mu);
+    g_lin_tuned[{dev, n}] = best_t;
+  }
+  *out = best_t;
+  return MR_OK;
+}
+
 static int mixed_alloc(Ctx* c) {
   if (c->mixed) return MR_OK;
   MixedState* m = new MixedState();
@@ -349,7 +445,11 @@ static int mixed_alloc(Ctx* c) {
       if (e != hipSuccess) return fail(MR_ENOMEM, "mixed precision buffers: %s", hipGetErrorString(e));
       m->owned.push_back(*b);
     }
-    if (l < c->nlev - 1) L.sw = lin_tiles(c->lv[l].n);
+  }
+  // linear sweep schedule per level, timed on the level's buffers
+  for (int l = 0; l + 1 < c->nlev; ++l) {
+    int rc = tune_lin_sweep(c, l, &m->lv[l].sw);
+    if (rc != MR_OK) return rc;
   }
   return MR_OK;
 }

@@ -280,38 +280,63 @@ inline __device__ void lin_resid_restrict_body(const float* __restrict__ e, cons
   double vv[2] = {acc, 0.0};
   grid_sum<2>(vv, red.partials, red.counter, red.result, nblocks, bid);
 }
-// e += P(ec) (trilinear: 3/4 of the coarse parent and 1/4 of the neighbour towards the fine cell in
-// each direction; a thread per fine cell pair k = 2m, 2m + 1).
-inline __device__ void prolong_add32_row(const float* __restrict__ ec, float* __restrict__ e, int n, int row, int m) {
-  const int nh = n >> 1;
-  const int i = row / n, j = row - i * n;
-  if (m >= nh) return;
-  const int nc = n >> 1;
-  const int I = i >> 1, J = j >> 1, K = m;
-  const int I2 = wrapi((i & 1) ? I + 1 : I - 1, nc);
-  const int J2 = wrapi((j & 1) ? J + 1 : J - 1, nc);
-  const int Km = wrapi(K - 1, nc), Kp = wrapi(K + 1, nc);
-  const float wI[2] = {0.75f, 0.25f};
-  float lo = 0.0f, hi = 0.0f;
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int ii = (s & 2) ? I2 : I, jj = (s & 1) ? J2 : J;
-    const float w = wI[(s >> 1) & 1] * wI[s & 1];
-    const float ek = ec[split_idx(nc, ii, jj, K)];
-    lo += w * (0.75f * ek + 0.25f * ec[split_idx(nc, ii, jj, Km)]);
-    hi += w * (0.75f * ek + 0.25f * ec[split_idx(nc, ii, jj, Kp)]);
-  }
+// e += P(ec) (trilinear: a fine cell takes 3/4 of its coarse parent and 1/4 of the neighbour
+// towards it in each direction, the weights multiplied across x, y, z). A thread per coarse cell
+// (I, J, K): it loads the 3 x 3 x 3 coarse neighbourhood once and updates the 8 fine sons (rows
+// 2I + a, 2J + b, the cell pair k = 2K, 2K + 1), all 8 fine loads issued before any store.
+// Coarse cells are dealt to blocks bid, bid + nblocks, ... of blockDim.x cells each.
+inline __device__ void prolong_add32_body(const float* __restrict__ ec, float* __restrict__ e, int n, int bid,
+                                          int nblocks) {
+  const int nc = n >> 1, nh = nc;
+  const long total = (long)nc * nc * nc;
   const unsigned half = (unsigned)n * (unsigned)n * (unsigned)nh;
-  const unsigned off = ((unsigned)i * n + j) * (unsigned)nh + m;
-  const int c0 = (i + j) & 1;
-  e[c0 * half + off] += lo;
-  e[(1 - c0) * half + off] += hi;
+  const float wI[2] = {0.75f, 0.25f};
+  for (long gid = (long)xcd_remap(bid, nblocks) * blockDim.x + threadIdx.x; gid < total;
+       gid += (long)nblocks * blockDim.x) {
+    const int K = (int)(gid % nc);
+    const long rest = gid / nc;
+    const int J = (int)(rest % nc), I = (int)(rest / nc);
+    float c[3][3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          c[a][b][k] = ec[split_idx(nc, wrapi(I - 1 + a, nc), wrapi(J - 1 + b, nc), wrapi(K - 1 + k, nc))];
+    unsigned off[2][2];
+    int c0[2][2];
+    float t[2][2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int i = 2 * I + a, j = 2 * J + b;
+        off[a][b] = ((unsigned)i * n + j) * (unsigned)nh + K;
+        c0[a][b] = (i + j) & 1;
+        t[a][b][0] = e[c0[a][b] * half + off[a][b]];
+        t[a][b][1] = e[(1 - c0[a][b]) * half + off[a][b]];
+      }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int a2 = a ? 2 : 0, b2 = b ? 2 : 0;
+        float lo = 0.0f, hi = 0.0f;   // cells k = 2K (neighbour K - 1) and k = 2K + 1 (neighbour K + 1)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int ia = (q & 2) ? a2 : 1, jb = (q & 1) ? b2 : 1;
+          const float w = wI[(q >> 1) & 1] * wI[q & 1];
+          const float ek = c[ia][jb][1];
+          lo += w * (0.75f * ek + 0.25f * c[ia][jb][0]);
+          hi += w * (0.75f * ek + 0.25f * c[ia][jb][2]);
+        }
+        e[c0[a][b] * half + off[a][b]] = t[a][b][0] + lo;
+        e[(1 - c0[a][b]) * half + off[a][b]] = t[a][b][1] + hi;
+      }
+  }
 }
 
-inline __device__ void prolong_add32_body(const float* __restrict__ ec, float* __restrict__ e, int n, int bid, int nblocks) {
-  for (int row = xcd_remap(bid, nblocks); row < n * n; row += nblocks)
-    for (int m = threadIdx.x; m < n / 2; m += blockDim.x) prolong_add32_row(ec, e, n, row, m);
-}
 // Linear coarsest solve: nsweeps red-black sweeps in one block (FP32, natural order in LDS).
 struct LinCoarsestShared {
   float te[kMaxCoarsest], tb[kMaxCoarsest], ts[kMaxCoarsest], tr[kMaxCoarsest], tn[kMaxCoarsest];
@@ -408,12 +433,15 @@ __device__ void lin_sweep_pipe_body(const LinSweepArgs& a, int logical, int bid,
   const int tj_i = (logical / a.tiles_m) % a.tiles_j;
   const int chunk = logical / (a.tiles_m * a.tiles_j);
   const int j0 = tj_i * TJ, m0 = tm_i * TM, i0 = chunk * a.ci, ci = a.ci;
-  const unsigned half = (unsigned)n * (unsigned)n * (unsigned)nh;
-  const unsigned plane = (unsigned)n * (unsigned)nh;
+  const size_t plane = (size_t)n * nh;
+  const size_t half = plane * n;
+  const unsigned pbytes = (unsigned)plane * 4u;
   const float* __restrict__ f0 = COL == 1 ? a.e_red_new : a.e_in;   // e red
   const float* __restrict__ f1 = a.e_in + half;                      // e black
   const float* __restrict__ f2 = a.base;                             // base red
   const float* __restrict__ f3 = a.base + half;                      // base black
+  // global accesses through a buffer resource of one plane (uniform) and a per-lane byte offset
+  auto prs = [&](const float* arr, int p) { return plane_rsrc(arr + (size_t)p * plane, pbytes); };
 
   // loader: element k of field f is f * SLOT + (k % PER) * NT + tid (clamped inside the field), so
   // that the source field of every load is a compile-time constant
@@ -425,17 +453,18 @@ __device__ void lin_sweep_pipe_body(const LinSweepArgs& a, int logical, int bid,
     e = e < SLOT ? e : SLOT - 1;
     const int r = e / RW;
     const int c = e - r * RW;
-    goff[k] = (unsigned)wrapi(j0 - 1 + r, n) * nh + (unsigned)wrapi(m0 - 1 + c, nh);
+    goff[k] = ((unsigned)wrapi(j0 - 1 + r, n) * nh + (unsigned)wrapi(m0 - 1 + c, nh)) * 4u;
     loff[k] = e;
   }
   auto fetch = [&](int rel, float (&v)[NPF]) {
-    const unsigned base = (unsigned)wrapi(i0 - 1 + rel, n) * plane;
+    const int p = wrapi(i0 - 1 + rel, n);
+    const auto b0 = prs(f0, p), b1 = prs(f1, p), b2 = prs(f2, p), b3 = prs(f3, p);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      v[0 * PER + k] = f0[base + goff[k]];
-      v[1 * PER + k] = f1[base + goff[k]];
-      v[2 * PER + k] = f2[base + goff[k]];
-      v[3 * PER + k] = f3[base + goff[k]];
+      v[0 * PER + k] = ld_rs_f(b0, goff[k]);
+      v[1 * PER + k] = ld_rs_f(b1, goff[k]);
+      v[2 * PER + k] = ld_rs_f(b2, goff[k]);
+      v[3 * PER + k] = ld_rs_f(b3, goff[k]);
     }
   };
   auto store = [&](int slot, const float (&v)[NPF]) {
@@ -447,16 +476,16 @@ __device__ void lin_sweep_pipe_body(const LinSweepArgs& a, int logical, int bid,
 
   const int s = tid % TM, r = tid / TM;
   const int j = j0 + r, m = m0 + s;
-  const unsigned own = (unsigned)j * nh + m;
+  const unsigned o_c = ((unsigned)j * nh + m) * 4u;   // own cell inside a plane (bytes)
   const int ob = (r + 1) * RW + (s + 1);
   const int q0 = (i0 + j + COL) & 1;
   const int oq0 = ob + q0, oq1 = ob + (q0 ^ 1);
   const double Cd = (a.c_sum ? (a.c_sum[0] + a.c_sum[1]) * a.c_scale : 0.0) + a.c_add;
   const float C = (float)Cd;
   const float h2 = a.h2, ih2 = a.ih2;
-  const float* __restrict__ sbc = a.sb + COL * half + own;
-  const float* __restrict__ rc = a.rhs + COL * half + own;
-  float* __restrict__ out = a.e_out + COL * half + own;
+  const float* __restrict__ sbc = a.sb + COL * half;
+  const float* __restrict__ rc = a.rhs + COL * half;
+  float* __restrict__ out = a.e_out + COL * half;
   const int last_plane = n - 1;
   double acc = 0.0;
 
@@ -472,19 +501,19 @@ __device__ void lin_sweep_pipe_body(const LinSweepArgs& a, int logical, int bid,
     store(2, vc);
   }
   fetch(3, V0);
-  SB[0] = sbc[(unsigned)i0 * plane];
-  RH[0] = rc[(unsigned)i0 * plane];
-  SB[1] = sbc[(unsigned)min(i0 + 1, last_plane) * plane];
-  RH[1] = rc[(unsigned)min(i0 + 1, last_plane) * plane];
+  SB[0] = ld_rs_f(prs(sbc, i0), o_c);
+  RH[0] = ld_rs_f(prs(rc, i0), o_c);
+  SB[1] = ld_rs_f(prs(sbc, min(i0 + 1, last_plane)), o_c);
+  RH[1] = ld_rs_f(prs(rc, min(i0 + 1, last_plane)), o_c);
   __syncthreads();
 
   auto step = [&](auto kc, int t, float (&vst)[NPF], float (&vft)[NPF]) {
     constexpr int K = decltype(kc)::value;
     constexpr int SM = K & 3, S0 = (K + 1) & 3, SP = (K + 2) & 3, SN = (K + 3) & 3;
     fetch(t + 4, vft);
-    const unsigned pn = (unsigned)min(i0 + t + 2, last_plane) * plane;
-    SB[(K + 2) & 3] = sbc[pn];
-    RH[(K + 2) & 3] = rc[pn];
+    const int pn = min(i0 + t + 2, last_plane);
+    SB[(K + 2) & 3] = ld_rs_f(prs(sbc, pn), o_c);
+    RH[(K + 2) & 3] = ld_rs_f(prs(rc, pn), o_c);
     const int oq = (K & 1) ? oq1 : oq0;
     Nb18f te, tb;
 #define MR_LP_GATHER(T, LO, LC)                                                        \
@@ -507,7 +536,7 @@ __device__ void lin_sweep_pipe_body(const LinSweepArgs& a, int logical, int bid,
     float Se;
     const float g = lin_source(tb, SB[K], ih2, te, Se) * ih2;
     const float rhs = RH[K];
-    out[(unsigned)(i0 + t) * plane] = (Se - h2 * (g + rhs - C)) * (1.0f / 6.0f);
+    st_rs_f(prs(out, i0 + t), o_c, (Se - h2 * (g + rhs - C)) * (1.0f / 6.0f));
     acc += (double)(g + rhs);
     store(SN, vst);
     __syncthreads();

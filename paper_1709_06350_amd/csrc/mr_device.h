@@ -247,6 +247,16 @@ __device__ __forceinline__ void st_rs(__amdgpu_buffer_rsrc_t r, unsigned byte_of
                                        r, (int)byte_off, 0, 0);
 }
 
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float* base, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float ld_rs_f(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0));
+}
+__device__ __forceinline__ void st_rs_f(__amdgpu_buffer_rsrc_t r, unsigned byte_off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)byte_off, 0, 0);
+}
+
 // Map a launch-order block index to a logical tile index so that each of the 8 XCDs (which
 // receive blocks round-robin) works on one contiguous range of tiles and shares halos in its L2.
 __device__ __forceinline__ int xcd_remap(int b, int nb) {
