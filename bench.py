@@ -46,16 +46,21 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per finest sweep launch from the committed PMC summary, if it matches the source."""
+def measured_traffic(schedule: str):
+    """HBM bytes per finest sweep from the committed PMC summary, if it was taken on the same kernel
+    source and the same finest-level schedule as this run."""
     if not os.path.exists(PROFILE_PMC):
         return None
     txt = open(PROFILE_PMC).read()
     m = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", txt)
     b = re.search(r"hbm_bytes_per_sweep:\s*([0-9.eE+]+)", txt)
-    if not m or not b or m.group(1) != kernel_hash():
+    c = re.search(r"schedule:\s*([0-9,]+)", txt)
+    if not m or not b or not c or m.group(1) != kernel_hash() or c.group(1) != schedule:
         return None
     return float(b.group(1))
+
+
+SCHED_KERNEL = {0: "half_sweep_tiled", 1: "half_sweep_pipe", 2: "sweep_fused"}
 
 
 def cpu_baseline(delta_np, seconds_target=15.0):
@@ -176,6 +181,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the CIC and adjoint timings")
+    ap.add_argument("--schedule", default="", metavar="KIND,TM,TJ,NCHUNKS",
+                    help="pin the finest-level FP64 relaxation schedule (mr_set_schedule) instead of the timed one")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a device copy of BYTES bytes (counter calibration)")
     args = ap.parse_args()
@@ -199,6 +206,10 @@ def main():
     theta = torch.zeros_like(delta)
     theta_m = torch.zeros_like(delta)
     ctx = mr.Context(n, tol=1e-10, max_cycles=100)
+    if args.schedule:
+        ctx.set_schedule(0, tuple(int(x) for x in args.schedule.split(",")))
+    sched = ctx.get_schedule(0)
+    sched_str = ",".join(str(x) for x in sched)
     run_mixed = not args.no_mixed
     ctxm = None
     if run_mixed:
@@ -243,7 +254,7 @@ def main():
     cells = float(n) ** 3
     gcups = cells / avg_sweep_s / 1e9
     achieved = SWEEP_BYTES_PER_UPDATE * cells / avg_sweep_s / 1e9
-    traffic = measured_traffic()
+    traffic = measured_traffic(sched_str)
     out = {
         "metric": "NGS smoother Gcell-updates/s (% HBM peak); 512^3 time-to-1e-10, mixed vs FP64",
         "value": round(gcups, 3),
@@ -273,7 +284,9 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None if traffic is None else round(traffic / avg_sweep_s / 1e9, 1),
-            "kernel": "half_sweep_pipe (finest-mesh FP64 red-black sweep: red + black launch)",
+            "kernel": f"{SCHED_KERNEL[sched[0]]}<{sched[1]},{sched[2]}> (finest-mesh FP64 red-black sweep"
+                      + (", one launch" if sched[0] == 2 else ": red + black launch") + f", {sched[3]} chunks)",
+            "schedule": sched_str,
             "sweep_us": round(avg_sweep_s * 1e6, 2),
             "algorithmic_bytes_per_sweep": SWEEP_BYTES_PER_UPDATE * cells,
             "traffic_bytes_per_sweep": traffic,

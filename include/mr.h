@@ -113,6 +113,23 @@ int mr_set_opts(mr_ctx* ctx, const mr_opts* opts);
 int mr_size(const mr_ctx* ctx);
 int mr_levels(const mr_ctx* ctx);
 
+/* FP64 relaxation schedule of one level (0 = finest .. mr_levels - 2; the coarsest level has none):
+ * sched[0] = kind (MR_SCHED_TILED: two launches per sweep, general tiled kernel;
+ * MR_SCHED_PIPELINED: two launches, plane-pipelined kernel; MR_SCHED_FUSED: one launch for both
+ * colours), sched[1] = tile width in columns m (cells of one colour along k), sched[2] = tile
+ * height in rows j, sched[3] = number of chunks the planes i are split into. mr_create picks each
+ * level's schedule by timing the candidates on this device; all schedules compute the same update
+ * and differ only in the rounding order of the sums of Sigma. For callers that need the schedule
+ * the solve ran (reports, profiling of one configuration) or identical schedules in several
+ * processes (bitwise-equal results): mr_get_schedule reads it, mr_set_schedule pins it (not a
+ * passage of the paper). Host-only, no device work. Returns MR_EINVAL for a NULL argument, a level
+ * out of range, or a schedule the library has no kernel for (set: the tile must be compiled and
+ * divide the level's mesh, chunks must divide the planes into equal whole chunks of at least 4
+ * planes (a multiple of 4 for MR_SCHED_PIPELINED) and the grid must fit the reduction buffers). */
+enum { MR_SCHED_TILED = 0, MR_SCHED_PIPELINED = 1, MR_SCHED_FUSED = 2 };
+int mr_get_schedule(const mr_ctx* ctx, int level, int sched[4]);
+int mr_set_schedule(mr_ctx* ctx, int level, const int sched[4]);
+
 /* Cloud-in-cell density assignment (the paper's footnote on density assignment, Sec. I).
  * pos: device, np x 3 doubles (x, y, z) in cell units, any real value (wrapped periodically);
  * mesh points sit at integer coordinates and a particle at x gives weight (1 - f) to floor(x)

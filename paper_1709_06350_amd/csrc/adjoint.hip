@@ -591,33 +591,15 @@ static int tune_adj_sweep(const AdjSweepArgs& base, hipStream_t s, AdjCfg* out) 
 #define MR_AP_ADD(TM, TJ) add(TM, TJ);
   MR_AP_TILES(MR_AP_ADD)
 #undef MR_AP_ADD
-  hipEvent_t ea = nullptr, eb = nullptr;
-  hipError_t e = hipEventCreate(&ea);
-  if (e == hipSuccess) e = hipEventCreate(&eb);
   const size_t cells = (size_t)n * n * n;
   const int reps = cells >= ((size_t)1 << 24) ? 2 : 4;
   auto run = [&](const AdjCfg& c) {
     hipError_t r = launch_adj_half(base, 0, c, s);
     return r == hipSuccess ? launch_adj_half(base, 1, c, s) : r;
   };
-  float best = 3.0e38f;
-  AdjCfg best_c;
-  for (const AdjCfg& c : cand) {
-    if (e != hipSuccess) break;
-    e = run(c);   // warm-up
-    if (e == hipSuccess) e = hipEventRecord(ea, s);
-    for (int k = 0; k < reps && e == hipSuccess; ++k) e = run(c);
-    if (e == hipSuccess) e = hipEventRecord(eb, s);
-    if (e == hipSuccess) e = hipEventSynchronize(eb);
-    float ms = 0.0f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ea, eb);
-    if (e == hipSuccess && ms < best) {
-      best = ms;
-      best_c = c;
-    }
-  }
-  if (ea) (void)hipEventDestroy(ea);
-  if (eb) (void)hipEventDestroy(eb);
+  size_t bi = 0;
+  hipError_t e = pick_fastest(cand.size(), reps, s, [&](size_t i) { return run(cand[i]); }, &bi);
+  const AdjCfg best_c = cand[bi];
   if (e != hipSuccess) return hip_fail(e, "adjoint tuner");
   {
     std::lock_guard<std::mutex> lk(g_adj_tune_mu);

@@ -572,6 +572,66 @@ int mr_set_opts(mr_ctx* h, const mr_opts* opts) {
 int mr_size(const mr_ctx* h) { return h ? reinterpret_cast<const Ctx*>(h)->n : 0; }
 int mr_levels(const mr_ctx* h) { return h ? reinterpret_cast<const Ctx*>(h)->nlev : 0; }
 
+int mr_get_schedule(const mr_ctx* h, int level, int sched[4]) {
+  if (!h || !sched) return fail(MR_EINVAL, "mr_get_schedule: null argument");
+  const Ctx* c = reinterpret_cast<const Ctx*>(h);
+  if (level < 0 || level >= c->nlev - 1) return fail(MR_EINVAL, "mr_get_schedule: level %d has no sweep schedule", level);
+  const Level& L = c->lv[level];
+  const bool fused = L.has_fz && !(c->opts.flags & MR_FLAG_TWO_PASS);
+  if (fused) {
+    sched[0] = MR_SCHED_FUSED;
+    sched[1] = L.fz.tm;
+    sched[2] = L.fz.tj;
+    sched[3] = L.fz.nchunks;
+  } else {
+    sched[0] = L.sw.pipe ? MR_SCHED_PIPELINED : MR_SCHED_TILED;
+    sched[1] = L.sw.tm;
+    sched[2] = L.sw.tj;
+    sched[3] = L.n / L.sw.ci;
+  }
+  return MR_OK;
+}
+
+int mr_set_schedule(mr_ctx* h, int level, const int sched[4]) {
+  if (!h || !sched) return fail(MR_EINVAL, "mr_set_schedule: null argument");
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (level < 0 || level >= c->nlev - 1) return fail(MR_EINVAL, "mr_set_schedule: level %d has no sweep schedule", level);
+  Level& L = c->lv[level];
+  const int n = L.n, nh = n / 2, kind = sched[0], tm = sched[1], tj = sched[2], nch = sched[3];
+  if (tm < 1 || tj < 1 || nh % tm != 0 || n % tj != 0 || nch < 1 || n % nch != 0 || n / nch < 4 ||
+      (long)(nh / tm) * (n / tj) * nch > kMaxReduceBlocks)
+    return fail(MR_EINVAL, "mr_set_schedule: tile %d x %d, %d chunks do not fit the %d^3 level", tm, tj, nch, n);
+  if (kind == MR_SCHED_FUSED) {
+    if (!fused_tile_supported(tm, tj)) return fail(MR_EINVAL, "mr_set_schedule: no fused kernel for tile %d x %d", tm, tj);
+    L.fz.tm = tm;
+    L.fz.tj = tj;
+    L.fz.tiles_j = n / tj;
+    L.fz.tiles_m = nh / tm;
+    L.fz.nchunks = nch;
+    L.has_fz = true;
+    return MR_OK;
+  }
+  TileCfg t;
+  t.tm = tm;
+  t.tj = tj;
+  t.cpt = 1;
+  t.ci = n / nch;
+  t.tiles_j = n / tj;
+  t.tiles_m = nh / tm;
+  if (kind == MR_SCHED_PIPELINED) {
+    if (!half_sweep_pipe_supported(tm, tj) || t.ci % 4 != 0)
+      return fail(MR_EINVAL, "mr_set_schedule: no pipelined kernel for tile %d x %d, %d-plane chunks", tm, tj, t.ci);
+    t.pipe = true;
+  } else if (kind == MR_SCHED_TILED) {
+    if (!half_sweep_tile_supported(tm, tj, 1)) return fail(MR_EINVAL, "mr_set_schedule: no tiled kernel for tile %d x %d", tm, tj);
+  } else {
+    return fail(MR_EINVAL, "mr_set_schedule: unknown kind %d", kind);
+  }
+  L.sw = t;
+  L.has_fz = false;
+  return MR_OK;
+}
+
 int mr_timing_enable(mr_ctx* h, int on) {
   if (!h) return fail(MR_EINVAL, "mr_timing_enable: null context");
   Ctx* c = reinterpret_cast<Ctx*>(h);

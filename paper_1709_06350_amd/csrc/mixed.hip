@@ -379,9 +379,6 @@ static int tune_lin_sweep(Ctx* c, int l, TileCfg* out) {
   hipError_t e = hipSuccess;
   for (float* b : {L.e[0], L.e[1], L.base, L.sb, L.rhs})
     if (e == hipSuccess) e = hipMemsetAsync(b, 0, cells * sizeof(float), c->stream);
-  hipEvent_t ea = nullptr, eb = nullptr;
-  if (e == hipSuccess) e = hipEventCreate(&ea);
-  if (e == hipSuccess) e = hipEventCreate(&eb);
   LinSweepArgs a{};
   a.e_in = L.e[0];
   a.e_out = L.e[1];
@@ -403,25 +400,13 @@ static int tune_lin_sweep(Ctx* c, int l, TileCfg* out) {
     return x == hipSuccess ? launch_lin_half_sweep(r, t, c->stream) : x;
   };
   const int reps = cells >= ((size_t)1 << 24) ? 2 : 4;
-  float best = 3.0e38f;
-  TileCfg best_t = cand[0];
-  for (const TileCfg& t : cand) {
-    if (e != hipSuccess) break;
-    if (t.tm == 0) continue;
-    e = run(t);   // warm-up
-    if (e == hipSuccess) e = hipEventRecord(ea, c->stream);
-    for (int k = 0; k < reps && e == hipSuccess; ++k) e = run(t);
-    if (e == hipSuccess) e = hipEventRecord(eb, c->stream);
-    if (e == hipSuccess) e = hipEventSynchronize(eb);
-    float ms = 0.0f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ea, eb);
-    if (e == hipSuccess && ms < best) {
-      best = ms;
-      best_t = t;
-    }
-  }
-  if (ea) (void)hipEventDestroy(ea);
-  if (eb) (void)hipEventDestroy(eb);
+  // the default tile can be unsupported on tiny meshes (tm == 0): it is then never picked
+  std::vector<TileCfg> ok;
+  for (const TileCfg& t : cand)
+    if (t.tm != 0) ok.push_back(t);
+  size_t bi = 0;
+  if (e == hipSuccess && !ok.empty()) e = pick_fastest(ok.size(), reps, c->stream, [&](size_t i) { return run(ok[i]); }, &bi);
+  const TileCfg best_t = ok.empty() ? cand[0] : ok[bi];
   if (e != hipSuccess) return hip_fail(e, "linear sweep tuner");
   {
     std::lock_guard<std::mutex> lk(g_lin_tune_mu);

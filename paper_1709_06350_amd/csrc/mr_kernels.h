@@ -2,6 +2,10 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <utility>
+#include <vector>
 #include <stddef.h>
 #include <stdint.h>
 
@@ -138,6 +142,55 @@ hipError_t launch_coarsest(const CoarsestArgs& a, hipStream_t s);
 // Chooses a fused-sweep tile for an n^3 mesh on the current device by occupancy (false: no
 // compiled tile fits).
 bool pick_fused(int n, FusedCfg& cfg);
+
+// Picks the fastest of ncand launch candidates; run(i) launches candidate i once on stream s.
+// First pass: one warm-up and `reps` timed launches of every candidate; second pass: the four
+// fastest again with 3 x reps launches, in two interleaved rounds (close candidates are a few
+// percent apart, and a single short timing can misorder them). *best receives the index.
+template <class Run>
+hipError_t pick_fastest(size_t ncand, int reps, hipStream_t s, Run&& run, size_t* best) {
+  *best = 0;
+  if (ncand == 0) return hipSuccess;
+  hipEvent_t ea = nullptr, eb = nullptr;
+  hipError_t e = hipEventCreate(&ea);
+  if (e == hipSuccess) e = hipEventCreate(&eb);
+  auto time_it = [&](size_t i, int r, float* ms) -> hipError_t {
+    hipError_t x = hipEventRecord(ea, s);
+    for (int k = 0; k < r && x == hipSuccess; ++k) x = run(i);
+    if (x == hipSuccess) x = hipEventRecord(eb, s);
+    if (x == hipSuccess) x = hipEventSynchronize(eb);
+    if (x == hipSuccess) x = hipEventElapsedTime(ms, ea, eb);
+    return x;
+  };
+  std::vector<std::pair<float, size_t>> first;
+  for (size_t i = 0; i < ncand && e == hipSuccess; ++i) {
+    float ms = 0.0f;
+    e = run(i);   // warm-up
+    if (e == hipSuccess) e = time_it(i, reps, &ms);
+    if (e == hipSuccess) first.push_back({ms, i});
+  }
+  if (e == hipSuccess) {
+    std::stable_sort(first.begin(), first.end(),
+                     [](const std::pair<float, size_t>& a, const std::pair<float, size_t>& b) { return a.first < b.first; });
+    const size_t top = std::min<size_t>(4, first.size());
+    std::vector<float> tot(top, 0.0f);
+    for (int round = 0; round < 2 && e == hipSuccess; ++round)
+      for (size_t k = 0; k < top && e == hipSuccess; ++k) {
+        float ms = 0.0f;
+        e = time_it(first[k].second, 3 * reps, &ms);
+        tot[k] += ms;
+      }
+    size_t bk = 0;
+    for (size_t k = 1; k < top; ++k)
+      if (tot[k] < tot[bk]) bk = k;
+    if (top > 0) *best = first[bk].second;
+  }
+  if (ea) (void)hipEventDestroy(ea);
+  if (eb) (void)hipEventDestroy(eb);
+  return e;
+}
+
+bool fused_tile_supported(int tm, int tj);
 // Times the fused candidates and the two-launch sweep (tiles *two, general and pipelined kernel)
 // on the given n^3 buffers, which it overwrites; *use_fused tells whether the fused launch is
 // fastest, *cfg its configuration, *two the faster two-launch variant. The result is cached per

@@ -1411,6 +1411,13 @@ static std::vector<std::pair<double, FusedCfg>> fused_candidates(int n) {
   return out;
 }
 
+bool fused_tile_supported(int tm, int tj) {
+#define MR_FZ_MATCH(TM, TJ) if (tm == TM && tj == TJ) return true;
+  MR_FUSED_TILES(MR_FZ_MATCH)
+#undef MR_FZ_MATCH
+  return false;
+}
+
 bool pick_fused(int n, FusedCfg& cfg) {
   const auto c = fused_candidates(n);
   if (c.empty()) return false;
@@ -1485,21 +1492,7 @@ int tune_sweep(int n, double* th_a, double* th_b, double* delta, double* partial
   const size_t cells = (size_t)n * n * n;
   hipLaunchKernelGGL(tune_fill_kernel, dim3(1024), dim3(256), 0, s, th_a, delta, n);
   hipError_t e = hipGetLastError();
-  hipEvent_t ea = nullptr, eb = nullptr;
-  if (e == hipSuccess) e = hipEventCreate(&ea);
-  if (e == hipSuccess) e = hipEventCreate(&eb);
   const int reps = cells >= ((size_t)1 << 24) ? 2 : 4;
-  auto time_it = [&](auto&& run, float* ms) -> hipError_t {
-    hipError_t r = run();                                   // warm-up
-    if (r == hipSuccess) r = hipEventRecord(ea, s);
-    for (int k = 0; k < reps && r == hipSuccess; ++k) r = run();
-    if (r == hipSuccess) r = hipEventRecord(eb, s);
-    if (r == hipSuccess) r = hipEventSynchronize(eb);
-    if (r == hipSuccess) r = hipEventElapsedTime(ms, ea, eb);
-    *ms /= reps;
-    return r;
-  };
-  float best = 3.0e38f;
   FusedCfg best_cfg;
   bool best_fused = false;
   // two launches per sweep: the general kernel, and the pipelined one on every compiled tile that
@@ -1523,9 +1516,29 @@ int tune_sweep(int n, double* th_a, double* th_b, double* delta, double* partial
 #define MR_HP_ADD(TM, TJ) add_pipe(TM, TJ);
   MR_HP_TILES(MR_HP_ADD)
 #undef MR_HP_ADD
-  TileCfg best_two = *two;
-  for (const TileCfg& tw : twos) {
-    if (e != hipSuccess) break;
+  // every candidate: two launches per sweep (general or pipelined tile) or the fused launch
+  struct Cand {
+    bool fused;
+    TileCfg two;
+    FusedCfg fz;
+  };
+  std::vector<Cand> all;
+  for (const TileCfg& tw : twos) all.push_back(Cand{false, tw, FusedCfg{}});
+  for (const auto& c : cand) all.push_back(Cand{true, *two, c.second});
+  auto run = [&](const Cand& c) -> hipError_t {
+    if (c.fused) {
+      FusedSweepArgs a{};
+      a.th_in = th_a;
+      a.th_out = th_b;
+      a.delta = delta;
+      a.n = n;
+      a.h2 = 1.0;
+      a.ih2 = 1.0;
+      a.sum_out = sums;
+      a.partials = partials;
+      a.counter = counter;
+      return launch_sweep_fused(a, c.fz, s);
+    }
     HalfSweepArgs a{};
     a.th_in = th_a;
     a.th_out = th_b;
@@ -1535,44 +1548,27 @@ int tune_sweep(int n, double* th_a, double* th_b, double* delta, double* partial
     a.ih2 = 1.0;
     a.partials = partials;
     a.counter = counter;
-    float ms = 0.0f;
-    e = time_it([&]() {
-      HalfSweepArgs r = a;
-      r.colour = 0;
-      r.sum_out = sums;
-      hipError_t x = launch_half_sweep(r, tw, s);
-      r.colour = 1;
-      r.th_red_new = th_b;
-      r.sum_out = sums + 1;
-      return x == hipSuccess ? launch_half_sweep(r, tw, s) : x;
-    }, &ms);
-    if (e == hipSuccess && ms < best) {
-      best = ms;
-      best_two = tw;
-    }
-  }
-  for (const auto& c : cand) {
-    if (e != hipSuccess) break;
-    FusedSweepArgs a{};
-    a.th_in = th_a;
-    a.th_out = th_b;
-    a.delta = delta;
-    a.n = n;
-    a.h2 = 1.0;
-    a.ih2 = 1.0;
+    a.colour = 0;
     a.sum_out = sums;
-    a.partials = partials;
-    a.counter = counter;
-    float ms = 0.0f;
-    e = time_it([&]() { return launch_sweep_fused(a, c.second, s); }, &ms);
-    if (e == hipSuccess && ms < best) {
-      best = ms;
-      best_cfg = c.second;
-      best_fused = true;
+    hipError_t x = launch_half_sweep(a, c.two, s);
+    a.colour = 1;
+    a.th_red_new = th_b;
+    a.sum_out = sums + 1;
+    return x == hipSuccess ? launch_half_sweep(a, c.two, s) : x;
+  };
+  size_t bk = 0;
+  if (e == hipSuccess) e = pick_fastest(all.size(), reps, s, [&](size_t i) { return run(all[i]); }, &bk);
+  // when the fused launch wins, the two-launch schedule (used only on request, MR_FLAG_TWO_PASS)
+  // stays the default tile
+  TileCfg best_two = *two;
+  if (!all.empty()) {
+    best_fused = all[bk].fused;
+    if (best_fused) {
+      best_cfg = all[bk].fz;
+    } else {
+      best_two = all[bk].two;
     }
   }
-  if (ea) (void)hipEventDestroy(ea);
-  if (eb) (void)hipEventDestroy(eb);
   if (e != hipSuccess) return hip_fail(e, "sweep tuner");
   {
     std::lock_guard<std::mutex> lk(g_sweep_tune_mu);

@@ -29,9 +29,13 @@ MR_FLAG_ADJ_ROWS = 4
 MR_FLAG_ADJ_TILED = 8
 PREC_FP64 = 0
 PREC_MIXED = 1
+MR_SCHED_TILED = 0
+MR_SCHED_PIPELINED = 1
+MR_SCHED_FUSED = 2
 
 EXPORTED = [
     "mr_default_opts", "mr_create", "mr_destroy", "mr_set_opts", "mr_size", "mr_levels",
+    "mr_get_schedule", "mr_set_schedule",
     "mr_deposit_cic", "mr_residual", "mr_solve", "mr_adjoint_solve", "mr_solve_batched",
     "mr_tune_lin_tiles",
     "mr_sweep", "mr_defect_restrict", "mr_tau_rhs", "mr_prolong_correct", "mr_restrict",
@@ -103,6 +107,8 @@ def load(path: Optional[str] = None):
     lib.mr_set_opts.argtypes = [vp, ctypes.POINTER(mr_opts)]
     lib.mr_size.argtypes = [vp]
     lib.mr_levels.argtypes = [vp]
+    lib.mr_get_schedule.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int)]
+    lib.mr_set_schedule.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int)]
     lib.mr_deposit_cic.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, vp]
     lib.mr_residual.argtypes = [vp, vp, vp, vp, dp, dp]
     lib.mr_solve.argtypes = [vp, vp, vp, ctypes.POINTER(mr_info)]
@@ -203,6 +209,17 @@ class Context:
     @property
     def levels(self) -> int:
         return self.lib.mr_levels(self.h)
+
+    def get_schedule(self, level: int = 0):
+        """FP64 relaxation schedule of a level (mr_get_schedule): (kind, tm, tj, nchunks)."""
+        a = (ctypes.c_int * 4)()
+        _check(self.lib.mr_get_schedule(self.h, level, a))
+        return tuple(a)
+
+    def set_schedule(self, level: int, sched):
+        """Pin a level's FP64 relaxation schedule (mr_set_schedule); sched = (kind, tm, tj, nchunks)."""
+        a = (ctypes.c_int * 4)(*sched)
+        _check(self.lib.mr_set_schedule(self.h, level, a))
 
     def _empty(self, n=None):
         n = self.n if n is None else n

@@ -115,3 +115,46 @@ def test_error_paths():
         c.set_opts(max_cycles=1, tol=1e-14)
         theta, info = c.solve(dev(d), check=False)
         assert info.status == mr.MR_NOT_CONVERGED and info.cycles == 1
+
+
+def test_schedule_get_set_and_pinned_reproducibility():
+    """mr_get_schedule / mr_set_schedule: the timed schedule is readable; a pinned schedule is used
+    (two contexts with the same pinned schedule give bitwise-equal solves); pipelined and fused
+    schedules solve the same equation (the oracle residual of both meets the tolerance, results
+    agree to rounding); schedules without a kernel are rejected."""
+    require_gpu()
+    n = 64
+    announce("schedule get/set n=64")
+    delta = inputs.lognormal(n, 0.8, 2.0, 77)
+    d = dev(delta)
+    pipe = (mr.MR_SCHED_PIPELINED, 32, 8, 4)
+    fused = (mr.MR_SCHED_FUSED, 32, 8, 4)
+    out = {}
+    for name, sched in (("a", pipe), ("b", pipe), ("f", fused)):
+        with mr.Context(n, tol=1e-12) as c:
+            k, tm, tj, nch = c.get_schedule(0)
+            assert k in (mr.MR_SCHED_TILED, mr.MR_SCHED_PIPELINED, mr.MR_SCHED_FUSED)
+            assert (n // 2) % tm == 0 and n % tj == 0 and n % nch == 0
+            c.set_schedule(0, sched)
+            assert c.get_schedule(0) == sched
+            th, info = c.solve(d)
+            assert info.status == 0
+            out[name] = host(th)
+    assert np.array_equal(out["a"], out["b"])
+    err = np.abs(out["f"] - out["a"]).max() / np.abs(out["a"]).max()
+    assert err <= 1e-10, err
+    for name in ("a", "f"):
+        rel, _ = oop.relative_residual_slabs(out[name], delta)
+        assert rel <= 2e-12, (name, rel)
+    with mr.Context(n) as c:
+        c.set_schedule(0, (mr.MR_SCHED_PIPELINED, 32, 8, 8))          # 8-plane chunks: accepted
+        for bad_level, bad in ((0, (mr.MR_SCHED_PIPELINED, 48, 8, 4)),   # tile does not divide
+                               (0, (mr.MR_SCHED_PIPELINED, 32, 8, 32)),  # 2-plane chunks
+                               (0, (mr.MR_SCHED_FUSED, 64, 4, 4)),       # no fused kernel for 64 x 4
+                               (0, (7, 32, 8, 4)),                       # unknown kind
+                               (c.levels - 1, pipe),                      # coarsest level
+                               (-1, pipe)):
+            with pytest.raises(mr.MRError):
+                c.set_schedule(bad_level, bad)
+        with pytest.raises(mr.MRError):
+            c.get_schedule(c.levels - 1)
