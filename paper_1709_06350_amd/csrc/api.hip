@@ -532,6 +532,25 @@ int mr_create(mr_ctx** out, int n, const mr_opts* opts, void* hip_stream) {
       Level& L = c->lv[l];
       rc = tune_sweep(L.n, L.th[0], L.th[1], L.delta, c->partials, c->counter, c->scal + kSlotAux, &L.sw, c->stream,
                       &L.has_fz, &L.fz);
+      // defect + restriction of the level, on the synthetic state the sweep tuner left in th[0]
+      // and delta (f zeroed on coarse levels; outputs into the coarse level's buffers)
+      Level& Lc = c->lv[l + 1];
+      if (rc == MR_OK && l > 0 && hipMemsetAsync(L.f, 0, L.cells * sizeof(double), c->stream) != hipSuccess)
+        rc = hip_fail(hipErrorInvalidValue, "mr_create");
+      if (rc == MR_OK) {
+        DefectArgs a{};
+        a.theta = L.th[0];
+        a.delta = L.delta;
+        a.f = (l == 0) ? nullptr : L.f;
+        a.n = L.n;
+        a.ih2 = 1.0;
+        a.theta_c = Lc.th[0];
+        a.dr = Lc.th[1];
+        a.sums_out = c->scal + kSlotAux;
+        a.partials = c->partials;
+        a.counter = c->counter;
+        rc = tune_defect(a, c->stream);
+      }
       if (rc != MR_OK) {
         mr_destroy(reinterpret_cast<mr_ctx*>(c));
         return rc;

@@ -195,6 +195,8 @@ bool fused_tile_supported(int tm, int tj);
 // on the given n^3 buffers, which it overwrites; *use_fused tells whether the fused launch is
 // fastest, *cfg its configuration, *two the faster two-launch variant. The result is cached per
 // device and n. Returns an MR_ status code.
+// Times the pipelined defect + restriction configurations for a's mesh on a's buffers; cached.
+int tune_defect(const DefectArgs& a, hipStream_t s);
 int tune_sweep(int n, double* th_a, double* th_b, double* delta, double* partials, unsigned* counter, double* sums,
                TileCfg* two, hipStream_t s, bool* use_fused, FusedCfg* cfg);
 // The cached tuning result for n on the current device (false: not tuned or two launches won).

@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <type_traits>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <utility>
 #include <vector>
@@ -1266,63 +1267,129 @@ bool half_sweep_pipe_supported(int tm, int tj) {
   return false;
 }
 
-#define MR_DR_TILES(X) X(64, 8) X(32, 8) X(16, 8) X(8, 8) X(4, 8)
+#define MR_DR_TILES(X) X(64, 8) X(64, 4) X(32, 8) X(32, 4) X(16, 8) X(8, 8) X(4, 8)
 
-// Tile and chunk count of the pipelined defect + restriction: the largest compiled tile dividing
-// the mesh, and the largest number of chunks (multiples of 4 planes) whose grid still fits in one
-// round of the device's resident block slots.
+// Tile and chunk count of the pipelined defect + restriction (chunks are multiples of 4 planes).
+struct DefectCfg {
+  int tm = 0, tj = 0, nchunks = 0;
+};
+static std::mutex g_defect_tune_mu;
+static std::map<std::tuple<int, int, bool>, DefectCfg> g_defect_tuned;   // (device, n, has f)
+
+// Untimed choice: the compiled tile dividing the mesh with the most resident waves per CU (ties: the
+// larger tile), and the largest number of chunks (at least 8 planes each) whose grid still fits in
+// one round of the device's resident blocks. A timed choice (tune_defect) takes precedence.
 static bool defect_pipe_cfg(int n, bool has_f, int& tm, int& tj, int& nchunks) {
-  static const int pref[][2] = {{64, 8}, {32, 8}, {16, 8}, {8, 8}, {4, 8}};
   if (n % 8 != 0) return false;
   int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
-    return false;
-  for (const auto& p : pref) {
-    if ((n / 2) % p[0] != 0 || n % p[1] != 0) continue;
-    const void* k = nullptr;
-#define MR_DR_PTR(TM, TJ)                                                                                  \
-    if (p[0] == TM && p[1] == TJ)                                                                          \
-      k = has_f ? reinterpret_cast<const void*>(&defect_restrict_pipe<TM, TJ, true>)                        \
-                : reinterpret_cast<const void*>(&defect_restrict_pipe<TM, TJ, false>);
-    MR_DR_TILES(MR_DR_PTR)
-#undef MR_DR_PTR
-    int bpc = 0;
-    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, k, p[0] * p[1], 0) != hipSuccess || bpc < 1) continue;
-    const long tiles = (long)(n / p[1]) * (n / 2 / p[0]);
-    const long cap = (long)cus * bpc;
-    long ch = cap / tiles;
-    ch = std::max(1L, std::min(ch, (long)(n / 8)));
-    while (ch > 1 && tiles * ch > kMaxReduceBlocks) --ch;
-    if (tiles * ch > kMaxReduceBlocks) return false;
-    tm = p[0];
-    tj = p[1];
-    nchunks = (int)ch;
-    return true;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  {
+    std::lock_guard<std::mutex> lk(g_defect_tune_mu);
+    auto it = g_defect_tuned.find(std::make_tuple(dev, n, has_f));
+    if (it != g_defect_tuned.end()) {
+      tm = it->second.tm;
+      tj = it->second.tj;
+      nchunks = it->second.nchunks;
+      return true;
+    }
   }
-  return false;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) return false;
+  int best_waves = 0, best_bpc = 0;
+  auto consider = [&](int ctm, int ctj, const void* k) {
+    if ((n / 2) % ctm != 0 || n % ctj != 0 || ctj > n) return;
+    int bpc = 0;
+    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, k, ctm * ctj, 0) != hipSuccess || bpc < 1) return;
+    const int waves = bpc * ((ctm * ctj + 63) / 64);
+    if (waves > best_waves || (waves == best_waves && ctm * ctj > tm * tj)) {
+      best_waves = waves;
+      best_bpc = bpc;
+      tm = ctm;
+      tj = ctj;
+    }
+  };
+  tm = 0;
+  tj = 0;
+#define MR_DR_CONSIDER(TM, TJ)                                                                                \
+  consider(TM, TJ, has_f ? reinterpret_cast<const void*>(&defect_restrict_pipe<TM, TJ, true>)                 \
+                         : reinterpret_cast<const void*>(&defect_restrict_pipe<TM, TJ, false>));
+  MR_DR_TILES(MR_DR_CONSIDER)
+#undef MR_DR_CONSIDER
+  if (best_waves == 0) return false;
+  const long tiles = (long)(n / tj) * (n / 2 / tm);
+  const long cap = (long)cus * best_bpc;
+  long ch = cap / tiles;
+  ch = std::max(1L, std::min(ch, (long)(n / 8)));
+  while (ch > 1 && tiles * ch > kMaxReduceBlocks) --ch;
+  if (tiles * ch > kMaxReduceBlocks) return false;
+  nchunks = (int)ch;
+  return true;
+}
+
+static hipError_t launch_defect_pipe(const DefectArgs& a, int tm, int tj, int nch, hipStream_t s) {
+  const int n = a.n;
+  if (tm < 1 || tj < 2 || (n / 2) % tm != 0 || n % tj != 0 || nch < 1 || nch > n / 8 || n % 8 != 0 ||
+      (long)(n / tj) * (n / 2 / tm) * nch > kMaxReduceBlocks)
+    return hipErrorInvalidValue;
+  DefectArgs b = a;
+  b.tj = tj;
+  b.tiles_j = n / tj;
+  b.tiles_m = n / 2 / tm;
+  const unsigned blocks = (unsigned)(b.tiles_j * b.tiles_m * nch);
+#define MR_DR_GO(TM, TJ)                                                                                   \
+  if (tm == TM && tj == TJ) {                                                                              \
+    if (a.f)                                                                                               \
+      hipLaunchKernelGGL((defect_restrict_pipe<TM, TJ, true>), dim3(blocks), dim3(TM * TJ), 0, s, b, nch);  \
+    else                                                                                                   \
+      hipLaunchKernelGGL((defect_restrict_pipe<TM, TJ, false>), dim3(blocks), dim3(TM * TJ), 0, s, b, nch); \
+    return hipGetLastError();                                                                              \
+  }
+  MR_DR_TILES(MR_DR_GO)
+#undef MR_DR_GO
+  return hipErrorInvalidValue;
+}
+
+// Times the pipelined defect + restriction on every compiled tile with 1 to n/8 chunks (powers of
+// two, plus the occupancy-derived default) on the caller's buffers (the kernel only reads theta,
+// delta, f and overwrites its outputs, so repeated launches are harmless) and caches the fastest
+// per (device, n, f present).
+int tune_defect(const DefectArgs& a, hipStream_t s) {
+  const int n = a.n, nh = n / 2;
+  const bool has_f = a.f != nullptr;
+  int dev = 0;
+  if (n % 8 != 0) return MR_OK;
+  if (hipGetDevice(&dev) != hipSuccess) return hip_fail(hipErrorInvalidDevice, "defect tuner");
+  {
+    std::lock_guard<std::mutex> lk(g_defect_tune_mu);
+    if (g_defect_tuned.count(std::make_tuple(dev, n, has_f))) return MR_OK;
+  }
+  std::vector<DefectCfg> cand;
+  int tm0 = 0, tj0 = 0, nch0 = 0;
+  if (defect_pipe_cfg(n, has_f, tm0, tj0, nch0)) cand.push_back(DefectCfg{tm0, tj0, nch0});
+  auto add = [&](int tm, int tj) {
+    if (nh % tm != 0 || n % tj != 0 || tj > n) return;
+    for (int nch = 1; nch <= n / 8; nch *= 2)
+      if ((long)(n / tj) * (nh / tm) * nch <= kMaxReduceBlocks) cand.push_back(DefectCfg{tm, tj, nch});
+  };
+#define MR_DR_ADD(TM, TJ) add(TM, TJ);
+  MR_DR_TILES(MR_DR_ADD)
+#undef MR_DR_ADD
+  if (cand.empty()) return MR_OK;
+  const size_t cells = (size_t)n * n * n;
+  const int reps = cells >= ((size_t)1 << 24) ? 2 : 4;
+  size_t bi = 0;
+  const hipError_t e = pick_fastest(cand.size(), reps, s,
+                                    [&](size_t i) { return launch_defect_pipe(a, cand[i].tm, cand[i].tj, cand[i].nchunks, s); },
+                                    &bi);
+  if (e != hipSuccess) return hip_fail(e, "defect tuner");
+  std::lock_guard<std::mutex> lk(g_defect_tune_mu);
+  g_defect_tuned[std::make_tuple(dev, n, has_f)] = cand[bi];
+  return MR_OK;
 }
 
 hipError_t launch_defect_restrict_tiled(const DefectArgs& a, const TileCfg& t, hipStream_t s) {
   {
     int tm = 0, tj = 0, nch = 0;
-    if (defect_pipe_cfg(a.n, a.f != nullptr, tm, tj, nch)) {
-      DefectArgs b = a;
-      b.tj = tj;
-      b.tiles_j = a.n / tj;
-      b.tiles_m = a.n / 2 / tm;
-      const unsigned blocks = (unsigned)(b.tiles_j * b.tiles_m * nch);
-#define MR_DR_LAUNCH(TM, TJ)                                                                                 \
-      if (tm == TM && tj == TJ) {                                                                            \
-        if (a.f)                                                                                             \
-          hipLaunchKernelGGL((defect_restrict_pipe<TM, TJ, true>), dim3(blocks), dim3(TM * TJ), 0, s, b, nch);  \
-        else                                                                                                 \
-          hipLaunchKernelGGL((defect_restrict_pipe<TM, TJ, false>), dim3(blocks), dim3(TM * TJ), 0, s, b, nch); \
-        return hipGetLastError();                                                                            \
-      }
-      MR_DR_TILES(MR_DR_LAUNCH)
-#undef MR_DR_LAUNCH
-    }
+    if (defect_pipe_cfg(a.n, a.f != nullptr, tm, tj, nch)) return launch_defect_pipe(a, tm, tj, nch, s);
   }
   const int threads = tile_threads(t, t.tm * (t.tj / 2));
   if (!tile_ok(t, a.n, threads) || t.tj % 2 != 0 || t.ci % 2 != 0) return hipErrorInvalidValue;
