@@ -179,9 +179,11 @@ int mr_solve_batched(int nbox, const int* n, const double* const* delta, double*
                      const mr_opts* opts, mr_info* infos, void* hip_stream);
 
 /* Tile tuner of the FP32 linear sweep used by mr_solve_batched: times every compiled tile shape
- * and plane-chunk length on one synthetic n^3 box on the current device, and returns (and caches
- * per device and n) the fastest: tm cells along z/2, tj rows, ci planes per block, ms the time of
- * one red+black sweep. Any output pointer may be NULL. n: multiple of 4, 8..1024. */
+ * and plane-chunk length on a launch over several synthetic n^3 boxes (as many as fill 2^25 cells,
+ * 1 to 64: the batched solve launches all boxes of a size together) on the current device, and
+ * returns (and caches per device and n) the fastest: tm cells along z/2, tj rows, ci planes per
+ * block, ms the time of one red+black sweep per box. Any output pointer may be NULL.
+ * n: multiple of 4, 8..1024. */
 int mr_tune_lin_tiles(int n, void* hip_stream, int* tm, int* tj, int* ci, float* ms);
 
 /* ---- Building blocks of the cycle, exported so that each can be checked in isolation. ----

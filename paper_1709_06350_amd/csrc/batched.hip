@@ -219,7 +219,7 @@ __global__ void __launch_bounds__(256) b_update_kernel(const BBox* boxes, const 
 
 // ---- FP32 sweep tile tuner ----------------------------------------------------------------
 
-#define MR_BLIN_TILES(X) X(64, 4) X(32, 8) X(16, 16) X(8, 16) X(4, 8) X(2, 4)
+#define MR_BLIN_TILES(X) X(64, 16) X(64, 8) X(64, 4) X(32, 8) X(16, 16) X(8, 16) X(4, 8) X(2, 4)
 #define MR_BRT_TILES(X) X(64, 8) X(32, 8) X(16, 8) X(8, 8) X(4, 8)
 
 static hipError_t launch_b_lin_sweep(const BBox* boxes, const int* cls, int nb, const TileCfg& t, int l, int colour, int cur,
@@ -245,10 +245,10 @@ static hipError_t launch_b_lin_sweep(const BBox* boxes, const int* cls, int nb, 
 static std::vector<TileCfg> lin_candidates(int n) {
   std::vector<TileCfg> out;
   const int nh = n / 2;
-  static const int shapes[][2] = {{64, 4}, {32, 8}, {16, 16}, {8, 16}, {4, 8}, {2, 4}};
+  static const int shapes[][2] = {{64, 16}, {64, 8}, {64, 4}, {32, 8}, {16, 16}, {8, 16}, {4, 8}, {2, 4}};
   for (const auto& sh : shapes) {
     if (nh % sh[0] != 0 || sh[0] > nh || n % sh[1] != 0 || sh[1] > n) continue;
-    for (int ci : {4, 8, 16, 32, 64}) {
+    for (int ci : {4, 8, 16, 32, 64, 128, 256}) {
       if (ci > n || n % ci != 0) continue;
       TileCfg t;
       t.tm = sh[0];
@@ -267,11 +267,17 @@ static std::vector<TileCfg> lin_candidates(int n) {
 static std::mutex g_tune_mu;
 static std::map<std::pair<int, int>, std::pair<TileCfg, float>> g_tuned;   // (device, n) -> (tile, ms)
 
-// Times every compiled FP32 sweep shape on one synthetic n^3 box (red + black half-sweeps) and
-// keeps the fastest. The measurement uses the same multi-box kernel as the batched solve.
+// Times every compiled FP32 sweep shape and chunk length on nb synthetic n^3 boxes (red + black
+// half-sweeps of all of them in one launch each, as the batched solve launches a size class) and
+// keeps the fastest: with many boxes in a launch the best tile is larger and the chunks longer
+// than for one box. The box count is a fixed function of n (as many boxes as fill 2^25 cells,
+// 1 to 64), not the batch's, so a box's schedule and hence its result do not depend on the other
+// boxes of a batch. Cached per (device, n).
 int tune_lin_tiles(int n, hipStream_t s, TileCfg* out, float* ms_out) {
   int dev = 0;
   (void)hipGetDevice(&dev);
+  const size_t cells = (size_t)n * n * n;
+  const int nb = (int)std::max<size_t>(1, std::min<size_t>(64, ((size_t)1 << 25) / cells));
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tuned.find({dev, n});
@@ -281,7 +287,6 @@ int tune_lin_tiles(int n, hipStream_t s, TileCfg* out, float* ms_out) {
       return MR_OK;
     }
   }
-  const size_t cells = (size_t)n * n * n;
   std::vector<void*> mem;
   auto get = [&](size_t bytes) -> void* {
     void* p = nullptr;
@@ -289,79 +294,81 @@ int tune_lin_tiles(int n, hipStream_t s, TileCfg* out, float* ms_out) {
     mem.push_back(p);
     return p;
   };
-  float *e0 = (float*)get(cells * 4), *e1 = (float*)get(cells * 4), *rhs = (float*)get(cells * 4),
-        *base = (float*)get(cells * 4), *sb = (float*)get(cells * 4);
-  double* aux = (double*)get(64 * 8);
-  double* part = (double*)get((size_t)kBoxPartials * kMaxNV * 8);
-  unsigned* cnt = (unsigned*)get(64 * 4);
-  BBox* dbox = (BBox*)get(sizeof(BBox));
-  BStat* dst = (BStat*)get(sizeof(BStat));
-  int* dcls = (int*)get(sizeof(int));
+  std::vector<BBox> hb(nb);
+  bool ok = true;
+  for (int k = 0; k < nb && ok; ++k) {
+    float *e0 = (float*)get(cells * 4), *e1 = (float*)get(cells * 4), *rhs = (float*)get(cells * 4),
+          *base = (float*)get(cells * 4), *sb = (float*)get(cells * 4);
+    double* aux = (double*)get(64 * 8);
+    double* part = (double*)get((size_t)kBoxPartials * kMaxNV * 8);
+    unsigned* cnt = (unsigned*)get(64 * 4);
+    BStat* dst = (BStat*)get(sizeof(BStat));
+    ok = e0 && e1 && rhs && base && sb && aux && part && cnt && dst;
+    if (!ok) break;
+    hb[k] = BBox{};
+    hb[k].lv[0].e[0] = e0;
+    hb[k].lv[0].e[1] = e1;
+    hb[k].lv[0].rhs = rhs;
+    hb[k].lv[0].base = base;
+    hb[k].lv[0].sb = sb;
+    hb[k].lv[0].lsum = aux;
+    hb[k].partials = part;
+    hb[k].counter = cnt;
+    hb[k].st = dst;
+  }
+  BBox* dbox = ok ? (BBox*)get(sizeof(BBox) * nb) : nullptr;
+  int* dcls = ok ? (int*)get(sizeof(int) * nb) : nullptr;
   int rc = MR_OK;
   std::vector<TileCfg> cand = lin_candidates(n);
-  TileCfg best;
-  float best_ms = 1e30f;
-  hipEvent_t a = nullptr, b = nullptr;
-  if (!e0 || !e1 || !rhs || !base || !sb || !aux || !part || !cnt || !dbox || !dst || !dcls || cand.empty()) {
+  size_t bi = 0;
+  float best_ms = 0.0f;
+  if (!ok || !dbox || !dcls || cand.empty()) {
     rc = fail(MR_ENOMEM, "tile tuner: allocation failed or no candidate shape for n = %d", n);
   } else {
     // benign synthetic state: e = 0, rhs = 0, flat base potential, base root 3
-    hipError_t e = hipMemsetAsync(e0, 0, cells * 4, s);
-    if (e == hipSuccess) e = hipMemsetAsync(e1, 0, cells * 4, s);
-    if (e == hipSuccess) e = hipMemsetAsync(rhs, 0, cells * 4, s);
-    if (e == hipSuccess) e = hipMemsetAsync(base, 0, cells * 4, s);
-    if (e == hipSuccess) e = launch_fill32(sb, 3.0f, cells, s);
-    if (e == hipSuccess) e = hipMemsetAsync(aux, 0, 64 * 8, s);
-    if (e == hipSuccess) e = hipMemsetAsync(cnt, 0, 64 * 4, s);
-    BBox hb{};
-    hb.lv[0].e[0] = e0;
-    hb.lv[0].e[1] = e1;
-    hb.lv[0].rhs = rhs;
-    hb.lv[0].base = base;
-    hb.lv[0].sb = sb;
-    hb.lv[0].lsum = aux;
-    hb.partials = part;
-    hb.counter = cnt;
-    hb.st = dst;
+    hipError_t e = hipSuccess;
     BStat hs{};
     hs.active = 1;
-    const int zero = 0;
-    if (e == hipSuccess) e = hipMemcpyAsync(dbox, &hb, sizeof hb, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(dst, &hs, sizeof hs, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(dcls, &zero, sizeof zero, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipEventCreate(&a);
-    if (e == hipSuccess) e = hipEventCreate(&b);
-    for (const TileCfg& t : cand) {
-      if (e != hipSuccess) break;
-      for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_b_lin_sweep(dbox, dcls, 1, t, 0, w & 1, 0, n, 1.0, s);
-      if (e == hipSuccess) e = hipEventRecord(a, s);
-      const int reps = 6;
-      for (int r = 0; r < reps && e == hipSuccess; ++r) {
-        e = launch_b_lin_sweep(dbox, dcls, 1, t, 0, 0, 0, n, 1.0, s);
-        if (e == hipSuccess) e = launch_b_lin_sweep(dbox, dcls, 1, t, 0, 1, 0, n, 1.0, s);
-      }
-      if (e == hipSuccess) e = hipEventRecord(b, s);
-      if (e == hipSuccess) e = hipEventSynchronize(b);
-      float ms = 0.0f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, a, b);
-      ms /= 6.0f;
-      if (e == hipSuccess && ms < best_ms) {
-        best_ms = ms;
-        best = t;
-      }
+    std::vector<int> idx(nb);
+    for (int k = 0; k < nb && e == hipSuccess; ++k) {
+      const BLevel& L = hb[k].lv[0];
+      for (float* f : {L.e[0], L.e[1], L.rhs, L.base})
+        if (e == hipSuccess) e = hipMemsetAsync(f, 0, cells * 4, s);
+      if (e == hipSuccess) e = launch_fill32(L.sb, 3.0f, cells, s);
+      if (e == hipSuccess) e = hipMemsetAsync(L.lsum, 0, 64 * 8, s);
+      if (e == hipSuccess) e = hipMemsetAsync(hb[k].counter, 0, 64 * 4, s);
+      if (e == hipSuccess) e = hipMemcpyAsync(hb[k].st, &hs, sizeof hs, hipMemcpyHostToDevice, s);
+      idx[k] = k;
     }
+    if (e == hipSuccess) e = hipMemcpyAsync(dbox, hb.data(), sizeof(BBox) * nb, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dcls, idx.data(), sizeof(int) * nb, hipMemcpyHostToDevice, s);
+    auto run = [&](size_t i) {
+      hipError_t x = launch_b_lin_sweep(dbox, dcls, nb, cand[i], 0, 0, 0, n, 1.0, s);
+      return x == hipSuccess ? launch_b_lin_sweep(dbox, dcls, nb, cand[i], 0, 1, 0, n, 1.0, s) : x;
+    };
+    if (e == hipSuccess) e = pick_fastest(cand.size(), 4, s, run, &bi);
+    // time of the winner alone (reported)
+    hipEvent_t ea = nullptr, eb = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&ea);
+    if (e == hipSuccess) e = hipEventCreate(&eb);
+    if (e == hipSuccess) e = hipEventRecord(ea, s);
+    for (int r = 0; r < 4 && e == hipSuccess; ++r) e = run(bi);
+    if (e == hipSuccess) e = hipEventRecord(eb, s);
+    if (e == hipSuccess) e = hipEventSynchronize(eb);
+    if (e == hipSuccess) e = hipEventElapsedTime(&best_ms, ea, eb);
+    best_ms /= 4.0f * nb;
+    if (ea) (void)hipEventDestroy(ea);
+    if (eb) (void)hipEventDestroy(eb);
     if (e != hipSuccess) rc = hip_fail(e, "tile tuner");
   }
-  if (a) (void)hipEventDestroy(a);
-  if (b) (void)hipEventDestroy(b);
   (void)hipStreamSynchronize(s);
   for (void* p : mem) (void)hipFree(p);
   if (rc != MR_OK) return rc;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tuned[{dev, n}] = {best, best_ms};
+    g_tuned[{dev, n}] = {cand[bi], best_ms};
   }
-  *out = best;
+  *out = cand[bi];
   if (ms_out) *ms_out = best_ms;
   return MR_OK;
 }
@@ -583,18 +590,20 @@ int solve_batched(int nbox, const int* n, const double* const* delta, double* co
       c.nlev = (int)c.ns.size();
       if (c.nlev < 2) return fail(MR_EINVAL, "batched: box size %d has a single level", n[b]);
       for (int l = 0; l < c.nlev; ++l) c.hs.push_back(std::ldexp(1.0, l));
-      for (int l = 0; l < c.nlev; ++l) {
-        TileCfg t;
-        if (l < c.nlev - 1) {
-          int rc = tune_lin_tiles(c.ns[l], s, &t, nullptr);
-          if (rc != MR_OK) return rc;
-        }
-        c.tiles.push_back(t);
-      }
       cls.push_back(c);
     }
     cls[cls_of_n[n[b]]].boxes.push_back(b);
   }
+  // FP32 sweep tile per level (timed once per device and size)
+  for (auto& c : cls)
+    for (int l = 0; l < c.nlev; ++l) {
+      TileCfg t;
+      if (l < c.nlev - 1) {
+        int rc = tune_lin_tiles(c.ns[l], s, &t, nullptr);
+        if (rc != MR_OK) return rc;
+      }
+      c.tiles.push_back(t);
+    }
   for (auto& c : cls) {
     c.resid = pick_btile(c.n);
     c.rr.assign(c.nlev, BTile{});
