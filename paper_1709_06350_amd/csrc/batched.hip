@@ -242,14 +242,20 @@ static hipError_t launch_b_lin_sweep(const BBox* boxes, const int* cls, int nb, 
   return hipErrorInvalidValue;
 }
 
+// Candidate shapes and chunk lengths: tiles of at least 128 threads and chunks of at least 8
+// planes where the mesh allows them (smaller ones only on meshes too small for those).
 static std::vector<TileCfg> lin_candidates(int n) {
   std::vector<TileCfg> out;
   const int nh = n / 2;
   static const int shapes[][2] = {{64, 16}, {64, 8}, {64, 4}, {32, 8}, {16, 16}, {8, 16}, {4, 8}, {2, 4}};
+  auto fits = [&](const int* sh) { return nh % sh[0] == 0 && sh[0] <= nh && n % sh[1] == 0 && sh[1] <= n; };
+  bool big = false;
+  for (const auto& sh : shapes) big = big || (fits(sh) && sh[0] * sh[1] >= 128);
+  const int min_ci = n >= 16 ? 8 : 4;
   for (const auto& sh : shapes) {
-    if (nh % sh[0] != 0 || sh[0] > nh || n % sh[1] != 0 || sh[1] > n) continue;
+    if (!fits(sh) || (big && sh[0] * sh[1] < 128)) continue;
     for (int ci : {4, 8, 16, 32, 64, 128, 256}) {
-      if (ci > n || n % ci != 0) continue;
+      if (ci > n || n % ci != 0 || ci < min_ci) continue;
       TileCfg t;
       t.tm = sh[0];
       t.tj = sh[1];
