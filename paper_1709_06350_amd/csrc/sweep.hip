@@ -745,13 +745,24 @@ __global__ void __launch_bounds__(TM * TJ) tau_pipe(const double* __restrict__ t
     const double* l1 = lds + 4 * SLOT;
     const int oqc0 = (K & 1) ? oq01 : oq00;
     const int oqc1 = (K & 1) ? oq00 : oq01;
-    Nb18 c0, c1;
-    gather(l1, l0, SM, S0, SP, oqc0, c0);
-    gather(l0, l1, SM, S0, SP, oqc1, c1);
-    double S[2], pp[2], qq[2], sr[2];
-    cell_pq(c0, 1.0 + D[K][0], ih2, S[0], pp[0], qq[0]);
-    cell_pq(c1, 1.0 + D[K][1], ih2, S[1], pp[1], qq[1]);
-    largest_roots<2>(pp, qq, sr);
+    // the two colours' roots one after the other (fewer live registers than iterating both)
+    double S[2], sr[2];
+    {
+      Nb18 c0;
+      gather(l1, l0, SM, S0, SP, oqc0, c0);
+      double pp[1], qq[1], r1[1];
+      cell_pq(c0, 1.0 + D[K][0], ih2, S[0], pp[0], qq[0]);
+      largest_roots<1>(pp, qq, r1);
+      sr[0] = r1[0];
+    }
+    {
+      Nb18 c1;
+      gather(l0, l1, SM, S0, SP, oqc1, c1);
+      double pp[1], qq[1], r1[1];
+      cell_pq(c1, 1.0 + D[K][1], ih2, S[1], pp[0], qq[0]);
+      largest_roots<1>(pp, qq, r1);
+      sr[1] = r1[0];
+    }
     const unsigned e0 = (unsigned)(i0 + t) * plane + own;
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
