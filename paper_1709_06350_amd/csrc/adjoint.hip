@@ -558,8 +558,9 @@ static AdjCfg fixed_tiled_cfg(int n, int level) {
 static std::mutex g_adj_tune_mu;
 static std::map<std::pair<int, int>, AdjCfg> g_adj_tuned;   // (device, n)
 
-// Times both colours of a sweep for the row kernel and every compiled tile with chunks of 8 to
-// 256 planes (with and without the coefficient prefetch), on the level's own (zeroed) buffers, and keeps the fastest. Cached per (device, n).
+// Times both colours of a sweep for the row kernel and every compiled tile (of at least 128
+// threads where one fits) with chunks of 8 to 256 planes, with and without the coefficient
+// prefetch, on the level's own (zeroed) buffers, and keeps the fastest. Cached per (device, n).
 static int tune_adj_sweep(const AdjSweepArgs& base, hipStream_t s, AdjCfg* out) {
   const int n = base.n, nh = n / 2;
   int dev = 0;
@@ -573,8 +574,14 @@ static int tune_adj_sweep(const AdjSweepArgs& base, hipStream_t s, AdjCfg* out) 
     }
   }
   std::vector<AdjCfg> cand{AdjCfg{}};
+  // tiles of at least 128 threads where one fits (smaller ones only on small meshes)
+  bool big = false;
+  auto fits = [&](int tm, int tj) { return nh % tm == 0 && n % tj == 0 && tj <= n; };
+#define MR_AP_BIG(TM, TJ) big = big || (fits(TM, TJ) && TM * TJ >= 128);
+  MR_AP_TILES(MR_AP_BIG)
+#undef MR_AP_BIG
   auto add = [&](int tm, int tj) {
-    if (nh % tm != 0 || n % tj != 0 || tj > n) return;
+    if (!fits(tm, tj) || (big && tm * tj < 128)) return;
     const long tiles = (long)(nh / tm) * (n / tj);
     for (int ci = 8; ci <= 256 && ci <= n; ci *= 2) {
       if (n % ci != 0 || tiles * (n / ci) > kMaxReduceBlocks) continue;
