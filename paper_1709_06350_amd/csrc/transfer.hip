@@ -143,10 +143,94 @@ __global__ void __launch_bounds__(256) prolong_quad_kernel(const double* __restr
     }
 }
 
+// The same update with the coarse neighbourhood staged in LDS: a block of 256 threads covers coarse
+// plane I, rows J0 .. J0 + R - 1 (R = 256 / nc) and every column K; it first copies the coarse rows
+// I-1..I+1 x J0-1..J0+R of both colours into LDS in natural k order (coalesced along each colour),
+// then each thread reads its 3 x 3 x 3 neighbourhood from LDS. Requires nc = n / 2 to divide 256
+// and R <= nc (16 <= nc <= 256).
+template <bool SHIFT>
+__global__ void __launch_bounds__(256) prolong_rows_kernel(const double* __restrict__ ec, const double* mu_sum,
+                                                           double mu_scale, double* __restrict__ theta, int n) {
+  __shared__ double cl[3 * (256 + 2 * 256)];   // 3 planes x (R + 2) rows x nc = 3 (256 + 2 nc), nc <= 256
+  const int nc = n >> 1, nh = nc, nch = nc >> 1;
+  const int R = 256 / nc;
+  const int groups = nc / R;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int I = blk / groups, J0 = (blk - I * groups) * R;
+  const int tid = threadIdx.x;
+  const double mu = SHIFT && mu_sum ? (mu_sum[0] + mu_sum[1]) * mu_scale : 0.0;
+  const unsigned halfc = (unsigned)nc * (unsigned)nc * (unsigned)nch;
+  // loader: LDS row w = a * (R + 2) + b holds coarse row (I - 1 + a, J0 - 1 + b); element index
+  // x = w * nc + c * nch + m (colour-major inside a row) goes to position k = 2m + ((ii + jj + c) & 1)
+  const int rows = 3 * (R + 2);
+  for (int x = tid; x < rows * nc; x += 256) {
+    const int w = x / nc, pos = x - w * nc;
+    const int a = w / (R + 2), b = w - a * (R + 2);
+    const int c = pos / nch, m = pos - c * nch;
+    const int ii = wrapi(I - 1 + a, nc), jj = wrapi(J0 - 1 + b, nc);
+    const double v = ec[(unsigned)c * halfc + ((unsigned)ii * nc + jj) * (unsigned)nch + m];
+    cl[w * nc + 2 * m + ((ii + jj + c) & 1)] = SHIFT ? v - mu : v;
+  }
+  __syncthreads();
+  const int r = tid / nc, K = tid - r * nc;
+  const int J = J0 + r;
+  const int km = K == 0 ? nc - 1 : K - 1, kp = K == nc - 1 ? 0 : K + 1;
+  double e[3][3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const double* row = cl + (a * (R + 2) + r + b) * nc;
+      e[a][b][0] = row[km];
+      e[a][b][1] = row[K];
+      e[a][b][2] = row[kp];
+    }
+  const unsigned half = (unsigned)n * (unsigned)n * (unsigned)nh;
+  unsigned off[2][2];
+  int c0[2][2];
+  double t[2][2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int i = 2 * I + a, j = 2 * J + b;
+      off[a][b] = ((unsigned)i * n + j) * (unsigned)nh + K;
+      c0[a][b] = (i + j) & 1;
+      t[a][b][0] = theta[c0[a][b] * half + off[a][b]];
+      t[a][b][1] = theta[(1 - c0[a][b]) * half + off[a][b]];
+    }
+  const double wI[2] = {0.75, 0.25};
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int a2 = a ? 2 : 0, b2 = b ? 2 : 0;
+      double lo = 0.0, hi = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ia = (q & 2) ? a2 : 1, jb = (q & 1) ? b2 : 1;
+        const double w = wI[(q >> 1) & 1] * wI[q & 1];
+        const double ek = e[ia][jb][1];
+        lo += w * (0.75 * ek + 0.25 * e[ia][jb][0]);
+        hi += w * (0.75 * ek + 0.25 * e[ia][jb][2]);
+      }
+      theta[c0[a][b] * half + off[a][b]] = t[a][b][0] + lo;
+      theta[(1 - c0[a][b]) * half + off[a][b]] = t[a][b][1] + hi;
+    }
+}
+
 hipError_t launch_prolong_add(const double* ec, const double* mu_sum, double mu_scale, double* theta, int n,
                               hipStream_t s) {
   const long total = (long)(n / 2) * (n / 2) * (n / 2);
   const unsigned blocks = (unsigned)((total + 255) / 256);
+  const int nc = n / 2;
+  if (nc >= 16 && nc <= 256 && 256 % nc == 0) {   // blocks = nc^3 / 256: whole row groups
+    if (mu_sum)
+      hipLaunchKernelGGL((prolong_rows_kernel<true>), dim3(blocks), dim3(256), 0, s, ec, mu_sum, mu_scale, theta, n);
+    else
+      hipLaunchKernelGGL((prolong_rows_kernel<false>), dim3(blocks), dim3(256), 0, s, ec, mu_sum, mu_scale, theta, n);
+    return hipGetLastError();
+  }
   if (mu_sum)
     hipLaunchKernelGGL((prolong_quad_kernel<true>), dim3(blocks), dim3(256), 0, s, ec, mu_sum, mu_scale, theta, n);
   else

@@ -115,7 +115,9 @@ def test_tau_rhs_matches_oracle(ctx, n, h):
     assert abs(s - (sig + ref).sum()) <= 1e-11 * (np.abs(sig).sum() + 1)
 
 
-@pytest.mark.parametrize("n", [8, 32, 48])
+# 8 and 48: one coarse cell per thread (coarse size does not divide 256); 32 ... 512: coarse rows
+# staged in LDS (32: 16 rows per block, 512: one row segment per block, the 512^3 solve's finest)
+@pytest.mark.parametrize("n", [8, 32, 48, 64, 128, 512])
 def test_prolong_correct_and_restrict_match_oracle(ctx, n):
     announce(f"prolong/restrict n={n}")
     rng = np.random.default_rng(n)
