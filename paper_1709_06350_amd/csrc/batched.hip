@@ -201,6 +201,16 @@ __global__ void __launch_bounds__(512) b_prolong_kernel(const BBox* boxes, const
   prolong_add32_body(x.lv[l + 1].e[cur_c], x.lv[l].e[cur_f], n, t, bpb);
 }
 
+// Sizes with prolong_rows_ok: bpb = (n/2)^3 / 256 row groups per box, 256 threads each.
+__global__ void __launch_bounds__(256) b_prolong_rows_kernel(const BBox* boxes, const int* cls, int bpb, int l,
+                                                             int cur_c, int cur_f, int n) {
+  __shared__ float cl[kProlongRowsLds];
+  int b, t;
+  if (!box_of(boxes, cls, bpb, b, t)) return;
+  const BBox& x = boxes[b];
+  prolong_rows32_body(x.lv[l + 1].e[cur_c], x.lv[l].e[cur_f], n, t, cl);
+}
+
 __global__ void __launch_bounds__(256) b_coarsest_kernel(const BBox* boxes, const int* cls, int l, int cur, int n,
                                                          int nsweeps, float h2, float ih2) {
   extern __shared__ unsigned char smem[];
@@ -555,9 +565,15 @@ static int record_iteration(std::vector<SizeClass>& cls, BBox* dboxes, const mr_
         if (l >= c.nlev - 1) continue;
         const int n = c.ns[l];
         const double h = c.hs[l];
-        const int bpb = rows_grid_b(n * n);
-        hipLaunchKernelGGL(b_prolong_kernel, dim3(nb * bpb), dim3(n / 2 < 512 ? n / 2 : 512), 0, s, dboxes, c.d_boxes, bpb,
-                           l, cur[ci][l + 1], cur[ci][l], n);
+        if (prolong_rows_ok(n)) {
+          const int bpb = (n / 2) * (n / 2) * (n / 2) / 256;
+          hipLaunchKernelGGL(b_prolong_rows_kernel, dim3(nb * bpb), dim3(256), 0, s, dboxes, c.d_boxes, bpb, l,
+                             cur[ci][l + 1], cur[ci][l], n);
+        } else {
+          const int bpb = rows_grid_b(n * n);
+          hipLaunchKernelGGL(b_prolong_kernel, dim3(nb * bpb), dim3(n / 2 < 512 ? n / 2 : 512), 0, s, dboxes, c.d_boxes,
+                             bpb, l, cur[ci][l + 1], cur[ci][l], n);
+        }
         if (!ok()) return hip_fail(e, "batched prolongation");
         for (int sw = 0; sw < o.npost; ++sw) {
           e = launch_b_lin_sweep(dboxes, c.d_boxes, nb, c.tiles[l], l, 0, cur[ci][l], n, h, s);

@@ -273,8 +273,17 @@ hipError_t launch_lin_resid_restrict(const float* e, const float* base, const fl
   return hipGetLastError();
 }
 
+__global__ void __launch_bounds__(256) prolong_rows32_kernel(const float* __restrict__ ec, float* __restrict__ e, int n) {
+  __shared__ float cl[kProlongRowsLds];
+  prolong_rows32_body(ec, e, n, xcd_remap(blockIdx.x, gridDim.x), cl);
+}
+
 hipError_t launch_prolong_add32(const float* ec, float* e, int n, hipStream_t s) {
   const long cc = (long)(n / 2) * (n / 2) * (n / 2);   // one thread per coarse cell
+  if (prolong_rows_ok(n)) {   // cc / 256 whole row groups
+    hipLaunchKernelGGL(prolong_rows32_kernel, dim3((unsigned)(cc / 256)), dim3(256), 0, s, ec, e, n);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(prolong_add32_kernel, dim3((unsigned)((cc + 255) / 256)), dim3(256), 0, s, ec, e, n);
   return hipGetLastError();
 }

@@ -337,6 +337,80 @@ inline __device__ void prolong_add32_body(const float* __restrict__ ec, float* _
   }
 }
 
+// The same update with the coarse neighbourhood staged in LDS, for coarse sizes nc = n / 2 that
+// divide 256 with 16 <= nc <= 256: row group blk (of nc^3 / 256) covers coarse plane I, rows
+// J0 .. J0 + R - 1 (R = 256 / nc) and every column; its 256 threads first copy coarse rows
+// I-1..I+1 x J0-1..J0+R of both colours into cl (3 (256 + 2 nc) floats) in natural k order, then
+// each thread updates the 8 fine sons of its coarse cell from the staged neighbourhood.
+inline __host__ __device__ bool prolong_rows_ok(int n) {
+  const int nc = n / 2;
+  return nc >= 16 && nc <= 256 && 256 % nc == 0;
+}
+inline __device__ void prolong_rows32_body(const float* __restrict__ ec, float* __restrict__ e, int n, int blk,
+                                           float* __restrict__ cl) {
+  const int nc = n >> 1, nh = nc, nch = nc >> 1;
+  const int R = 256 / nc;
+  const int groups = nc / R;
+  const int I = blk / groups, J0 = (blk - I * groups) * R;
+  const int tid = threadIdx.x;
+  const unsigned halfc = (unsigned)nc * (unsigned)nc * (unsigned)nch;
+  const int rows = 3 * (R + 2);
+  for (int x = tid; x < rows * nc; x += 256) {
+    const int w = x / nc, pos = x - w * nc;
+    const int a = w / (R + 2), b = w - a * (R + 2);
+    const int c = pos / nch, m = pos - c * nch;
+    const int ii = wrapi(I - 1 + a, nc), jj = wrapi(J0 - 1 + b, nc);
+    cl[w * nc + 2 * m + ((ii + jj + c) & 1)] = ec[(unsigned)c * halfc + ((unsigned)ii * nc + jj) * (unsigned)nch + m];
+  }
+  __syncthreads();
+  const int r = tid / nc, K = tid - r * nc;
+  const int J = J0 + r;
+  const int km = K == 0 ? nc - 1 : K - 1, kp = K == nc - 1 ? 0 : K + 1;
+  float c3[3][3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const float* row = cl + (a * (R + 2) + r + b) * nc;
+      c3[a][b][0] = row[km];
+      c3[a][b][1] = row[K];
+      c3[a][b][2] = row[kp];
+    }
+  const unsigned half = (unsigned)n * (unsigned)n * (unsigned)nh;
+  unsigned off[2][2];
+  int c0[2][2];
+  float t[2][2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int i = 2 * I + a, j = 2 * J + b;
+      off[a][b] = ((unsigned)i * n + j) * (unsigned)nh + K;
+      c0[a][b] = (i + j) & 1;
+      t[a][b][0] = e[c0[a][b] * half + off[a][b]];
+      t[a][b][1] = e[(1 - c0[a][b]) * half + off[a][b]];
+    }
+  const float wI[2] = {0.75f, 0.25f};
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int a2 = a ? 2 : 0, b2 = b ? 2 : 0;
+      float lo = 0.0f, hi = 0.0f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int ia = (q & 2) ? a2 : 1, jb = (q & 1) ? b2 : 1;
+        const float w = wI[(q >> 1) & 1] * wI[q & 1];
+        const float ek = c3[ia][jb][1];
+        lo += w * (0.75f * ek + 0.25f * c3[ia][jb][0]);
+        hi += w * (0.75f * ek + 0.25f * c3[ia][jb][2]);
+      }
+      e[c0[a][b] * half + off[a][b]] = t[a][b][0] + lo;
+      e[(1 - c0[a][b]) * half + off[a][b]] = t[a][b][1] + hi;
+    }
+}
+constexpr int kProlongRowsLds = 3 * (256 + 2 * 256);   // floats of cl
+
 // Linear coarsest solve: nsweeps red-black sweeps in one block (FP32, natural order in LDS).
 struct LinCoarsestShared {
   float te[kMaxCoarsest], tb[kMaxCoarsest], ts[kMaxCoarsest], tr[kMaxCoarsest], tn[kMaxCoarsest];
