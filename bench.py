@@ -140,6 +140,7 @@ def cic_run():
 
     n = 256
     pos = torch.from_numpy(inputs.zeldovich_particles(n, 4.0, 1001)).cuda()
+    theta = torch.from_numpy(40.0 * inputs.grf(n, 4.0, 1006)).cuda()   # a smooth synthetic potential
     with mr.Context(n) as c:
         out = c.deposit_cic(pos)
         torch.cuda.synchronize()
@@ -149,9 +150,19 @@ def cic_run():
             c.deposit_cic(pos, out=out)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
+        # Lagrangian mapping of the same particles (mesh displacement + CIC gather)
+        disp, psi = c.lagrangian(theta, pos, want_psi=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            c.lagrangian(theta, pos, want_psi=True, out=disp)
+        torch.cuda.synchronize()
+        dl = (time.perf_counter() - t0) / reps
     npart = pos.shape[0]
-    return {"particles": npart, "mesh": n, "seconds": round(dt, 5),
-            "gparticles_per_s": round(npart / dt / 1e9, 3)}
+    cic = {"particles": npart, "mesh": n, "seconds": round(dt, 5), "gparticles_per_s": round(npart / dt / 1e9, 3)}
+    lag = {"particles": npart, "mesh": n, "seconds": round(dl, 5), "gparticles_per_s": round(npart / dl / 1e9, 3),
+           "note": "mesh displacement grad(theta) into a caller buffer + CIC gather to the particles"}
+    return cic, lag
 
 
 def adjoint_run(ctx, delta, theta):
@@ -304,7 +315,7 @@ def main():
     }
     if not args.no_extra:
         out["adjoint"] = adjoint_run(ctx, delta, theta)
-        out["cic"] = cic_run()
+        out["cic"], out["lagrangian"] = cic_run()
     if not args.no_batched:
         out["batched"] = batched_run()
     if not args.no_cpu_baseline:

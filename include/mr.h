@@ -140,6 +140,22 @@ int mr_set_schedule(mr_ctx* ctx, int level, const int sched[4]);
  * of weight; the total is checked after the deposit and an overflow returns MR_EINVAL. */
 int mr_deposit_cic(mr_ctx* ctx, const double* pos, int64_t np, double mass, double* delta_out);
 
+/* Lagrangian mapping (the step after the solve). With Theta = Theta_0 + theta and
+ * Theta_0 = |x|^2 / 2 (Sec. II), the Lagrangian coordinate is q = grad Theta = x + grad theta, so the
+ * displacement is psi = grad theta (x - q = -grad theta, Sec. III). theta: device n^3 in natural
+ * order (e.g. the output of mr_solve). On the mesh psi is the second-order central difference
+ * (theta(i+1) - theta(i-1)) / 2 per axis (cell units; the discretisation section), periodic; at
+ * each particle (pos: device np x 3 doubles in cell units, any real value, wrapped as in
+ * mr_deposit_cic) it is interpolated with the CIC weights of mr_deposit_cic (the transpose of the
+ * deposit). disp_out: device np x 3, receives psi(x_p), so that q_p = x_p + disp_p. psi_out: device
+ * n^3 x 3 doubles laid out [i][j][k][axis], receives the mesh field, or NULL (the field then lives
+ * in a temporary allocated and freed by the call). The call synchronizes the context's stream.
+ * Returns MR_EINVAL for a NULL argument, np < 1 or a particle with a non-finite coordinate (such a
+ * particle's output is NaN, the others are computed), MR_ENOMEM if the temporary cannot be
+ * allocated. */
+int mr_lagrangian(mr_ctx* ctx, const double* theta, const double* pos, int64_t np, double* disp_out,
+                  double* psi_out);
+
 /* Residual of a given theta (Sec. II.A.1, Eq. 15 with the mean projection):
  * r = nabla^2 theta - (Sigma - <Sigma>). r_out: device n^3 or NULL. rel_out: host, receives
  * ||r||_2 / ||r(theta = 0)||_2 (NULL allowed). msum_out: host, receives <Sigma> (NULL allowed). */

@@ -8,6 +8,7 @@
 // so the result is bitwise reproducible. Particles are processed in their input order by
 // consecutive threads; for lattice-ordered catalogues (as produced by displacing a lattice)
 // neighbouring lanes hit neighbouring cells, which keeps the L2 atomics local.
+#include <algorithm>
 #include <cmath>
 
 #include "mr.h"
@@ -113,6 +114,111 @@ int Ctx::deposit_cic(const double* pos, long long np, double mass, double* delta
   return MR_OK;
 }
 
+// ---- Lagrangian mapping -----------------------------------------------------------------------
+// q = grad Theta = x + grad theta (Theta_0 = |x|^2 / 2, Sec. II; x - q = -grad theta, Sec. III), so
+// the displacement is psi = grad theta: the central difference (theta(i+1) - theta(i-1)) / 2 per
+// axis on the mesh (cell units), interpolated to each particle with the CIC weights above (the
+// transpose of the deposit).
+
+// psi[(i n + j) n + k][a], a = x, y, z; one row (i, j) per block, theta in natural order. The row's
+// 3n outputs are assembled in LDS and written with consecutive lanes on consecutive doubles.
+constexpr int kLagRowMax = 1024;  // largest mesh a context accepts
+// Block 0 also clears the non-finite particle count that the gather that follows accumulates.
+__global__ void __launch_bounds__(256) lag_grad_kernel(const double* __restrict__ theta, int n,
+                                                       double* __restrict__ psi, double* __restrict__ bad_count) {
+  __shared__ double stage[3 * kLagRowMax];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *bad_count = 0.0;
+  const int row = xcd_remap(blockIdx.x, gridDim.x);
+  const int i = row / n, j = row - i * n;
+  const int im = i == 0 ? n - 1 : i - 1, ip = i == n - 1 ? 0 : i + 1;
+  const int jm = j == 0 ? n - 1 : j - 1, jp = j == n - 1 ? 0 : j + 1;
+  const double* __restrict__ r0 = theta + ((size_t)i * n + j) * n;
+  const double* __restrict__ rxm = theta + ((size_t)im * n + j) * n;
+  const double* __restrict__ rxp = theta + ((size_t)ip * n + j) * n;
+  const double* __restrict__ rym = theta + ((size_t)i * n + jm) * n;
+  const double* __restrict__ ryp = theta + ((size_t)i * n + jp) * n;
+  double* __restrict__ out = psi + ((size_t)i * n + j) * n * 3;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) {
+    const int km = k == 0 ? n - 1 : k - 1, kp = k == n - 1 ? 0 : k + 1;
+    stage[3 * k + 0] = (rxp[k] - rxm[k]) * 0.5;
+    stage[3 * k + 1] = (ryp[k] - rym[k]) * 0.5;
+    stage[3 * k + 2] = (r0[kp] - r0[km]) * 0.5;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < 3 * n; t += blockDim.x) out[t] = stage[t];
+}
+
+// disp[p] = sum over the 8 mesh points around x_p of w * psi (corners in x-major order). A particle
+// with a non-finite coordinate is not interpolated (its output is NaN) and adds 1 to *bad_count
+// with a relaxed atomic: an exact, order-independent integer count that needs no grid-wide
+// reduction (whose per-block release/acquire would write back and invalidate the L2 that the
+// concurrently running blocks reuse mesh lines from).
+__global__ void __launch_bounds__(256) lag_gather_kernel(const double* __restrict__ pos, long long np, int n,
+                                                        const double* __restrict__ psi, double* __restrict__ disp,
+                                                        double* __restrict__ bad_count) {
+  // consecutive particles on one XCD: lattice-ordered catalogues then reuse mesh lines in its L2
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long p = xcd_remap(blockIdx.x, gridDim.x) * (long long)blockDim.x + threadIdx.x; p < np; p += stride) {
+    const double x = pos[3 * p], y = pos[3 * p + 1], z = pos[3 * p + 2];
+    if (!__builtin_isfinite(x) || !__builtin_isfinite(y) || !__builtin_isfinite(z)) {
+      __hip_atomic_fetch_add(bad_count, 1.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      disp[3 * p] = disp[3 * p + 1] = disp[3 * p + 2] = __builtin_nan("");
+      continue;
+    }
+    int ix0, ix1, iy0, iy1, iz0, iz1;
+    double fx, fy, fz;
+    wrap_coord(x, n, ix0, ix1, fx);
+    wrap_coord(y, n, iy0, iy1, fy);
+    wrap_coord(z, n, iz0, iz1, fz);
+    const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
+    const int ix[2] = {ix0, ix1}, iy[2] = {iy0, iy1}, iz[2] = {iz0, iz1};
+    // all 24 loads are issued before the first use so that their latencies overlap
+    double v[8][3];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int a = c >> 2, b = (c >> 1) & 1, d = c & 1;
+      const double* __restrict__ src = psi + (((size_t)ix[a] * n + iy[b]) * n + iz[d]) * 3;
+      v[c][0] = src[0];
+      v[c][1] = src[1];
+      v[c][2] = src[2];
+    }
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int a = c >> 2, b = (c >> 1) & 1, d = c & 1;
+      const double w = wx[a] * wy[b] * wz[d];
+      a0 += w * v[c][0];
+      a1 += w * v[c][1];
+      a2 += w * v[c][2];
+    }
+    disp[3 * p] = a0;
+    disp[3 * p + 1] = a1;
+    disp[3 * p + 2] = a2;
+  }
+}
+
+int Ctx::lagrangian(const double* theta, const double* pos, long long np, double* disp_out, double* psi_out) {
+  const size_t cells = lv[0].cells;
+  double* psi = psi_out;
+  if (!psi) {
+    hipError_t e = hipMalloc((void**)&psi, cells * 3 * sizeof(double));
+    if (e != hipSuccess) return fail(MR_ENOMEM, "mr_lagrangian: mesh displacement: %s", hipGetErrorString(e));
+  }
+  double* bad_count = scal + kSlotRes;
+  hipLaunchKernelGGL(lag_grad_kernel, dim3((unsigned)n * n), dim3(n < 256 ? (n < 64 ? 64 : n) : 256), 0, stream, theta, n,
+                     psi, bad_count);
+  // one particle per thread up to 2^28 particles, a grid-stride loop beyond
+  const long long gb = std::min<long long>((np + 255) / 256, 1 << 20);
+  hipLaunchKernelGGL(lag_gather_kernel, dim3((unsigned)gb), dim3(256), 0, stream, pos, np, n, psi, disp_out, bad_count);
+  hipError_t e = hipGetLastError();
+  double bad = 0.0;
+  int rc = e == hipSuccess ? read_scalars(kSlotRes, 1, &bad) : hip_fail(e, "mr_lagrangian");
+  if (!psi_out) (void)hipFree(psi);
+  if (rc != MR_OK) return rc;
+  if (bad != 0.0) return fail(MR_EINVAL, "mr_lagrangian: %.0f particles with non-finite coordinates", bad);
+  return MR_OK;
+}
+
 }  // namespace mr
 
 extern "C" int mr_deposit_cic(mr_ctx* h, const double* pos, int64_t np, double mass, double* delta_out) {
@@ -120,4 +226,11 @@ extern "C" int mr_deposit_cic(mr_ctx* h, const double* pos, int64_t np, double m
   if (np < 1) return mr::fail(MR_EINVAL, "mr_deposit_cic: no particles");
   if (!(mass > 0.0) || !std::isfinite(mass)) return mr::fail(MR_EINVAL, "mr_deposit_cic: mass must be positive");
   return reinterpret_cast<mr::Ctx*>(h)->deposit_cic(pos, (long long)np, mass, delta_out);
+}
+
+extern "C" int mr_lagrangian(mr_ctx* h, const double* theta, const double* pos, int64_t np, double* disp_out,
+                             double* psi_out) {
+  if (!h || !theta || !pos || !disp_out) return mr::fail(MR_EINVAL, "mr_lagrangian: null argument");
+  if (np < 1) return mr::fail(MR_EINVAL, "mr_lagrangian: no particles");
+  return reinterpret_cast<mr::Ctx*>(h)->lagrangian(theta, pos, (long long)np, disp_out, psi_out);
 }

@@ -36,7 +36,7 @@ MR_SCHED_FUSED = 2
 EXPORTED = [
     "mr_default_opts", "mr_create", "mr_destroy", "mr_set_opts", "mr_size", "mr_levels",
     "mr_get_schedule", "mr_set_schedule",
-    "mr_deposit_cic", "mr_residual", "mr_solve", "mr_adjoint_solve", "mr_solve_batched",
+    "mr_deposit_cic", "mr_lagrangian", "mr_residual", "mr_solve", "mr_adjoint_solve", "mr_solve_batched",
     "mr_tune_lin_tiles",
     "mr_sweep", "mr_defect_restrict", "mr_tau_rhs", "mr_prolong_correct", "mr_restrict",
     "mr_timing_enable", "mr_timing_read", "mr_last_error",
@@ -107,6 +107,7 @@ def load(path: Optional[str] = None):
     lib.mr_set_opts.argtypes = [vp, ctypes.POINTER(mr_opts)]
     lib.mr_size.argtypes = [vp]
     lib.mr_levels.argtypes = [vp]
+    lib.mr_lagrangian.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp]
     lib.mr_get_schedule.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int)]
     lib.mr_set_schedule.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int)]
     lib.mr_deposit_cic.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, vp]
@@ -231,6 +232,15 @@ class Context:
         npart = pos.numel() // 3
         _check(self.lib.mr_deposit_cic(self.h, _ptr(pos), npart, mass, _ptr(out)))
         return out
+
+    def lagrangian(self, theta: torch.Tensor, pos: torch.Tensor, want_psi: bool = False, out=None):
+        """Lagrangian mapping (mr_lagrangian): per-particle displacement psi(x_p) (np x 3, so that
+        q = pos + disp) and, if want_psi, the mesh field psi (n x n x n x 3)."""
+        npart = pos.numel() // 3
+        disp = torch.empty((npart, 3), dtype=torch.float64, device="cuda") if out is None else out
+        psi = torch.empty((self.n, self.n, self.n, 3), dtype=torch.float64, device="cuda") if want_psi else None
+        _check(self.lib.mr_lagrangian(self.h, _ptr(theta), _ptr(pos), npart, _ptr(disp), _ptr(psi)))
+        return disp, psi
 
     def residual(self, delta: torch.Tensor, theta: torch.Tensor, want_r: bool = True):
         r = self._empty() if want_r else None
