@@ -141,15 +141,19 @@ def cic_run():
     n = 256
     pos = torch.from_numpy(inputs.zeldovich_particles(n, 4.0, 1001)).cuda()
     theta = torch.from_numpy(40.0 * inputs.grf(n, 4.0, 1006)).cuda()   # a smooth synthetic potential
+    npart = pos.shape[0]
+    reps = 5
     with mr.Context(n) as c:
-        out = c.deposit_cic(pos)
-        torch.cuda.synchronize()
-        reps = 5
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            c.deposit_cic(pos, out=out)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / reps
+        schemes = {}
+        for scheme in ("ngp", "cic", "tsc"):
+            out = c.deposit(pos, 1.0, scheme)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                c.deposit(pos, 1.0, scheme, out=out)
+            torch.cuda.synchronize()
+            schemes[scheme] = (time.perf_counter() - t0) / reps
+        dt = schemes["cic"]
         # Lagrangian mapping of the same particles (mesh displacement + CIC gather)
         disp, psi = c.lagrangian(theta, pos, want_psi=True)
         torch.cuda.synchronize()
@@ -158,8 +162,8 @@ def cic_run():
             c.lagrangian(theta, pos, want_psi=True, out=disp)
         torch.cuda.synchronize()
         dl = (time.perf_counter() - t0) / reps
-    npart = pos.shape[0]
-    cic = {"particles": npart, "mesh": n, "seconds": round(dt, 5), "gparticles_per_s": round(npart / dt / 1e9, 3)}
+    cic = {"particles": npart, "mesh": n, "seconds": round(dt, 5), "gparticles_per_s": round(npart / dt / 1e9, 3),
+           "ngp_seconds": round(schemes["ngp"], 5), "tsc_seconds": round(schemes["tsc"], 5)}
     lag = {"particles": npart, "mesh": n, "seconds": round(dl, 5), "gparticles_per_s": round(npart / dl / 1e9, 3),
            "note": "mesh displacement grad(theta) into a caller buffer + CIC gather to the particles"}
     return cic, lag

@@ -130,14 +130,23 @@ enum { MR_SCHED_TILED = 0, MR_SCHED_PIPELINED = 1, MR_SCHED_FUSED = 2 };
 int mr_get_schedule(const mr_ctx* ctx, int level, int sched[4]);
 int mr_set_schedule(mr_ctx* ctx, int level, const int sched[4]);
 
-/* Cloud-in-cell density assignment (the paper's footnote on density assignment, Sec. I).
- * pos: device, np x 3 doubles (x, y, z) in cell units, any real value (wrapped periodically);
- * mesh points sit at integer coordinates and a particle at x gives weight (1 - f) to floor(x)
- * and f to floor(x) + 1 per axis, f = x - floor(x). delta_out: device n^3, receives
- * rho / <rho> - 1 with <rho> = np * mass / n^3 (mass > 0). Accumulation is in unsigned 64-bit
- * fixed point (each weight rounded to a multiple of 2^-40 of a particle's mass before the
- * sum), so the result is bitwise reproducible. A cell can hold at most 2^24 particles' worth
- * of weight; the total is checked after the deposit and an overflow returns MR_EINVAL. */
+/* Density assignment (the paper's footnote on density assignment, Sec. I, allows NGP, CIC or TSC).
+ * pos: device, np x 3 doubles (x, y, z) in cell units, any finite real value (wrapped
+ * periodically); mesh points sit at integer coordinates. Per axis, with b = floor(x) and
+ * f = x - b: MR_DEPOSIT_NGP gives weight 1 to the nearest point (b, or b + 1 when f >= 1/2);
+ * MR_DEPOSIT_CIC gives 1 - f to b and f to b + 1; MR_DEPOSIT_TSC, with i the NGP point and
+ * d = x - i, gives (1/2 - d)^2 / 2, 3/4 - d^2 and (1/2 + d)^2 / 2 to i - 1, i and i + 1. A particle
+ * deposits mass times the product of its three axis weights on each point. delta_out: device
+ * n^3, receives rho / <rho> - 1 with <rho> = np * mass / n^3 (mass > 0). Accumulation is in
+ * unsigned 64-bit fixed point (each weight rounded to a multiple of 2^-40 of a particle's mass
+ * before the sum), so the result is bitwise reproducible. Returns MR_EINVAL for a NULL argument,
+ * np < 1, a mass that is not positive and finite, an unknown scheme, or particles with a
+ * non-finite coordinate (then delta_out is left unchanged); a cell can hold at most 2^24
+ * particles' worth of weight, and an overflow (detected from the total) returns MR_EINVAL. */
+enum { MR_DEPOSIT_NGP = 0, MR_DEPOSIT_CIC = 1, MR_DEPOSIT_TSC = 2 };
+int mr_deposit(mr_ctx* ctx, const double* pos, int64_t np, double mass, int scheme, double* delta_out);
+
+/* Cloud-in-cell density assignment: mr_deposit with MR_DEPOSIT_CIC. */
 int mr_deposit_cic(mr_ctx* ctx, const double* pos, int64_t np, double mass, double* delta_out);
 
 /* Lagrangian mapping (the step after the solve). With Theta = Theta_0 + theta and

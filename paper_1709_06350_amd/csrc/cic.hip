@@ -1,7 +1,9 @@
-// Cloud-in-cell density assignment (the density-assignment step the paper requires before the
-// solve; footnote in Sec. I): each particle spreads its mass over the 8 mesh points around it
-// with weights prod_d (1 - f_d) or f_d, f = x - floor(x), mesh points at integer coordinates,
-// periodic wrap; then delta = rho / <rho> - 1 with <rho> = np * mass / n^3.
+// Density assignment (the paper's footnote in Sec. I allows NGP, CIC or TSC): each particle
+// spreads its mass over the 1, 8 or 27 mesh points around it with weights prod_d w_d, mesh points at
+// integer coordinates, periodic wrap; then delta = rho / <rho> - 1 with <rho> = np * mass / n^3.
+// Per axis, with b = floor(x) and f = x - b: NGP puts weight 1 on the nearest point (b, or b + 1
+// when f >= 1/2); CIC puts 1 - f on b and f on b + 1; TSC, with i the NGP point and d = x - i,
+// puts (1/2 - d)^2 / 2, 3/4 - d^2, (1/2 + d)^2 / 2 on i - 1, i, i + 1 (the quadratic B-spline).
 //
 // Accumulation is in unsigned 64-bit fixed point (2^40 units per particle mass): every weight is
 // rounded once, the integer sums are exact and independent of the order in which atomics land,
@@ -32,31 +34,75 @@ __device__ __forceinline__ void wrap_coord(double x, int n, int& i0, int& i1, do
   i1 = i0 + 1 == n ? 0 : i0 + 1;
 }
 
-__global__ void __launch_bounds__(256) cic_scatter_kernel(const double* __restrict__ pos, long long np, int n,
-                                                          unsigned long long* __restrict__ grid) {
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < np; p += stride) {
-    const double x = pos[3 * p], y = pos[3 * p + 1], z = pos[3 * p + 2];
-    int ix0, ix1, iy0, iy1, iz0, iz1;
-    double fx, fy, fz;
-    wrap_coord(x, n, ix0, ix1, fx);
-    wrap_coord(y, n, iy0, iy1, fy);
-    wrap_coord(z, n, iz0, iz1, fz);
-    const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
-    const int ix[2] = {ix0, ix1}, iy[2] = {iy0, iy1}, iz[2] = {iz0, iz1};
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int a = c >> 2, b = (c >> 1) & 1, d = c & 1;
-      const double w = wx[a] * wy[b] * wz[d];
-      const unsigned long long q = (unsigned long long)__double2ull_rn(w * kFixScale);
-      if (q) atomicAdd(&grid[((size_t)ix[a] * n + iy[b]) * n + iz[d]], q);
+// Per-axis points and weights of one coordinate for a scheme of S points (1 NGP, 2 CIC, 3 TSC).
+template <int S>
+__device__ __forceinline__ void axis_assign(double x, int n, int (&idx)[S], double (&w)[S]) {
+  int i0, i1;
+  double f;
+  wrap_coord(x, n, i0, i1, f);  // i0 = floor of the wrapped coordinate, f its fraction (exact)
+  if constexpr (S == 2) {
+    idx[0] = i0;
+    idx[1] = i1;
+    w[0] = 1.0 - f;
+    w[1] = f;
+  } else {
+    const bool up = f >= 0.5;
+    const int c = up ? i1 : i0;  // nearest point, a tie goes up
+    if constexpr (S == 1) {
+      idx[0] = c;
+      w[0] = 1.0;
+    } else {
+      const double d = up ? f - 1.0 : f;  // x - c, exact
+      idx[0] = c == 0 ? n - 1 : c - 1;
+      idx[1] = c;
+      idx[2] = c == n - 1 ? 0 : c + 1;
+      const double lo = 0.5 - d, hi = 0.5 + d;
+      w[0] = 0.5 * (lo * lo);
+      w[1] = 0.75 - d * d;
+      w[2] = 0.5 * (hi * hi);
     }
   }
 }
 
-// delta = count * n^3 / (np * 2^40) - 1; result[0] = sum of counts / 2^40 (total particles).
+// A particle with a non-finite coordinate deposits nothing and adds 1 to *bad_count (relaxed
+// atomic: an exact integer count that needs no grid-wide reduction).
+template <int S>
+__global__ void __launch_bounds__(256) deposit_scatter_kernel(const double* __restrict__ pos, long long np, int n,
+                                                              unsigned long long* __restrict__ grid,
+                                                              double* __restrict__ bad_count) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long p = blockIdx.x * (long long)blockDim.x + threadIdx.x; p < np; p += stride) {
+    const double x = pos[3 * p], y = pos[3 * p + 1], z = pos[3 * p + 2];
+    if (!__builtin_isfinite(x) || !__builtin_isfinite(y) || !__builtin_isfinite(z)) {
+      __hip_atomic_fetch_add(bad_count, 1.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      continue;
+    }
+    int ix[S], iy[S], iz[S];
+    double wx[S], wy[S], wz[S];
+    axis_assign<S>(x, n, ix, wx);
+    axis_assign<S>(y, n, iy, wy);
+    axis_assign<S>(z, n, iz, wz);
+#pragma unroll
+    for (int a = 0; a < S; ++a)
+#pragma unroll
+      for (int b = 0; b < S; ++b) {
+        const size_t row = ((size_t)ix[a] * n + iy[b]) * n;
+#pragma unroll
+        for (int d = 0; d < S; ++d) {
+          const double w = wx[a] * wy[b] * wz[d];
+          const unsigned long long q = (unsigned long long)__double2ull_rn(w * kFixScale);
+          if (q) atomicAdd(&grid[row + iz[d]], q);
+        }
+      }
+  }
+}
+
+// delta = count * n^3 / (np * 2^40) - 1; partials[block] = the block's sum of counts / 2^40. The
+// partials are added by sum_partials_kernel in the next launch (fixed order, no per-block fences).
 __global__ void __launch_bounds__(256) cic_normalise_kernel(const unsigned long long* __restrict__ grid, size_t cells,
-                                                            double scale, double* __restrict__ delta, Reduce red) {
+                                                            double scale, double* __restrict__ delta,
+                                                            double* __restrict__ partials) {
+  __shared__ double red[16][1];
   double acc = 0.0;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < cells; e += (size_t)gridDim.x * blockDim.x) {
     const double cnt = (double)grid[e];
@@ -64,19 +110,25 @@ __global__ void __launch_bounds__(256) cic_normalise_kernel(const unsigned long 
     acc += cnt * (1.0 / kFixScale);
   }
   double v[1] = {acc};
-  grid_sum<1>(v, red.partials, red.counter, red.result, gridDim.x, blockIdx.x);
+  block_sum<1>(v, red, threadIdx.x, blockDim.x);
+  if (threadIdx.x == 0) partials[blockIdx.x] = v[0];
 }
 
-// Number of non-finite coordinates.
-__global__ void __launch_bounds__(256) cic_validate_kernel(const double* __restrict__ pos, size_t count, Reduce red) {
-  double bad = 0.0;
-  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x)
-    if (!__builtin_isfinite(pos[e])) bad += 1.0;
-  double v[1] = {bad};
-  grid_sum<1>(v, red.partials, red.counter, red.result, gridDim.x, blockIdx.x);
+// out[0] = sum of partials[0 .. count) in a fixed order (one block).
+__global__ void __launch_bounds__(256) sum_partials_kernel(const double* __restrict__ partials, int count,
+                                                           double* __restrict__ out) {
+  __shared__ double red[16][1];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < count; b += blockDim.x) acc += partials[b];
+  double v[1] = {acc};
+  block_sum<1>(v, red, threadIdx.x, blockDim.x);
+  if (threadIdx.x == 0) out[0] = v[0];
 }
 
-__global__ void __launch_bounds__(256) zero_u64_kernel(unsigned long long* __restrict__ a, size_t cells) {
+// Clears the accumulation grid; block 0 also clears the non-finite particle count.
+__global__ void __launch_bounds__(256) zero_u64_kernel(unsigned long long* __restrict__ a, size_t cells,
+                                                       double* __restrict__ bad_count) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *bad_count = 0.0;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < cells; e += (size_t)gridDim.x * blockDim.x) a[e] = 0ull;
 }
 
@@ -85,31 +137,39 @@ static int blocks_for(size_t work, int cap) {
   return (int)(b < 1 ? 1 : (b > (size_t)cap ? cap : b));
 }
 
-int Ctx::deposit_cic(const double* pos, long long np, double mass, double* delta_out) {
+int Ctx::deposit(const double* pos, long long np, double mass, int scheme, double* delta_out) {
   const size_t cells = lv[0].cells;
   if (!cic_grid) {
     hipError_t e = hipMalloc((void**)&cic_grid, cells * sizeof(unsigned long long));
-    if (e != hipSuccess) return fail(MR_ENOMEM, "CIC accumulation grid: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return fail(MR_ENOMEM, "density assignment grid: %s", hipGetErrorString(e));
   }
-  hipLaunchKernelGGL(cic_validate_kernel, dim3(blocks_for((size_t)np * 3, 4096)), dim3(256), 0, stream, pos,
-                     (size_t)np * 3, reducer(kSlotRes));
+  double* bad_count = scal + kSlotRes;
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(blocks_for(cells, 1 << 16)), dim3(256), 0, stream, cic_grid, cells,
+                     bad_count);
+  const dim3 pg(blocks_for((size_t)np, 1 << 16));
+  if (scheme == MR_DEPOSIT_NGP)
+    hipLaunchKernelGGL(deposit_scatter_kernel<1>, pg, dim3(256), 0, stream, pos, np, n, cic_grid, bad_count);
+  else if (scheme == MR_DEPOSIT_CIC)
+    hipLaunchKernelGGL(deposit_scatter_kernel<2>, pg, dim3(256), 0, stream, pos, np, n, cic_grid, bad_count);
+  else
+    hipLaunchKernelGGL(deposit_scatter_kernel<3>, pg, dim3(256), 0, stream, pos, np, n, cic_grid, bad_count);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "mr_deposit");
   double bad;
   int rc = read_scalars(kSlotRes, 1, &bad);
   if (rc != MR_OK) return rc;
-  if (bad != 0.0) return fail(MR_EINVAL, "mr_deposit_cic: %.0f non-finite coordinates", bad);
-  hipLaunchKernelGGL(zero_u64_kernel, dim3(blocks_for(cells, 1 << 16)), dim3(256), 0, stream, cic_grid, cells);
-  hipLaunchKernelGGL(cic_scatter_kernel, dim3(blocks_for((size_t)np, 1 << 16)), dim3(256), 0, stream, pos, np, n,
-                     cic_grid);
+  if (bad != 0.0) return fail(MR_EINVAL, "mr_deposit: %.0f particles with non-finite coordinates", bad);
   const double scale = (double)cells / ((double)np * kFixScale);
-  hipLaunchKernelGGL(cic_normalise_kernel, dim3(blocks_for(cells, 4096)), dim3(256), 0, stream, cic_grid, cells, scale,
-                     delta_out, reducer(kSlotRes));
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(e, "mr_deposit_cic");
+  const int nb = blocks_for(cells, kMaxReduceBlocks);
+  hipLaunchKernelGGL(cic_normalise_kernel, dim3(nb), dim3(256), 0, stream, cic_grid, cells, scale, delta_out, partials);
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, stream, partials, nb, scal + kSlotRes);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "mr_deposit");
   double total;
   if ((rc = read_scalars(kSlotRes, 1, &total)) != MR_OK) return rc;
-  // Each particle contributes 1 up to 8 roundings of 2^-41; a wrapped 64-bit cell loses 2^24.
+  // Each particle contributes 1 up to 27 roundings of 2^-41; a wrapped 64-bit cell loses 2^24.
   if (!(std::fabs(total - (double)np) <= 0.5 + 1e-9 * (double)np))
-    return fail(MR_EINVAL, "mr_deposit_cic: fixed-point overflow (deposited %.6g of %lld particles)", total, np);
+    return fail(MR_EINVAL, "mr_deposit: fixed-point overflow (deposited %.6g of %lld particles)", total, np);
   (void)mass;
   return MR_OK;
 }
@@ -221,11 +281,17 @@ int Ctx::lagrangian(const double* theta, const double* pos, long long np, double
 
 }  // namespace mr
 
+extern "C" int mr_deposit(mr_ctx* h, const double* pos, int64_t np, double mass, int scheme, double* delta_out) {
+  if (!h || !pos || !delta_out) return mr::fail(MR_EINVAL, "mr_deposit: null argument");
+  if (np < 1) return mr::fail(MR_EINVAL, "mr_deposit: no particles");
+  if (!(mass > 0.0) || !std::isfinite(mass)) return mr::fail(MR_EINVAL, "mr_deposit: mass must be positive");
+  if (scheme != MR_DEPOSIT_NGP && scheme != MR_DEPOSIT_CIC && scheme != MR_DEPOSIT_TSC)
+    return mr::fail(MR_EINVAL, "mr_deposit: unknown scheme %d", scheme);
+  return reinterpret_cast<mr::Ctx*>(h)->deposit(pos, (long long)np, mass, scheme, delta_out);
+}
+
 extern "C" int mr_deposit_cic(mr_ctx* h, const double* pos, int64_t np, double mass, double* delta_out) {
-  if (!h || !pos || !delta_out) return mr::fail(MR_EINVAL, "mr_deposit_cic: null argument");
-  if (np < 1) return mr::fail(MR_EINVAL, "mr_deposit_cic: no particles");
-  if (!(mass > 0.0) || !std::isfinite(mass)) return mr::fail(MR_EINVAL, "mr_deposit_cic: mass must be positive");
-  return reinterpret_cast<mr::Ctx*>(h)->deposit_cic(pos, (long long)np, mass, delta_out);
+  return mr_deposit(h, pos, np, mass, MR_DEPOSIT_CIC, delta_out);
 }
 
 extern "C" int mr_lagrangian(mr_ctx* h, const double* theta, const double* pos, int64_t np, double* disp_out,

@@ -86,7 +86,7 @@ struct Ctx {
   int prepare(const double* delta_natural);
   int solve_fp64(const double* delta, double* theta, mr_info* info);
   int solve_mixed(const double* delta, double* theta, mr_info* info);
-  int deposit_cic(const double* pos, long long np, double mass, double* delta_out);
+  int deposit(const double* pos, long long np, double mass, int scheme, double* delta_out);
   int lagrangian(const double* theta, const double* pos, long long np, double* disp_out, double* psi_out);
   int adjoint_solve(const double* delta, const double* theta_star, const double* g, double* grad, mr_info* info);
   int adj_sweep(int l);

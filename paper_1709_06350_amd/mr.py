@@ -32,11 +32,15 @@ PREC_MIXED = 1
 MR_SCHED_TILED = 0
 MR_SCHED_PIPELINED = 1
 MR_SCHED_FUSED = 2
+MR_DEPOSIT_NGP = 0
+MR_DEPOSIT_CIC = 1
+MR_DEPOSIT_TSC = 2
+DEPOSIT_SCHEMES = {"ngp": MR_DEPOSIT_NGP, "cic": MR_DEPOSIT_CIC, "tsc": MR_DEPOSIT_TSC}
 
 EXPORTED = [
     "mr_default_opts", "mr_create", "mr_destroy", "mr_set_opts", "mr_size", "mr_levels",
     "mr_get_schedule", "mr_set_schedule",
-    "mr_deposit_cic", "mr_lagrangian", "mr_residual", "mr_solve", "mr_adjoint_solve", "mr_solve_batched",
+    "mr_deposit", "mr_deposit_cic", "mr_lagrangian", "mr_residual", "mr_solve", "mr_adjoint_solve", "mr_solve_batched",
     "mr_tune_lin_tiles",
     "mr_sweep", "mr_defect_restrict", "mr_tau_rhs", "mr_prolong_correct", "mr_restrict",
     "mr_timing_enable", "mr_timing_read", "mr_last_error",
@@ -111,6 +115,7 @@ def load(path: Optional[str] = None):
     lib.mr_get_schedule.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int)]
     lib.mr_set_schedule.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int)]
     lib.mr_deposit_cic.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, vp]
+    lib.mr_deposit.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int, vp]
     lib.mr_residual.argtypes = [vp, vp, vp, vp, dp, dp]
     lib.mr_solve.argtypes = [vp, vp, vp, ctypes.POINTER(mr_info)]
     lib.mr_adjoint_solve.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(mr_info)]
@@ -227,6 +232,16 @@ class Context:
         return torch.empty((n, n, n), dtype=torch.float64, device="cuda")
 
     # -- the four calls of the path ----------------------------------------------------------
+    def deposit(self, pos: torch.Tensor, mass: float = 1.0, scheme: str = "cic",
+                out: Optional[torch.Tensor] = None):
+        """Density assignment (mr_deposit) with scheme "ngp", "cic" or "tsc"; returns delta."""
+        if scheme not in DEPOSIT_SCHEMES:
+            raise ValueError(f"unknown scheme {scheme!r}")
+        out = self._empty() if out is None else out
+        npart = pos.numel() // 3
+        _check(self.lib.mr_deposit(self.h, _ptr(pos), npart, mass, DEPOSIT_SCHEMES[scheme], _ptr(out)))
+        return out
+
     def deposit_cic(self, pos: torch.Tensor, mass: float = 1.0, out: Optional[torch.Tensor] = None):
         out = self._empty() if out is None else out
         npart = pos.numel() // 3
