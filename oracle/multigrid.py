@@ -18,6 +18,13 @@ Readings where the paper is silent or garbled:
     (4^3 for powers of two, 6^3 for 96^3); the coarsest mesh gets nu_c red-black sweeps;
   * convergence is tested on ||r|| / ||r(theta = 0)|| on the finest mesh (the paper uses
     the absolute rms residual < 1e-8 in code units); the gauge <theta> = 0 is fixed at the end.
+
+A second ordering, ``ordering="4c"``, splits a sweep into 4 sub-sweeps (the paper suggests
+this as a possible improvement in Sec. II.A.2 and does not pursue it). Its classes are
+c = 2 ((j + k) mod 2) + ((i + k) mod 2): a face step changes one parity of i, j, k and an
+edge step two, and in either case (j + k, i + k) mod 2 changes, so no cell of the 19-point
+stencil shares the class of its centre. Within a sub-sweep the sources therefore stay fixed
+and the snapshot update is an exact Gauss-Seidel sub-sweep in any cell order.
 """
 from __future__ import annotations
 
@@ -29,6 +36,9 @@ __all__ = [
     "restrict",
     "prolong",
     "red_mask",
+    "four_colour_classes",
+    "class_sweep",
+    "sweep",
     "level_sizes",
     "half_sweep",
     "rb_sweep",
@@ -75,6 +85,12 @@ def red_mask(n: int) -> np.ndarray:
     return (i + j + k) % 2 == 0
 
 
+def four_colour_classes(n: int) -> np.ndarray:
+    """Class index 2 ((j + k) mod 2) + ((i + k) mod 2) of every cell (n even)."""
+    i, j, k = np.indices((n, n, n))
+    return 2 * ((j + k) % 2) + (i + k) % 2
+
+
 def level_sizes(n: int):
     """Mesh sizes from the finest down: halve while the coarse mesh stays even and >= 4."""
     sizes = [n]
@@ -83,12 +99,12 @@ def level_sizes(n: int):
     return sizes
 
 
-def half_sweep(theta, delta, f, h, red: bool, m=None):
-    """One colour's Newton-Gauss-Seidel update from a snapshot (Sec. II.A.2, Eq. 17).
+def class_sweep(theta, delta, f, h, mask, m=None):
+    """Newton-Gauss-Seidel update of the cells in ``mask`` from a snapshot (Sec. II.A.2, Eq. 17).
 
-    theta_new = theta - L/(dL/dtheta) with dL/dtheta = -6/h^2 on the cells of the active
-    colour, where L = nabla^2 theta - (Sigma - m) - f is evaluated on the snapshot. ``m``
-    defaults to <Sigma> of the snapshot; it may be given explicitly.
+    theta_new = theta - L/(dL/dtheta) with dL/dtheta = -6/h^2 on the masked cells, where
+    L = nabla^2 theta - (Sigma - m) - f is evaluated on the snapshot. ``m`` defaults to
+    <Sigma> of the snapshot; it may be given explicitly.
     """
     sig = source(theta, delta, h)
     if m is None:
@@ -97,10 +113,13 @@ def half_sweep(theta, delta, f, h, red: bool, m=None):
     if f is not None:
         L = L - f
     new = theta - L / (-6.0 / (h * h))
-    mask = red_mask(theta.shape[0])
-    if not red:
-        mask = ~mask
     return np.where(mask, new, theta)
+
+
+def half_sweep(theta, delta, f, h, red: bool, m=None):
+    """One colour's update (red: (i + j + k) even) from a snapshot; see ``class_sweep``."""
+    mask = red_mask(theta.shape[0])
+    return class_sweep(theta, delta, f, h, mask if red else ~mask, m)
 
 
 def rb_sweep(theta, delta, f, h, m=None):
@@ -110,31 +129,43 @@ def rb_sweep(theta, delta, f, h, m=None):
     return theta
 
 
-def vcycle(thetas, deltas, fs, level, nu1=2, nu2=2, nu_c=20):
+def sweep(theta, delta, f, h, m=None, ordering: str = "rb"):
+    """A sweep in the given ordering: "rb" (red then black) or "4c" (classes 0, 1, 2, 3)."""
+    if ordering == "rb":
+        return rb_sweep(theta, delta, f, h, m)
+    if ordering != "4c":
+        raise ValueError(f"unknown ordering {ordering!r}")
+    cls = four_colour_classes(theta.shape[0])
+    for c in range(4):
+        theta = class_sweep(theta, delta, f, h, cls == c, m)
+    return theta
+
+
+def vcycle(thetas, deltas, fs, level, nu1=2, nu2=2, nu_c=20, ordering="rb"):
     """FAS V-cycle on ``level`` (Sec. II.A.3, Eqs. 18-20). Updates thetas[level] in place."""
     h = float(2 ** level)
     th = thetas[level]
     if level == len(deltas) - 1:
         for _ in range(nu_c):
-            th = rb_sweep(th, deltas[level], fs[level], h)
+            th = sweep(th, deltas[level], fs[level], h, ordering=ordering)
         thetas[level] = th
         return
     for _ in range(nu1):
-        th = rb_sweep(th, deltas[level], fs[level], h)
+        th = sweep(th, deltas[level], fs[level], h, ordering=ordering)
     d = defect(th, deltas[level], fs[level], h)               # Eq. 18
     th_c = restrict(th)
     H = 2.0 * h
     fs[level + 1] = projected_operator(th_c, deltas[level + 1], H) - restrict(d)   # Eq. 19
     thetas[level + 1] = th_c.copy()
-    vcycle(thetas, deltas, fs, level + 1, nu1, nu2, nu_c)
+    vcycle(thetas, deltas, fs, level + 1, nu1, nu2, nu_c, ordering)
     th = th + prolong(thetas[level + 1] - th_c)               # Eq. 20
     for _ in range(nu2):
-        th = rb_sweep(th, deltas[level], fs[level], h)
+        th = sweep(th, deltas[level], fs[level], h, ordering=ordering)
     thetas[level] = th
 
 
 def solve(delta: np.ndarray, tol: float = 1e-10, max_cycles: int = 100, nu1: int = 2,
-          nu2: int = 2, nu_c: int = 20, theta0=None):
+          nu2: int = 2, nu_c: int = 20, theta0=None, ordering: str = "rb"):
     """Solve the mean-projected reconstruction equation for theta with <theta> = 0.
 
     Starts from theta = 0 (Sec. II.A.2) unless ``theta0`` is given (warm start). Returns
@@ -157,7 +188,7 @@ def solve(delta: np.ndarray, tol: float = 1e-10, max_cycles: int = 100, nu1: int
     history = [rel]
     cycles = 0
     while rel > tol and cycles < max_cycles:
-        vcycle(thetas, deltas, fs, 0, nu1, nu2, nu_c)
+        vcycle(thetas, deltas, fs, 0, nu1, nu2, nu_c, ordering)
         cycles += 1
         rel = residual_norm(projected_operator(thetas[0], delta, 1.0)) / r0
         history.append(rel)
