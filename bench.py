@@ -196,6 +196,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the CIC and adjoint timings")
+    ap.add_argument("--particles-only", action="store_true",
+                    help="only time the deposits and the Lagrangian mapping (256^3 mesh, 256^3 particles)")
     ap.add_argument("--schedule", default="", metavar="KIND,TM,TJ,NCHUNKS",
                     help="pin the finest-level FP64 relaxation schedule (mr_set_schedule) instead of the timed one")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -214,6 +216,10 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration, 3)
+        return
+    if args.particles_only:
+        cic, lag = cic_run()
+        print(json.dumps({"deposit": cic, "lagrangian": lag}), flush=True)
         return
     n = args.n
     delta_np = inputs.config2_delta(n)
