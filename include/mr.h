@@ -77,8 +77,15 @@ typedef struct {
  * MR_FLAG_ADJ_ROWS / MR_FLAG_ADJ_TILED (mr_adjoint_solve): relax the adjoint with the untiled
  * row kernel on every level, or with the tiled plane-marching kernel on every level a compiled
  * tile fits, instead of the per-level timed choice; all compute the same update up to rounding
- * order. Setting both is an error. */
-enum { MR_FLAG_EAGER = 1, MR_FLAG_TWO_PASS = 2, MR_FLAG_ADJ_ROWS = 4, MR_FLAG_ADJ_TILED = 8 };
+ * order. Setting both is an error.
+ * MR_FLAG_ORDER4 (FP64 relaxation: mr_solve at MR_PREC_FP64 and mr_sweep): split each sweep into
+ * 4 sub-sweeps instead of the red and black ones (the alternative ordering suggested in
+ * Sec. II.A.2). Sub-sweep c = 0..3 updates the cells with 2 ((j + k) mod 2) + ((i + k) mod 2) = c;
+ * no cell of the 19-point stencil shares its centre's class, so the sources of a sub-sweep stay
+ * fixed while it runs and the update is exact Gauss-Seidel. Each sub-sweep costs about as much as
+ * a red-black sweep (row-filtered per-colour launches); the coarsest mesh keeps red-black. The
+ * fixed point is the same as with red-black. */
+enum { MR_FLAG_EAGER = 1, MR_FLAG_TWO_PASS = 2, MR_FLAG_ADJ_ROWS = 4, MR_FLAG_ADJ_TILED = 8, MR_FLAG_ORDER4 = 16 };
 
 /* Per-solve report. history[c] is the relative residual after cycle c (history[0] = start). */
 typedef struct {
@@ -221,7 +228,9 @@ int mr_tune_lin_tiles(int n, void* hip_stream, int* tm, int* tj, int* ci, float*
  * f may be NULL (zero). theta_out must not alias theta_in. sum_out (host, may be NULL)
  * receives sum over all cells of (Sigma_c + f_c) as evaluated during the sweep. Runs the fused
  * red-black kernel, or the two per-colour launches (the pipelined kernel where the tile allows
- * it) when the context's opts.flags has MR_FLAG_TWO_PASS. */
+ * it) when the context's opts.flags has MR_FLAG_TWO_PASS. With MR_FLAG_ORDER4 it runs the four
+ * class sub-sweeps instead (cells of class 0, then 1, 2, 3, each from the previous result) and
+ * sum_out is the sum evaluated during the last sub-sweep. */
 int mr_sweep(mr_ctx* ctx, int nl, double h, const double* delta, const double* f, double cshift,
              const double* theta_in, double* theta_out, double* sum_out);
 

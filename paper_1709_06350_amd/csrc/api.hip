@@ -52,7 +52,8 @@ int check_opts(const mr_opts& o) {
   if (!(o.tol >= 0.0) || o.max_cycles < 1 || o.max_cycles > 127 || o.npre < 0 || o.npost < 0 ||
       o.npre + o.npost < 1 || o.ncoarse < 1 ||
       (o.precision != MR_PREC_FP64 && o.precision != MR_PREC_MIXED) || o.inner_cycles < 1 ||
-      o.inner_cycles > 8 || (o.flags & ~(MR_FLAG_EAGER | MR_FLAG_TWO_PASS | MR_FLAG_ADJ_ROWS | MR_FLAG_ADJ_TILED)) != 0 ||
+      o.inner_cycles > 8 ||
+      (o.flags & ~(MR_FLAG_EAGER | MR_FLAG_TWO_PASS | MR_FLAG_ADJ_ROWS | MR_FLAG_ADJ_TILED | MR_FLAG_ORDER4)) != 0 ||
       (o.flags & MR_FLAG_ADJ_ROWS && o.flags & MR_FLAG_ADJ_TILED))
     return fail(MR_EINVAL, "invalid options");
   return MR_OK;
@@ -200,13 +201,64 @@ void EventTimer::destroy() {
 
 // ---- FP64 sweep / V-cycle on the level hierarchy --------------------------------------------
 
-// One red-black sweep: red half-sweep from the current iterate, black half-sweep from the new
-// red values and the old black values; both use the shift of the previous sweep. The red sum goes
-// to the staging slot, the black sum to slot [1]; the black launch then moves staging to [0].
+// The two per-colour launches of a sweep (or of one 4-class sub-sweep): colour 0 from the current
+// iterate, colour 1 from the new colour-0 values and the old colour-1 values; both use the shift
+// of the previous (sub-)sweep. The colour-0 sum goes to the staging slot, the colour-1 sum to slot
+// [1]; the colour-1 launch then moves staging to [0]. filter0 / filter1: row filters of the two
+// launches (0: every row).
+static int colour_pair(Ctx& c, int l, const TileCfg& t, int filter0, int filter1) {
+  Level& L = c.lv[l];
+  double* cs = c.lsum(l);
+  HalfSweepArgs a{};
+  a.th_in = L.th[L.cur];
+  a.th_red_new = nullptr;
+  a.th_out = L.th[L.cur ^ 1];
+  a.delta = L.delta;
+  a.f = (l == 0) ? nullptr : L.f;
+  a.n = L.n;
+  a.colour = 0;
+  a.h2 = L.h * L.h;
+  a.ih2 = 1.0 / a.h2;
+  a.c_sum = cs;
+  a.c_scale = 1.0 / (double)L.cells;
+  a.c_add = 0.0;
+  a.sum_out = cs + 2;
+  a.copy_from = nullptr;
+  a.copy_to = nullptr;
+  a.partials = c.partials;
+  a.counter = c.counter;
+  a.row_filter = filter0;
+  hipError_t e = launch_half_sweep(a, t, c.stream);
+  if (e != hipSuccess) return hip_fail(e, "colour-0 half-sweep");
+  a.colour = 1;
+  a.th_red_new = L.th[L.cur ^ 1];
+  a.sum_out = cs + 1;
+  a.copy_from = cs + 2;
+  a.copy_to = cs + 0;
+  a.row_filter = filter1;
+  e = launch_half_sweep(a, t, c.stream);
+  if (e != hipSuccess) return hip_fail(e, "colour-1 half-sweep");
+  L.cur ^= 1;
+  return MR_OK;
+}
+
+// Row filters of the two colour launches of 4-class sub-sweep cls. The class of cell (i, j, k) is
+// 2 ((j + k) mod 2) + ((i + k) mod 2); with A = cls >> 1 and B = cls & 1 its cells of colour 0
+// ((i + j + k) even) lie in the rows with (i, j) parity (A, B) and its cells of colour 1 in the
+// rows with parity (1 - A, 1 - B), one colour row each.
+static void class_filters(int cls, int& filter0, int& filter1) {
+  const int A = cls >> 1, B = cls & 1;
+  filter0 = 4 + 2 * A + B;
+  filter1 = 4 + 2 * (A ^ 1) + (B ^ 1);
+}
+
+// One sweep on level l: the fused red-black launch, the two per-colour launches, or (with
+// MR_FLAG_ORDER4) four class sub-sweeps of two row-filtered tiled launches each.
 int Ctx::sweep(int l) {
   Level& L = lv[l];
   double* cs = lsum(l);
-  if (L.has_fz && !(opts.flags & MR_FLAG_TWO_PASS)) {
+  const bool order4 = (opts.flags & MR_FLAG_ORDER4) != 0;
+  if (!order4 && L.has_fz && !(opts.flags & MR_FLAG_TWO_PASS)) {
     FusedSweepArgs a{};
     a.th_in = L.th[L.cur];
     a.th_out = L.th[L.cur ^ 1];
@@ -228,36 +280,20 @@ int Ctx::sweep(int l) {
     L.cur ^= 1;
     return MR_OK;
   }
-  HalfSweepArgs a{};
-  a.th_in = L.th[L.cur];
-  a.th_red_new = nullptr;
-  a.th_out = L.th[L.cur ^ 1];
-  a.delta = L.delta;
-  a.f = (l == 0) ? nullptr : L.f;
-  a.n = L.n;
-  a.colour = 0;
-  a.h2 = L.h * L.h;
-  a.ih2 = 1.0 / a.h2;
-  a.c_sum = cs;
-  a.c_scale = 1.0 / (double)L.cells;
-  a.c_add = 0.0;
-  a.sum_out = cs + 2;
-  a.copy_from = nullptr;
-  a.copy_to = nullptr;
-  a.partials = partials;
-  a.counter = counter;
   const int ev = (l == 0) ? timer.begin(stream) : -1;
-  hipError_t e = launch_half_sweep(a, L.sw, stream);
-  if (e != hipSuccess) return hip_fail(e, "red half-sweep");
-  a.colour = 1;
-  a.th_red_new = L.th[L.cur ^ 1];
-  a.sum_out = cs + 1;
-  a.copy_from = cs + 2;
-  a.copy_to = cs + 0;
-  e = launch_half_sweep(a, L.sw, stream);
-  if (e != hipSuccess) return hip_fail(e, "black half-sweep");
+  int rc = MR_OK;
+  if (!order4) {
+    rc = colour_pair(*this, l, L.sw, 0, 0);
+  } else {
+    const TileCfg t = sweep_tiles(L.n);
+    for (int cls = 0; cls < 4 && rc == MR_OK; ++cls) {
+      int f0, f1;
+      class_filters(cls, f0, f1);
+      rc = colour_pair(*this, l, t, f0, f1);
+    }
+  }
+  if (rc != MR_OK) return rc;
   timer.end(0, ev, stream);
-  L.cur ^= 1;
   return MR_OK;
 }
 
@@ -731,7 +767,38 @@ int mr_sweep(mr_ctx* h, int nl, double hcell, const double* delta, const double*
   if (e == hipSuccess) e = launch_to_split(theta_in, tin, nl, c->stream);
   if (e != hipSuccess) return hip_fail(e, "mr_sweep");
   FusedCfg fz;
-  if (!(c->opts.flags & MR_FLAG_TWO_PASS) && (tuned_sweep(nl, &fz) || pick_fused(nl, fz))) {
+  const bool order4 = (c->opts.flags & MR_FLAG_ORDER4) != 0;
+  double* final_out = tout;
+  if (order4) {
+    // four class sub-sweeps, each two row-filtered tiled launches, ping-ponging tin and tout
+    const TileCfg t = sweep_tiles(nl);
+    double* bufs[2] = {tin, tout};
+    for (int cls = 0; cls < 4 && e == hipSuccess; ++cls) {
+      int f0, f1;
+      class_filters(cls, f0, f1);
+      HalfSweepArgs a{};
+      a.th_in = bufs[cls & 1];
+      a.th_out = bufs[(cls & 1) ^ 1];
+      a.delta = ds;
+      a.f = fs;
+      a.n = nl;
+      a.h2 = hcell * hcell;
+      a.ih2 = 1.0 / a.h2;
+      a.c_add = cshift;
+      a.partials = c->partials;
+      a.counter = c->counter;
+      a.colour = 0;
+      a.row_filter = f0;
+      a.sum_out = c->scal + kSlotAux + 0;
+      e = launch_half_sweep(a, t, c->stream);
+      a.colour = 1;
+      a.row_filter = f1;
+      a.th_red_new = a.th_out;
+      a.sum_out = c->scal + kSlotAux + 1;
+      if (e == hipSuccess) e = launch_half_sweep(a, t, c->stream);
+    }
+    final_out = bufs[0];   // four sub-sweeps: the last one wrote back into the first buffer
+  } else if (!(c->opts.flags & MR_FLAG_TWO_PASS) && (tuned_sweep(nl, &fz) || pick_fused(nl, fz))) {
     FusedSweepArgs a{};
     a.th_in = tin;
     a.th_out = tout;
@@ -767,7 +834,7 @@ int mr_sweep(mr_ctx* h, int nl, double hcell, const double* delta, const double*
     a.sum_out = c->scal + kSlotAux + 1;
     if (e == hipSuccess) e = launch_half_sweep(a, t, c->stream);
   }
-  if (e == hipSuccess) e = launch_from_split(tout, theta_out, nl, nullptr, 0.0, c->stream);
+  if (e == hipSuccess) e = launch_from_split(final_out, theta_out, nl, nullptr, 0.0, c->stream);
   if (e != hipSuccess) return hip_fail(e, "mr_sweep");
   double s[2];
   if ((rc = c->read_scalars(kSlotAux, 2, s)) != MR_OK) return rc;

@@ -50,6 +50,9 @@ struct HalfSweepArgs {
   double* partials;
   unsigned int* counter;
   int tj, tiles_j, tiles_m, ci;
+  // 0: update every row of the colour. 4 + 2 (i & 1) + (j & 1): update only the rows (i, j) of
+  // that parity and copy the others (a sub-sweep of the 4-class ordering; tiled kernel only).
+  int row_filter;
 };
 
 // Fused defect + restriction: theta_c (and theta_c2) = R theta, dr = R d with

@@ -225,7 +225,8 @@ __global__ void __launch_bounds__(TM * TJ / CPT) half_sweep_tiled(HalfSweepArgs 
       const double fc = ff ? ff[e] : 0.0;
       double Ssum;
       const double sig = sigma_cell(t, 1.0 + dl[e], ih2, Ssum);
-      out[e] = (Ssum - h2 * (sig + fc - C)) * (1.0 / 6.0);
+      const bool keep = a.row_filter != 0 && (4 + 2 * (i & 1) + (j & 1)) != a.row_filter;
+      out[e] = keep ? L(c, i, R, S) : (Ssum - h2 * (sig + fc - C)) * (1.0 / 6.0);
       acc += sig + fc;
     }
     if (pre) store(i + 2, v);
@@ -1255,7 +1256,8 @@ hipError_t launch_half_sweep(const HalfSweepArgs& a, const TileCfg& t, hipStream
   b.ci = t.ci;
   const int blocks = (int)blocks_l;
   if (t.pipe) {
-    if (t.ci % 4 != 0 || t.cpt != 1 || (a.colour == 1 && !a.th_red_new)) return hipErrorInvalidValue;
+    if (t.ci % 4 != 0 || t.cpt != 1 || (a.colour == 1 && !a.th_red_new) || a.row_filter != 0)
+      return hipErrorInvalidValue;
 #define MR_HP_LAUNCH(TM, TJ)                                                                            \
     if (t.tm == TM && t.tj == TJ) {                                                                     \
       if (a.colour == 0 && !a.f)                                                                        \

@@ -27,6 +27,7 @@ MR_FLAG_EAGER = 1
 MR_FLAG_TWO_PASS = 2
 MR_FLAG_ADJ_ROWS = 4
 MR_FLAG_ADJ_TILED = 8
+MR_FLAG_ORDER4 = 16
 PREC_FP64 = 0
 PREC_MIXED = 1
 MR_SCHED_TILED = 0
