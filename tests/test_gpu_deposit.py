@@ -123,3 +123,15 @@ def test_particles_per_cell_convergence(scheme):
         cycles[m] = info.cycles
     print(f"{scheme}: V-cycles to 1e-8 by mesh (8, 1, 1/8 particles per cell): {cycles}")
     assert max(cycles.values()) <= 1.5 * min(cycles.values())
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("n,count", [(48, 2000), (8, 1), (96, 1)])
+def test_ragged_meshes_and_single_particle(scheme, n, count):
+    require_gpu()
+    announce(f"deposit {scheme} n={n} particles={count}")
+    pos = np.random.default_rng(700 + n + count).uniform(-n, 2 * n, (count, 3))
+    with mr.Context(n) as c:
+        got = host(c.deposit(dev(pos), 2.5, scheme))
+    ref = odep.overdensity(odep.deposit_loop(pos, n, 2.5, scheme) if count < 50 else odep.deposit(pos, n, 2.5, scheme))
+    np.testing.assert_allclose(got, ref, rtol=0, atol=_tol(n, count) + 1e-13 * np.abs(ref).max())

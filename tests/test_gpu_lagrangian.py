@@ -104,3 +104,18 @@ def test_lagrangian_errors():
         assert np.isnan(got[[2, 4]]).all()
         with pytest.raises(mr.MRError):
             c.lagrangian(theta, torch.zeros((0, 3), dtype=torch.float64, device="cuda"))
+
+
+@pytest.mark.parametrize("n,count", [(48, 3000), (8, 1), (96, 1)])
+def test_lagrangian_ragged_meshes_and_single_particle(n, count):
+    """Non-power-of-two meshes (rows not a multiple of the block width) and a single particle."""
+    require_gpu()
+    announce(f"lagrangian n={n} particles={count}")
+    theta = np.random.default_rng(500 + n).standard_normal((n, n, n))
+    pos = _particles(n, max(count, 11), 600 + n)[:count] if count >= 11 else \
+        np.random.default_rng(n).uniform(-n, 2 * n, (count, 3))
+    ref_disp, ref_psi = olag.lagrangian_map(theta, pos)
+    with mr.Context(n) as c:
+        disp, psi = c.lagrangian(dev(theta), dev(pos), want_psi=True)
+    np.testing.assert_array_equal(host(psi), ref_psi)
+    np.testing.assert_allclose(host(disp), ref_disp, rtol=0, atol=1e-13 * np.abs(ref_psi).max())
