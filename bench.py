@@ -217,6 +217,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the CIC and adjoint timings")
+    ap.add_argument("--no-order4", action="store_true", help="skip the 4-class ordering solve")
     ap.add_argument("--particles-only", action="store_true",
                     help="only time the deposits and the Lagrangian mapping (256^3 mesh, 256^3 particles)")
     ap.add_argument("--schedule", default="", metavar="KIND,TM,TJ,NCHUNKS",
@@ -347,7 +348,8 @@ def main():
     if not args.no_extra:
         out["adjoint"] = adjoint_run(ctx, delta, theta)
         out["cic"], out["lagrangian"] = cic_run()
-        out["order4"] = order4_run(ctx, delta, theta, info64.cycles if info64 else None)
+        if not args.no_order4:
+            out["order4"] = order4_run(ctx, delta, theta, info64.cycles if info64 else None)
     if not args.no_batched:
         out["batched"] = batched_run()
     if not args.no_cpu_baseline:
