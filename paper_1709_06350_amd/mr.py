@@ -155,6 +155,18 @@ def _ptr(t: Optional[torch.Tensor]):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _need(t: Optional[torch.Tensor], count: int, what: str):
+    """Host-side size check: the kernels index the buffers by the mesh and particle counts."""
+    if t is not None and t.numel() != count:
+        raise ValueError(f"{what}: expected {count} values, got {t.numel()}")
+
+
+def _particles(pos: torch.Tensor) -> int:
+    if pos.numel() % 3 != 0:
+        raise ValueError("pos: expected np x 3 coordinates")
+    return pos.numel() // 3
+
+
 def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -239,27 +251,33 @@ class Context:
         if scheme not in DEPOSIT_SCHEMES:
             raise ValueError(f"unknown scheme {scheme!r}")
         out = self._empty() if out is None else out
-        npart = pos.numel() // 3
+        npart = _particles(pos)
+        _need(out, self.n ** 3, "out")
         _check(self.lib.mr_deposit(self.h, _ptr(pos), npart, mass, DEPOSIT_SCHEMES[scheme], _ptr(out)))
         return out
 
     def deposit_cic(self, pos: torch.Tensor, mass: float = 1.0, out: Optional[torch.Tensor] = None):
         out = self._empty() if out is None else out
-        npart = pos.numel() // 3
+        npart = _particles(pos)
+        _need(out, self.n ** 3, "out")
         _check(self.lib.mr_deposit_cic(self.h, _ptr(pos), npart, mass, _ptr(out)))
         return out
 
     def lagrangian(self, theta: torch.Tensor, pos: torch.Tensor, want_psi: bool = False, out=None):
         """Lagrangian mapping (mr_lagrangian): per-particle displacement psi(x_p) (np x 3, so that
         q = pos + disp) and, if want_psi, the mesh field psi (n x n x n x 3)."""
-        npart = pos.numel() // 3
+        npart = _particles(pos)
+        _need(theta, self.n ** 3, "theta")
         disp = torch.empty((npart, 3), dtype=torch.float64, device="cuda") if out is None else out
+        _need(disp, 3 * npart, "out")
         psi = torch.empty((self.n, self.n, self.n, 3), dtype=torch.float64, device="cuda") if want_psi else None
         _check(self.lib.mr_lagrangian(self.h, _ptr(theta), _ptr(pos), npart, _ptr(disp), _ptr(psi)))
         return disp, psi
 
     def residual(self, delta: torch.Tensor, theta: torch.Tensor, want_r: bool = True):
         r = self._empty() if want_r else None
+        _need(delta, self.n ** 3, "delta")
+        _need(theta, self.n ** 3, "theta")
         rel = ctypes.c_double()
         ms = ctypes.c_double()
         _check(self.lib.mr_residual(self.h, _ptr(delta), _ptr(theta), _ptr(r), ctypes.byref(rel),
@@ -268,6 +286,8 @@ class Context:
 
     def solve(self, delta: torch.Tensor, theta: Optional[torch.Tensor] = None, check: bool = True):
         theta = torch.zeros_like(delta) if theta is None else theta
+        _need(delta, self.n ** 3, "delta")
+        _need(theta, self.n ** 3, "theta")
         info = mr_info()
         code = self.lib.mr_solve(self.h, _ptr(delta), _ptr(theta), ctypes.byref(info))
         if check:
@@ -284,6 +304,8 @@ class Context:
 
     def adjoint_solve(self, delta, theta_star, g, out=None, check: bool = True):
         out = self._empty() if out is None else out
+        for t, what in ((delta, "delta"), (theta_star, "theta_star"), (g, "g"), (out, "out")):
+            _need(t, self.n ** 3, what)
         info = mr_info()
         code = self.lib.mr_adjoint_solve(self.h, _ptr(delta), _ptr(theta_star), _ptr(g), _ptr(out),
                                          ctypes.byref(info))
@@ -305,6 +327,8 @@ class Context:
     def sweep(self, delta, theta_in, h=1.0, f=None, cshift=0.0, out=None):
         nl = theta_in.shape[0]
         out = self._empty(nl) if out is None else out
+        for t, what in ((delta, "delta"), (f, "f"), (theta_in, "theta_in"), (out, "out")):
+            _need(t, nl ** 3, what)
         s = ctypes.c_double()
         _check(self.lib.mr_sweep(self.h, nl, h, _ptr(delta), _ptr(f), cshift, _ptr(theta_in), _ptr(out),
                                  ctypes.byref(s)))
@@ -312,6 +336,8 @@ class Context:
 
     def defect_restrict(self, delta, theta, h=1.0, f=None, cshift=0.0):
         nl = theta.shape[0]
+        for t, what in ((delta, "delta"), (f, "f"), (theta, "theta")):
+            _need(t, nl ** 3, what)
         tc = self._empty(nl // 2)
         dr = self._empty(nl // 2)
         _check(self.lib.mr_defect_restrict(self.h, nl, h, _ptr(delta), _ptr(f), cshift, _ptr(theta),
@@ -320,6 +346,8 @@ class Context:
 
     def tau_rhs(self, delta, theta_hat, rd, h):
         nl = theta_hat.shape[0]
+        for t, what in ((delta, "delta"), (theta_hat, "theta_hat"), (rd, "rd")):
+            _need(t, nl ** 3, what)
         f = self._empty(nl)
         s = ctypes.c_double()
         _check(self.lib.mr_tau_rhs(self.h, nl, h, _ptr(delta), _ptr(theta_hat), _ptr(rd), _ptr(f),
@@ -328,11 +356,15 @@ class Context:
 
     def prolong_correct(self, theta_c, theta_hat_c, theta):
         nl = theta.shape[0]
+        _need(theta, nl ** 3, "theta")
+        _need(theta_c, (nl // 2) ** 3, "theta_c")
+        _need(theta_hat_c, (nl // 2) ** 3, "theta_hat_c")
         _check(self.lib.mr_prolong_correct(self.h, nl, _ptr(theta_c), _ptr(theta_hat_c), _ptr(theta)))
         return theta
 
     def restrict(self, fine):
         nl = fine.shape[0]
+        _need(fine, nl ** 3, "fine")
         out = self._empty(nl // 2)
         _check(self.lib.mr_restrict(self.h, nl, _ptr(fine), _ptr(out)))
         return out

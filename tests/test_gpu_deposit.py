@@ -135,3 +135,23 @@ def test_ragged_meshes_and_single_particle(scheme, n, count):
         got = host(c.deposit(dev(pos), 2.5, scheme))
     ref = odep.overdensity(odep.deposit_loop(pos, n, 2.5, scheme) if count < 50 else odep.deposit(pos, n, 2.5, scheme))
     np.testing.assert_allclose(got, ref, rtol=0, atol=_tol(n, count) + 1e-13 * np.abs(ref).max())
+
+
+def test_binding_rejects_mismatched_buffers_before_any_launch():
+    """The kernels index the buffers by the mesh and particle counts; the binding checks them."""
+    require_gpu()
+    n = 8
+    with mr.Context(n) as c:
+        pos = dev(np.random.default_rng(1).uniform(0, n, (10, 3)))
+        small = torch.zeros(n ** 3 - 1, dtype=torch.float64, device="cuda")
+        with pytest.raises(ValueError):
+            c.deposit(pos, 1.0, "cic", out=small)
+        with pytest.raises(ValueError):
+            c.deposit(dev(np.zeros(7)), 1.0, "ngp")
+        theta = dev(np.zeros((n, n, n)))
+        with pytest.raises(ValueError):
+            c.lagrangian(theta, pos, out=torch.zeros((9, 3), dtype=torch.float64, device="cuda"))
+        with pytest.raises(ValueError):
+            c.lagrangian(dev(np.zeros((n, n, n - 2))), pos)
+        with pytest.raises(ValueError):
+            c.solve(dev(np.zeros((n, n, n + 2))))
