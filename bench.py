@@ -344,6 +344,8 @@ def main():
                    "mixed": infom.cycles if infom else None},
         "rel_residual": {"fp64": info64.rel_residual if info64 else None,
                          "mixed": infom.rel_residual if infom else None},
+        "paper_context": "CPU code of the paper: 8 V-cycles, < 1 min on 64 CPUs (128^3) and about 6 min on "
+                         "360 CPUs (512^3), absolute rms residual 1e-8; other hardware and inputs, not a target",
     }
     if not args.no_extra:
         out["adjoint"] = adjoint_run(ctx, delta, theta)
