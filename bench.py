@@ -207,6 +207,20 @@ def order4_run(ctx, delta, theta, rb_cycles):
             "note": "4 conflict-free class sub-sweeps per sweep (row-filtered tiled launches)"}
 
 
+def anderson_run(ctx, delta, theta, rb_cycles, depth=4):
+    """The same FP64 solve with Anderson-accelerated V-cycles (one untimed and one timed run)."""
+    import torch
+
+    ctx.solve_anderson(delta, theta, depth=depth, check=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, info = ctx.solve_anderson(delta, theta, depth=depth, check=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"seconds": round(dt, 4), "cycles": info.cycles, "plain_cycles": rb_cycles, "depth": depth,
+            "rel_residual": info.rel_residual, "status": info.status}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -352,6 +366,7 @@ def main():
         out["cic"], out["lagrangian"] = cic_run()
         if not args.no_order4:
             out["order4"] = order4_run(ctx, delta, theta, info64.cycles if info64 else None)
+        out["anderson"] = anderson_run(ctx, delta, theta, info64.cycles if info64 else None)
     if not args.no_batched:
         out["batched"] = batched_run()
     if not args.no_cpu_baseline:

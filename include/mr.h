@@ -183,6 +183,18 @@ int mr_residual(mr_ctx* ctx, const double* delta, const double* theta, double* r
  * delta is validated (finite, 1 + delta > 0). info: host, may be NULL. */
 int mr_solve(mr_ctx* ctx, const double* delta, double* theta, mr_info* info);
 
+/* mr_solve (FP64 only) with Anderson acceleration of the V-cycle, for inputs on which the plain
+ * cycle converges slowly (cells close to empty, 1 + delta << 1, where the coarse-grid correction
+ * contributes little). This is an addition to the paper's method (Sec. II.A.3 runs plain V-cycles);
+ * the fixed point, and so the solution, is the same. With y_k the iterate after one V-cycle from
+ * x_k and f_k = y_k - x_k, the next iterate is y_k - sum_i gamma_i (y_{i+1} - y_i) over the last
+ * `depth` steps (1..8), gamma minimising |f_k - sum_i gamma_i (f_{i+1} - f_i)|_2 (solved from the
+ * Gram matrix of the stored f on the host; an ill-conditioned history restarts). The convergence
+ * test, tolerances, warm start and the returned info are those of mr_solve. Needs 2 (depth + 1) + 1
+ * extra fields of n^3 doubles, allocated on first use and kept with the context. Returns MR_EINVAL
+ * for a NULL argument, a depth outside 1..8 or a context at MR_PREC_MIXED; otherwise as mr_solve. */
+int mr_solve_anderson(mr_ctx* ctx, const double* delta, double* theta, int depth, mr_info* info);
+
 /* Gradient of a loss through the solve. Given delta, the converged theta_star = solve(delta)
  * and g = dLoss/dtheta (device n^3 each), writes grad_delta = dLoss/ddelta (device n^3):
  * solves J_p^T lambda = g - <g> (J_p the Jacobian of the mean-projected operator, obtained by

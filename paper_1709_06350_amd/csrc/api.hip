@@ -398,10 +398,12 @@ int Ctx::prepare(const double* delta) {
   return MR_OK;
 }
 
-int Ctx::solve_fp64(const double* delta, double* theta, mr_info* info) {
+int Ctx::solve_fp64(const double* delta, double* theta, mr_info* info, int aa_depth) {
   auto t0 = std::chrono::steady_clock::now();
   int rc = prepare(delta);
   if (rc != MR_OK) return rc;
+  if (aa_depth > 0 && (rc = aa_reserve(aa_depth)) != MR_OK) return rc;
+  AAState aa(aa_depth, aa_depth + 1);
   Level& L0 = lv[0];
   const double N3 = (double)L0.cells;
   hipError_t e;
@@ -431,6 +433,10 @@ int Ctx::solve_fp64(const double* delta, double* theta, mr_info* info) {
   // Each cycle: pre-relaxation, then the defect pass, whose sums give the residual norm of the
   // current iterate (convergence test); if not converged, coarse correction and post-relaxation.
   while (rel > opts.tol && cyc < opts.max_cycles) {
+    if (aa_depth > 0) {
+      e = aa_save(*this, L0.th[L0.cur]);
+      if (e != hipSuccess) return hip_fail(e, "Anderson save");
+    }
     if ((rc = down(0, scal + kSlotRes)) != MR_OK) return rc;
     double r[kSlotRes + 2];
     if ((rc = read_scalars(0, kSlotRes + 2, r)) != MR_OK) return rc;
@@ -447,6 +453,7 @@ int Ctx::solve_fp64(const double* delta, double* theta, mr_info* info) {
     if (rel < best) best = rel;
     if (rel <= opts.tol || cyc >= opts.max_cycles) break;
     if ((rc = up(0)) != MR_OK) return rc;
+    if (aa_depth > 0 && (rc = aa_step(aa, L0.th[L0.cur])) != MR_OK) return rc;
   }
   if (status == MR_OK && rel > opts.tol) {
     status = MR_NOT_CONVERGED;
@@ -734,6 +741,14 @@ int mr_residual(mr_ctx* h, const double* delta, const double* theta, double* r_o
   if (rel_out) *rel_out = (r0 > 0.0) ? n2 / r0 : n2;
   if (msum_out) *msum_out = m1;
   return MR_OK;
+}
+
+int mr_solve_anderson(mr_ctx* h, const double* delta, double* theta, int depth, mr_info* info) {
+  if (!h || !delta || !theta) return fail(MR_EINVAL, "mr_solve_anderson: null argument");
+  if (depth < 1 || depth > kAAMaxDepth) return fail(MR_EINVAL, "mr_solve_anderson: depth %d not in 1..%d", depth, kAAMaxDepth);
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (c->opts.precision != MR_PREC_FP64) return fail(MR_EINVAL, "mr_solve_anderson: FP64 precision only");
+  return c->solve_fp64(delta, theta, info, depth);
 }
 
 int mr_solve(mr_ctx* h, const double* delta, double* theta, mr_info* info) {

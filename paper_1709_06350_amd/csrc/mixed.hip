@@ -459,6 +459,7 @@ void Ctx::release_extra() {
     mixed = nullptr;
   }
   release_adjoint();
+  aa_release();
 }
 
 double* Ctx::linsum(int l) { return scal + kSlotLin + 3 * l; }

@@ -58,6 +58,18 @@ struct EventTimer {
 struct MixedState;
 struct AdjointState;
 
+constexpr int kAAMaxDepth = 8;   // longest Anderson history (steps)
+
+// Host side of one Anderson-accelerated solve: the chronological ring slots in use and the Gram
+// matrix of the stored fixed-point residuals f (indexed by slot).
+struct AAState {
+  int depth, ring;
+  long long steps = 0;
+  std::vector<int> order;
+  std::vector<double> gram;
+  AAState(int depth_, int ring_);
+};
+
 struct Ctx {
   int n = 0, nlev = 0, device = 0, max_lds = 65536;
   hipStream_t stream = nullptr;
@@ -72,6 +84,8 @@ struct Ctx {
   unsigned long long* cic_grid = nullptr;   // fixed-point CIC accumulation grid (allocated on first use)
   MixedState* mixed = nullptr;
   AdjointState* adj = nullptr;
+  double* aa_mem = nullptr;   // Anderson history (x save, f and y rings, partials), on first use
+  int aa_ring = 0;
 
   int dev_alloc(double** p, size_t count);
   Reduce reducer(int slot);
@@ -84,7 +98,10 @@ struct Ctx {
   int vcycle(int l);
   int finest_norm(const double* theta_split, ShiftRef sh, double* nrm, double* msig);
   int prepare(const double* delta_natural);
-  int solve_fp64(const double* delta, double* theta, mr_info* info);
+  int solve_fp64(const double* delta, double* theta, mr_info* info, int aa_depth = 0);
+  int aa_reserve(int depth);
+  int aa_step(AAState& st, double* iterate);
+  void aa_release();
   int solve_mixed(const double* delta, double* theta, mr_info* info);
   int deposit(const double* pos, long long np, double mass, int scheme, double* delta_out);
   int lagrangian(const double* theta, const double* pos, long long np, double* disp_out, double* psi_out);
@@ -105,5 +122,6 @@ std::vector<int> level_sizes(int n);
 int check_opts(const mr_opts& o);
 TileCfg sweep_tiles(int n);
 TileCfg defect_tiles(int n);
+hipError_t aa_save(const Ctx& c, const double* iterate);
 
 }  // namespace mr

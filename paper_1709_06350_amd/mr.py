@@ -41,7 +41,7 @@ DEPOSIT_SCHEMES = {"ngp": MR_DEPOSIT_NGP, "cic": MR_DEPOSIT_CIC, "tsc": MR_DEPOS
 EXPORTED = [
     "mr_default_opts", "mr_create", "mr_destroy", "mr_set_opts", "mr_size", "mr_levels",
     "mr_get_schedule", "mr_set_schedule",
-    "mr_deposit", "mr_deposit_cic", "mr_lagrangian", "mr_residual", "mr_solve", "mr_adjoint_solve", "mr_solve_batched",
+    "mr_deposit", "mr_deposit_cic", "mr_lagrangian", "mr_residual", "mr_solve", "mr_solve_anderson", "mr_adjoint_solve", "mr_solve_batched",
     "mr_tune_lin_tiles",
     "mr_sweep", "mr_defect_restrict", "mr_tau_rhs", "mr_prolong_correct", "mr_restrict",
     "mr_timing_enable", "mr_timing_read", "mr_last_error",
@@ -119,6 +119,7 @@ def load(path: Optional[str] = None):
     lib.mr_deposit.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int, vp]
     lib.mr_residual.argtypes = [vp, vp, vp, vp, dp, dp]
     lib.mr_solve.argtypes = [vp, vp, vp, ctypes.POINTER(mr_info)]
+    lib.mr_solve_anderson.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.POINTER(mr_info)]
     lib.mr_adjoint_solve.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(mr_info)]
     lib.mr_solve_batched.argtypes = [ip, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(vp),
                                      ctypes.POINTER(vp), ctypes.POINTER(mr_opts),
@@ -290,6 +291,18 @@ class Context:
         _need(theta, self.n ** 3, "theta")
         info = mr_info()
         code = self.lib.mr_solve(self.h, _ptr(delta), _ptr(theta), ctypes.byref(info))
+        if check:
+            _check(code)
+        return theta, Info.from_c(info)
+
+    def solve_anderson(self, delta: torch.Tensor, theta: Optional[torch.Tensor] = None, depth: int = 6,
+                       check: bool = True):
+        """FP64 solve with Anderson-accelerated V-cycles (mr_solve_anderson)."""
+        theta = torch.zeros_like(delta) if theta is None else theta
+        _need(delta, self.n ** 3, "delta")
+        _need(theta, self.n ** 3, "theta")
+        info = mr_info()
+        code = self.lib.mr_solve_anderson(self.h, _ptr(delta), _ptr(theta), depth, ctypes.byref(info))
         if check:
             _check(code)
         return theta, Info.from_c(info)
