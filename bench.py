@@ -207,7 +207,7 @@ def order4_run(ctx, delta, theta, rb_cycles):
             "note": "4 conflict-free class sub-sweeps per sweep (row-filtered tiled launches)"}
 
 
-def anderson_run(ctx, delta, theta, rb_cycles, depth=4):
+def anderson_run(ctx, delta, theta, rb_cycles, depth=2):
     """The same FP64 solve with Anderson-accelerated V-cycles (one untimed and one timed run)."""
     import torch
 

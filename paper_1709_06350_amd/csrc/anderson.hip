@@ -75,15 +75,16 @@ struct AACoef {
   double c[kAAMaxRing];
 };
 
-// out = sum_j c_j ring_j.
+// out = out2 = sum_j c_j ring_j (the new iterate, and its copy kept as x for the next step).
 __global__ void __launch_bounds__(256) aa_combine_kernel(AAPtrs ring, AACoef c, int nr, size_t cells,
-                                                         double* __restrict__ out) {
+                                                         double* __restrict__ out, double* __restrict__ out2) {
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < cells; e += (size_t)gridDim.x * blockDim.x) {
     double v = 0.0;
 #pragma unroll
     for (int j = 0; j < kAAMaxRing; ++j)
       if (j < nr) v += c.c[j] * ring.p[j][e];
     out[e] = v;
+    out2[e] = v;
   }
 }
 
@@ -144,8 +145,9 @@ static bool solve_small(std::vector<double> a, std::vector<double> b, int n, std
   return true;
 }
 
-// Called after a V-cycle took x (saved before the cycle) to y = the level-0 iterate. Records the
-// step, then overwrites the iterate with the Anderson combination.
+// Called after a V-cycle took x (st.x_prev: the saved start of the first cycle, the previous
+// combination, or the previous cycle's result in the y ring) to y = the level-0 iterate. Records
+// the step, then overwrites the iterate with the Anderson combination (also kept as the next x).
 int Ctx::aa_step(AAState& st, double* iterate) {
   const size_t cells = lv[0].cells;
   double* xsave = aa_mem;
@@ -160,8 +162,8 @@ int Ctx::aa_step(AAState& st, double* iterate) {
   AAPtrs rp{};
   for (int j = 0; j < nr; ++j) rp.p[j] = F + cells * (size_t)st.order[j];
   const int nb = (int)std::min<size_t>((cells + 255) / 256, (size_t)kAABlocks);
-  hipLaunchKernelGGL(aa_record_kernel, dim3(nb), dim3(256), 0, stream, xsave, iterate, F + cells * (size_t)slot,
-                     Y + cells * (size_t)slot, rp, nr, cells, part);
+  hipLaunchKernelGGL(aa_record_kernel, dim3(nb), dim3(256), 0, stream, st.x_prev ? st.x_prev : xsave, iterate,
+                     F + cells * (size_t)slot, Y + cells * (size_t)slot, rp, nr, cells, part);
   hipLaunchKernelGGL(aa_sum_kernel, dim3(1), dim3(256), 0, stream, part, nb, dots);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "Anderson record");
@@ -200,10 +202,14 @@ int Ctx::aa_step(AAState& st, double* iterate) {
       st.order.erase(st.order.begin(), st.order.end() - 1);
     }
   }
-  if (!mixed) return MR_OK;  // x_{k+1} = y_k, already in place
+  if (!mixed) {  // x_{k+1} = y_k: already the iterate, and stored in the y ring
+    st.x_prev = Y + cells * (size_t)slot;
+    return MR_OK;
+  }
   AAPtrs yp{};
   for (int j = 0; j < nr; ++j) yp.p[j] = Y + cells * (size_t)st.order[j];
-  hipLaunchKernelGGL(aa_combine_kernel, dim3(nb), dim3(256), 0, stream, yp, cf, nr, cells, iterate);
+  hipLaunchKernelGGL(aa_combine_kernel, dim3(nb), dim3(256), 0, stream, yp, cf, nr, cells, iterate, xsave);
+  st.x_prev = xsave;
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "Anderson combine");
   return MR_OK;

@@ -433,7 +433,7 @@ int Ctx::solve_fp64(const double* delta, double* theta, mr_info* info, int aa_de
   // Each cycle: pre-relaxation, then the defect pass, whose sums give the residual norm of the
   // current iterate (convergence test); if not converged, coarse correction and post-relaxation.
   while (rel > opts.tol && cyc < opts.max_cycles) {
-    if (aa_depth > 0) {
+    if (aa_depth > 0 && aa.steps == 0) {   // later cycles start from a state aa_step keeps
       e = aa_save(*this, L0.th[L0.cur]);
       if (e != hipSuccess) return hip_fail(e, "Anderson save");
     }

@@ -67,6 +67,7 @@ struct AAState {
   long long steps = 0;
   std::vector<int> order;
   std::vector<double> gram;
+  const double* x_prev = nullptr;   // start of the current cycle (null: the saved first iterate)
   AAState(int depth_, int ring_);
 };
 
