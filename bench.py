@@ -366,7 +366,9 @@ def main():
         out["cic"], out["lagrangian"] = cic_run()
         if not args.no_order4:
             out["order4"] = order4_run(ctx, delta, theta, info64.cycles if info64 else None)
-        out["anderson"] = anderson_run(ctx, delta, theta, info64.cycles if info64 else None)
+        out["anderson"] = {"fp64": anderson_run(ctx, delta, theta, info64.cycles if info64 else None)}
+        if run_mixed:
+            out["anderson"]["mixed"] = anderson_run(ctxm, delta, theta_m, infom.cycles if infom else None)
     if not args.no_batched:
         out["batched"] = batched_run()
     if not args.no_cpu_baseline:

@@ -183,7 +183,7 @@ int mr_residual(mr_ctx* ctx, const double* delta, const double* theta, double* r
  * delta is validated (finite, 1 + delta > 0). info: host, may be NULL. */
 int mr_solve(mr_ctx* ctx, const double* delta, double* theta, mr_info* info);
 
-/* mr_solve (FP64 only) with Anderson acceleration of the V-cycle, for inputs on which the plain
+/* mr_solve with Anderson acceleration of the V-cycle, for inputs on which the plain
  * cycle converges slowly (cells close to empty, 1 + delta << 1, where the coarse-grid correction
  * contributes little). This is an addition to the paper's method (Sec. II.A.3 runs plain V-cycles);
  * the fixed point, and so the solution, is the same. With y_k the iterate after one V-cycle from
@@ -191,8 +191,9 @@ int mr_solve(mr_ctx* ctx, const double* delta, double* theta, mr_info* info);
  * `depth` steps (1..8), gamma minimising |f_k - sum_i gamma_i (f_{i+1} - f_i)|_2 (solved from the
  * Gram matrix of the stored f on the host; an ill-conditioned history restarts). The convergence
  * test, tolerances, warm start and the returned info are those of mr_solve. Needs 2 (depth + 1) + 1
- * extra fields of n^3 doubles, allocated on first use and kept with the context. Returns MR_EINVAL
- * for a NULL argument, a depth outside 1..8 or a context at MR_PREC_MIXED; otherwise as mr_solve. */
+ * extra fields of n^3 doubles, allocated on first use and kept with the context. At MR_PREC_MIXED
+ * the mixed outer iteration theta -> theta + e(theta) is accelerated the same way. Returns MR_EINVAL
+ * for a NULL argument or a depth outside 1..8; otherwise as mr_solve. */
 int mr_solve_anderson(mr_ctx* ctx, const double* delta, double* theta, int depth, mr_info* info);
 
 /* Gradient of a loss through the solve. Given delta, the converged theta_star = solve(delta)

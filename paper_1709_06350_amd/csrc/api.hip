@@ -747,7 +747,7 @@ int mr_solve_anderson(mr_ctx* h, const double* delta, double* theta, int depth, 
   if (!h || !delta || !theta) return fail(MR_EINVAL, "mr_solve_anderson: null argument");
   if (depth < 1 || depth > kAAMaxDepth) return fail(MR_EINVAL, "mr_solve_anderson: depth %d not in 1..%d", depth, kAAMaxDepth);
   Ctx* c = reinterpret_cast<Ctx*>(h);
-  if (c->opts.precision != MR_PREC_FP64) return fail(MR_EINVAL, "mr_solve_anderson: FP64 precision only");
+  if (c->opts.precision == MR_PREC_MIXED) return c->solve_mixed(delta, theta, info, depth);
   return c->solve_fp64(delta, theta, info, depth);
 }
 

@@ -525,11 +525,13 @@ int Ctx::lin_vcycle(int l) {
   return MR_OK;
 }
 
-int Ctx::solve_mixed(const double* delta, double* theta, mr_info* info) {
+int Ctx::solve_mixed(const double* delta, double* theta, mr_info* info, int aa_depth) {
   auto t0 = std::chrono::steady_clock::now();
   int rc = mixed_alloc(this);
   if (rc != MR_OK) return rc;
   if ((rc = prepare(delta)) != MR_OK) return rc;
+  if (aa_depth > 0 && (rc = aa_reserve(aa_depth)) != MR_OK) return rc;
+  AAState aa(aa_depth, aa_depth + 1);
   Level& L0 = lv[0];
   const double N3 = (double)L0.cells;
   L0.cur = 0;
@@ -576,7 +578,10 @@ int Ctx::solve_mixed(const double* delta, double* theta, mr_info* info) {
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "inner shift");
     for (int k = 0; k < opts.inner_cycles; ++k)
       if ((rc = lin_vcycle(0)) != MR_OK) return rc;
+    if (aa_depth > 0 && aa.steps == 0 && (e = aa_save(*this, L0.th[0])) != hipSuccess) return hip_fail(e, "Anderson save");
     if ((e = launch_update64(L0.th[0], M0.e[M0.cur], L0.cells, stream)) != hipSuccess) return hip_fail(e, "update");
+    // Anderson mixing of the outer iteration theta -> theta + e(theta), as for the FP64 cycle
+    if (aa_depth > 0 && (rc = aa_step(aa, L0.th[0])) != MR_OK) return rc;
     ++it;
   }
   if (status == MR_OK && rel > opts.tol) {

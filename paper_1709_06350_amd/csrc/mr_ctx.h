@@ -103,7 +103,7 @@ struct Ctx {
   int aa_reserve(int depth);
   int aa_step(AAState& st, double* iterate);
   void aa_release();
-  int solve_mixed(const double* delta, double* theta, mr_info* info);
+  int solve_mixed(const double* delta, double* theta, mr_info* info, int aa_depth = 0);
   int deposit(const double* pos, long long np, double mass, int scheme, double* delta_out);
   int lagrangian(const double* theta, const double* pos, long long np, double* disp_out, double* psi_out);
   int adjoint_solve(const double* delta, const double* theta_star, const double* g, double* grad, mr_info* info);

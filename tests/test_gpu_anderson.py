@@ -89,6 +89,19 @@ def test_anderson_errors():
         for depth in (0, 9):
             with pytest.raises(mr.MRError):
                 c.solve_anderson(delta, depth=depth)
-    with mr.Context(32, precision=mr.PREC_MIXED) as c:
-        with pytest.raises(mr.MRError):
-            c.solve_anderson(delta, depth=3)
+
+
+def test_anderson_mixed_precision_reaches_the_fp64_fixed_point():
+    require_gpu()
+    announce("anderson mixed 64^3")
+    delta = inputs.lognormal(64, 1.0, 2.0, 1002)
+    with mr.Context(64, tol=1e-10) as c:
+        ref, _ = c.solve(dev(delta))
+    with mr.Context(64, tol=1e-10, precision=mr.PREC_MIXED) as c:
+        _, im = c.solve(dev(delta))
+        th, ia = c.solve_anderson(dev(delta), depth=2)
+    assert ia.status == 0
+    h = host(th)
+    assert _rel_residual(h, delta) <= 2e-10
+    np.testing.assert_allclose(h, host(ref), rtol=0, atol=1e-8 * np.abs(host(ref)).max())
+    print(f"mixed 64^3: outer iterations plain {im.cycles}, Anderson(2) {ia.cycles}")
