@@ -206,6 +206,13 @@ int mr_solve_anderson(mr_ctx* ctx, const double* delta, double* theta, int depth
 int mr_adjoint_solve(mr_ctx* ctx, const double* delta, const double* theta_star,
                      const double* g, double* grad_delta, mr_info* info);
 
+/* mr_adjoint_solve with Anderson mixing of lambda between the transposed V-cycles, as
+ * mr_solve_anderson does for theta (not in the paper; same solution). depth 1..8; the history
+ * (2 (depth + 1) + 1 fields of n^3 doubles) is shared with mr_solve_anderson. Returns MR_EINVAL for
+ * a NULL argument or a depth outside 1..8; otherwise as mr_adjoint_solve. */
+int mr_adjoint_solve_anderson(mr_ctx* ctx, const double* delta, const double* theta_star, const double* g,
+                              double* grad_delta, int depth, mr_info* info);
+
 /* Batched solve of nbox independent periodic boxes of possibly different sizes (the one-mesh
  * solve applied box by box, Sec. II.A, in the mixed-precision form). n: host array of nbox box
  * sizes (each even, 8..1024, coarsest level at most 12^3). delta, theta: host arrays of nbox

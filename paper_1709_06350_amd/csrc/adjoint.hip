@@ -778,11 +778,14 @@ int Ctx::adj_vcycle(int l, double* norm2) {
   return MR_OK;
 }
 
-int Ctx::adjoint_solve(const double* delta, const double* theta_star, const double* g, double* grad, mr_info* info) {
+int Ctx::adjoint_solve(const double* delta, const double* theta_star, const double* g, double* grad, mr_info* info,
+                       int aa_depth) {
   auto t0 = std::chrono::steady_clock::now();
   if (nlev == 1) return fail(MR_EINVAL, "adjoint needs at least two levels (n >= 8)");
   int rc = adjoint_alloc(this);
   if (rc != MR_OK) return rc;
+  if (aa_depth > 0 && (rc = aa_reserve(aa_depth)) != MR_OK) return rc;
+  AAState aa(aa_depth, aa_depth + 1);
   if ((rc = prepare(delta)) != MR_OK) return rc;
   Level& L0 = lv[0];
   AdjLevel& A0 = adj->lv[0];
@@ -823,6 +826,8 @@ int Ctx::adjoint_solve(const double* delta, const double* theta_star, const doub
   int cyc = 0, status = MR_OK;
   double rel = (loc.r0_norm == 0.0) ? 0.0 : 1.0;
   while (rel > opts.tol && cyc < opts.max_cycles) {
+    if (aa_depth > 0 && aa.steps == 0 && (e = aa_save(*this, A0.lam[A0.cur])) != hipSuccess)
+      return hip_fail(e, "Anderson save");
     if ((rc = adj_vcycle(0, scal + kSlotAux + 6)) != MR_OK) return rc;
     ++cyc;
     rel = adj_last_norm / r0;
@@ -831,6 +836,10 @@ int Ctx::adjoint_solve(const double* delta, const double* theta_star, const doub
       status = fail(MR_EDIVERGED, "adjoint diverged at cycle %d", cyc);
       break;
     }
+    // Anderson mixing of lambda between cycles (not after the last one, whose running sums the
+    // gradient uses); the mixed lambda stays mean-free up to the lag of those sums
+    if (aa_depth > 0 && rel > opts.tol && cyc < opts.max_cycles && (rc = aa_step(aa, A0.lam[A0.cur])) != MR_OK)
+      return rc;
   }
   if (status == MR_OK && rel > opts.tol) {
     status = MR_NOT_CONVERGED;
@@ -855,4 +864,13 @@ extern "C" int mr_adjoint_solve(mr_ctx* h, const double* delta, const double* th
                                 double* grad_delta, mr_info* info) {
   if (!h || !delta || !theta_star || !g || !grad_delta) return mr::fail(MR_EINVAL, "mr_adjoint_solve: null argument");
   return reinterpret_cast<mr::Ctx*>(h)->adjoint_solve(delta, theta_star, g, grad_delta, info);
+}
+
+extern "C" int mr_adjoint_solve_anderson(mr_ctx* h, const double* delta, const double* theta_star, const double* g,
+                                         double* grad_delta, int depth, mr_info* info) {
+  if (!h || !delta || !theta_star || !g || !grad_delta)
+    return mr::fail(MR_EINVAL, "mr_adjoint_solve_anderson: null argument");
+  if (depth < 1 || depth > mr::kAAMaxDepth)
+    return mr::fail(MR_EINVAL, "mr_adjoint_solve_anderson: depth %d not in 1..%d", depth, mr::kAAMaxDepth);
+  return reinterpret_cast<mr::Ctx*>(h)->adjoint_solve(delta, theta_star, g, grad_delta, info, depth);
 }

@@ -106,7 +106,8 @@ struct Ctx {
   int solve_mixed(const double* delta, double* theta, mr_info* info, int aa_depth = 0);
   int deposit(const double* pos, long long np, double mass, int scheme, double* delta_out);
   int lagrangian(const double* theta, const double* pos, long long np, double* disp_out, double* psi_out);
-  int adjoint_solve(const double* delta, const double* theta_star, const double* g, double* grad, mr_info* info);
+  int adjoint_solve(const double* delta, const double* theta_star, const double* g, double* grad, mr_info* info,
+                    int aa_depth = 0);
   int adj_sweep(int l);
   int adj_vcycle(int l, double* norm2);
   double adj_last_norm = 0.0, adj_stop = 0.0;

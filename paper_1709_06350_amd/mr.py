@@ -41,7 +41,7 @@ DEPOSIT_SCHEMES = {"ngp": MR_DEPOSIT_NGP, "cic": MR_DEPOSIT_CIC, "tsc": MR_DEPOS
 EXPORTED = [
     "mr_default_opts", "mr_create", "mr_destroy", "mr_set_opts", "mr_size", "mr_levels",
     "mr_get_schedule", "mr_set_schedule",
-    "mr_deposit", "mr_deposit_cic", "mr_lagrangian", "mr_residual", "mr_solve", "mr_solve_anderson", "mr_adjoint_solve", "mr_solve_batched",
+    "mr_deposit", "mr_deposit_cic", "mr_lagrangian", "mr_residual", "mr_solve", "mr_solve_anderson", "mr_adjoint_solve", "mr_adjoint_solve_anderson", "mr_solve_batched",
     "mr_tune_lin_tiles",
     "mr_sweep", "mr_defect_restrict", "mr_tau_rhs", "mr_prolong_correct", "mr_restrict",
     "mr_timing_enable", "mr_timing_read", "mr_last_error",
@@ -121,6 +121,7 @@ def load(path: Optional[str] = None):
     lib.mr_solve.argtypes = [vp, vp, vp, ctypes.POINTER(mr_info)]
     lib.mr_solve_anderson.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.POINTER(mr_info)]
     lib.mr_adjoint_solve.argtypes = [vp, vp, vp, vp, vp, ctypes.POINTER(mr_info)]
+    lib.mr_adjoint_solve_anderson.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int, ctypes.POINTER(mr_info)]
     lib.mr_solve_batched.argtypes = [ip, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(vp),
                                      ctypes.POINTER(vp), ctypes.POINTER(mr_opts),
                                      ctypes.POINTER(mr_info), vp]
@@ -315,13 +316,18 @@ class Context:
             setattr(self.opts, k, v)
         _check(self.lib.mr_set_opts(self.h, ctypes.byref(self.opts)))
 
-    def adjoint_solve(self, delta, theta_star, g, out=None, check: bool = True):
+    def adjoint_solve(self, delta, theta_star, g, out=None, check: bool = True, anderson_depth: int = 0):
+        """dL/ddelta (mr_adjoint_solve, or mr_adjoint_solve_anderson when anderson_depth > 0)."""
         out = self._empty() if out is None else out
         for t, what in ((delta, "delta"), (theta_star, "theta_star"), (g, "g"), (out, "out")):
             _need(t, self.n ** 3, what)
         info = mr_info()
-        code = self.lib.mr_adjoint_solve(self.h, _ptr(delta), _ptr(theta_star), _ptr(g), _ptr(out),
-                                         ctypes.byref(info))
+        if anderson_depth > 0:
+            code = self.lib.mr_adjoint_solve_anderson(self.h, _ptr(delta), _ptr(theta_star), _ptr(g), _ptr(out),
+                                                      anderson_depth, ctypes.byref(info))
+        else:
+            code = self.lib.mr_adjoint_solve(self.h, _ptr(delta), _ptr(theta_star), _ptr(g), _ptr(out),
+                                             ctypes.byref(info))
         if check:
             _check(code)
         return out, Info.from_c(info)

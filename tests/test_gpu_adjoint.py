@@ -175,3 +175,34 @@ def test_config_adjoint_256_fd_32_cells():
     print(f"adjoint 256^3: eps=1e-4 max per-cell rel err {rel4.max():.3e}; eps=1e-6 max err / max|g| {err6:.3e}")
     assert rel4.max() <= 1e-4
     assert err6 <= 2e-2
+
+
+@pytest.mark.parametrize("n,depth", [(16, 2), (24, 4)])
+def test_anderson_adjoint_matches_oracle_direct(n, depth):
+    """mr_adjoint_solve_anderson: the same linear system, so the same gradient as the oracle's
+    direct adjoint (<= 1e-8 relative L2)."""
+    require_gpu()
+    announce(f"anderson adjoint vs oracle n={n} depth={depth}")
+    delta, theta, g, ref = _oracle_case(n)
+    with mr.Context(n, tol=1e-13) as c:
+        got, info = c.adjoint_solve(dev(delta), dev(theta), dev(g), anderson_depth=depth)
+    err = np.linalg.norm(host(got) - ref) / np.linalg.norm(ref)
+    print(f"anderson adjoint n={n}: cycles={info.cycles} rel L2 err={err:.3e}")
+    assert info.status == 0 and err <= 1e-8
+
+
+def test_anderson_adjoint_matches_plain_adjoint_128():
+    require_gpu()
+    n = 128
+    announce("anderson adjoint vs plain n=128")
+    delta = inputs.lognormal(n, 1.0, 2.0, 1002)
+    with mr.Context(n, tol=1e-10) as c:
+        theta, _ = c.solve(dev(delta))
+        g = theta - theta.mean()
+        c.set_opts(tol=1e-10)
+        a, ia = c.adjoint_solve(dev(delta), theta, g)
+        b, ib = c.adjoint_solve(dev(delta), theta, g, anderson_depth=2)
+    ha, hb = host(a), host(b)
+    err = np.linalg.norm(hb - ha) / np.linalg.norm(ha)
+    print(f"adjoint 128^3: cycles plain {ia.cycles}, Anderson(2) {ib.cycles}; rel L2 diff {err:.2e}")
+    assert ia.status == 0 and ib.status == 0 and err <= 1e-8
