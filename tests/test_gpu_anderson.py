@@ -105,3 +105,19 @@ def test_anderson_mixed_precision_reaches_the_fp64_fixed_point():
     assert _rel_residual(h, delta) <= 2e-10
     np.testing.assert_allclose(h, host(ref), rtol=0, atol=1e-8 * np.abs(host(ref)).max())
     print(f"mixed 64^3: outer iterations plain {im.cycles}, Anderson(2) {ia.cycles}")
+
+
+def test_autograd_with_anderson_matches_plain():
+    require_gpu()
+    from paper_1709_06350_amd import autograd as mag
+    announce("autograd with anderson 32^3")
+    delta = inputs.config0_delta()
+    grads = []
+    with mr.Context(32, tol=1e-12) as c:
+        for depth in (0, 2):
+            d = dev(delta).requires_grad_(True)
+            theta = mag.solve(d, c, anderson_depth=depth)
+            (theta * theta).sum().backward()
+            grads.append(host(d.grad))
+    err = np.linalg.norm(grads[1] - grads[0]) / np.linalg.norm(grads[0])
+    assert err <= 1e-8, err
