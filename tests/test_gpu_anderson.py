@@ -121,3 +121,41 @@ def test_autograd_with_anderson_matches_plain():
             grads.append(host(d.grad))
     err = np.linalg.norm(grads[1] - grads[0]) / np.linalg.norm(grads[0])
     assert err <= 1e-8, err
+
+
+@pytest.mark.timeout(300)
+def test_cubic_test_at_the_papers_size():
+    """128^3 particles in a 10-cell cube on a 128^3 mesh (the paper's setup in cell units), empty
+    cells floored at eps = 0.01. One accelerated solve is capped at 127 cycles, so the solve is
+    restarted from its own result (warm start, fresh history) until it converges."""
+    require_gpu()
+    n, L, eps = 128, 10.0, 0.01
+    announce("cubic test 128^3 eps=0.01")
+    pos, inside = _cube(n, L)
+    with mr.Context(n, tol=1e-8, max_cycles=127) as c:
+        rho = 1.0 + host(c.deposit(dev(pos)))
+        r = np.maximum(rho, eps)
+        delta = r / r.mean() - 1.0
+        d = dev(delta)
+        theta = torch.zeros_like(d)
+        total = 0
+        for k in range(6):
+            c.set_opts(warm_start=1 if k else 0)
+            theta, info = c.solve_anderson(d, theta, depth=8, check=False)
+            total += info.cycles
+            if info.status == 0:
+                break
+        disp, _ = c.lagrangian(theta, dev(inside))
+    assert info.status == 0
+    assert _rel_residual(host(theta), delta) <= 2e-8
+    q = inside + host(disp)
+    A = np.c_[np.ones(len(inside)), inside]
+    coef, *_ = np.linalg.lstsq(A, q, rcond=None)
+    fit_rms = np.sqrt(((q - A @ coef) ** 2).mean())
+    f = (r.sum() - eps * (rho < eps).sum()) / r.sum()
+    expect = n * f ** (1.0 / 3.0) / L
+    slopes = np.diag(coef[1:])
+    print(f"128^3 cube, eps=0.01: {total} cycles; slopes {np.round(slopes, 4)} expected {expect:.4f}; "
+          f"iso-q fit rms {fit_rms:.3f} cells (spacing {expect:.2f})")
+    assert np.all(np.abs(slopes - expect) <= 0.005 * expect)
+    assert fit_rms <= 0.02 * expect   # measured 0.124 cells = 1 % of the spacing
