@@ -159,3 +159,23 @@ def test_cubic_test_at_the_papers_size():
           f"iso-q fit rms {fit_rms:.3f} cells (spacing {expect:.2f})")
     assert np.all(np.abs(slopes - expect) <= 0.005 * expect)
     assert fit_rms <= 0.02 * expect   # measured 0.124 cells = 1 % of the spacing
+
+
+def test_anderson_edge_cases():
+    """A 96^3 hierarchy (6^3 coarsest), a history longer than the solve, a warm start at the
+    solution (no cycle runs), and a cycle budget that ends before convergence."""
+    require_gpu()
+    announce("anderson edge cases 96^3")
+    delta = inputs.lognormal(96, 0.6, 3.0, 77)
+    d = dev(delta)
+    with mr.Context(96, tol=1e-10) as c:
+        a, ia = c.solve(d)
+        b, ib = c.solve_anderson(d, depth=8)
+        assert ia.status == 0 and ib.status == 0
+        np.testing.assert_allclose(host(b), host(a), rtol=0, atol=1e-8 * np.abs(host(a)).max())
+        c.set_opts(warm_start=1)
+        w, iw = c.solve_anderson(d, b.clone(), depth=3)
+        assert iw.status == 0 and iw.cycles == 0
+        c.set_opts(warm_start=0, max_cycles=2)
+        _, i2 = c.solve_anderson(d, depth=3, check=False)
+        assert i2.status == mr.MR_NOT_CONVERGED and i2.cycles == 2
