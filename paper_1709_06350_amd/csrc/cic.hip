@@ -97,6 +97,115 @@ __global__ void __launch_bounds__(256) deposit_scatter_kernel(const double* __re
   }
 }
 
+// The same deposit with each wave's contributions binned in LDS first. A wave takes 64 consecutive
+// particles, finds the bounding box of the mesh points they reach (wrapped base indices, so a wave
+// straddling the periodic seam gets a wide box) and, when the box holds at most CAP points,
+// accumulates into a private LDS box with LDS atomics and then adds every non-zero box point to the
+// grid with one global atomic; otherwise it adds to the grid directly. For lattice-ordered
+// catalogues consecutive particles are neighbours, so a box point collects several contributions
+// and the global atomics (performed beyond the L2, the bound of the plain scatter) drop by that
+// factor. The integer sums per cell are the plain scatter's, so the result is bitwise identical.
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+  return v;
+}
+
+template <int S, int CAP>
+__global__ void __launch_bounds__(256) deposit_scatter_binned_kernel(const double* __restrict__ pos, long long np, int n,
+                                                                     unsigned long long* __restrict__ grid,
+                                                                     double* __restrict__ bad_count) {
+  __shared__ unsigned long long boxes[4][CAP];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  unsigned long long* box = boxes[w];
+  const long long nwaves = (long long)gridDim.x * 4;
+  for (long long seg = (long long)blockIdx.x * 4 + w; seg * 64 < np; seg += nwaves) {
+    const long long p = seg * 64 + lane;
+    bool valid = p < np;
+    double x = 0.0, y = 0.0, z = 0.0;
+    if (valid) {
+      x = pos[3 * p];
+      y = pos[3 * p + 1];
+      z = pos[3 * p + 2];
+      if (!__builtin_isfinite(x) || !__builtin_isfinite(y) || !__builtin_isfinite(z)) {
+        __hip_atomic_fetch_add(bad_count, 1.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        valid = false;
+      }
+    }
+    int ix[S], iy[S], iz[S];
+    double wx[S], wy[S], wz[S];
+    if (valid) {
+      axis_assign<S>(x, n, ix, wx);
+      axis_assign<S>(y, n, iy, wy);
+      axis_assign<S>(z, n, iz, wz);
+    }
+    // first point per axis before wrapping: ix[0] for CIC and NGP; for TSC ix[0] may have wrapped
+    // from -1 to n - 1, which only widens the box (then the wave takes the direct path)
+    const int bx = valid ? ix[0] : 0x3fffffff, by = valid ? iy[0] : 0x3fffffff, bz = valid ? iz[0] : 0x3fffffff;
+    const int lox = wave_min_i(bx), loy = wave_min_i(by), loz = wave_min_i(bz);
+    const int hix = wave_max_i(valid ? bx : -1), hiy = wave_max_i(valid ? by : -1), hiz = wave_max_i(valid ? bz : -1);
+    if (hix < 0) continue;  // no valid particle in this segment (wave-uniform)
+    const int ex = hix - lox + S, ey = hiy - loy + S, ez = hiz - loz + S;
+    const bool binned = (long long)ex * ey * ez <= CAP;  // wave-uniform
+    if (binned) {
+      const int vol = ex * ey * ez;
+      for (int t = lane; t < vol; t += 64) box[t] = 0ull;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (valid) {
+#pragma unroll
+        for (int a = 0; a < S; ++a)
+#pragma unroll
+          for (int b = 0; b < S; ++b)
+#pragma unroll
+            for (int d = 0; d < S; ++d) {
+              const double wgt = wx[a] * wy[b] * wz[d];
+              const unsigned long long q = (unsigned long long)__double2ull_rn(wgt * kFixScale);
+              // local coordinates from the unwrapped neighbours of the first point
+              const int l = ((bx + a - lox) * ey + (by + b - loy)) * ez + (bz + d - loz);
+              if (q) atomicAdd(&box[l], q);
+            }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int t = lane; t < vol; t += 64) {
+        const unsigned long long v = box[t];
+        if (v) {
+          const int lz = t % ez, ly = (t / ez) % ey, lx = t / (ez * ey);
+          int gx = lox + lx, gy = loy + ly, gz = loz + lz;
+          gx -= gx >= n ? n : 0;
+          gy -= gy >= n ? n : 0;
+          gz -= gz >= n ? n : 0;
+          atomicAdd(&grid[((size_t)gx * n + gy) * n + gz], v);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else if (valid) {
+#pragma unroll
+      for (int a = 0; a < S; ++a)
+#pragma unroll
+        for (int b = 0; b < S; ++b) {
+          const size_t row = ((size_t)ix[a] * n + iy[b]) * n;
+#pragma unroll
+          for (int d = 0; d < S; ++d) {
+            const double wgt = wx[a] * wy[b] * wz[d];
+            const unsigned long long q = (unsigned long long)__double2ull_rn(wgt * kFixScale);
+            if (q) atomicAdd(&grid[row + iz[d]], q);
+          }
+        }
+    }
+  }
+}
+
 // delta = count * n^3 / (np * 2^40) - 1; partials[block] = the block's sum of counts / 2^40. The
 // partials are added by sum_partials_kernel in the next launch (fixed order, no per-block fences).
 __global__ void __launch_bounds__(256) cic_normalise_kernel(const unsigned long long* __restrict__ grid, size_t cells,
@@ -147,12 +256,17 @@ int Ctx::deposit(const double* pos, long long np, double mass, int scheme, doubl
   hipLaunchKernelGGL(zero_u64_kernel, dim3(blocks_for(cells, 1 << 16)), dim3(256), 0, stream, cic_grid, cells,
                      bad_count);
   const dim3 pg(blocks_for((size_t)np, 1 << 16));
+  // CIC and TSC bin each wave's contributions in LDS (boxes of up to 1024 / 2048 mesh points);
+  // NGP has one contribution per particle and little to combine.
+  const dim3 wg((unsigned)std::min<long long>((np + 255) / 256, 1 << 16));
   if (scheme == MR_DEPOSIT_NGP)
     hipLaunchKernelGGL(deposit_scatter_kernel<1>, pg, dim3(256), 0, stream, pos, np, n, cic_grid, bad_count);
   else if (scheme == MR_DEPOSIT_CIC)
-    hipLaunchKernelGGL(deposit_scatter_kernel<2>, pg, dim3(256), 0, stream, pos, np, n, cic_grid, bad_count);
+    hipLaunchKernelGGL((deposit_scatter_binned_kernel<2, 1024>), wg, dim3(256), 0, stream, pos, np, n, cic_grid,
+                       bad_count);
   else
-    hipLaunchKernelGGL(deposit_scatter_kernel<3>, pg, dim3(256), 0, stream, pos, np, n, cic_grid, bad_count);
+    hipLaunchKernelGGL((deposit_scatter_binned_kernel<3, 2048>), wg, dim3(256), 0, stream, pos, np, n, cic_grid,
+                       bad_count);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "mr_deposit");
   double bad;
