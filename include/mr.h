@@ -164,11 +164,11 @@ int mr_deposit_cic(mr_ctx* ctx, const double* pos, int64_t np, double mass, doub
  * each particle (pos: device np x 3 doubles in cell units, any real value, wrapped as in
  * mr_deposit_cic) it is interpolated with the CIC weights of mr_deposit_cic (the transpose of the
  * deposit). disp_out: device np x 3, receives psi(x_p), so that q_p = x_p + disp_p. psi_out: device
- * n^3 x 3 doubles laid out [i][j][k][axis], receives the mesh field, or NULL (the field then lives
- * in a temporary allocated and freed by the call). The call synchronizes the context's stream.
- * Returns MR_EINVAL for a NULL argument, np < 1 or a particle with a non-finite coordinate (such a
- * particle's output is NaN, the others are computed), MR_ENOMEM if the temporary cannot be
- * allocated. */
+ * n^3 x 3 doubles laid out [i][j][k][axis], receives the mesh field, or NULL (then the differences
+ * at the 8 mesh points around each particle are formed from theta directly, with the same
+ * operations, so disp_out is bitwise the same; nothing is allocated). The call synchronizes the
+ * context's stream. Returns MR_EINVAL for a NULL argument, np < 1 or a particle with a non-finite
+ * coordinate (such a particle's output is NaN, the others are computed). */
 int mr_lagrangian(mr_ctx* ctx, const double* theta, const double* pos, int64_t np, double* disp_out,
                   double* psi_out);
 

@@ -371,23 +371,104 @@ __global__ void __launch_bounds__(256) lag_gather_kernel(const double* __restric
   }
 }
 
-int Ctx::lagrangian(const double* theta, const double* pos, long long np, double* disp_out, double* psi_out) {
-  const size_t cells = lv[0].cells;
-  double* psi = psi_out;
-  if (!psi) {
-    hipError_t e = hipMalloc((void**)&psi, cells * 3 * sizeof(double));
-    if (e != hipSuccess) return fail(MR_ENOMEM, "mr_lagrangian: mesh displacement: %s", hipGetErrorString(e));
+// Without the mesh field: the central differences of the 8 corners are formed at the particle from
+// theta itself (32 loads: per (y, z) corner pair the 4 points of the x line, per (x, z) and (x, y)
+// pair the 2 outer points of the y and z lines), with the same operations in the same order as
+// lag_grad_kernel followed by lag_gather_kernel, so the result is bitwise the same; theta (1/3 of the
+// mesh field) is read instead of writing and reading psi.
+__global__ void __launch_bounds__(256) lag_gather_theta_kernel(const double* __restrict__ pos, long long np, int n,
+                                                              const double* __restrict__ theta,
+                                                              double* __restrict__ disp,
+                                                              double* __restrict__ bad_count) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long p = xcd_remap(blockIdx.x, gridDim.x) * (long long)blockDim.x + threadIdx.x; p < np; p += stride) {
+    const double x = pos[3 * p], y = pos[3 * p + 1], z = pos[3 * p + 2];
+    if (!__builtin_isfinite(x) || !__builtin_isfinite(y) || !__builtin_isfinite(z)) {
+      __hip_atomic_fetch_add(bad_count, 1.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      disp[3 * p] = disp[3 * p + 1] = disp[3 * p + 2] = __builtin_nan("");
+      continue;
+    }
+    int ix0, ix1, iy0, iy1, iz0, iz1;
+    double fx, fy, fz;
+    wrap_coord(x, n, ix0, ix1, fx);
+    wrap_coord(y, n, iy0, iy1, fy);
+    wrap_coord(z, n, iz0, iz1, fz);
+    const int xm = ix0 == 0 ? n - 1 : ix0 - 1, xp = ix1 == n - 1 ? 0 : ix1 + 1;
+    const int ym = iy0 == 0 ? n - 1 : iy0 - 1, yp = iy1 == n - 1 ? 0 : iy1 + 1;
+    const int zm = iz0 == 0 ? n - 1 : iz0 - 1, zp = iz1 == n - 1 ? 0 : iz1 + 1;
+    const int xs[4] = {xm, ix0, ix1, xp}, ys[4] = {ym, iy0, iy1, yp}, zs[4] = {zm, iz0, iz1, zp};
+    auto T = [&](int i, int j, int k) { return theta[((size_t)i * n + j) * n + k]; };
+    double lx[2][2][4];   // [b][d][x line]
+    double ly[2][2][2];   // [a][d][y minus / plus]
+    double lz[2][2][2];   // [a][b][z minus / plus]
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) lx[b][d][t] = T(xs[t], ys[b + 1], zs[d + 1]);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int d = 0; d < 2; ++d) {
+        ly[a][d][0] = T(xs[a + 1], ys[0], zs[d + 1]);
+        ly[a][d][1] = T(xs[a + 1], ys[3], zs[d + 1]);
+      }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        lz[a][b][0] = T(xs[a + 1], ys[b + 1], zs[0]);
+        lz[a][b][1] = T(xs[a + 1], ys[b + 1], zs[3]);
+      }
+    const double wx[2] = {1.0 - fx, fx}, wy[2] = {1.0 - fy, fy}, wz[2] = {1.0 - fz, fz};
+    double v[8][3];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int a = c >> 2, b = (c >> 1) & 1, d = c & 1;
+      // the x, y and z central differences at corner (a, b, d), as lag_grad_kernel forms them
+      v[c][0] = (lx[b][d][a + 2] - lx[b][d][a]) * 0.5;
+      const double ylo = b == 0 ? ly[a][d][0] : lx[0][d][a + 1];
+      const double yhi = b == 0 ? lx[1][d][a + 1] : ly[a][d][1];
+      v[c][1] = (yhi - ylo) * 0.5;
+      const double zlo = d == 0 ? lz[a][b][0] : lx[b][0][a + 1];
+      const double zhi = d == 0 ? lx[b][1][a + 1] : lz[a][b][1];
+      v[c][2] = (zhi - zlo) * 0.5;
+    }
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int a = c >> 2, b = (c >> 1) & 1, d = c & 1;
+      const double w = wx[a] * wy[b] * wz[d];
+      a0 += w * v[c][0];
+      a1 += w * v[c][1];
+      a2 += w * v[c][2];
+    }
+    disp[3 * p] = a0;
+    disp[3 * p + 1] = a1;
+    disp[3 * p + 2] = a2;
   }
+}
+
+__global__ void zero_scalar_kernel(double* __restrict__ v) { *v = 0.0; }
+
+int Ctx::lagrangian(const double* theta, const double* pos, long long np, double* disp_out, double* psi_out) {
   double* bad_count = scal + kSlotRes;
-  hipLaunchKernelGGL(lag_grad_kernel, dim3((unsigned)n * n), dim3(n < 256 ? (n < 64 ? 64 : n) : 256), 0, stream, theta, n,
-                     psi, bad_count);
   // one particle per thread up to 2^28 particles, a grid-stride loop beyond
   const long long gb = std::min<long long>((np + 255) / 256, 1 << 20);
-  hipLaunchKernelGGL(lag_gather_kernel, dim3((unsigned)gb), dim3(256), 0, stream, pos, np, n, psi, disp_out, bad_count);
+  if (psi_out) {
+    hipLaunchKernelGGL(lag_grad_kernel, dim3((unsigned)n * n), dim3(n < 256 ? (n < 64 ? 64 : n) : 256), 0, stream, theta,
+                       n, psi_out, bad_count);
+    hipLaunchKernelGGL(lag_gather_kernel, dim3((unsigned)gb), dim3(256), 0, stream, pos, np, n, psi_out, disp_out,
+                       bad_count);
+  } else {
+    hipLaunchKernelGGL(zero_scalar_kernel, dim3(1), dim3(1), 0, stream, bad_count);
+    hipLaunchKernelGGL(lag_gather_theta_kernel, dim3((unsigned)gb), dim3(256), 0, stream, pos, np, n, theta, disp_out,
+                       bad_count);
+  }
   hipError_t e = hipGetLastError();
   double bad = 0.0;
   int rc = e == hipSuccess ? read_scalars(kSlotRes, 1, &bad) : hip_fail(e, "mr_lagrangian");
-  if (!psi_out) (void)hipFree(psi);
   if (rc != MR_OK) return rc;
   if (bad != 0.0) return fail(MR_EINVAL, "mr_lagrangian: %.0f particles with non-finite coordinates", bad);
   return MR_OK;
