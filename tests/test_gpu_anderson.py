@@ -3,7 +3,7 @@
 Parity is on the fixed point: the oracle evaluates the relative residual of the GPU result
 independently, and on a regular field the result equals the plain solve's. The cubic test is
 the paper's Sec. III check: particles uniform in a small cube at the centre of the box; with the
-empty cells floored at 1 + delta = eps (the library's policy: the equation needs 1 + delta > 0),
+empty cells floored at 1 + delta = eps by the caller (the equation needs 1 + delta > 0),
 the Lagrangian coordinates q = x + grad theta of the mesh points inside the cube must form a
 uniform grid. Mass conservation fixes the expected spacing: the cube holds a fraction f of the
 mass, so it maps onto a cube of side n f^(1/3) and the slope dq/dx is n f^(1/3) / L.
