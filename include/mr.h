@@ -84,8 +84,18 @@ typedef struct {
  * no cell of the 19-point stencil shares its centre's class, so the sources of a sub-sweep stay
  * fixed while it runs and the update is exact Gauss-Seidel. Each sub-sweep costs about as much as
  * a red-black sweep (row-filtered per-colour launches); the coarsest mesh keeps red-black. The
- * fixed point is the same as with red-black. */
-enum { MR_FLAG_EAGER = 1, MR_FLAG_TWO_PASS = 2, MR_FLAG_ADJ_ROWS = 4, MR_FLAG_ADJ_TILED = 8, MR_FLAG_ORDER4 = 16 };
+ * fixed point is the same as with red-black.
+ * MR_FLAG_ANDERSON (mr_solve_batched only): mix each box's outer iterations as mr_solve_anderson
+ * does, with depth 2 (the state stays on the device, inside the replayed graph); not in the paper,
+ * same solutions. */
+enum {
+  MR_FLAG_EAGER = 1,
+  MR_FLAG_TWO_PASS = 2,
+  MR_FLAG_ADJ_ROWS = 4,
+  MR_FLAG_ADJ_TILED = 8,
+  MR_FLAG_ORDER4 = 16,
+  MR_FLAG_ANDERSON = 32
+};
 
 /* Per-solve report. history[c] is the relative residual after cycle c (history[0] = start). */
 typedef struct {

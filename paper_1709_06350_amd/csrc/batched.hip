@@ -47,9 +47,27 @@ struct BStat {
   double hist[128]; // relative residual before update 0, 1, ...
 };
 
+// Anderson mixing of a box's outer iteration (MR_FLAG_ANDERSON, depth 2): with theta_k the
+// iterate after update k and e_k = theta_k - x_k the FP32 correction of that update, the next
+// start is sum_j c_j theta_j over the last three updates, c from the least squares on the e's. The
+// state lives on the device and is advanced by one thread per box, so the mixing stays inside the
+// captured outer iteration.
+constexpr int kBAARing = 3;
+struct BAAState {
+  long long steps;          // updates recorded since the last restart
+  int nr, mix;              // entries used by the last combination; 1 if it mixes
+  int order[kBAARing];      // ring slots of those entries, oldest first
+  double gram[kBAARing * kBAARing];
+  double c[kBAARing];
+};
+
 struct BBox {
   BLevel lv[kMaxLevels];
   double* theta;    // FP64 colour-split potential (finest)
+  double* aaY;      // Anderson history (null without MR_FLAG_ANDERSON): kBAARing iterates
+  float* aaF;       // ... and their corrections
+  double* aaPart;   // ... per-block partial dot products (256 x kBAARing)
+  BAAState* aa;
   double* res;      // 4 doubles: (sum Sigma, 0, sum b, sum b^2) of the last outer residual
   double* partials;
   unsigned int* counter;
@@ -225,6 +243,122 @@ __global__ void __launch_bounds__(256) b_update_kernel(const BBox* boxes, const 
   int b, t;
   if (!box_of(boxes, cls, bpb, b, t)) return;
   update64_body(boxes[b].theta, boxes[b].lv[0].e[cur0], cells, t, bpb);
+}
+
+// Slots of the history entries after recording update number `steps` (0-based), oldest first.
+__device__ __forceinline__ void baa_order(long long steps, int& nr, int (&order)[kBAARing]) {
+  nr = (int)(steps < kBAARing - 1 ? steps : kBAARing - 1) + 1;
+  for (int j = 0; j < kBAARing; ++j) order[j] = j < nr ? (int)((steps - (nr - 1) + j) % kBAARing) : 0;
+}
+
+// Records theta and e of the update just applied and the dot products of e with the stored e's
+// (per-block partials; bpb = 256 blocks per box, the partition of b_update_kernel).
+__global__ void __launch_bounds__(256) b_aa_record_kernel(const BBox* boxes, const int* cls, int bpb, int cur0,
+                                                          size_t cells) {
+  __shared__ double red[4][kBAARing];
+  int b, t;
+  if (!box_of(boxes, cls, bpb, b, t)) return;
+  const BBox& x = boxes[b];
+  int nr, order[kBAARing];
+  baa_order(x.aa->steps, nr, order);
+  const int slot = order[nr - 1];
+  const float* __restrict__ e = x.lv[0].e[cur0];
+  float* fnew = x.aaF + (size_t)slot * cells;
+  double* ynew = x.aaY + (size_t)slot * cells;
+  double acc[kBAARing] = {0.0, 0.0, 0.0};
+  for (size_t i = t * (size_t)blockDim.x + threadIdx.x; i < cells; i += (size_t)bpb * blockDim.x) {
+    const float f = e[i];
+    fnew[i] = f;
+    ynew[i] = x.theta[i];
+#pragma unroll
+    for (int j = 0; j < kBAARing; ++j)
+      if (j < nr) acc[j] += (double)f * (double)(order[j] == slot ? f : x.aaF[(size_t)order[j] * cells + i]);
+  }
+  block_sum<kBAARing>(acc, red, threadIdx.x, blockDim.x);
+  if (threadIdx.x == 0)
+    for (int j = 0; j < kBAARing; ++j) x.aaPart[(size_t)t * kBAARing + j] = acc[j];
+}
+
+// One block per box of a size class: adds the partials in block order, updates the Gram matrix
+// and solves the 1x1 or 2x2 least-squares problem (a 1e-12 relative Tikhonov term; a negligible
+// determinant restarts the history).
+__global__ void __launch_bounds__(256) b_aa_solve_kernel(const BBox* boxes, const int* cls, int nparts) {
+  __shared__ double red[4][kBAARing];
+  const BBox& x = boxes[cls[blockIdx.x]];
+  if (!x.st->active) return;
+  double acc[kBAARing] = {0.0, 0.0, 0.0};
+  for (int p = threadIdx.x; p < nparts; p += blockDim.x)
+#pragma unroll
+    for (int j = 0; j < kBAARing; ++j) acc[j] += x.aaPart[(size_t)p * kBAARing + j];
+  block_sum<kBAARing>(acc, red, threadIdx.x, blockDim.x);
+  if (threadIdx.x != 0) return;
+  BAAState& st = *x.aa;
+  int nr, order[kBAARing];
+  baa_order(st.steps, nr, order);
+  const int slot = order[nr - 1];
+  for (int j = 0; j < nr; ++j) {
+    st.gram[slot * kBAARing + order[j]] = acc[j];
+    st.gram[order[j] * kBAARing + slot] = acc[j];
+  }
+  auto G = [&](int a, int c) { return st.gram[order[a] * kBAARing + order[c]]; };
+  const int m = nr - 1;
+  double gam[2] = {0.0, 0.0};
+  bool mix = false;
+  if (m == 1) {
+    const double M = G(1, 1) - 2.0 * G(1, 0) + G(0, 0);
+    const double r = G(1, 1) - G(0, 1);
+    if (M > 0.0) {
+      gam[0] = r / (M * (1.0 + 1e-12));
+      mix = true;
+    }
+  } else if (m == 2) {
+    double M00 = G(1, 1) - G(1, 0) - G(0, 1) + G(0, 0);
+    const double M01 = G(1, 2) - G(1, 1) - G(0, 2) + G(0, 1);
+    double M11 = G(2, 2) - G(2, 1) - G(1, 2) + G(1, 1);
+    const double b0 = G(1, 2) - G(0, 2), b1 = G(2, 2) - G(1, 2);
+    const double reg = 1e-12 * 0.5 * (M00 + M11);
+    M00 += reg;
+    M11 += reg;
+    const double det = M00 * M11 - M01 * M01;
+    if (det > 1e-13 * M00 * M11) {
+      gam[0] = (b0 * M11 - b1 * M01) / det;
+      gam[1] = (M00 * b1 - M01 * b0) / det;
+      mix = true;
+    }
+  }
+  st.nr = nr;
+  for (int j = 0; j < kBAARing; ++j) {
+    st.order[j] = order[j];
+    st.c[j] = 0.0;
+  }
+  if (mix) {
+    st.c[m] = 1.0;
+    for (int i = 0; i < m; ++i) {
+      st.c[i + 1] -= gam[i];
+      st.c[i] += gam[i];
+    }
+    st.mix = 1;
+    st.steps += 1;
+  } else {
+    st.mix = 0;
+    st.steps = m >= 1 ? 0 : st.steps + 1;   // an unusable history restarts; the first step has none
+  }
+}
+
+// theta = sum_j c_j theta_j for the boxes whose last solve mixes.
+__global__ void __launch_bounds__(256) b_aa_combine_kernel(const BBox* boxes, const int* cls, int bpb, size_t cells) {
+  int b, t;
+  if (!box_of(boxes, cls, bpb, b, t)) return;
+  const BBox& x = boxes[b];
+  const BAAState& st = *x.aa;
+  if (!st.mix) return;
+  for (size_t i = t * (size_t)blockDim.x + threadIdx.x; i < cells; i += (size_t)bpb * blockDim.x) {
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < kBAARing; ++j)
+      if (j < st.nr) v += st.c[j] * x.aaY[(size_t)st.order[j] * cells + i];
+    x.theta[i] = v;
+  }
 }
 
 // ---- FP32 sweep tile tuner ----------------------------------------------------------------
@@ -585,13 +719,19 @@ static int record_iteration(std::vector<SizeClass>& cls, BBox* dboxes, const mr_
     }
     // a further inner cycle restarts from the current level-0 correction: nothing to reset
   }
-  // 4. theta += e
+  // 4. theta += e, then (MR_FLAG_ANDERSON) the mixing of the box's last updates
   for (size_t ci = 0; ci < cls.size(); ++ci) {
     SizeClass& c = cls[ci];
     const int nb = (int)c.boxes.size();
     const size_t cells = (size_t)c.n * c.n * c.n;
     hipLaunchKernelGGL(b_update_kernel, dim3(nb * 256), dim3(256), 0, s, dboxes, c.d_boxes, 256, cur[ci][0], cells);
     if (!ok()) return hip_fail(e, "batched update");
+    if (o.flags & MR_FLAG_ANDERSON) {
+      hipLaunchKernelGGL(b_aa_record_kernel, dim3(nb * 256), dim3(256), 0, s, dboxes, c.d_boxes, 256, cur[ci][0], cells);
+      hipLaunchKernelGGL(b_aa_solve_kernel, dim3(nb), dim3(256), 0, s, dboxes, c.d_boxes, 256);
+      hipLaunchKernelGGL(b_aa_combine_kernel, dim3(nb * 256), dim3(256), 0, s, dboxes, c.d_boxes, 256, cells);
+      if (!ok()) return hip_fail(e, "batched Anderson mixing");
+    }
   }
   return MR_OK;
 }
@@ -653,6 +793,14 @@ int solve_batched(int nbox, const int* n, const double* const* delta, double* co
     x.counter = mem.get<unsigned>(16);
     x.st = dstat + b;
     if (!x.theta || !x.res || !x.partials || !x.counter) return fail(MR_ENOMEM, "batched: box buffers");
+    if (o.flags & MR_FLAG_ANDERSON) {
+      const size_t cells = (size_t)c.n * c.n * c.n;
+      x.aaY = mem.get<double>(kBAARing * cells);
+      x.aaF = mem.get<float>(kBAARing * cells);
+      x.aaPart = mem.get<double>(256 * kBAARing);
+      x.aa = mem.get<BAAState>(1);
+      if (!x.aaY || !x.aaF || !x.aaPart || !x.aa) return fail(MR_ENOMEM, "batched: Anderson history");
+    }
     for (int l = 0; l < c.nlev; ++l) {
       const size_t cells = (size_t)c.ns[l] * c.ns[l] * c.ns[l];
       BLevel& L = x.lv[l];
@@ -737,6 +885,10 @@ int solve_batched(int nbox, const int* n, const double* const* delta, double* co
   e = hipMemcpy(resall, resinit.data(), resinit.size() * sizeof(double), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(dboxes, hb.data(), nbox * sizeof(BBox), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(dstat, hs.data(), nbox * sizeof(BStat), hipMemcpyHostToDevice);
+  if (o.flags & MR_FLAG_ANDERSON) {
+    const BAAState zero{};
+    for (int b = 0; b < nbox && e == hipSuccess; ++b) e = hipMemcpy(hb[b].aa, &zero, sizeof(BAAState), hipMemcpyHostToDevice);
+  }
   if (e != hipSuccess) return hip_fail(e, "batched setup");
   // capture one outer iteration
   const bool eager = (o.flags & MR_FLAG_EAGER) != 0;

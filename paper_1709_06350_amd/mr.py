@@ -28,6 +28,7 @@ MR_FLAG_TWO_PASS = 2
 MR_FLAG_ADJ_ROWS = 4
 MR_FLAG_ADJ_TILED = 8
 MR_FLAG_ORDER4 = 16
+MR_FLAG_ANDERSON = 32
 PREC_FP64 = 0
 PREC_MIXED = 1
 MR_SCHED_TILED = 0
@@ -390,20 +391,22 @@ class Context:
 
 
 def solve_batched(deltas: Sequence[torch.Tensor], thetas: Optional[Sequence[torch.Tensor]] = None,
-                  check: bool = True, eager: bool = False, **opts):
+                  check: bool = True, eager: bool = False, anderson: bool = False, **opts):
     """Solve independent periodic boxes of possibly different sizes in one batched call
     (mr_solve_batched: mixed precision, one launch per phase and box size, graph replay).
 
     deltas: contiguous float64 CUDA tensors of shapes (n_b, n_b, n_b). thetas: output tensors of
     the same shapes (allocated when None). eager: launch every pass directly instead of replaying
-    the captured graph. Remaining keywords set mr_opts fields (tol, max_cycles, npre, ...).
-    Returns (thetas, infos)."""
+    the captured graph. anderson: mix each box's outer iterations (MR_FLAG_ANDERSON). Remaining
+    keywords set mr_opts fields (tol, max_cycles, npre, ...). Returns (thetas, infos)."""
     lib = load()
     nbox = len(deltas)
     thetas = [torch.zeros_like(d) for d in deltas] if thetas is None else list(thetas)
     o = default_opts(**opts)
     if eager:
         o.flags |= MR_FLAG_EAGER
+    if anderson:
+        o.flags |= MR_FLAG_ANDERSON
     for t in list(deltas) + thetas:
         _ptr(t)
     ns = (ctypes.c_int * nbox)(*[d.shape[0] for d in deltas])

@@ -144,3 +144,31 @@ def test_batched_full_workload():
     cyc = [i.cycles for i in infos]
     print(f"64 boxes: outer iterations {min(cyc)}..{max(cyc)}, worst oracle rel residual {worst_rel:.3e}, "
           f"worst max|theta - theta_fp64| / max|theta_fp64| {worst_err:.3e}")
+
+
+def test_batched_anderson_matches_oracle_graph_and_isolation():
+    """MR_FLAG_ANDERSON: every box still reaches the oracle-checked residual and the oracle's
+    potential within the bound above; the graph equals direct launches and a box alone equals the
+    box in the batch (the mixing state is per box), bitwise."""
+    require_gpu()
+    announce("batched anderson, 6 boxes")
+    deltas = _fields(SMALL)
+    dd = [dev(d) for d in deltas]
+    thetas, infos = mr.solve_batched(dd, tol=TOL, anderson=True)
+    _, plain = mr.solve_batched(dd, tol=TOL)
+    for (n, s, rc, seed), d, t, inf, p in zip(SMALL, deltas, thetas, infos, plain):
+        th = host(t)
+        assert inf.status == 0 and inf.rel_residual <= TOL
+        rel = oop.relative_residual(th, d)
+        ref, _ = omg.solve(d, tol=1e-12, max_cycles=80)
+        err = np.abs(th - ref).max()
+        print(f"n={n} sigma={s}: outer {inf.cycles} (plain {p.cycles}), rel {rel:.3e}, max err {err:.3e}")
+        assert rel <= TOL * (1 + 1e-6)
+        assert err <= _theta_bound(n, inf.r0_norm)
+        assert inf.cycles <= p.cycles
+    te, ie = mr.solve_batched(dd, tol=TOL, anderson=True, eager=True)
+    for a, b, x, y in zip(thetas, te, infos, ie):
+        assert torch.equal(a, b) and x.cycles == y.cycles
+    for k in (1, 2):
+        ta, ia = mr.solve_batched([dd[k]], tol=TOL, anderson=True)
+        assert torch.equal(ta[0], thetas[k]) and ia[0].cycles == infos[k].cycles
