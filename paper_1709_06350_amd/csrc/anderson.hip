@@ -5,8 +5,9 @@
 // gamma minimises |f_k - sum_i gamma_i (f_{i+1} - f_i)|_2 (Anderson mixing with unit damping).
 // The fixed point, and so the solution, is that of the plain V-cycle.
 //
-// Device side: one pass records f_k and y_k into the history ring and forms the dot products of
-// f_k with every stored f (deterministic: per-block partials, added in block order by one block);
+// Device side: one pass records f_k (in FP32: it only enters the small least-squares problem) and
+// y_k (FP64) into the history ring and forms the dot products of f_k with every stored f
+// (deterministic: per-block partials, added in block order by one block);
 // one pass forms x_{k+1} as a linear combination of stored y. The small least-squares problem is
 // solved on the host from the Gram matrix of the stored f.
 #include <algorithm>
@@ -26,13 +27,16 @@ constexpr int kAABlocks = 2048;
 struct AAPtrs {
   const double* p[kAAMaxRing];
 };
+struct AAPtrsF {
+  const float* p[kAAMaxRing];
+};
 
 // f = y - x into f_out, y into y_out; partials[block][j] = sum over the block's cells of f * ring_j
 // (ring_j == f_out gives |f|^2).
 // f_out is one of the ring entries, so it is not declared __restrict__; its own dot product uses
 // the value in registers.
 __global__ void __launch_bounds__(256) aa_record_kernel(const double* __restrict__ x, const double* __restrict__ y,
-                                                        double* f_out, double* __restrict__ y_out, AAPtrs ring,
+                                                        float* f_out, double* __restrict__ y_out, AAPtrsF ring,
                                                         int nr, size_t cells, double* __restrict__ partials) {
   __shared__ double red[4][kAAMaxRing];
   double acc[kAAMaxRing];
@@ -40,12 +44,12 @@ __global__ void __launch_bounds__(256) aa_record_kernel(const double* __restrict
   for (int j = 0; j < kAAMaxRing; ++j) acc[j] = 0.0;
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < cells; e += (size_t)gridDim.x * blockDim.x) {
     const double yv = y[e];
-    const double f = yv - x[e];
+    const float f = (float)(yv - x[e]);
     f_out[e] = f;
     y_out[e] = yv;
 #pragma unroll
     for (int j = 0; j < kAAMaxRing; ++j)
-      if (j < nr) acc[j] += f * (ring.p[j] == f_out ? f : ring.p[j][e]);
+      if (j < nr) acc[j] += (double)f * (double)(ring.p[j] == f_out ? f : ring.p[j][e]);
   }
   block_sum<kAAMaxRing>(acc, red, threadIdx.x, blockDim.x);
   if (threadIdx.x == 0) {
@@ -96,8 +100,9 @@ int Ctx::aa_reserve(int depth) {
     aa_mem = nullptr;
   }
   const int ring = depth + 1;
-  // x save, ring of f and y, partials, dot results
-  const size_t count = cells * (1 + 2 * (size_t)ring) + (size_t)kAABlocks * kAAMaxRing + kAAMaxRing;
+  // x save, ring of y (FP64), ring of f (FP32, counted in doubles), partials, dot results
+  const size_t count = cells * (1 + (size_t)ring) + (cells * (size_t)ring + 1) / 2 + (size_t)kAABlocks * kAAMaxRing +
+                       kAAMaxRing;
   hipError_t e = hipMalloc((void**)&aa_mem, count * sizeof(double));
   if (e != hipSuccess) {
     aa_mem = nullptr;
@@ -151,15 +156,15 @@ static bool solve_small(std::vector<double> a, std::vector<double> b, int n, std
 int Ctx::aa_step(AAState& st, double* iterate) {
   const size_t cells = lv[0].cells;
   double* xsave = aa_mem;
-  double* F = aa_mem + cells;
-  double* Y = F + cells * (size_t)aa_ring;
+  double* Y = aa_mem + cells;
   double* part = Y + cells * (size_t)aa_ring;
   double* dots = part + (size_t)kAABlocks * kAAMaxRing;
+  float* F = reinterpret_cast<float*>(dots + kAAMaxRing);
   const int slot = (int)(st.steps % st.ring);
   st.order.push_back(slot);
   if ((int)st.order.size() > st.depth + 1) st.order.erase(st.order.begin());
   const int nr = (int)st.order.size();
-  AAPtrs rp{};
+  AAPtrsF rp{};
   for (int j = 0; j < nr; ++j) rp.p[j] = F + cells * (size_t)st.order[j];
   const int nb = (int)std::min<size_t>((cells + 255) / 256, (size_t)kAABlocks);
   hipLaunchKernelGGL(aa_record_kernel, dim3(nb), dim3(256), 0, stream, st.x_prev ? st.x_prev : xsave, iterate,
