@@ -200,8 +200,9 @@ int mr_solve(mr_ctx* ctx, const double* delta, double* theta, mr_info* info);
  * x_k and f_k = y_k - x_k, the next iterate is y_k - sum_i gamma_i (y_{i+1} - y_i) over the last
  * `depth` steps (1..8), gamma minimising |f_k - sum_i gamma_i (f_{i+1} - f_i)|_2 (solved from the
  * Gram matrix of the stored f on the host; an ill-conditioned history restarts). The convergence
- * test, tolerances, warm start and the returned info are those of mr_solve. Needs 2 (depth + 1) + 1
- * extra fields of n^3 doubles, allocated on first use and kept with the context. At MR_PREC_MIXED
+ * test, tolerances, warm start and the returned info are those of mr_solve. Needs depth + 2 extra
+ * fields of n^3 doubles and depth + 1 of floats, allocated on first use and kept with the context.
+ * At MR_PREC_MIXED
  * the mixed outer iteration theta -> theta + e(theta) is accelerated the same way. Returns MR_EINVAL
  * for a NULL argument or a depth outside 1..8; otherwise as mr_solve. */
 int mr_solve_anderson(mr_ctx* ctx, const double* delta, double* theta, int depth, mr_info* info);
@@ -217,8 +218,8 @@ int mr_adjoint_solve(mr_ctx* ctx, const double* delta, const double* theta_star,
                      const double* g, double* grad_delta, mr_info* info);
 
 /* mr_adjoint_solve with Anderson mixing of lambda between the transposed V-cycles, as
- * mr_solve_anderson does for theta (not in the paper; same solution). depth 1..8; the history
- * (2 (depth + 1) + 1 fields of n^3 doubles) is shared with mr_solve_anderson. Returns MR_EINVAL for
+ * mr_solve_anderson does for theta (not in the paper; same solution). depth 1..8; the history is
+ * the one of mr_solve_anderson (shared). Returns MR_EINVAL for
  * a NULL argument or a depth outside 1..8; otherwise as mr_adjoint_solve. */
 int mr_adjoint_solve_anderson(mr_ctx* ctx, const double* delta, const double* theta_star, const double* g,
                               double* grad_delta, int depth, mr_info* info);

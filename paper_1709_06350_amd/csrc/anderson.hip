@@ -31,8 +31,8 @@ struct AAPtrsF {
   const float* p[kAAMaxRing];
 };
 
-// f = y - x into f_out, y into y_out; partials[block][j] = sum over the block's cells of f * ring_j
-// (ring_j == f_out gives |f|^2).
+// f = y - x (rounded to FP32) into f_out, y into y_out; partials[block][j] = sum over the block's
+// cells of f * ring_j (ring_j == f_out gives |f|^2).
 // f_out is one of the ring entries, so it is not declared __restrict__; its own dot product uses
 // the value in registers.
 __global__ void __launch_bounds__(256) aa_record_kernel(const double* __restrict__ x, const double* __restrict__ y,
