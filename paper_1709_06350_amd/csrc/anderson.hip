@@ -22,7 +22,7 @@
 namespace mr {
 
 constexpr int kAAMaxRing = kAAMaxDepth + 1;
-constexpr int kAABlocks = 2048;
+constexpr int kAABlocks = 8192;
 
 struct AAPtrs {
   const double* p[kAAMaxRing];
