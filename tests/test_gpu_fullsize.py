@@ -122,3 +122,31 @@ def test_largest_mesh_1024_tiled_periodic_field():
     print(f"1024^3 tiled: fp64 cycles={i64.cycles} oracle_rel={r64:.3e}; mixed outer={im.cycles} oracle_rel={rm:.3e}; "
           f"adjoint cycles={ia.cycles} vs 256^3 adjoint rel L2 {gerr:.3e}")
     assert r64 <= 1e-10 and rm <= 1e-10 and gerr <= 1e-6
+
+
+@pytest.mark.timeout(900)
+def test_largest_mesh_1024_anderson():
+    """The accelerated FP64 solve on the largest mesh (the same tiled field): it converges and each
+    checked tile equals the first tile and the plain solve's tile."""
+    require_gpu()
+    import torch
+    torch.cuda.empty_cache()
+    n, t = 1024, 256
+    announce("largest mesh 1024^3: Anderson solve")
+    d256 = inputs.lognormal(t, 1.0, 2.0, 1010)
+    d = dev(np.tile(d256, (4, 4, 4)))
+    with mr.Context(n, tol=1e-10) as c:
+        th, ip = c.solve(d)
+        ref = host(th[:t, :t, :t])
+        del th
+        tha, ia = c.solve_anderson(d, depth=2)
+        assert ip.status == 0 and ia.status == 0 and ia.rel_residual <= 1e-10
+        tiles = [(0, 0, 0), (2, 1, 3)]
+        got = [host(tha[a * t:(a + 1) * t, b * t:(b + 1) * t, e * t:(e + 1) * t]) for a, b, e in tiles]
+        del tha
+    del d
+    torch.cuda.empty_cache()
+    scale = np.abs(ref).max()
+    np.testing.assert_allclose(got[1], got[0], rtol=0, atol=1e-12 * scale)
+    np.testing.assert_allclose(got[0], ref, rtol=0, atol=1e-8 * scale)
+    print(f"1024^3 Anderson: {ia.cycles} cycles (plain {ip.cycles})")
