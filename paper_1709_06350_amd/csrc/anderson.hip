@@ -58,6 +58,30 @@ __global__ void __launch_bounds__(256) aa_record_kernel(const double* __restrict
   }
 }
 
+// The same record for an iteration whose step is a known FP32 correction (the mixed-precision outer
+// iteration theta -> theta + e): f = e exactly and y = theta + e, so the update pass is not needed.
+__global__ void __launch_bounds__(256) aa_record_e_kernel(const double* __restrict__ theta, const float* __restrict__ e,
+                                                          float* f_out, double* __restrict__ y_out, AAPtrsF ring, int nr,
+                                                          size_t cells, double* __restrict__ partials) {
+  __shared__ double red[4][kAAMaxRing];
+  double acc[kAAMaxRing];
+#pragma unroll
+  for (int j = 0; j < kAAMaxRing; ++j) acc[j] = 0.0;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < cells; i += (size_t)gridDim.x * blockDim.x) {
+    const float f = e[i];
+    f_out[i] = f;
+    y_out[i] = theta[i] + (double)f;
+#pragma unroll
+    for (int j = 0; j < kAAMaxRing; ++j)
+      if (j < nr) acc[j] += (double)f * (double)(ring.p[j] == f_out ? f : ring.p[j][i]);
+  }
+  block_sum<kAAMaxRing>(acc, red, threadIdx.x, blockDim.x);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < kAAMaxRing; ++j) partials[(size_t)blockIdx.x * kAAMaxRing + j] = acc[j];
+  }
+}
+
 // out[j] = sum over blocks of partials[block][j], in block order (one block).
 __global__ void __launch_bounds__(256) aa_sum_kernel(const double* __restrict__ partials, int nblocks,
                                                      double* __restrict__ out) {
@@ -79,7 +103,8 @@ struct AACoef {
   double c[kAAMaxRing];
 };
 
-// out = out2 = sum_j c_j ring_j (the new iterate, and its copy kept as x for the next step).
+// out = out2 = sum_j c_j ring_j (the new iterate, and its copy kept as x for the next step; out2
+// may be null).
 __global__ void __launch_bounds__(256) aa_combine_kernel(AAPtrs ring, AACoef c, int nr, size_t cells,
                                                          double* __restrict__ out, double* __restrict__ out2) {
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < cells; e += (size_t)gridDim.x * blockDim.x) {
@@ -88,7 +113,7 @@ __global__ void __launch_bounds__(256) aa_combine_kernel(AAPtrs ring, AACoef c, 
     for (int j = 0; j < kAAMaxRing; ++j)
       if (j < nr) v += c.c[j] * ring.p[j][e];
     out[e] = v;
-    out2[e] = v;
+    if (out2) out2[e] = v;
   }
 }
 
@@ -153,7 +178,9 @@ static bool solve_small(std::vector<double> a, std::vector<double> b, int n, std
 // Called after a V-cycle took x (st.x_prev: the saved start of the first cycle, the previous
 // combination, or the previous cycle's result in the y ring) to y = the level-0 iterate. Records
 // the step, then overwrites the iterate with the Anderson combination (also kept as the next x).
-int Ctx::aa_step(AAState& st, double* iterate) {
+// With `correction` (the mixed outer iteration) the iterate is x itself, not yet updated, and the
+// step is y = x + correction: the record forms y, and the iterate receives the combination or y.
+int Ctx::aa_step(AAState& st, double* iterate, const float* correction) {
   const size_t cells = lv[0].cells;
   double* xsave = aa_mem;
   double* Y = aa_mem + cells;
@@ -167,8 +194,12 @@ int Ctx::aa_step(AAState& st, double* iterate) {
   AAPtrsF rp{};
   for (int j = 0; j < nr; ++j) rp.p[j] = F + cells * (size_t)st.order[j];
   const int nb = (int)std::min<size_t>((cells + 255) / 256, (size_t)kAABlocks);
-  hipLaunchKernelGGL(aa_record_kernel, dim3(nb), dim3(256), 0, stream, st.x_prev ? st.x_prev : xsave, iterate,
-                     F + cells * (size_t)slot, Y + cells * (size_t)slot, rp, nr, cells, part);
+  if (correction)
+    hipLaunchKernelGGL(aa_record_e_kernel, dim3(nb), dim3(256), 0, stream, iterate, correction,
+                       F + cells * (size_t)slot, Y + cells * (size_t)slot, rp, nr, cells, part);
+  else
+    hipLaunchKernelGGL(aa_record_kernel, dim3(nb), dim3(256), 0, stream, st.x_prev ? st.x_prev : xsave, iterate,
+                       F + cells * (size_t)slot, Y + cells * (size_t)slot, rp, nr, cells, part);
   hipLaunchKernelGGL(aa_sum_kernel, dim3(1), dim3(256), 0, stream, part, nb, dots);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "Anderson record");
@@ -207,13 +238,18 @@ int Ctx::aa_step(AAState& st, double* iterate) {
       st.order.erase(st.order.begin(), st.order.end() - 1);
     }
   }
-  if (!mixed) {  // x_{k+1} = y_k: already the iterate, and stored in the y ring
+  if (!mixed) {  // x_{k+1} = y_k: stored in the y ring (and already the iterate without a correction)
     st.x_prev = Y + cells * (size_t)slot;
+    if (correction) {
+      e = hipMemcpyAsync(iterate, Y + cells * (size_t)slot, cells * sizeof(double), hipMemcpyDeviceToDevice, stream);
+      if (e != hipSuccess) return hip_fail(e, "Anderson step");
+    }
     return MR_OK;
   }
   AAPtrs yp{};
   for (int j = 0; j < nr; ++j) yp.p[j] = Y + cells * (size_t)st.order[j];
-  hipLaunchKernelGGL(aa_combine_kernel, dim3(nb), dim3(256), 0, stream, yp, cf, nr, cells, iterate, xsave);
+  hipLaunchKernelGGL(aa_combine_kernel, dim3(nb), dim3(256), 0, stream, yp, cf, nr, cells, iterate,
+                     correction ? (double*)nullptr : xsave);
   st.x_prev = xsave;
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(e, "Anderson combine");

@@ -578,10 +578,13 @@ int Ctx::solve_mixed(const double* delta, double* theta, mr_info* info, int aa_d
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "inner shift");
     for (int k = 0; k < opts.inner_cycles; ++k)
       if ((rc = lin_vcycle(0)) != MR_OK) return rc;
-    if (aa_depth > 0 && aa.steps == 0 && (e = aa_save(*this, L0.th[0])) != hipSuccess) return hip_fail(e, "Anderson save");
-    if ((e = launch_update64(L0.th[0], M0.e[M0.cur], L0.cells, stream)) != hipSuccess) return hip_fail(e, "update");
-    // Anderson mixing of the outer iteration theta -> theta + e(theta), as for the FP64 cycle
-    if (aa_depth > 0 && (rc = aa_step(aa, L0.th[0])) != MR_OK) return rc;
+    if (aa_depth > 0) {
+      // Anderson mixing of the outer iteration theta -> theta + e(theta): the step forms theta + e
+      // itself and writes the mixed (or plain) new iterate
+      if ((rc = aa_step(aa, L0.th[0], M0.e[M0.cur])) != MR_OK) return rc;
+    } else if ((e = launch_update64(L0.th[0], M0.e[M0.cur], L0.cells, stream)) != hipSuccess) {
+      return hip_fail(e, "update");
+    }
     ++it;
   }
   if (status == MR_OK && rel > opts.tol) {

@@ -101,7 +101,7 @@ struct Ctx {
   int prepare(const double* delta_natural);
   int solve_fp64(const double* delta, double* theta, mr_info* info, int aa_depth = 0);
   int aa_reserve(int depth);
-  int aa_step(AAState& st, double* iterate);
+  int aa_step(AAState& st, double* iterate, const float* correction = nullptr);
   void aa_release();
   int solve_mixed(const double* delta, double* theta, mr_info* info, int aa_depth = 0);
   int deposit(const double* pos, long long np, double mass, int scheme, double* delta_out);
