@@ -404,6 +404,9 @@ def main():
         out["anderson"] = {"fp64": anderson_run(ctx, delta, theta, info64.cycles if info64 else None)}
         if run_mixed:
             out["anderson"]["mixed"] = anderson_run(ctxm, delta, theta_m, infom.cycles if infom else None)
+            if t64 > 0:
+                out["anderson"]["mixed_over_plain_fp64"] = round(
+                    out["anderson"]["mixed"]["seconds"] / (t64 / args.steps), 4)
     if not args.no_batched:
         out["batched"] = batched_run()
     if not args.no_cpu_baseline:
