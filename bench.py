@@ -63,7 +63,7 @@ def measured_traffic(schedule: str):
 SCHED_KERNEL = {0: "half_sweep_tiled", 1: "half_sweep_pipe", 2: "sweep_fused"}
 
 
-def cpu_baseline(delta_np, seconds_target=15.0):
+def cpu_baseline(delta_np, seconds_target=12.0):
     """The oracle's red-black sweep timed on host cores on a bounded 128^3 periodic sample."""
     import numpy as np
 
@@ -77,7 +77,7 @@ def cpu_baseline(delta_np, seconds_target=15.0):
     while True:
         th = omg.rb_sweep(th, d, None, 1.0)
         sweeps += 1
-        if time.perf_counter() - t0 > seconds_target or sweeps >= 8:
+        if time.perf_counter() - t0 > seconds_target or sweeps >= 32:
             break
     dt = time.perf_counter() - t0
     return {
