@@ -117,9 +117,10 @@ __device__ __forceinline__ int wave_max_i(int v) {
 }
 
 // lattice > 0: the catalogue holds lattice^3 particles in lattice order (k fastest) and lattice is a
-// multiple of 16; a wave then takes a patch of 16 (k) x 4 (j) particles of one plane i, whose
-// cloud-in-cell points overlap along two axes, instead of 64 consecutive particles of one row.
-// Either way every particle is taken exactly once.
+// multiple of 8; a wave then takes a block of 2 (i) x 4 (j) x 8 (k) particles of the lattice, whose
+// assignment points overlap along all three axes, instead of 64 consecutive particles of one row.
+// Either way every particle is taken exactly once. (A 4 x 4 x 4 cube needs fewer global adds but
+// timed slower, probably from more lanes meeting on the same LDS box entries.)
 template <int S, int CAP>
 __global__ void __launch_bounds__(256) deposit_scatter_binned_kernel(const double* __restrict__ pos, long long np, int n,
                                                                      unsigned long long* __restrict__ grid,
@@ -128,12 +129,12 @@ __global__ void __launch_bounds__(256) deposit_scatter_binned_kernel(const doubl
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   unsigned long long* box = boxes[w];
   const long long nwaves = (long long)gridDim.x * 4;
-  const long long kb_n = lattice / 16, jb_n = lattice / 4;
+  const long long kb_n = lattice / 8, jb_n = lattice / 4;
   for (long long seg = (long long)blockIdx.x * 4 + w; seg * 64 < np; seg += nwaves) {
     long long p = seg * 64 + lane;
     if (lattice > 0) {
-      const long long kb = seg % kb_n, jb = (seg / kb_n) % jb_n, i = seg / (kb_n * jb_n);
-      p = (i * lattice + jb * 4 + (lane >> 4)) * lattice + kb * 16 + (lane & 15);
+      const long long kb = seg % kb_n, jb = (seg / kb_n) % jb_n, ib = seg / (kb_n * jb_n);
+      p = ((ib * 2 + (lane >> 5)) * lattice + jb * 4 + ((lane >> 3) & 3)) * lattice + kb * 8 + (lane & 7);
     }
     bool valid = p < np;
     double x = 0.0, y = 0.0, z = 0.0;
@@ -268,11 +269,11 @@ int Ctx::deposit(const double* pos, long long np, double mass, int scheme, doubl
   // CIC and TSC bin each wave's contributions in LDS (boxes of up to 1024 / 2048 mesh points);
   // NGP has one contribution per particle and little to combine.
   const dim3 wg((unsigned)std::min<long long>((np + 255) / 256, 1 << 16));
-  // np = m^3 with m a multiple of 16: let each wave take a 16 x 4 patch of the particle lattice
+  // np = m^3 with m a multiple of 8: let each wave take a 2 x 4 x 8 block of the particle lattice
   long long m = (long long)std::llround(std::cbrt((double)np));
   while (m > 0 && m * m * m > np) --m;
   while ((m + 1) * (m + 1) * (m + 1) <= np) ++m;
-  const int lattice = (m * m * m == np && m % 16 == 0 && m <= (1 << 20)) ? (int)m : 0;
+  const int lattice = (m * m * m == np && m % 8 == 0 && m <= (1 << 20)) ? (int)m : 0;
   if (scheme == MR_DEPOSIT_NGP)
     hipLaunchKernelGGL(deposit_scatter_kernel<1>, pg, dim3(256), 0, stream, pos, np, n, cic_grid, bad_count);
   else if (scheme == MR_DEPOSIT_CIC)
