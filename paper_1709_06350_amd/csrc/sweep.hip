@@ -1446,7 +1446,7 @@ hipError_t launch_coarsest(const CoarsestArgs& a, hipStream_t s) {
 
 namespace mr {
 
-#define MR_FUSED_TILES(X) X(64, 8) X(32, 16) X(32, 8) X(16, 16) X(16, 8) X(8, 8) X(8, 4) X(4, 8)
+#define MR_FUSED_TILES(X) X(64, 16) X(64, 8) X(32, 16) X(32, 8) X(16, 16) X(16, 8) X(8, 8) X(8, 4) X(4, 8)
 
 static const void* fused_kernel(int tm, int tj) {
 #define MR_FZ_PTR(TM, TJ) \
@@ -1462,7 +1462,7 @@ static const void* fused_kernel(int tm, int tj) {
 // over its rounds and a chunk of ci planes takes ci + 3 plane steps. Ordered by that score.
 static std::vector<std::pair<double, FusedCfg>> fused_candidates(int n) {
   std::vector<std::pair<double, FusedCfg>> out;
-  static const int pref[][2] = {{64, 8}, {32, 16}, {32, 8}, {16, 16}, {16, 8}, {8, 8}, {8, 4}, {4, 8}};
+  static const int pref[][2] = {{64, 16}, {64, 8}, {32, 16}, {32, 8}, {16, 16}, {16, 8}, {8, 8}, {8, 4}, {4, 8}};
   const int nh = n / 2;
   int dev = 0, cus = 0;
   if (n < 8 || hipGetDevice(&dev) != hipSuccess ||

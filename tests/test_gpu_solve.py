@@ -158,3 +158,27 @@ def test_schedule_get_set_and_pinned_reproducibility():
                 c.set_schedule(bad_level, bad)
         with pytest.raises(mr.MRError):
             c.get_schedule(c.levels - 1)
+
+
+@pytest.mark.parametrize("nch", [1, 2])
+def test_fused_64x16_schedule_solves_the_same_equation(nch):
+    """The fused red-black launch on its largest tile (64 x 16 cells of a colour, 1024 threads):
+    a 128^3 solve pinned to it meets the oracle residual and agrees to rounding with the same
+    solve on a pipelined two-launch schedule."""
+    require_gpu()
+    n = 128
+    announce(f"fused 64x16 schedule n={n} chunks={nch}")
+    delta = inputs.lognormal(n, 0.8, 2.0, 78)
+    d = dev(delta)
+    out = {}
+    for name, sched in (("pipe", (mr.MR_SCHED_PIPELINED, 32, 8, 4)), ("fused", (mr.MR_SCHED_FUSED, 64, 16, nch))):
+        with mr.Context(n, tol=1e-11) as c:
+            c.set_schedule(0, sched)
+            assert c.get_schedule(0) == sched
+            th, info = c.solve(d)
+            assert info.status == 0
+            out[name] = host(th)
+    err = np.abs(out["fused"] - out["pipe"]).max() / np.abs(out["pipe"]).max()
+    assert err <= 1e-9, err
+    rel, _ = oop.relative_residual_slabs(out["fused"], delta)
+    assert rel <= 2e-11, rel
