@@ -102,6 +102,33 @@ def copy_calibration(nbytes: int, reps: int):
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}), flush=True)
 
 
+def stream_probe(nbytes: int = 1 << 30, reps: int = 5, configs=None):
+    """Achievable HBM bandwidth from the library's hand-written streaming kernels (mr_hbm_stream):
+    copy (16 B per element), read (8 B) and triad (24 B: the relaxation update's two reads and one
+    write), plain and non-temporal, several grid sizes; the median of `reps` launches each."""
+    import statistics
+
+    import torch
+
+    from paper_1709_06350_amd import mr
+
+    count = nbytes // 8
+    a = torch.ones(count, dtype=torch.float64, device="cuda")
+    b = torch.ones_like(a)
+    c = torch.empty_like(a)
+    per_elem = {mr.MR_STREAM_COPY: 16, mr.MR_STREAM_READ: 8, mr.MR_STREAM_TRIAD: 24}
+    names = {mr.MR_STREAM_COPY: "copy", mr.MR_STREAM_READ: "read", mr.MR_STREAM_TRIAD: "triad"}
+    configs = configs or [(k, nt, bpc) for k in per_elem for nt in (False, True) for bpc in (4, 8, 16)]
+    out = {}
+    for kind, nt, bpc in configs:
+        mr.hbm_stream(kind, a, c, b, nt, bpc)
+        ms = statistics.median(mr.hbm_stream(kind, a, c, b, nt, bpc) for _ in range(reps))
+        key = f"{names[kind]}{'_nt' if nt else ''}_{bpc}"
+        out[key] = round(per_elem[kind] * count / (ms * 1e-3) / 1e9, 1)
+    best = {names[k]: max(v for kk, v in out.items() if kk.startswith(names[k] + "_")) for k in per_elem}
+    return {"GBps": out, "best_GBps": best, "bytes_per_array": nbytes, "reps": reps}
+
+
 def _batched_anderson(mr, deltas, thetas, cells):
     """The same boxes with each box's outer iterations mixed (MR_FLAG_ANDERSON)."""
     import torch
@@ -271,6 +298,8 @@ def main():
                     help="only time the deposits and the Lagrangian mapping (256^3 mesh, 256^3 particles)")
     ap.add_argument("--schedule", default="", metavar="KIND,TM,TJ,NCHUNKS",
                     help="pin the finest-level FP64 relaxation schedule (mr_set_schedule) instead of the timed one")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="only measure the achievable HBM bandwidth with the library's streaming kernels")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a device copy of BYTES bytes (counter calibration)")
     args = ap.parse_args()
@@ -287,6 +316,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration, 3)
+        return
+    if args.stream_probe:
+        print(json.dumps({"hbm_stream": stream_probe()}), flush=True)
         return
     if args.particles_only:
         cic, lag = cic_run()

@@ -141,11 +141,20 @@ int mr_levels(const mr_ctx* ctx);
  * processes (bitwise-equal results): mr_get_schedule reads it, mr_set_schedule pins it (not a
  * passage of the paper). Host-only, no device work. Returns MR_EINVAL for a NULL argument, a level
  * out of range, or a schedule the library has no kernel for (set: the tile must be compiled and
- * divide the level's mesh, chunks must divide the planes into equal whole chunks of at least 4
- * planes (a multiple of 4 for MR_SCHED_PIPELINED) and the grid must fit the reduction buffers). */
+ * divide the level's mesh, chunks must hold at least 4 planes each (MR_SCHED_FUSED splits the
+ * planes into nearly equal chunks; the two-launch kinds need equal whole chunks, a multiple of 4
+ * planes for MR_SCHED_PIPELINED) and the grid must fit the reduction buffers). */
 enum { MR_SCHED_TILED = 0, MR_SCHED_PIPELINED = 1, MR_SCHED_FUSED = 2 };
 int mr_get_schedule(const mr_ctx* ctx, int level, int sched[4]);
 int mr_set_schedule(mr_ctx* ctx, int level, const int sched[4]);
+
+/* Lists the schedules mr_create's tuner times for one level (0 .. mr_levels - 2), in the format of
+ * mr_get_schedule, into sched[4 * i .. 4 * i + 3] for i < max_count, and returns how many there are
+ * (the count may exceed max_count; max_count = 0 with sched = NULL only counts). Any of them can be
+ * pinned with mr_set_schedule. For callers that check or profile every schedule the tuner may pick
+ * (not a passage of the paper). Host-only. Returns MR_EINVAL for a NULL context, a level out of range,
+ * max_count < 0, or sched = NULL with max_count > 0. */
+int mr_schedule_candidates(const mr_ctx* ctx, int level, int* sched, int max_count);
 
 /* Density assignment (the paper's footnote on density assignment, Sec. I, allows NGP, CIC or TSC).
  * pos: device, np x 3 doubles (x, y, z) in cell units, any finite real value (wrapped
@@ -257,9 +266,12 @@ int mr_tune_lin_tiles(int n, void* hip_stream, int* tm, int* tj, int* ci, float*
  * are updated from theta_in, then black cells from the red results and theta_in's black values:
  *     theta_c <- (sum of 6 face neighbours - h^2 (Sigma_c + f_c - cshift)) / 6.
  * f may be NULL (zero). theta_out must not alias theta_in. sum_out (host, may be NULL)
- * receives sum over all cells of (Sigma_c + f_c) as evaluated during the sweep. Runs the fused
- * red-black kernel, or the two per-colour launches (the pipelined kernel where the tile allows
- * it) when the context's opts.flags has MR_FLAG_TWO_PASS. With MR_FLAG_ORDER4 it runs the four
+ * receives sum over all cells of (Sigma_c + f_c) as evaluated during the sweep. When nl is the mesh
+ * size of a relaxed level of the context, the sweep runs that level's schedule (the one the solve
+ * uses, as read by mr_get_schedule and pinned by mr_set_schedule; with MR_FLAG_TWO_PASS the level's
+ * two-launch tile). Other sizes run the fused red-black kernel, or the two per-colour launches
+ * (the pipelined kernel where the default tile allows it) when the context's opts.flags has
+ * MR_FLAG_TWO_PASS. With MR_FLAG_ORDER4 it runs the four
  * class sub-sweeps instead (cells of class 0, then 1, 2, 3, each from the previous result) and
  * sum_out is the sum evaluated during the last sub-sweep. */
 int mr_sweep(mr_ctx* ctx, int nl, double h, const double* delta, const double* f, double cshift,
@@ -285,6 +297,39 @@ int mr_prolong_correct(mr_ctx* ctx, int nl, const double* theta_c, const double*
 /* 8-son average R from an nl^3 to an (nl/2)^3 mesh (Sec. II.A.3). */
 int mr_restrict(mr_ctx* ctx, int nl, const double* fine, double* coarse);
 
+/* ---- Building blocks of the FP32 inner solve of the mixed-precision form. ----
+ * The inner operator is the Jacobian of the mean-projected operator at a base potential theta_b
+ * (differentiating the physical root s of the cubic of Sec. II, Eqs. 8-10, with the discrete
+ * Hessian of Eqs. 11-14):
+ *     J_p e = nabla^2 e - dSigma(e) + <dSigma(e)>,   dSigma(e) = tr(W dMbar(e)),
+ *     W = (9 s Mbar - 27 Mbar^2) / (3 s^2 + p),
+ * Mbar, p and s those of theta_b (cell size h). It is evaluated in FP32: theta_b is rounded to
+ * FP32, and s is the largest real root computed (in FP64) from the FP32 theta_b and delta, as on
+ * the coarse levels of the inner solve. Arrays are natural-order doubles on the device. */
+
+/* Defect of the linear level equation J e = rhs - cshift (the uniform shift as in mr_sweep):
+ * r_out = rhs + dSigma(e) - nabla^2 e - cshift on the nl^3 mesh with cell size h (with
+ * cshift = <rhs + dSigma(e)> this is (rhs - <rhs>) - J_p e). rhs may be NULL (zero). r_out receives
+ * the FP32 result widened to FP64. Returns MR_EINVAL for a NULL argument, an unsupported nl or
+ * h <= 0. */
+int mr_lin_residual(mr_ctx* ctx, int nl, double h, const double* delta, const double* theta_base,
+                    const double* e, const double* rhs, double cshift, double* r_out);
+
+/* The inner solve's fused defect and restriction (the linear counterpart of mr_defect_restrict,
+ * Sec. II.A.3 Eq. 18 and R): rc_out = R(rhs + dSigma(e) - nabla^2 e - cshift) on the (nl/2)^3 mesh,
+ * computed by the kernel the inner V-cycle runs. rhs may be NULL. Returns MR_EINVAL for a NULL
+ * argument, nl not a multiple of 4 or h <= 0. */
+int mr_lin_defect_restrict(mr_ctx* ctx, int nl, double h, const double* delta, const double* theta_base,
+                           const double* e, const double* rhs, double cshift, double* rc_out);
+
+/* ncycles (1..64) inner linear V-cycles of the mixed-precision solve on the context's mesh, from
+ * e = 0, for J_p e = rhs at the base theta_base (the finest level's FP32 base and root come from
+ * the same FP64 residual pass as in mr_solve; coarse levels restrict the base and take their own
+ * root, as in the solve). e_out receives e (its mean is not fixed: J_p annihilates constants).
+ * The options' npre, npost and ncoarse apply. delta is validated as for mr_solve. */
+int mr_lin_vcycles(mr_ctx* ctx, const double* delta, const double* theta_base, const double* rhs,
+                   int ncycles, double* e_out);
+
 /* Kernel timing with HIP events on the context's stream, for benchmarking. mr_timing_enable
  * resets the counters and turns recording on (on != 0) or off. Recorded: every finest-mesh
  * relaxation sweep launch (FP64 sweep, and the FP32 sweep of the mixed-precision form).
@@ -299,6 +344,19 @@ typedef struct {
 
 int mr_timing_enable(mr_ctx* ctx, int on);
 int mr_timing_read(mr_ctx* ctx, mr_timing* out);
+
+/* HBM bandwidth probe (not part of the method): the ceiling that the memory-bound kernels are
+ * judged against, measured with hand-written streaming kernels on the current device.
+ * MR_STREAM_COPY: c[i] = a[i] (16 B per element); MR_STREAM_READ: per-block partial sums of a into
+ * c[0 .. blocks-1] (8 B per element); MR_STREAM_TRIAD: c[i] = a[i] + b[i] / 2 (24 B per element, the
+ * traffic of one FP64 relaxation update: two reads and one write). count doubles (even, >= 2) per
+ * array, device memory; nontemporal != 0 uses non-temporal loads and stores. The grid is
+ * blocks_per_cu (1..64) blocks of 256 threads per compute unit. ms_out (host, may be NULL) receives
+ * the launch's duration from HIP events on hip_stream (the call then synchronises the event).
+ * Returns MR_EINVAL for a bad argument (for MR_STREAM_READ, c must hold one value per block). */
+enum { MR_STREAM_COPY = 0, MR_STREAM_READ = 1, MR_STREAM_TRIAD = 2 };
+int mr_hbm_stream(int kind, int nontemporal, const double* a, const double* b, double* c, size_t count,
+                  int blocks_per_cu, void* hip_stream, float* ms_out);
 
 const char* mr_last_error(void);
 

@@ -661,8 +661,9 @@ int mr_set_schedule(mr_ctx* h, int level, const int sched[4]) {
   if (level < 0 || level >= c->nlev - 1) return fail(MR_EINVAL, "mr_set_schedule: level %d has no sweep schedule", level);
   Level& L = c->lv[level];
   const int n = L.n, nh = n / 2, kind = sched[0], tm = sched[1], tj = sched[2], nch = sched[3];
-  if (tm < 1 || tj < 1 || nh % tm != 0 || n % tj != 0 || nch < 1 || n % nch != 0 || n / nch < 4 ||
-      (long)(nh / tm) * (n / tj) * nch > kMaxReduceBlocks)
+  // the fused launch splits the planes into nch nearly equal chunks; the two-launch kernels need equal ones
+  if (tm < 1 || tj < 1 || nh % tm != 0 || n % tj != 0 || nch < 1 || (kind != MR_SCHED_FUSED && n % nch != 0) ||
+      n / nch < 4 || (long)(nh / tm) * (n / tj) * nch > kMaxReduceBlocks)
     return fail(MR_EINVAL, "mr_set_schedule: tile %d x %d, %d chunks do not fit the %d^3 level", tm, tj, nch, n);
   if (kind == MR_SCHED_FUSED) {
     if (!fused_tile_supported(tm, tj)) return fail(MR_EINVAL, "mr_set_schedule: no fused kernel for tile %d x %d", tm, tj);
@@ -686,13 +687,45 @@ int mr_set_schedule(mr_ctx* h, int level, const int sched[4]) {
       return fail(MR_EINVAL, "mr_set_schedule: no pipelined kernel for tile %d x %d, %d-plane chunks", tm, tj, t.ci);
     t.pipe = true;
   } else if (kind == MR_SCHED_TILED) {
-    if (!half_sweep_tile_supported(tm, tj, 1)) return fail(MR_EINVAL, "mr_set_schedule: no tiled kernel for tile %d x %d", tm, tj);
+    // the general kernel is compiled with 1, 2 or 4 cells per thread and plane depending on the tile
+    t.cpt = 0;
+    for (int cpt : {1, 2, 4})
+      if (t.cpt == 0 && half_sweep_tile_supported(tm, tj, cpt)) t.cpt = cpt;
+    if (t.cpt == 0) return fail(MR_EINVAL, "mr_set_schedule: no tiled kernel for tile %d x %d", tm, tj);
   } else {
     return fail(MR_EINVAL, "mr_set_schedule: unknown kind %d", kind);
   }
   L.sw = t;
   L.has_fz = false;
   return MR_OK;
+}
+
+int mr_schedule_candidates(const mr_ctx* h, int level, int* sched, int max_count) {
+  if (!h || (!sched && max_count > 0) || max_count < 0) return fail(MR_EINVAL, "mr_schedule_candidates: bad argument");
+  const Ctx* c = reinterpret_cast<const Ctx*>(h);
+  if (level < 0 || level >= c->nlev - 1)
+    return fail(MR_EINVAL, "mr_schedule_candidates: level %d has no sweep schedule", level);
+  const int n = c->lv[level].n;
+  const std::vector<SweepCand> all = sweep_candidates(n, sweep_tiles(n));
+  int k = 0;
+  for (const SweepCand& x : all) {
+    if (k < max_count) {
+      int* o = sched + 4 * k;
+      if (x.fused) {
+        o[0] = MR_SCHED_FUSED;
+        o[1] = x.fz.tm;
+        o[2] = x.fz.tj;
+        o[3] = x.fz.nchunks;
+      } else {
+        o[0] = x.two.pipe ? MR_SCHED_PIPELINED : MR_SCHED_TILED;
+        o[1] = x.two.tm;
+        o[2] = x.two.tj;
+        o[3] = n / x.two.ci;
+      }
+    }
+    ++k;
+  }
+  return k;
 }
 
 int mr_timing_enable(mr_ctx* h, int on) {
@@ -784,7 +817,23 @@ int mr_sweep(mr_ctx* h, int nl, double hcell, const double* delta, const double*
   if (e != hipSuccess) return hip_fail(e, "mr_sweep");
   FusedCfg fz;
   const bool order4 = (c->opts.flags & MR_FLAG_ORDER4) != 0;
+  const bool two_pass = (c->opts.flags & MR_FLAG_TWO_PASS) != 0;
+  // a mesh size that is a relaxed level of this context runs that level's schedule
+  const Level* lev = nullptr;
+  for (int l = 0; l + 1 < c->nlev; ++l)
+    if (c->lv[l].n == nl) lev = &c->lv[l];
   double* final_out = tout;
+  bool use_fused = false;
+  TileCfg two;
+  if (lev) {
+    use_fused = lev->has_fz && !two_pass;
+    fz = lev->fz;
+    two = lev->sw;
+  } else {
+    use_fused = !two_pass && (tuned_sweep(nl, &fz) || pick_fused(nl, fz));
+    two = sweep_tiles(nl);
+    two.pipe = two.cpt == 1 && two.ci % 4 == 0 && half_sweep_pipe_supported(two.tm, two.tj);
+  }
   if (order4) {
     // four class sub-sweeps, each two row-filtered tiled launches, ping-ponging tin and tout
     const TileCfg t = sweep_tiles(nl);
@@ -814,7 +863,7 @@ int mr_sweep(mr_ctx* h, int nl, double hcell, const double* delta, const double*
       if (e == hipSuccess) e = launch_half_sweep(a, t, c->stream);
     }
     final_out = bufs[0];   // four sub-sweeps: the last one wrote back into the first buffer
-  } else if (!(c->opts.flags & MR_FLAG_TWO_PASS) && (tuned_sweep(nl, &fz) || pick_fused(nl, fz))) {
+  } else if (use_fused) {
     FusedSweepArgs a{};
     a.th_in = tin;
     a.th_out = tout;
@@ -829,8 +878,7 @@ int mr_sweep(mr_ctx* h, int nl, double hcell, const double* delta, const double*
     a.counter = c->counter;
     if (e == hipSuccess) e = launch_sweep_fused(a, fz, c->stream);
   } else {
-    TileCfg t = sweep_tiles(nl);
-    t.pipe = t.cpt == 1 && t.ci % 4 == 0 && half_sweep_pipe_supported(t.tm, t.tj);
+    const TileCfg& t = two;
     HalfSweepArgs a{};
     a.th_in = tin;
     a.th_out = tout;
@@ -929,6 +977,103 @@ int mr_prolong_correct(mr_ctx* h, int nl, const double* theta_c, const double* t
   if (e == hipSuccess) e = launch_from_split(t, theta, nl, nullptr, 0.0, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   return e == hipSuccess ? MR_OK : hip_fail(e, "mr_prolong_correct");
+}
+
+// Inputs of the linear building blocks on an nl^3 mesh: delta, base potential, e and rhs (rhs NULL:
+// zero) converted to colour-split FP32 where the inner solve keeps them, and the base root at
+// cell size h from the FP32 base (as on the coarse levels of the inner solve).
+namespace {
+struct LinInputs {
+  double* ds = nullptr;
+  float *base = nullptr, *sb = nullptr, *e = nullptr, *rhs = nullptr;
+};
+}  // namespace
+
+static int lin_inputs(Ctx* c, Temps& tmp, int nl, double hcell, const double* delta, const double* theta_base,
+                      const double* e, const double* rhs, LinInputs& in) {
+  const size_t cells = (size_t)nl * nl * nl, fw = (cells + 1) / 2;   // doubles holding cells floats
+  double* t64 = tmp.get(cells);
+  in.ds = tmp.get(cells);
+  in.base = (float*)tmp.get(fw);
+  in.sb = (float*)tmp.get(fw);
+  in.e = (float*)tmp.get(fw);
+  in.rhs = (float*)tmp.get(fw);
+  if (!t64 || !in.ds || !in.base || !in.sb || !in.e || !in.rhs) return fail(MR_ENOMEM, "linear building block: temporaries");
+  hipError_t x = launch_to_split(delta, in.ds, nl, c->stream);
+  if (x == hipSuccess) x = launch_to_split(theta_base, t64, nl, c->stream);
+  if (x == hipSuccess) x = launch_cast32(t64, in.base, cells, c->stream);
+  if (x == hipSuccess) x = launch_to_split(e, t64, nl, c->stream);
+  if (x == hipSuccess) x = launch_cast32(t64, in.e, cells, c->stream);
+  if (x == hipSuccess && rhs) x = launch_to_split(rhs, t64, nl, c->stream);
+  if (x == hipSuccess && rhs) x = launch_cast32(t64, in.rhs, cells, c->stream);
+  if (x == hipSuccess && !rhs) x = launch_fill32(in.rhs, 0.0f, cells, c->stream);
+  if (x == hipSuccess) x = launch_base_root(in.base, in.ds, nl, hcell, in.sb, c->stream);
+  return x == hipSuccess ? MR_OK : hip_fail(x, "linear building block");
+}
+
+int mr_lin_residual(mr_ctx* h, int nl, double hcell, const double* delta, const double* theta_base, const double* e,
+                    const double* rhs, double cshift, double* r_out) {
+  if (!h || !delta || !theta_base || !e || !r_out) return fail(MR_EINVAL, "mr_lin_residual: null argument");
+  int rc = check_level(nl, false);
+  if (rc != MR_OK) return rc;
+  if (!(hcell > 0.0)) return fail(MR_EINVAL, "mr_lin_residual: cell size must be positive");
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  const size_t cells = (size_t)nl * nl * nl;
+  Temps tmp(c->stream);
+  LinInputs in;
+  if ((rc = lin_inputs(c, tmp, nl, hcell, delta, theta_base, e, rhs, in)) != MR_OK) return rc;
+  double* rs = tmp.get(cells);
+  if (!rs) return fail(MR_ENOMEM, "mr_lin_residual: temporaries");
+  hipError_t x = launch_lin_residual(in.e, in.base, in.sb, in.rhs, nl, hcell, cshift, rs, c->stream);
+  if (x == hipSuccess) x = launch_from_split(rs, r_out, nl, nullptr, 0.0, c->stream);
+  if (x == hipSuccess) x = hipStreamSynchronize(c->stream);
+  return x == hipSuccess ? MR_OK : hip_fail(x, "mr_lin_residual");
+}
+
+int mr_lin_defect_restrict(mr_ctx* h, int nl, double hcell, const double* delta, const double* theta_base,
+                           const double* e, const double* rhs, double cshift, double* rc_out) {
+  if (!h || !delta || !theta_base || !e || !rc_out) return fail(MR_EINVAL, "mr_lin_defect_restrict: null argument");
+  int rc = check_level(nl, true);
+  if (rc != MR_OK) return rc;
+  if (!(hcell > 0.0)) return fail(MR_EINVAL, "mr_lin_defect_restrict: cell size must be positive");
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  const size_t cc = (size_t)(nl / 2) * (nl / 2) * (nl / 2);
+  Temps tmp(c->stream);
+  LinInputs in;
+  if ((rc = lin_inputs(c, tmp, nl, hcell, delta, theta_base, e, rhs, in)) != MR_OK) return rc;
+  float* rc32 = (float*)tmp.get((cc + 1) / 2);
+  double* rcs = tmp.get(cc);
+  if (!rc32 || !rcs) return fail(MR_ENOMEM, "mr_lin_defect_restrict: temporaries");
+  hipError_t x = launch_lin_resid_restrict(in.e, in.base, in.sb, in.rhs, nl, hcell, ShiftRef{nullptr, 0.0, cshift}, rc32,
+                                           c->reducer(kSlotAux), c->stream);
+  if (x == hipSuccess) x = launch_widen64(rc32, rcs, cc, c->stream);
+  if (x == hipSuccess) x = launch_from_split(rcs, rc_out, nl / 2, nullptr, 0.0, c->stream);
+  if (x == hipSuccess) x = hipStreamSynchronize(c->stream);
+  return x == hipSuccess ? MR_OK : hip_fail(x, "mr_lin_defect_restrict");
+}
+
+int mr_lin_vcycles(mr_ctx* h, const double* delta, const double* theta_base, const double* rhs, int ncycles,
+                   double* e_out) {
+  if (!h || !delta || !theta_base || !rhs || !e_out) return fail(MR_EINVAL, "mr_lin_vcycles: null argument");
+  if (ncycles < 1 || ncycles > 64) return fail(MR_EINVAL, "mr_lin_vcycles: ncycles %d not in 1..64", ncycles);
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  int rc = c->mixed_ready();
+  if (rc != MR_OK) return rc;
+  if ((rc = c->prepare(delta)) != MR_OK) return rc;
+  const int n = c->n;
+  const size_t cells = c->lv[0].cells;
+  Temps tmp(c->stream);
+  double *ts = tmp.get(cells), *rs = tmp.get(cells);
+  if (!ts || !rs) return fail(MR_ENOMEM, "mr_lin_vcycles: temporaries");
+  hipError_t x = launch_to_split(theta_base, ts, n, c->stream);
+  if (x == hipSuccess) x = launch_to_split(rhs, rs, n, c->stream);
+  if (x != hipSuccess) return hip_fail(x, "mr_lin_vcycles");
+  float* e32 = nullptr;
+  if ((rc = c->lin_vcycles_split(ts, rs, ncycles, &e32)) != MR_OK) return rc;
+  x = launch_widen64(e32, ts, cells, c->stream);
+  if (x == hipSuccess) x = launch_from_split(ts, e_out, n, nullptr, 0.0, c->stream);
+  if (x == hipSuccess) x = hipStreamSynchronize(c->stream);
+  return x == hipSuccess ? MR_OK : hip_fail(x, "mr_lin_vcycles");
 }
 
 int mr_restrict(mr_ctx* h, int nl, const double* fine, double* coarse) {

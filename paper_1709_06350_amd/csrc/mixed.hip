@@ -171,6 +171,47 @@ __global__ void inner_shift_kernel(const double* __restrict__ res, double* __res
   }
 }
 
+// FP64 colour-split field -> FP32 copy (same layout).
+__global__ void __launch_bounds__(256) cast32_kernel(const double* __restrict__ src, float* __restrict__ dst, size_t cells) {
+  for (size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x; x < cells; x += (size_t)gridDim.x * blockDim.x)
+    dst[x] = (float)src[x];
+}
+
+// Defect of the linear level equation at every cell, in FP64 for the caller (the arithmetic is the
+// FP32 operator of the inner solve): r = rhs + dSigma(e) - nabla^2 e - cshift. Rows of the mesh
+// dealt to blocks; result[0] = sum r.
+__global__ void __launch_bounds__(256) lin_residual_kernel(const float* __restrict__ e, const float* __restrict__ base,
+    const float* __restrict__ sb, const float* __restrict__ rhs, int n, float ih2, float cshift,
+    double* __restrict__ r_out) {
+  for (int row = blockIdx.x; row < n * n; row += gridDim.x) {
+    const int i = row / n, j = row - i * n;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+      const unsigned g = split_idx(n, i, j, k);
+      Nb18f te, tb;
+      gather18_split_t(e, n, i, j, k, te);
+      gather18_split_t(base, n, i, j, k, tb);
+      float Se;
+      const float src = lin_source(tb, sb[g], ih2, te, Se) * ih2;
+      const float lap = (Se - 6.0f * e[g]) * ih2;
+      r_out[g] = (double)((rhs ? rhs[g] : 0.0f) + src - lap - cshift);
+    }
+  }
+}
+
+// FP32 colour-split field -> FP64 copy (same layout).
+__global__ void __launch_bounds__(256) widen64_kernel(const float* __restrict__ src, double* __restrict__ dst, size_t cells) {
+  for (size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x; x < cells; x += (size_t)gridDim.x * blockDim.x)
+    dst[x] = (double)src[x];
+}
+
+// Level-0 shift of the inner solve from a sum of the right-hand side: (sum rhs, 0).
+__global__ void set_shift_kernel(const double* __restrict__ sum, double* __restrict__ lsum0) {
+  if (threadIdx.x == 0) {
+    lsum0[0] = sum[0];
+    lsum0[1] = 0.0;
+  }
+}
+
 // ---- launchers ----------------------------------------------------------------------------
 
 static int lin_blocks(size_t cells) {
@@ -303,6 +344,23 @@ hipError_t launch_update64(double* theta, const float* e, size_t cells, hipStrea
 
 hipError_t launch_fill32(float* a, float v, size_t cells, hipStream_t s) {
   hipLaunchKernelGGL(fill32_kernel, dim3(lin_blocks(cells)), dim3(256), 0, s, a, v, cells);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast32(const double* src, float* dst, size_t cells, hipStream_t s) {
+  hipLaunchKernelGGL(cast32_kernel, dim3(lin_blocks(cells)), dim3(256), 0, s, src, dst, cells);
+  return hipGetLastError();
+}
+
+hipError_t launch_widen64(const float* src, double* dst, size_t cells, hipStream_t s) {
+  hipLaunchKernelGGL(widen64_kernel, dim3(lin_blocks(cells)), dim3(256), 0, s, src, dst, cells);
+  return hipGetLastError();
+}
+
+hipError_t launch_lin_residual(const float* e, const float* base, const float* sb, const float* rhs, int n, double h,
+                               double cshift, double* r_out, hipStream_t s) {
+  hipLaunchKernelGGL(lin_residual_kernel, dim3(rows_blocks(n)), dim3(row_threads(n)), 0, s, e, base, sb, rhs, n,
+                     (float)(1.0 / (h * h)), (float)cshift, r_out);
   return hipGetLastError();
 }
 
@@ -525,6 +583,59 @@ int Ctx::lin_vcycle(int l) {
   return MR_OK;
 }
 
+int Ctx::mixed_ready() { return mixed_alloc(this); }
+
+// Base potential and root of every coarse level of the inner linear multigrid from those of the
+// finest level: base = R base (8-son mean), root from the coarse base and R delta at the level's h.
+int Ctx::lin_base_hierarchy() {
+  for (int l = 1; l < nlev; ++l) {
+    hipError_t e = launch_restrict32(mixed->lv[l - 1].base, mixed->lv[l].base, lv[l - 1].n, stream);
+    if (e == hipSuccess) e = launch_base_root(mixed->lv[l].base, lv[l].delta, lv[l].n, lv[l].h, mixed->lv[l].sb, stream);
+    if (e != hipSuccess) return hip_fail(e, "linear base hierarchy");
+  }
+  return MR_OK;
+}
+
+// Inner solve of J_p e = rhs on level 0 from e = 0 with ncycles linear V-cycles; the level-0
+// shift (linsum(0)) must hold (sum rhs, 0). The result is in mixed->lv[0].e[cur].
+int Ctx::lin_solve(int ncycles) {
+  LinLevel& M0 = mixed->lv[0];
+  M0.cur = 0;
+  hipError_t e = launch_fill32(M0.e[0], 0.0f, lv[0].cells, stream);
+  if (e != hipSuccess) return hip_fail(e, "fill");
+  int rc;
+  for (int k = 0; k < ncycles; ++k)
+    if ((rc = lin_vcycle(0)) != MR_OK) return rc;
+  return MR_OK;
+}
+
+// Building block: k inner V-cycles on J_p(theta_base) e = rhs, all inputs colour-split on level 0
+// (delta already in lv[0].delta and the hierarchy prepared); the FP32 base, root and right-hand
+// side of level 0 come from the same residual pass as in the solve, the right-hand side then
+// replaced by the caller's.
+int Ctx::lin_vcycles_split(const double* theta_split, const double* rhs_split, int ncycles, float** e_out) {
+  int rc = mixed_alloc(this);
+  if (rc != MR_OK) return rc;
+  LinLevel& M0 = mixed->lv[0];
+  Level& L0 = lv[0];
+  const double N3 = (double)L0.cells;
+  if ((rc = write_scalar(kSlotRes, 0.0)) != MR_OK) return rc;
+  if ((rc = write_scalar(kSlotRes + 1, 0.0)) != MR_OK) return rc;
+  hipError_t e = launch_mixed_resid64(theta_split, L0.delta, L0.n, ShiftRef{scal + kSlotRes, 1.0 / N3, 0.0}, M0.rhs,
+                                      M0.base, M0.sb, reducer(kSlotRes), stream);
+  if (e == hipSuccess) e = launch_cast32(rhs_split, M0.rhs, L0.cells, stream);
+  if (e == hipSuccess) e = launch_sum(rhs_split, L0.cells, reducer(kSlotAux), stream);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(set_shift_kernel, dim3(1), dim3(64), 0, stream, (const double*)(scal + kSlotAux), linsum(0));
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return hip_fail(e, "linear building block");
+  if ((rc = lin_base_hierarchy()) != MR_OK) return rc;
+  if ((rc = lin_solve(ncycles)) != MR_OK) return rc;
+  *e_out = M0.e[M0.cur];
+  return MR_OK;
+}
+
 int Ctx::solve_mixed(const double* delta, double* theta, mr_info* info, int aa_depth) {
   auto t0 = std::chrono::steady_clock::now();
   int rc = mixed_alloc(this);
@@ -565,19 +676,11 @@ int Ctx::solve_mixed(const double* delta, double* theta, mr_info* info, int aa_d
     }
     if (rel < best) best = rel;
     if (rel <= opts.tol || it >= opts.max_cycles) break;
-    // base hierarchy for the linear operator
-    for (int l = 1; l < nlev; ++l) {
-      e = launch_restrict32(mixed->lv[l - 1].base, mixed->lv[l].base, lv[l - 1].n, stream);
-      if (e == hipSuccess) e = launch_base_root(mixed->lv[l].base, lv[l].delta, lv[l].n, lv[l].h, mixed->lv[l].sb, stream);
-      if (e != hipSuccess) return hip_fail(e, "linear base hierarchy");
-    }
+    if ((rc = lin_base_hierarchy()) != MR_OK) return rc;
     // inner solve from e = 0; the shift starts at <rhs> = -<b>
-    M0.cur = 0;
-    if ((e = launch_fill32(M0.e[0], 0.0f, L0.cells, stream)) != hipSuccess) return hip_fail(e, "fill");
     hipLaunchKernelGGL(inner_shift_kernel, dim3(1), dim3(64), 0, stream, (const double*)(scal + kSlotRes), linsum(0));
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "inner shift");
-    for (int k = 0; k < opts.inner_cycles; ++k)
-      if ((rc = lin_vcycle(0)) != MR_OK) return rc;
+    if ((rc = lin_solve(opts.inner_cycles)) != MR_OK) return rc;
     if (aa_depth > 0) {
       // Anderson mixing of the outer iteration theta -> theta + e(theta): the step forms theta + e
       // itself and writes the mixed (or plain) new iterate

@@ -114,6 +114,10 @@ struct Ctx {
   double* linsum(int l);
   int lin_sweep(int l);
   int lin_vcycle(int l);
+  int mixed_ready();
+  int lin_base_hierarchy();
+  int lin_solve(int ncycles);
+  int lin_vcycles_split(const double* theta_split, const double* rhs_split, int ncycles, float** e_out);
   void release_extra();
   void release_adjoint();
 };

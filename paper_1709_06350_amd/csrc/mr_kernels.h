@@ -202,6 +202,15 @@ bool fused_tile_supported(int tm, int tj);
 int tune_defect(const DefectArgs& a, hipStream_t s);
 int tune_sweep(int n, double* th_a, double* th_b, double* delta, double* partials, unsigned* counter, double* sums,
                TileCfg* two, hipStream_t s, bool* use_fused, FusedCfg* cfg);
+// One schedule of the FP64 relaxation of a level: two launches per sweep (tile `two`, general or
+// pipelined kernel) or the fused red-black launch (tile fz).
+struct SweepCand {
+  bool fused;
+  TileCfg two;
+  FusedCfg fz;
+};
+// The schedules tune_sweep times for an n^3 level (two: the default two-launch tile).
+std::vector<SweepCand> sweep_candidates(int n, const TileCfg& two);
 // The cached tuning result for n on the current device (false: not tuned or two launches won).
 bool tuned_sweep(int n, FusedCfg* cfg);
 hipError_t launch_sweep_fused(const FusedSweepArgs& a, const FusedCfg& cfg, hipStream_t s);
@@ -232,6 +241,10 @@ hipError_t launch_from_split(const double* split, double* natural, int n, const 
 hipError_t launch_validate(const double* delta, size_t cells, Reduce red, hipStream_t s);
 // result[0] = sum of a (size cells).
 hipError_t launch_sum(const double* a, size_t cells, Reduce red, hipStream_t s);
+hipError_t launch_cast32(const double* src, float* dst, size_t cells, hipStream_t s);
+hipError_t launch_widen64(const float* src, double* dst, size_t cells, hipStream_t s);
+hipError_t launch_lin_residual(const float* e, const float* base, const float* sb, const float* rhs, int n, double h,
+                               double cshift, double* r_out, hipStream_t s);
 
 // ---- mixed precision (FP32 linearised multigrid) ----
 bool lin_tile_supported(int tm, int tj);

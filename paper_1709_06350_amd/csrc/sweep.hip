@@ -1564,6 +1564,33 @@ bool tuned_sweep(int n, FusedCfg* cfg) {
   return true;
 }
 
+// Every schedule the sweep tuner times for an n^3 level: two launches per sweep with the general
+// kernel on the default tile `two`, two launches with the pipelined kernel on every compiled tile that
+// fits with chunks of 16 to 256 planes, and the fused launch on the candidates of fused_candidates.
+std::vector<SweepCand> sweep_candidates(int n, const TileCfg& two) {
+  std::vector<SweepCand> all{SweepCand{false, two, FusedCfg{}}};
+  auto add_pipe = [&](int tm, int tj) {
+    if ((n / 2) % tm != 0 || n % tj != 0 || tj > n) return;
+    for (int ci = 16; ci <= 256 && ci <= n; ci *= 2) {
+      TileCfg tp;
+      tp.tm = tm;
+      tp.tj = tj;
+      tp.cpt = 1;
+      tp.ci = ci;
+      tp.tiles_j = n / tj;
+      tp.tiles_m = (n / 2) / tm;
+      tp.pipe = true;
+      const long blocks = (long)tp.tiles_j * tp.tiles_m * (n / ci);
+      if (n % ci == 0 && blocks <= kMaxReduceBlocks) all.push_back(SweepCand{false, tp, FusedCfg{}});
+    }
+  };
+#define MR_HP_ADD(TM, TJ) add_pipe(TM, TJ);
+  MR_HP_TILES(MR_HP_ADD)
+#undef MR_HP_ADD
+  for (const auto& c : fused_candidates(n)) all.push_back(SweepCand{true, two, c.second});
+  return all;
+}
+
 int tune_sweep(int n, double* th_a, double* th_b, double* delta, double* partials, unsigned* counter, double* sums,
                TileCfg* two, hipStream_t s, bool* use_fused, FusedCfg* cfg) {
   int dev = 0;
@@ -1579,43 +1606,14 @@ int tune_sweep(int n, double* th_a, double* th_b, double* delta, double* partial
       return MR_OK;
     }
   }
-  const auto cand = fused_candidates(n);
   const size_t cells = (size_t)n * n * n;
   hipLaunchKernelGGL(tune_fill_kernel, dim3(1024), dim3(256), 0, s, th_a, delta, n);
   hipError_t e = hipGetLastError();
   const int reps = cells >= ((size_t)1 << 24) ? 2 : 4;
   FusedCfg best_cfg;
   bool best_fused = false;
-  // two launches per sweep: the general kernel, and the pipelined one on every compiled tile that
-  // fits, with chunks of 16 to 256 planes
-  std::vector<TileCfg> twos{*two};
-  auto add_pipe = [&](int tm, int tj) {
-    if ((n / 2) % tm != 0 || n % tj != 0 || tj > n) return;
-    for (int ci = 16; ci <= 256 && ci <= n; ci *= 2) {
-      TileCfg tp;
-      tp.tm = tm;
-      tp.tj = tj;
-      tp.cpt = 1;
-      tp.ci = ci;
-      tp.tiles_j = n / tj;
-      tp.tiles_m = (n / 2) / tm;
-      tp.pipe = true;
-      const long blocks = (long)tp.tiles_j * tp.tiles_m * (n / ci);
-      if (n % ci == 0 && blocks <= kMaxReduceBlocks) twos.push_back(tp);
-    }
-  };
-#define MR_HP_ADD(TM, TJ) add_pipe(TM, TJ);
-  MR_HP_TILES(MR_HP_ADD)
-#undef MR_HP_ADD
-  // every candidate: two launches per sweep (general or pipelined tile) or the fused launch
-  struct Cand {
-    bool fused;
-    TileCfg two;
-    FusedCfg fz;
-  };
-  std::vector<Cand> all;
-  for (const TileCfg& tw : twos) all.push_back(Cand{false, tw, FusedCfg{}});
-  for (const auto& c : cand) all.push_back(Cand{true, *two, c.second});
+  const std::vector<SweepCand> all = sweep_candidates(n, *two);
+  using Cand = SweepCand;
   auto run = [&](const Cand& c) -> hipError_t {
     if (c.fused) {
       FusedSweepArgs a{};

@@ -34,6 +34,9 @@ PREC_MIXED = 1
 MR_SCHED_TILED = 0
 MR_SCHED_PIPELINED = 1
 MR_SCHED_FUSED = 2
+MR_STREAM_COPY = 0
+MR_STREAM_READ = 1
+MR_STREAM_TRIAD = 2
 MR_DEPOSIT_NGP = 0
 MR_DEPOSIT_CIC = 1
 MR_DEPOSIT_TSC = 2
@@ -41,11 +44,12 @@ DEPOSIT_SCHEMES = {"ngp": MR_DEPOSIT_NGP, "cic": MR_DEPOSIT_CIC, "tsc": MR_DEPOS
 
 EXPORTED = [
     "mr_default_opts", "mr_create", "mr_destroy", "mr_set_opts", "mr_size", "mr_levels",
-    "mr_get_schedule", "mr_set_schedule",
+    "mr_get_schedule", "mr_set_schedule", "mr_schedule_candidates",
     "mr_deposit", "mr_deposit_cic", "mr_lagrangian", "mr_residual", "mr_solve", "mr_solve_anderson", "mr_adjoint_solve", "mr_adjoint_solve_anderson", "mr_solve_batched",
     "mr_tune_lin_tiles",
     "mr_sweep", "mr_defect_restrict", "mr_tau_rhs", "mr_prolong_correct", "mr_restrict",
-    "mr_timing_enable", "mr_timing_read", "mr_last_error",
+    "mr_lin_residual", "mr_lin_defect_restrict", "mr_lin_vcycles",
+    "mr_timing_enable", "mr_timing_read", "mr_hbm_stream", "mr_last_error",
 ]
 
 
@@ -116,6 +120,7 @@ def load(path: Optional[str] = None):
     lib.mr_lagrangian.argtypes = [vp, vp, vp, ctypes.c_int64, vp, vp]
     lib.mr_get_schedule.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int)]
     lib.mr_set_schedule.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int)]
+    lib.mr_schedule_candidates.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int), ip]
     lib.mr_deposit_cic.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, vp]
     lib.mr_deposit.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_double, ctypes.c_int, vp]
     lib.mr_residual.argtypes = [vp, vp, vp, vp, dp, dp]
@@ -133,8 +138,12 @@ def load(path: Optional[str] = None):
     lib.mr_tau_rhs.argtypes = [vp, ip, ctypes.c_double, vp, vp, vp, vp, dp]
     lib.mr_prolong_correct.argtypes = [vp, ip, vp, vp, vp]
     lib.mr_restrict.argtypes = [vp, ip, vp, vp]
+    lib.mr_lin_residual.argtypes = [vp, ip, ctypes.c_double, vp, vp, vp, vp, ctypes.c_double, vp]
+    lib.mr_lin_defect_restrict.argtypes = [vp, ip, ctypes.c_double, vp, vp, vp, vp, ctypes.c_double, vp]
+    lib.mr_lin_vcycles.argtypes = [vp, vp, vp, vp, ip, vp]
     lib.mr_timing_enable.argtypes = [vp, ip]
     lib.mr_timing_read.argtypes = [vp, ctypes.POINTER(mr_timing)]
+    lib.mr_hbm_stream.argtypes = [ip, ip, vp, vp, vp, ctypes.c_size_t, ip, vp, ctypes.POINTER(ctypes.c_float)]
     lib.mr_last_error.argtypes = []
     lib.mr_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -242,6 +251,14 @@ class Context:
         """Pin a level's FP64 relaxation schedule (mr_set_schedule); sched = (kind, tm, tj, nchunks)."""
         a = (ctypes.c_int * 4)(*sched)
         _check(self.lib.mr_set_schedule(self.h, level, a))
+
+    def schedule_candidates(self, level: int = 0):
+        """Every schedule the tuner times for a level (mr_schedule_candidates), as (kind, tm, tj, nchunks)."""
+        count = self.lib.mr_schedule_candidates(self.h, level, None, 0)
+        _check(min(count, 0))
+        a = (ctypes.c_int * (4 * max(count, 1)))()
+        _check(min(self.lib.mr_schedule_candidates(self.h, level, a, count), 0))
+        return [tuple(a[4 * i:4 * i + 4]) for i in range(count)]
 
     def _empty(self, n=None):
         n = self.n if n is None else n
@@ -364,6 +381,34 @@ class Context:
                                            _ptr(tc), _ptr(dr)))
         return tc, dr
 
+    def lin_residual(self, delta, theta_base, e, h=1.0, rhs=None, cshift=0.0):
+        """mr_lin_residual: rhs + dSigma(e) - lap(e) - cshift of the FP32 inner operator at theta_base."""
+        nl = e.shape[0]
+        for t, what in ((delta, "delta"), (theta_base, "theta_base"), (e, "e"), (rhs, "rhs")):
+            _need(t, nl ** 3, what)
+        out = self._empty(nl)
+        _check(self.lib.mr_lin_residual(self.h, nl, h, _ptr(delta), _ptr(theta_base), _ptr(e), _ptr(rhs),
+                                        cshift, _ptr(out)))
+        return out
+
+    def lin_defect_restrict(self, delta, theta_base, e, h=1.0, rhs=None, cshift=0.0):
+        """mr_lin_defect_restrict: R(rhs + dSigma(e) - lap(e) - cshift) on the (nl/2)^3 mesh."""
+        nl = e.shape[0]
+        for t, what in ((delta, "delta"), (theta_base, "theta_base"), (e, "e"), (rhs, "rhs")):
+            _need(t, nl ** 3, what)
+        out = self._empty(nl // 2)
+        _check(self.lib.mr_lin_defect_restrict(self.h, nl, h, _ptr(delta), _ptr(theta_base), _ptr(e), _ptr(rhs),
+                                               cshift, _ptr(out)))
+        return out
+
+    def lin_vcycles(self, delta, theta_base, rhs, ncycles=1):
+        """mr_lin_vcycles: ncycles inner FP32 V-cycles for J_p(theta_base) e = rhs from e = 0."""
+        for t, what in ((delta, "delta"), (theta_base, "theta_base"), (rhs, "rhs")):
+            _need(t, self.n ** 3, what)
+        out = self._empty()
+        _check(self.lib.mr_lin_vcycles(self.h, _ptr(delta), _ptr(theta_base), _ptr(rhs), ncycles, _ptr(out)))
+        return out
+
     def tau_rhs(self, delta, theta_hat, rd, h):
         nl = theta_hat.shape[0]
         for t, what in ((delta, "delta"), (theta_hat, "theta_hat"), (rd, "rd")):
@@ -427,3 +472,13 @@ def tune_lin_tiles(n: int):
     ms = ctypes.c_float()
     _check(lib.mr_tune_lin_tiles(n, _stream(), ctypes.byref(tm), ctypes.byref(tj), ctypes.byref(ci), ctypes.byref(ms)))
     return tm.value, tj.value, ci.value, ms.value
+
+
+def hbm_stream(kind: int, a: torch.Tensor, c: torch.Tensor, b: Optional[torch.Tensor] = None,
+               nontemporal: bool = False, blocks_per_cu: int = 8) -> float:
+    """One launch of the HBM streaming probe (mr_hbm_stream); returns its duration in ms."""
+    lib = load()
+    ms = ctypes.c_float()
+    _check(lib.mr_hbm_stream(kind, int(nontemporal), _ptr(a), _ptr(b), _ptr(c), a.numel(), blocks_per_cu,
+                             _stream(), ctypes.byref(ms)))
+    return ms.value

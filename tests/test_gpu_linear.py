@@ -1,0 +1,131 @@
+"""The FP32 inner operator of the mixed-precision form against the oracle's linearisation.
+
+The inner solve of the mixed form works on J_p, the Jacobian of the mean-projected operator at a
+base potential (differentiating the physical root of the cubic, Sec. II, Eqs. 8-10, through the
+discrete Hessian of Eqs. 11-14). Its arithmetic is FP32, so the element-wise tolerance is FP32's:
+2e-5 of the largest value (the base potential is rounded to FP32 and the Jacobian weights are
+rebuilt from its second differences; inputs are of order one).
+
+* mr_lin_residual: rhs + dSigma(e) - lap(e) - C on meshes of several tiles, h = 1, 2, 4, and on the
+  coarse meshes of a hierarchy against the oracle's J_p at (R theta, R delta, 2h).
+* mr_lin_defect_restrict: the V-cycle's own defect + restriction kernel, the same quantity restricted.
+* mr_lin_vcycles: repeated inner V-cycles on J_p e = r at 32^3 (sigma_g = 1, the strongly non-linear
+  case) approach e* of the oracle's bordered sparse solve monotonically, down to the FP32 floor.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import inputs
+from gpu_util import announce, dev, host, require_gpu
+from oracle import linearized as olin
+from oracle import multigrid as omg
+from oracle import operator as oop
+
+pytestmark = pytest.mark.gpu
+
+from paper_1709_06350_amd import mr  # noqa: E402
+
+TOL32 = 2e-5
+
+
+def _state(n, seed):
+    delta = inputs.lognormal(n, 0.8, 2.0, seed)
+    theta = inputs.grf(n, 1.5, seed + 1)
+    theta *= 0.3 / theta.std()
+    e = inputs.grf(n, 1.0, seed + 2)
+    e /= e.std()
+    rhs = 0.1 * np.random.default_rng(seed).standard_normal((n, n, n))
+    return delta, theta, e, rhs
+
+
+def _dsigma(theta, delta, e, h):
+    W, _, _ = olin.linearisation(theta, delta, h)
+    return np.einsum("...ij,...ji->...", W, oop.traceless(oop.hessian(e, h)))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    require_gpu()
+    with mr.Context(32) as c:
+        yield c
+
+
+@pytest.mark.parametrize("n,h", [(16, 1.0), (32, 1.0), (48, 1.0), (64, 1.0), (32, 2.0), (16, 4.0)])
+def test_lin_residual_matches_oracle_jacobian(ctx, n, h):
+    announce(f"lin_residual n={n} h={h}")
+    delta, theta, e, rhs = _state(n, 500 + n)
+    dS = _dsigma(theta, delta, e, h)
+    # with cshift = <dSigma(e)> and no rhs the building block returns -J_p e
+    got = host(ctx.lin_residual(dev(delta), dev(theta), dev(e), h=h, cshift=float(dS.mean())))
+    ref = -olin.jacobian_apply(theta, delta, e, h)
+    err = np.max(np.abs(got - ref))
+    assert err <= TOL32 * np.abs(ref).max(), f"max abs diff {err:.3e} (scale {np.abs(ref).max():.3e})"
+    # with a right-hand side and an arbitrary shift
+    C = 0.037
+    got = host(ctx.lin_residual(dev(delta), dev(theta), dev(e), h=h, rhs=dev(rhs), cshift=C))
+    ref = rhs + dS - oop.laplacian(e, h) - C
+    err = np.max(np.abs(got - ref))
+    assert err <= TOL32 * np.abs(ref).max(), f"max abs diff {err:.3e}"
+
+
+def test_lin_residual_on_coarse_levels(ctx):
+    """Coarse levels of the inner solve take R theta and R delta with their own root at 2h, 4h."""
+    n = 64
+    delta, theta, _, _ = _state(n, 601)
+    th, de, h = theta, delta, 1.0
+    for level in range(1, 3):
+        th, de, h = omg.restrict(th), omg.restrict(de), 2.0 * h
+        nl = th.shape[0]
+        announce(f"lin_residual coarse level {level} n={nl} h={h}")
+        e = np.random.default_rng(level).standard_normal((nl,) * 3)
+        dS = _dsigma(th, de, e, h)
+        got = host(ctx.lin_residual(dev(de), dev(th), dev(e), h=h, cshift=float(dS.mean())))
+        ref = -olin.jacobian_apply(th, de, e, h)
+        err = np.max(np.abs(got - ref))
+        assert err <= TOL32 * np.abs(ref).max(), f"level {level}: max abs diff {err:.3e}"
+
+
+@pytest.mark.parametrize("n,h", [(16, 1.0), (64, 1.0), (128, 1.0), (32, 2.0)])
+def test_lin_defect_restrict_matches_oracle(ctx, n, h):
+    announce(f"lin_defect_restrict n={n} h={h}")
+    delta, theta, e, rhs = _state(n, 700 + n)
+    dS = _dsigma(theta, delta, e, h)
+    C = float(dS.mean() + rhs.mean())
+    got = host(ctx.lin_defect_restrict(dev(delta), dev(theta), dev(e), h=h, rhs=dev(rhs), cshift=C))
+    ref = omg.restrict(rhs - rhs.mean() - olin.jacobian_apply(theta, delta, e, h))
+    err = np.max(np.abs(got - ref))
+    assert err <= TOL32 * np.abs(ref).max(), f"max abs diff {err:.3e} (scale {np.abs(ref).max():.3e})"
+
+
+def _bordered_solve(theta, delta, b):
+    """e* with <e*> = 0 and J_p e* = b - <b>: J e = (b - <b>) + mu 1 for unknown mu (J_p e = J e - <J e>)."""
+    n = theta.shape[0]
+    J = olin.sparse_jacobian(olin.stencil(theta, delta, 1.0), n)
+    ones = sp.csr_matrix(np.ones((n ** 3, 1)))
+    A = sp.bmat([[J, -ones], [ones.T, None]], format="csc")
+    sol = spla.spsolve(A, np.concatenate([(b - b.mean()).ravel(), [0.0]]))
+    return sol[:-1].reshape(theta.shape)
+
+
+def test_inner_vcycles_contract_to_the_oracle_solution():
+    require_gpu()
+    n = 32
+    delta = inputs.lognormal(n, 1.0, 2.0, 1002)
+    # the base of an outer step: two FAS cycles from theta = 0, right-hand side -F(theta)
+    theta, _ = omg.solve(delta, tol=0.0, max_cycles=2)
+    b = -oop.projected_operator(theta, delta, 1.0)
+    estar = _bordered_solve(theta, delta, b)
+    assert np.abs(olin.jacobian_apply(theta, delta, estar) - b).max() <= 1e-9 * np.abs(b).max()
+    errs = []
+    with mr.Context(n, precision=mr.PREC_MIXED) as c:
+        for k in range(1, 9):
+            e = host(c.lin_vcycles(dev(delta), dev(theta), dev(b), ncycles=k))
+            e -= e.mean()
+            errs.append(float(np.linalg.norm(e - estar) / np.linalg.norm(estar)))
+    announce("inner V-cycle errors " + " ".join(f"{x:.2e}" for x in errs))
+    assert errs[0] < 0.5
+    for a, z in zip(errs, errs[1:]):
+        assert z < a or a < 1e-4, f"not contracting: {errs}"
+    assert errs[-1] < 1e-4, errs

@@ -132,3 +132,27 @@ def test_slab_residual_matches_full():
     full = op.relative_residual(theta, delta)
     slab, m = op.relative_residual_slabs(theta, delta, slab=5)
     assert slab == pytest.approx(full, rel=1e-12)
+
+
+@pytest.mark.parametrize("case", ["separable", "plane_wave", "manufactured"])
+def test_literal_operator_vanishes_on_exact_solutions(case):
+    """The paper's literal L^h = lap theta - Sigma (Sec. II.A.1, Eq. 15, no mean projection) is zero
+    at every closed-form solution: there <Sigma> = 0, so it equals the projected operator."""
+    make = {"separable": cf.separable_case, "plane_wave": cf.plane_wave_case,
+            "manufactured": cf.manufactured_case}[case]
+    delta, exact = make(16)
+    L = op.operator_L(exact, delta, 1.0)
+    assert np.abs(L).max() <= 1e-12 * max(1.0, np.abs(delta).max())
+
+
+def test_literal_operator_differs_from_projected_by_the_uniform_shift():
+    """On a generic field the literal operator at the projected solution is the constant -<Sigma>
+    (reading: the literal periodic system has no exact solution), and its rms floors at |<Sigma>|."""
+    delta = inputs.lognormal(16, 0.5, 2.0, 21)
+    theta, info = mg.solve(delta, tol=1e-12)
+    L = op.operator_L(theta, delta, 1.0)
+    m = info["m_shift"]
+    assert abs(m) > 1e-6
+    np.testing.assert_allclose(L, -m, atol=1e-10)
+    # pinned independently of the solve: sum of lap vanishes on a periodic mesh, so <L> = -<Sigma>
+    assert abs(L.mean() + op.source(theta, delta, 1.0).mean()) < 1e-13
