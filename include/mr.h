@@ -197,6 +197,19 @@ int mr_lagrangian(mr_ctx* ctx, const double* theta, const double* pos, int64_t n
 int mr_residual(mr_ctx* ctx, const double* delta, const double* theta, double* r_out,
                 double* rel_out, double* msum_out);
 
+/* mr_residual without a context and without device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc). n: 4..1024;
+ * delta, theta: device n^3 natural order; r_out (device n^3, may be NULL), rel_out and msum_out (host,
+ * may be NULL) as for mr_residual. Work is enqueued on hip_stream (a hipStream_t, NULL = default
+ * stream) and the call synchronises it before returning the host scalars. The only device memory
+ * used beyond the arguments is a fixed array of about 66 KB that the library holds on every device
+ * it runs on until the process ends (per-block partial sums, an arrival counter and the totals);
+ * it is shared by every call on a device, so calls that overlap on one device race. Nothing is
+ * allocated. Returns MR_EINVAL for a NULL delta or theta or n outside 4..1024, MR_EHIP on a HIP
+ * error. */
+int mr_residual_noalloc(int n, const double* delta, const double* theta, double* r_out,
+                        double* rel_out, double* msum_out, void* hip_stream);
+
 /* FP64 or mixed-precision solve (per opts.precision) for theta given delta (Sec. II.A).
  * theta: device n^3, input guess iff opts.warm_start, output the solution with <theta> = 0.
  * delta is validated (finite, 1 + delta > 0). info: host, may be NULL. */

@@ -49,7 +49,7 @@ EXPORTED = [
     "mr_tune_lin_tiles",
     "mr_sweep", "mr_defect_restrict", "mr_tau_rhs", "mr_prolong_correct", "mr_restrict",
     "mr_lin_residual", "mr_lin_defect_restrict", "mr_lin_vcycles",
-    "mr_timing_enable", "mr_timing_read", "mr_hbm_stream", "mr_last_error",
+    "mr_timing_enable", "mr_timing_read", "mr_hbm_stream", "mr_residual_noalloc", "mr_last_error",
 ]
 
 
@@ -144,6 +144,7 @@ def load(path: Optional[str] = None):
     lib.mr_timing_enable.argtypes = [vp, ip]
     lib.mr_timing_read.argtypes = [vp, ctypes.POINTER(mr_timing)]
     lib.mr_hbm_stream.argtypes = [ip, ip, vp, vp, vp, ctypes.c_size_t, ip, vp, ctypes.POINTER(ctypes.c_float)]
+    lib.mr_residual_noalloc.argtypes = [ip, vp, vp, vp, dp, dp, vp]
     lib.mr_last_error.argtypes = []
     lib.mr_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
@@ -482,3 +483,14 @@ def hbm_stream(kind: int, a: torch.Tensor, c: torch.Tensor, b: Optional[torch.Te
     _check(lib.mr_hbm_stream(kind, int(nontemporal), _ptr(a), _ptr(b), _ptr(c), a.numel(), blocks_per_cu,
                              _stream(), ctypes.byref(ms)))
     return ms.value
+
+
+def residual_noalloc(delta: torch.Tensor, theta: torch.Tensor, r_out: Optional[torch.Tensor] = None):
+    """mr_residual_noalloc: (r_out or None, rel, <Sigma>) without a context or device allocation."""
+    n = round(delta.numel() ** (1.0 / 3.0))
+    for t, what in ((delta, "delta"), (theta, "theta"), (r_out, "r_out")):
+        _need(t, n ** 3, what)
+    rel, ms = ctypes.c_double(), ctypes.c_double()
+    _check(load().mr_residual_noalloc(n, _ptr(delta), _ptr(theta), _ptr(r_out), ctypes.byref(rel), ctypes.byref(ms),
+                                      _stream()))
+    return r_out, rel.value, ms.value
