@@ -335,6 +335,18 @@ int mr_lin_residual(mr_ctx* ctx, int nl, double h, const double* delta, const do
 int mr_lin_defect_restrict(mr_ctx* ctx, int nl, double h, const double* delta, const double* theta_base,
                            const double* e, const double* rhs, double cshift, double* rc_out);
 
+/* One red-black sweep of the inner solve's smoother on the nl^3 mesh (cell size h): red cells
+ * ((i + j + k) even) from e_in, then black cells from the new red values, each by
+ *     e_c <- (sum of 6 face neighbours of e - h^2 (dSigma_c(e) + rhs_c - cshift)) / 6
+ * (the linear level equation nabla^2 e - dSigma(e) = rhs - cshift solved at the cell; dSigma does not
+ * depend on e_c). rhs may be NULL (zero). sched: (kind, tm, tj, nchunks) as for mr_set_schedule --
+ * MR_SCHED_FUSED runs the one-launch kernel of both colours, MR_SCHED_PIPELINED / MR_SCHED_TILED the
+ * two one-colour launches -- or NULL for a default two-launch schedule. e_out receives the FP32
+ * result widened to FP64 (e_out must not alias e_in). Returns MR_EINVAL for a NULL argument, nl not a
+ * multiple of 4, h <= 0, or a schedule the library has no kernel for. */
+int mr_lin_sweep(mr_ctx* ctx, int nl, double h, const double* delta, const double* theta_base,
+                 const double* e_in, const double* rhs, double cshift, const int* sched, double* e_out);
+
 /* ncycles (1..64) inner linear V-cycles of the mixed-precision solve on the context's mesh, from
  * e = 0, for J_p e = rhs at the base theta_base (the finest level's FP32 base and root come from
  * the same FP64 residual pass as in mr_solve; coarse levels restrict the base and take their own

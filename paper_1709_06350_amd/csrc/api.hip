@@ -985,7 +985,9 @@ int mr_prolong_correct(mr_ctx* h, int nl, const double* theta_c, const double* t
 namespace {
 struct LinInputs {
   double* ds = nullptr;
-  float *base = nullptr, *sb = nullptr, *e = nullptr, *rhs = nullptr;
+  int* base = nullptr;
+  const double* bq = nullptr;
+  float *sb = nullptr, *e = nullptr, *rhs = nullptr;
 };
 }  // namespace
 
@@ -994,20 +996,24 @@ static int lin_inputs(Ctx* c, Temps& tmp, int nl, double hcell, const double* de
   const size_t cells = (size_t)nl * nl * nl, fw = (cells + 1) / 2;   // doubles holding cells floats
   double* t64 = tmp.get(cells);
   in.ds = tmp.get(cells);
-  in.base = (float*)tmp.get(fw);
+  in.base = (int*)tmp.get(fw);
+  in.bq = c->scal + kSlotBase;
   in.sb = (float*)tmp.get(fw);
   in.e = (float*)tmp.get(fw);
   in.rhs = (float*)tmp.get(fw);
   if (!t64 || !in.ds || !in.base || !in.sb || !in.e || !in.rhs) return fail(MR_ENOMEM, "linear building block: temporaries");
   hipError_t x = launch_to_split(delta, in.ds, nl, c->stream);
   if (x == hipSuccess) x = launch_to_split(theta_base, t64, nl, c->stream);
-  if (x == hipSuccess) x = launch_cast32(t64, in.base, cells, c->stream);
+  // fixed-point base with the scale of max |theta_base| (the solve's representation)
+  if (x == hipSuccess) x = launch_absmax(t64, cells, c->scal + kSlotTmax, c->stream);
+  if (x == hipSuccess) x = launch_base_scale(c->scal + kSlotTmax, c->scal + kSlotBase, c->stream);
+  if (x == hipSuccess) x = launch_quantise(t64, in.base, cells, in.bq, c->stream);
   if (x == hipSuccess) x = launch_to_split(e, t64, nl, c->stream);
   if (x == hipSuccess) x = launch_cast32(t64, in.e, cells, c->stream);
   if (x == hipSuccess && rhs) x = launch_to_split(rhs, t64, nl, c->stream);
   if (x == hipSuccess && rhs) x = launch_cast32(t64, in.rhs, cells, c->stream);
   if (x == hipSuccess && !rhs) x = launch_fill32(in.rhs, 0.0f, cells, c->stream);
-  if (x == hipSuccess) x = launch_base_root(in.base, in.ds, nl, hcell, in.sb, c->stream);
+  if (x == hipSuccess) x = launch_base_root(in.base, in.bq, in.ds, nl, hcell, in.sb, c->stream);
   return x == hipSuccess ? MR_OK : hip_fail(x, "linear building block");
 }
 
@@ -1024,7 +1030,7 @@ int mr_lin_residual(mr_ctx* h, int nl, double hcell, const double* delta, const 
   if ((rc = lin_inputs(c, tmp, nl, hcell, delta, theta_base, e, rhs, in)) != MR_OK) return rc;
   double* rs = tmp.get(cells);
   if (!rs) return fail(MR_ENOMEM, "mr_lin_residual: temporaries");
-  hipError_t x = launch_lin_residual(in.e, in.base, in.sb, in.rhs, nl, hcell, cshift, rs, c->stream);
+  hipError_t x = launch_lin_residual(in.e, in.base, in.bq, in.sb, in.rhs, nl, hcell, cshift, rs, c->stream);
   if (x == hipSuccess) x = launch_from_split(rs, r_out, nl, nullptr, 0.0, c->stream);
   if (x == hipSuccess) x = hipStreamSynchronize(c->stream);
   return x == hipSuccess ? MR_OK : hip_fail(x, "mr_lin_residual");
@@ -1044,12 +1050,102 @@ int mr_lin_defect_restrict(mr_ctx* h, int nl, double hcell, const double* delta,
   float* rc32 = (float*)tmp.get((cc + 1) / 2);
   double* rcs = tmp.get(cc);
   if (!rc32 || !rcs) return fail(MR_ENOMEM, "mr_lin_defect_restrict: temporaries");
-  hipError_t x = launch_lin_resid_restrict(in.e, in.base, in.sb, in.rhs, nl, hcell, ShiftRef{nullptr, 0.0, cshift}, rc32,
+  hipError_t x = launch_lin_resid_restrict(in.e, in.base, in.bq, in.sb, in.rhs, nl, hcell, ShiftRef{nullptr, 0.0, cshift}, rc32,
                                            c->reducer(kSlotAux), c->stream);
   if (x == hipSuccess) x = launch_widen64(rc32, rcs, cc, c->stream);
   if (x == hipSuccess) x = launch_from_split(rcs, rc_out, nl / 2, nullptr, 0.0, c->stream);
   if (x == hipSuccess) x = hipStreamSynchronize(c->stream);
   return x == hipSuccess ? MR_OK : hip_fail(x, "mr_lin_defect_restrict");
+}
+
+int mr_lin_sweep(mr_ctx* h, int nl, double hcell, const double* delta, const double* theta_base, const double* e_in,
+                 const double* rhs, double cshift, const int* sched, double* e_out) {
+  if (!h || !delta || !theta_base || !e_in || !e_out || e_in == e_out) return fail(MR_EINVAL, "mr_lin_sweep: bad pointers");
+  int rc = check_level(nl, true);
+  if (rc != MR_OK) return rc;
+  if (!(hcell > 0.0)) return fail(MR_EINVAL, "mr_lin_sweep: cell size must be positive");
+  const int nh = nl / 2;
+  int kind = MR_SCHED_PIPELINED, tm = 0, tj = 0, nch = 0;
+  if (sched) {
+    kind = sched[0];
+    tm = sched[1];
+    tj = sched[2];
+    nch = sched[3];
+  } else {
+    static const int pref[][2] = {{64, 4}, {64, 8}, {32, 8}, {16, 16}, {8, 16}, {4, 8}, {2, 4}};
+    for (const auto& p : pref)
+      if (tm == 0 && nh % p[0] == 0 && nl % p[1] == 0) {
+        tm = p[0];
+        tj = p[1];
+      }
+    nch = nl % 8 == 0 ? nl / 8 : 1;
+    kind = (nl / nch) % 4 == 0 ? MR_SCHED_PIPELINED : MR_SCHED_TILED;
+  }
+  if (tm < 1 || tj < 1 || nh % tm != 0 || nl % tj != 0 || nch < 1 || nl % nch != 0 ||
+      (long)(nh / tm) * (nl / tj) * nch > kMaxReduceBlocks)
+    return fail(MR_EINVAL, "mr_lin_sweep: tile %d x %d, %d chunks do not fit the %d^3 mesh", tm, tj, nch, nl);
+  if (kind == MR_SCHED_FUSED ? !lin_fused_supported(tm, tj) || nl / nch < 2
+                             : !lin_tile_supported(tm, tj) || (kind == MR_SCHED_PIPELINED && (nl / nch) % 4 != 0) ||
+                                   (kind != MR_SCHED_PIPELINED && kind != MR_SCHED_TILED))
+    return fail(MR_EINVAL, "mr_lin_sweep: no kernel for schedule %d (%d x %d, %d chunks)", kind, tm, tj, nch);
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  const size_t cells = (size_t)nl * nl * nl;
+  Temps tmp(c->stream);
+  LinInputs in;
+  if ((rc = lin_inputs(c, tmp, nl, hcell, delta, theta_base, e_in, rhs, in)) != MR_OK) return rc;
+  float* eo = (float*)tmp.get((cells + 1) / 2);
+  double* es = tmp.get(cells);
+  if (!eo || !es) return fail(MR_ENOMEM, "mr_lin_sweep: temporaries");
+  hipError_t x = hipSuccess;
+  if (kind == MR_SCHED_FUSED) {
+    LinFusedArgs a{};
+    a.e_in = in.e;
+    a.e_out = eo;
+    a.base = in.base;
+    a.bq = in.bq;
+    a.sb = in.sb;
+    a.rhs = in.rhs;
+    a.n = nl;
+    a.h2 = (float)(hcell * hcell);
+    a.ih2 = (float)(1.0 / (hcell * hcell));
+    a.c_add = cshift;
+    a.sum_out = c->scal + kSlotAux;
+    a.partials = c->partials;
+    a.counter = c->counter;
+    x = launch_lin_fused(a, LinFusedCfg{tm, tj, nch}, c->stream);
+  } else {
+    TileCfg t;
+    t.tm = tm;
+    t.tj = tj;
+    t.ci = nl / nch;
+    t.tiles_j = nl / tj;
+    t.tiles_m = nh / tm;
+    t.pipe = kind == MR_SCHED_PIPELINED;
+    LinSweepArgs a{};
+    a.e_in = in.e;
+    a.e_out = eo;
+    a.base = in.base;
+    a.bq = in.bq;
+    a.sb = in.sb;
+    a.rhs = in.rhs;
+    a.n = nl;
+    a.colour = 0;
+    a.h2 = (float)(hcell * hcell);
+    a.ih2 = (float)(1.0 / (hcell * hcell));
+    a.c_add = cshift;
+    a.sum_out = c->scal + kSlotAux;
+    a.partials = c->partials;
+    a.counter = c->counter;
+    x = launch_lin_half_sweep(a, t, c->stream);
+    a.colour = 1;
+    a.e_red_new = eo;
+    a.sum_out = c->scal + kSlotAux + 1;
+    if (x == hipSuccess) x = launch_lin_half_sweep(a, t, c->stream);
+  }
+  if (x == hipSuccess) x = launch_widen64(eo, es, cells, c->stream);
+  if (x == hipSuccess) x = launch_from_split(es, e_out, nl, nullptr, 0.0, c->stream);
+  if (x == hipSuccess) x = hipStreamSynchronize(c->stream);
+  return x == hipSuccess ? MR_OK : hip_fail(x, "mr_lin_sweep");
 }
 
 int mr_lin_vcycles(mr_ctx* h, const double* delta, const double* theta_base, const double* rhs, int ncycles,

@@ -31,7 +31,7 @@ constexpr int kBoxPartials = 4096;   // partial-sum slots per box (x kMaxNV valu
 struct BLevel {
   float* e[2];
   float* rhs;
-  float* base;
+  int* base;        // fixed-point base potential (scale: the box's res[5], res[6])
   float* sb;
   const double* delta;
   double* lsum;     // 3 doubles: inner running sums of this level
@@ -68,7 +68,8 @@ struct BBox {
   float* aaF;       // ... and their corrections
   double* aaPart;   // ... per-block partial dot products (256 x kBAARing)
   BAAState* aa;
-  double* res;      // 4 doubles: (sum Sigma, 0, sum b, sum b^2) of the last outer residual
+  double* res;      // 8 doubles: (sum Sigma, 0, sum b, sum b^2) of the last outer residual; [4] max |theta|
+                    // (bits; zero between uses), [5] 2^-s and [6] 2^s of the fixed-point base scale
   double* partials;
   unsigned int* counter;
   BStat* st;
@@ -106,7 +107,8 @@ __global__ void __launch_bounds__(256) b_resid64_kernel(const BBox* boxes, const
   const BBox& x = boxes[b];
   const double N3 = (double)n * n * n;
   const bool last = mixed_resid64_body(x.theta, x.lv[0].delta, n, ShiftRef{x.res, 1.0 / N3, 0.0}, x.lv[0].rhs,
-                                       x.lv[0].base, x.lv[0].sb, Reduce{x.partials, x.counter, x.res}, t, bpb);
+                                       x.lv[0].base, x.res + 5, x.lv[0].sb, Reduce{x.partials, x.counter, x.res}, t,
+                                       bpb);
   if (last && threadIdx.x == 0) box_check(x, N3);
 }
 
@@ -119,8 +121,8 @@ __global__ void __launch_bounds__(TM * TJ) b_resid64_tiled_kernel(const BBox* bo
   if (!box_of(boxes, cls, bpb, b, t)) return;
   const BBox& x = boxes[b];
   const double N3 = (double)n * n * n;
-  ResidTiledArgs a{x.theta, x.lv[0].delta, n, ShiftRef{x.res, 1.0 / N3, 0.0}, x.lv[0].rhs, x.lv[0].base, x.lv[0].sb,
-                   Reduce{x.partials, x.counter, x.res}, tiles_j, tiles_m, nchunks};
+  ResidTiledArgs a{x.theta, x.lv[0].delta, n, ShiftRef{x.res, 1.0 / N3, 0.0}, x.lv[0].rhs, x.lv[0].base, x.res + 5,
+                   x.lv[0].sb, Reduce{x.partials, x.counter, x.res}, tiles_j, tiles_m, nchunks};
   const bool last = mixed_resid64_tiled_body<TM, TJ>(a, t, t, bpb, lds);
   if (last && threadIdx.x == 0) box_check(x, N3);
 }
@@ -129,14 +131,14 @@ __global__ void __launch_bounds__(512) b_base_kernel(const BBox* boxes, const in
   int b, t;
   if (!box_of(boxes, cls, bpb, b, t)) return;
   const BBox& x = boxes[b];
-  restrict32_body(x.lv[l].base, x.lv[l + 1].base, nf, t, bpb);
+  restrictq_body(x.lv[l].base, x.lv[l + 1].base, nf, t, bpb);
 }
 
 __global__ void __launch_bounds__(512) b_root_kernel(const BBox* boxes, const int* cls, int bpb, int l, int n, double ih2) {
   int b, t;
   if (!box_of(boxes, cls, bpb, b, t)) return;
   const BBox& x = boxes[b];
-  base_root_body(x.lv[l].base, x.lv[l].delta, n, ih2, x.lv[l].sb, t, bpb);
+  base_root_body(x.lv[l].base, x.res + 5, x.lv[l].delta, n, ih2, x.lv[l].sb, t, bpb);
 }
 
 __global__ void __launch_bounds__(256) b_fill_kernel(const BBox* boxes, const int* cls, int bpb, int l, int which,
@@ -144,6 +146,15 @@ __global__ void __launch_bounds__(256) b_fill_kernel(const BBox* boxes, const in
   int b, t;
   if (!box_of(boxes, cls, bpb, b, t)) return;
   fill32_body(boxes[b].lv[l].e[which], 0.0f, cells, t, bpb);
+}
+
+// Fixed-point base scale of every active box of a size class from its max |theta| (one thread per box).
+__global__ void b_scale_kernel(const BBox* boxes, const int* cls, int nb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const BBox& x = boxes[cls[i]];
+  if (!x.st->active) return;
+  base_scale_body(x.res + 4, x.res + 5);
 }
 
 __global__ void b_inner_shift_kernel(const BBox* boxes, const int* cls, int nb) {
@@ -169,6 +180,7 @@ __global__ void __launch_bounds__(TM * TJ) b_lin_sweep_kernel(const BBox* boxes,
   a.e_red_new = COL ? L.e[cur ^ 1] : nullptr;
   a.e_out = L.e[cur ^ 1];
   a.base = L.base;
+  a.bq = x.res + 5;
   a.sb = L.sb;
   a.rhs = L.rhs;
   a.n = n;
@@ -194,8 +206,9 @@ __global__ void __launch_bounds__(256) b_resid_restrict_kernel(const BBox* boxes
   if (!box_of(boxes, cls, bpb, b, t)) return;
   const BBox& x = boxes[b];
   const BLevel& L = x.lv[l];
-  lin_resid_restrict_body(L.e[cur], L.base, L.sb, L.rhs, n, ih2, ShiftRef{L.lsum, 1.0 / ((double)n * n * n), 0.0},
-                          x.lv[l + 1].rhs, Reduce{x.partials, x.counter, x.lv[l + 1].lsum}, t, bpb);
+  lin_resid_restrict_body(L.e[cur], L.base, x.res + 5, L.sb, L.rhs, n, ih2,
+                          ShiftRef{L.lsum, 1.0 / ((double)n * n * n), 0.0}, x.lv[l + 1].rhs,
+                          Reduce{x.partials, x.counter, x.lv[l + 1].lsum}, t, bpb);
 }
 
 template <int TM, int TJ>
@@ -206,8 +219,8 @@ __global__ void __launch_bounds__(TM * TJ / 2) b_resid_restrict_tiled_kernel(con
   if (!box_of(boxes, cls, bpb, b, t)) return;
   const BBox& x = boxes[b];
   const BLevel& L = x.lv[l];
-  LinRRArgs a{L.e[cur], L.base, L.sb, L.rhs, n, ih2, ShiftRef{L.lsum, 1.0 / ((double)n * n * n), 0.0}, x.lv[l + 1].rhs,
-              Reduce{x.partials, x.counter, x.lv[l + 1].lsum}, tiles_j, tiles_m, nchunks};
+  LinRRArgs a{L.e[cur], L.base, x.res + 5, L.sb, L.rhs, n, ih2, ShiftRef{L.lsum, 1.0 / ((double)n * n * n), 0.0},
+              x.lv[l + 1].rhs, Reduce{x.partials, x.counter, x.lv[l + 1].lsum}, tiles_j, tiles_m, nchunks};
   lin_resid_restrict_tiled_body<TM, TJ>(a, t, t, bpb, lds);
 }
 
@@ -235,14 +248,14 @@ __global__ void __launch_bounds__(256) b_coarsest_kernel(const BBox* boxes, cons
   const BBox& x = boxes[cls[blockIdx.x]];
   if (!x.st->active) return;
   const BLevel& L = x.lv[l];
-  lin_coarsest_body(L.e[cur], L.base, L.sb, L.rhs, n, nsweeps, h2, ih2, L.lsum, 1.0 / ((double)n * n * n),
+  lin_coarsest_body(L.e[cur], L.base, x.res + 5, L.sb, L.rhs, n, nsweeps, h2, ih2, L.lsum, 1.0 / ((double)n * n * n),
                     *reinterpret_cast<LinCoarsestShared*>(smem));
 }
 
 __global__ void __launch_bounds__(256) b_update_kernel(const BBox* boxes, const int* cls, int bpb, int cur0, size_t cells) {
   int b, t;
   if (!box_of(boxes, cls, bpb, b, t)) return;
-  update64_body(boxes[b].theta, boxes[b].lv[0].e[cur0], cells, t, bpb);
+  update64_body(boxes[b].theta, boxes[b].lv[0].e[cur0], cells, t, bpb, boxes[b].res + 4);
 }
 
 // Slots of the history entries after recording update number `steps` (0-based), oldest first.
@@ -332,6 +345,7 @@ __global__ void __launch_bounds__(256) b_aa_solve_kernel(const BBox* boxes, cons
     st.c[j] = 0.0;
   }
   if (mix) {
+    *(x.res + 4) = 0.0;   // the combination replaces theta: its maximum is taken again by the combine
     st.c[m] = 1.0;
     for (int i = 0; i < m; ++i) {
       st.c[i + 1] -= gam[i];
@@ -352,13 +366,16 @@ __global__ void __launch_bounds__(256) b_aa_combine_kernel(const BBox* boxes, co
   const BBox& x = boxes[b];
   const BAAState& st = *x.aa;
   if (!st.mix) return;
+  double mx = 0.0;
   for (size_t i = t * (size_t)blockDim.x + threadIdx.x; i < cells; i += (size_t)bpb * blockDim.x) {
     double v = 0.0;
 #pragma unroll
     for (int j = 0; j < kBAARing; ++j)
       if (j < st.nr) v += st.c[j] * x.aaY[(size_t)st.order[j] * cells + i];
     x.theta[i] = v;
+    mx = fmax(mx, fabs(v));
   }
+  block_absmax_to(mx, x.res + 4);
 }
 
 // ---- FP32 sweep tile tuner ----------------------------------------------------------------
@@ -448,7 +465,8 @@ int tune_lin_tiles(int n, hipStream_t s, TileCfg* out, float* ms_out) {
   bool ok = true;
   for (int k = 0; k < nb && ok; ++k) {
     float *e0 = (float*)get(cells * 4), *e1 = (float*)get(cells * 4), *rhs = (float*)get(cells * 4),
-          *base = (float*)get(cells * 4), *sb = (float*)get(cells * 4);
+          *sb = (float*)get(cells * 4);
+    int* base = (int*)get(cells * 4);
     double* aux = (double*)get(64 * 8);
     double* part = (double*)get((size_t)kBoxPartials * kMaxNV * 8);
     unsigned* cnt = (unsigned*)get(64 * 4);
@@ -462,6 +480,7 @@ int tune_lin_tiles(int n, hipStream_t s, TileCfg* out, float* ms_out) {
     hb[k].lv[0].base = base;
     hb[k].lv[0].sb = sb;
     hb[k].lv[0].lsum = aux;
+    hb[k].res = aux + 16;   // zero: base scale 0 (flat base)
     hb[k].partials = part;
     hb[k].counter = cnt;
     hb[k].st = dst;
@@ -482,7 +501,7 @@ int tune_lin_tiles(int n, hipStream_t s, TileCfg* out, float* ms_out) {
     std::vector<int> idx(nb);
     for (int k = 0; k < nb && e == hipSuccess; ++k) {
       const BLevel& L = hb[k].lv[0];
-      for (float* f : {L.e[0], L.e[1], L.rhs, L.base})
+      for (void* f : {(void*)L.e[0], (void*)L.e[1], (void*)L.rhs, (void*)L.base})
         if (e == hipSuccess) e = hipMemsetAsync(f, 0, cells * 4, s);
       if (e == hipSuccess) e = launch_fill32(L.sb, 3.0f, cells, s);
       if (e == hipSuccess) e = hipMemsetAsync(L.lsum, 0, 64 * 8, s);
@@ -608,9 +627,10 @@ static int record_iteration(std::vector<SizeClass>& cls, BBox* dboxes, const mr_
   int maxlev = 0;
   for (auto& c : cls) maxlev = std::max(maxlev, c.nlev);
   std::vector<std::vector<int>> cur(cls.size(), std::vector<int>(kMaxLevels, 0));
-  // 1. FP64 residual of every box (also the base state of level 0)
+  // 1. FP64 residual of every box (also the base state of level 0, fixed-point with the scale of max |theta|)
   for (auto& c : cls) {
     const int nb = (int)c.boxes.size();
+    hipLaunchKernelGGL(b_scale_kernel, dim3((nb + 63) / 64), dim3(64), 0, s, dboxes, c.d_boxes, nb);
     if (c.resid.ok) {
       const BTile& t = c.resid;
       const int bpb = t.bpb();
@@ -807,7 +827,7 @@ int solve_batched(int nbox, const int* n, const double* const* delta, double* co
       L.e[0] = mem.get<float>(cells);
       L.e[1] = mem.get<float>(cells);
       L.rhs = mem.get<float>(cells);
-      L.base = mem.get<float>(cells);
+      L.base = mem.get<int>(cells);
       L.sb = mem.get<float>(cells);
       double* d = mem.get<double>(cells);
       L.delta = d;

@@ -39,39 +39,55 @@ __global__ void __launch_bounds__(TM * TJ) lin_half_sweep_tiled(LinSweepArgs a) 
 }
 
 __global__ void __launch_bounds__(256) mixed_resid64_kernel(const double* __restrict__ theta,
-    const double* __restrict__ delta, int n, ShiftRef cref, float* __restrict__ rhs32, float* __restrict__ base32,
-    float* __restrict__ sb32, Reduce red) {
-  mixed_resid64_body(theta, delta, n, cref, rhs32, base32, sb32, red, blockIdx.x, gridDim.x);
+    const double* __restrict__ delta, int n, ShiftRef cref, float* __restrict__ rhs32, int* __restrict__ baseq,
+    const double* __restrict__ bq, float* __restrict__ sb32, Reduce red) {
+  mixed_resid64_body(theta, delta, n, cref, rhs32, baseq, bq, sb32, red, blockIdx.x, gridDim.x);
 }
 
-__global__ void __launch_bounds__(256) base_root_kernel(const float* __restrict__ base32,
+__global__ void __launch_bounds__(256) base_root_kernel(const int* __restrict__ baseq, const double* __restrict__ bq,
     const double* __restrict__ delta, int n, double ih2, float* __restrict__ sb32) {
-  base_root_body(base32, delta, n, ih2, sb32, blockIdx.x, gridDim.x);
+  base_root_body(baseq, bq, delta, n, ih2, sb32, blockIdx.x, gridDim.x);
 }
 
-__global__ void __launch_bounds__(512) restrict32_kernel(const float* __restrict__ fine, float* __restrict__ coarse, int n) {
-  restrict32_body(fine, coarse, n, blockIdx.x, gridDim.x);
+__global__ void __launch_bounds__(512) restrictq_kernel(const int* __restrict__ fine, int* __restrict__ coarse, int n) {
+  restrictq_body(fine, coarse, n, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(256) absmax_kernel(const double* __restrict__ a, size_t cells, double* tmax) {
+  absmax_body(a, cells, tmax, blockIdx.x, gridDim.x);
+}
+
+__global__ void base_scale_kernel(double* tmax, double* bq) {
+  if (threadIdx.x == 0) base_scale_body(tmax, bq);
+}
+
+__global__ void __launch_bounds__(256) quantise_kernel(const double* __restrict__ src, int* __restrict__ dst, size_t cells,
+                                                       const double* __restrict__ bq) {
+  const double qs = bq[1];
+  for (size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x; x < cells; x += (size_t)gridDim.x * blockDim.x)
+    dst[x] = base_quantise(src[x], qs);
 }
 
 __global__ void __launch_bounds__(256) lin_resid_restrict_kernel(const float* __restrict__ e,
-    const float* __restrict__ base, const float* __restrict__ sb, const float* __restrict__ rhs, int n, float ih2,
-    ShiftRef cref, float* __restrict__ rhs_c, Reduce red) {
-  lin_resid_restrict_body(e, base, sb, rhs, n, ih2, cref, rhs_c, red, blockIdx.x, gridDim.x);
+    const int* __restrict__ baseq, const double* __restrict__ bq, const float* __restrict__ sb,
+    const float* __restrict__ rhs, int n, float ih2, ShiftRef cref, float* __restrict__ rhs_c, Reduce red) {
+  lin_resid_restrict_body(e, baseq, bq, sb, rhs, n, ih2, cref, rhs_c, red, blockIdx.x, gridDim.x);
 }
 
 __global__ void __launch_bounds__(256) prolong_add32_kernel(const float* __restrict__ ec, float* __restrict__ e, int n) {
   prolong_add32_body(ec, e, n, blockIdx.x, gridDim.x);
 }
 
-__global__ void __launch_bounds__(256) lin_coarsest_kernel(float* __restrict__ e, const float* __restrict__ base,
-    const float* __restrict__ sb, const float* __restrict__ rhs, int n, int nsweeps, float h2, float ih2,
-    const double* c_sum, double c_scale) {
+__global__ void __launch_bounds__(256) lin_coarsest_kernel(float* __restrict__ e, const int* __restrict__ baseq,
+    const double* __restrict__ bq, const float* __restrict__ sb, const float* __restrict__ rhs, int n, int nsweeps,
+    float h2, float ih2, const double* c_sum, double c_scale) {
   __shared__ LinCoarsestShared sh;
-  lin_coarsest_body(e, base, sb, rhs, n, nsweeps, h2, ih2, c_sum, c_scale, sh);
+  lin_coarsest_body(e, baseq, bq, sb, rhs, n, nsweeps, h2, ih2, c_sum, c_scale, sh);
 }
 
-__global__ void __launch_bounds__(256) update64_kernel(double* __restrict__ theta, const float* __restrict__ e, size_t cells) {
-  update64_body(theta, e, cells, blockIdx.x, gridDim.x);
+__global__ void __launch_bounds__(256) update64_kernel(double* __restrict__ theta, const float* __restrict__ e, size_t cells,
+                                                       double* tmax) {
+  update64_body(theta, e, cells, blockIdx.x, gridDim.x, tmax);
 }
 
 __global__ void __launch_bounds__(256) fill32_kernel(float* __restrict__ a, float v, size_t cells) {
@@ -82,6 +98,15 @@ template <int TM, int TJ, int COL>
 __global__ void __launch_bounds__(TM * TJ) lin_sweep_pipe(LinSweepArgs a) {
   __shared__ float lds[LinTile<TM, TJ>::LDS];
   lin_sweep_pipe_body<TM, TJ, COL>(a, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x, gridDim.x, lds);
+}
+
+// Compiled tile shapes of the one-launch FP32 sweep.
+#define MR_LF_TILES(X) X(32, 16) X(64, 8) X(64, 16) X(16, 16) X(32, 8) X(16, 8) X(8, 8) X(4, 8)
+
+template <int TM, int TJ>
+__global__ void __launch_bounds__(TM * TJ) lin_fused_kernel(LinFusedArgs a) {
+  __shared__ float lds[LinFusedTile<TM, TJ>::LDS];
+  lin_fused_body<TM, TJ>(a, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x, gridDim.x, lds);
 }
 
 template <int TM, int TJ>
@@ -180,9 +205,11 @@ __global__ void __launch_bounds__(256) cast32_kernel(const double* __restrict__ 
 // Defect of the linear level equation at every cell, in FP64 for the caller (the arithmetic is the
 // FP32 operator of the inner solve): r = rhs + dSigma(e) - nabla^2 e - cshift. Rows of the mesh
 // dealt to blocks; result[0] = sum r.
-__global__ void __launch_bounds__(256) lin_residual_kernel(const float* __restrict__ e, const float* __restrict__ base,
-    const float* __restrict__ sb, const float* __restrict__ rhs, int n, float ih2, float cshift,
-    double* __restrict__ r_out) {
+__global__ void __launch_bounds__(256) lin_residual_kernel(const float* __restrict__ e, const int* __restrict__ baseq,
+    const double* __restrict__ bq, const float* __restrict__ sb, const float* __restrict__ rhs, int n, float ih2,
+    float cshift, double* __restrict__ r_out) {
+  const float* __restrict__ base = reinterpret_cast<const float*>(baseq);
+  const float bscl = (float)bq[0];
   for (int row = blockIdx.x; row < n * n; row += gridDim.x) {
     const int i = row / n, j = row - i * n;
     for (int k = threadIdx.x; k < n; k += blockDim.x) {
@@ -191,7 +218,7 @@ __global__ void __launch_bounds__(256) lin_residual_kernel(const float* __restri
       gather18_split_t(e, n, i, j, k, te);
       gather18_split_t(base, n, i, j, k, tb);
       float Se;
-      const float src = lin_source(tb, sb[g], ih2, te, Se) * ih2;
+      const float src = lin_source(tb, base[g], bscl, sb[g], ih2, te, Se) * ih2;
       const float lap = (Se - 6.0f * e[g]) * ih2;
       r_out[g] = (double)((rhs ? rhs[g] : 0.0f) + src - lap - cshift);
     }
@@ -263,11 +290,37 @@ hipError_t launch_lin_half_sweep(const LinSweepArgs& a, const TileCfg& t, hipStr
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_mixed_resid64(const double* theta, const double* delta, int n, ShiftRef C, float* rhs32, float* base32,
-                                float* sb32, Reduce red, hipStream_t s) {
+bool lin_fused_supported(int tm, int tj) {
+#define MR_LF_MATCH(TM, TJ) if (tm == TM && tj == TJ) return true;
+  MR_LF_TILES(MR_LF_MATCH)
+#undef MR_LF_MATCH
+  return false;
+}
+
+hipError_t launch_lin_fused(const LinFusedArgs& a, const LinFusedCfg& t, hipStream_t s) {
+  const long blocks = (long)(a.n / t.tj) * (a.n / 2 / t.tm) * t.nchunks;
+  if (t.tm < 1 || t.tj < 1 || a.n % t.tj != 0 || (a.n / 2) % t.tm != 0 || t.nchunks < 1 || a.n % t.nchunks != 0 ||
+      a.n / t.nchunks < 2 || blocks > kMaxReduceBlocks || a.e_in == a.e_out)
+    return hipErrorInvalidValue;
+  LinFusedArgs b = a;
+  b.tiles_j = a.n / t.tj;
+  b.tiles_m = a.n / 2 / t.tm;
+  b.nchunks = t.nchunks;
+#define MR_LF_LAUNCH(TM, TJ)                                                                           \
+  if (t.tm == TM && t.tj == TJ) {                                                                      \
+    hipLaunchKernelGGL((lin_fused_kernel<TM, TJ>), dim3((unsigned)blocks), dim3(TM * TJ), 0, s, b);    \
+    return hipGetLastError();                                                                          \
+  }
+  MR_LF_TILES(MR_LF_LAUNCH)
+#undef MR_LF_LAUNCH
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_mixed_resid64(const double* theta, const double* delta, int n, ShiftRef C, float* rhs32, int* baseq,
+                                const double* bq, float* sb32, Reduce red, hipStream_t s) {
   int tm = 0, tj = 0, nch = 0;
   if (resid_tiled_cfg(n, tm, tj, nch)) {
-    ResidTiledArgs a{theta, delta, n, C, rhs32, base32, sb32, red, n / tj, n / 2 / tm, nch};
+    ResidTiledArgs a{theta, delta, n, C, rhs32, baseq, bq, sb32, red, n / tj, n / 2 / tm, nch};
     const unsigned blocks = (unsigned)(a.tiles_j * a.tiles_m * nch);
 #define MR_RT_LAUNCH(TM, TJ)                                                                   \
     if (tm == TM && tj == TJ) {                                                                \
@@ -278,27 +331,43 @@ hipError_t launch_mixed_resid64(const double* theta, const double* delta, int n,
 #undef MR_RT_LAUNCH
   }
   hipLaunchKernelGGL(mixed_resid64_kernel, dim3(rows_blocks(n)), dim3(row_threads(n)), 0, s, theta, delta, n, C, rhs32,
-                     base32, sb32, red);
+                     baseq, bq, sb32, red);
   return hipGetLastError();
 }
 
-hipError_t launch_base_root(const float* base32, const double* delta, int n, double h, float* sb32, hipStream_t s) {
-  hipLaunchKernelGGL(base_root_kernel, dim3((unsigned)n * n), dim3(n < 256 ? n : 256), 0, s, base32, delta, n,
+hipError_t launch_base_root(const int* baseq, const double* bq, const double* delta, int n, double h, float* sb32,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(base_root_kernel, dim3((unsigned)n * n), dim3(n < 256 ? n : 256), 0, s, baseq, bq, delta, n,
                      1.0 / (h * h), sb32);
   return hipGetLastError();
 }
 
-hipError_t launch_restrict32(const float* fine, float* coarse, int n, hipStream_t s) {
+hipError_t launch_restrictq(const int* fine, int* coarse, int n, hipStream_t s) {
   const int m = n / 2;
-  hipLaunchKernelGGL(restrict32_kernel, dim3((unsigned)m * m), dim3(m), 0, s, fine, coarse, n);
+  hipLaunchKernelGGL(restrictq_kernel, dim3((unsigned)m * m), dim3(m), 0, s, fine, coarse, n);
   return hipGetLastError();
 }
 
-hipError_t launch_lin_resid_restrict(const float* e, const float* base, const float* sb, const float* rhs, int n, double h,
-                                     ShiftRef c, float* rhs_c, Reduce red, hipStream_t s) {
+hipError_t launch_absmax(const double* a, size_t cells, double* tmax, hipStream_t s) {
+  hipLaunchKernelGGL(absmax_kernel, dim3(lin_blocks(cells)), dim3(256), 0, s, a, cells, tmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_base_scale(double* tmax, double* bq, hipStream_t s) {
+  hipLaunchKernelGGL(base_scale_kernel, dim3(1), dim3(64), 0, s, tmax, bq);
+  return hipGetLastError();
+}
+
+hipError_t launch_quantise(const double* src, int* dst, size_t cells, const double* bq, hipStream_t s) {
+  hipLaunchKernelGGL(quantise_kernel, dim3(lin_blocks(cells)), dim3(256), 0, s, src, dst, cells, bq);
+  return hipGetLastError();
+}
+
+hipError_t launch_lin_resid_restrict(const float* e, const int* baseq, const double* bq, const float* sb, const float* rhs,
+                                     int n, double h, ShiftRef c, float* rhs_c, Reduce red, hipStream_t s) {
   int tm = 0, tj = 0, nch = 0;
   if (tiled_cfg(n, rr_tiled_kernel, 2, tm, tj, nch, kPref8)) {
-    LinRRArgs a{e, base, sb, rhs, n, (float)(1.0 / (h * h)), c, rhs_c, red, n / tj, n / 2 / tm, nch};
+    LinRRArgs a{e, baseq, bq, sb, rhs, n, (float)(1.0 / (h * h)), c, rhs_c, red, n / tj, n / 2 / tm, nch};
     const unsigned blocks = (unsigned)(a.tiles_j * a.tiles_m * nch);
 #define MR_RR_LAUNCH(TM, TJ)                                                                           \
     if (tm == TM && tj == TJ) {                                                                        \
@@ -309,8 +378,8 @@ hipError_t launch_lin_resid_restrict(const float* e, const float* base, const fl
 #undef MR_RR_LAUNCH
   }
   const int m = n / 2;
-  hipLaunchKernelGGL(lin_resid_restrict_kernel, dim3(rows_blocks(m)), dim3(row_threads(m)), 0, s, e, base, sb, rhs, n,
-                     (float)(1.0 / (h * h)), c, rhs_c, red);
+  hipLaunchKernelGGL(lin_resid_restrict_kernel, dim3(rows_blocks(m)), dim3(row_threads(m)), 0, s, e, baseq, bq, sb, rhs,
+                     n, (float)(1.0 / (h * h)), c, rhs_c, red);
   return hipGetLastError();
 }
 
@@ -329,16 +398,16 @@ hipError_t launch_prolong_add32(const float* ec, float* e, int n, hipStream_t s)
   return hipGetLastError();
 }
 
-hipError_t launch_lin_coarsest(float* e, const float* base, const float* sb, const float* rhs, int n, int nsweeps, double h,
-                               const double* c_sum, double c_scale, hipStream_t s) {
+hipError_t launch_lin_coarsest(float* e, const int* baseq, const double* bq, const float* sb, const float* rhs, int n,
+                               int nsweeps, double h, const double* c_sum, double c_scale, hipStream_t s) {
   if ((long)n * n * n > kMaxCoarsest) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(lin_coarsest_kernel, dim3(1), dim3(256), 0, s, e, base, sb, rhs, n, nsweeps, (float)(h * h),
+  hipLaunchKernelGGL(lin_coarsest_kernel, dim3(1), dim3(256), 0, s, e, baseq, bq, sb, rhs, n, nsweeps, (float)(h * h),
                      (float)(1.0 / (h * h)), c_sum, c_scale);
   return hipGetLastError();
 }
 
-hipError_t launch_update64(double* theta, const float* e, size_t cells, hipStream_t s) {
-  hipLaunchKernelGGL(update64_kernel, dim3(lin_blocks(cells)), dim3(256), 0, s, theta, e, cells);
+hipError_t launch_update64(double* theta, const float* e, size_t cells, double* tmax, hipStream_t s) {
+  hipLaunchKernelGGL(update64_kernel, dim3(lin_blocks(cells)), dim3(256), 0, s, theta, e, cells, tmax);
   return hipGetLastError();
 }
 
@@ -357,9 +426,9 @@ hipError_t launch_widen64(const float* src, double* dst, size_t cells, hipStream
   return hipGetLastError();
 }
 
-hipError_t launch_lin_residual(const float* e, const float* base, const float* sb, const float* rhs, int n, double h,
-                               double cshift, double* r_out, hipStream_t s) {
-  hipLaunchKernelGGL(lin_residual_kernel, dim3(rows_blocks(n)), dim3(row_threads(n)), 0, s, e, base, sb, rhs, n,
+hipError_t launch_lin_residual(const float* e, const int* baseq, const double* bq, const float* sb, const float* rhs,
+                               int n, double h, double cshift, double* r_out, hipStream_t s) {
+  hipLaunchKernelGGL(lin_residual_kernel, dim3(rows_blocks(n)), dim3(row_threads(n)), 0, s, e, baseq, bq, sb, rhs, n,
                      (float)(1.0 / (h * h)), (float)cshift, r_out);
   return hipGetLastError();
 }
@@ -371,9 +440,11 @@ struct LinLevel {
   float* e[2] = {nullptr, nullptr};
   int cur = 0;
   float* rhs = nullptr;
-  float* base = nullptr;
+  int* base = nullptr;   // fixed-point base potential (scale in the context's kSlotBase scalars)
   float* sb = nullptr;
-  TileCfg sw;
+  TileCfg sw;            // two-launch schedule
+  bool fused = false;    // the one-launch sweep (schedule fz) won the tuner
+  LinFusedCfg fz;
 };
 
 struct MixedState {
@@ -405,13 +476,18 @@ static TileCfg lin_tiles(int n) {
   return t;
 }
 
+struct LinSched {
+  TileCfg two;
+  bool fused = false;
+  LinFusedCfg fz;
+};
 static std::mutex g_lin_tune_mu;
-static std::map<std::pair<int, int>, TileCfg> g_lin_tuned;   // (device, n)
+static std::map<std::pair<int, int>, LinSched> g_lin_tuned;   // (device, n)
 
 // Times both colours of a linear sweep for the default tile and for the pipelined kernel on every
 // compiled tile with chunks of 16 to 256 planes, on the level's (zeroed) buffers, and keeps the
 // fastest. Cached per (device, n).
-static int tune_lin_sweep(Ctx* c, int l, TileCfg* out) {
+static int tune_lin_sweep(Ctx* c, int l, LinSched* out) {
   const int n = c->lv[l].n, nh = n / 2;
   LinLevel& L = c->mixed->lv[l];
   int dev = 0;
@@ -444,12 +520,13 @@ static int tune_lin_sweep(Ctx* c, int l, TileCfg* out) {
 #undef MR_LIN_ADD
   const size_t cells = c->lv[l].cells;
   hipError_t e = hipSuccess;
-  for (float* b : {L.e[0], L.e[1], L.base, L.sb, L.rhs})
+  for (void* b : {(void*)L.e[0], (void*)L.e[1], (void*)L.base, (void*)L.sb, (void*)L.rhs})
     if (e == hipSuccess) e = hipMemsetAsync(b, 0, cells * sizeof(float), c->stream);
   LinSweepArgs a{};
   a.e_in = L.e[0];
   a.e_out = L.e[1];
   a.base = L.base;
+  a.bq = c->scal + kSlotBase;
   a.sb = L.sb;
   a.rhs = L.rhs;
   a.n = n;
@@ -468,12 +545,41 @@ static int tune_lin_sweep(Ctx* c, int l, TileCfg* out) {
   };
   const int reps = cells >= ((size_t)1 << 24) ? 2 : 4;
   // the default tile can be unsupported on tiny meshes (tm == 0): it is then never picked
-  std::vector<TileCfg> ok;
+  std::vector<LinSched> ok;
   for (const TileCfg& t : cand)
-    if (t.tm != 0) ok.push_back(t);
+    if (t.tm != 0) ok.push_back(LinSched{t, false, LinFusedCfg{}});
+  // one-launch candidates: every compiled tile that fits, chunks of 16 to 256 planes
+  auto add_fused = [&](int tm, int tj) {
+    if (nh % tm != 0 || n % tj != 0 || tj > n || tm > nh) return;
+    for (int ci = 16; ci <= 256 && ci <= n; ci *= 2) {
+      const long blocks = (long)(n / tj) * (nh / tm) * (n / ci);
+      if (n % ci == 0 && blocks <= kMaxReduceBlocks) ok.push_back(LinSched{cand[0], true, LinFusedCfg{tm, tj, n / ci}});
+    }
+  };
+#define MR_LF_ADD(TM, TJ) add_fused(TM, TJ);
+  MR_LF_TILES(MR_LF_ADD)
+#undef MR_LF_ADD
+  LinFusedArgs fa{};
+  fa.e_in = L.e[0];
+  fa.e_out = L.e[1];
+  fa.base = L.base;
+  fa.bq = c->scal + kSlotBase;
+  fa.sb = L.sb;
+  fa.rhs = L.rhs;
+  fa.n = n;
+  fa.h2 = 1.0f;
+  fa.ih2 = 1.0f;
+  fa.sum_out = c->scal + kSlotAux;
+  fa.partials = c->partials;
+  fa.counter = c->counter;
+  auto run_any = [&](size_t i) {
+    return ok[i].fused ? launch_lin_fused(fa, ok[i].fz, c->stream) : run(ok[i].two);
+  };
   size_t bi = 0;
-  if (e == hipSuccess && !ok.empty()) e = pick_fastest(ok.size(), reps, c->stream, [&](size_t i) { return run(ok[i]); }, &bi);
-  const TileCfg best_t = ok.empty() ? cand[0] : ok[bi];
+  if (e == hipSuccess && !ok.empty()) e = pick_fastest(ok.size(), reps, c->stream, run_any, &bi);
+  LinSched best_t;
+  if (!ok.empty()) best_t = ok[bi];
+  else best_t.two = cand[0];
   if (e != hipSuccess) return hip_fail(e, "linear sweep tuner");
   {
     std::lock_guard<std::mutex> lk(g_lin_tune_mu);
@@ -491,17 +597,21 @@ static int mixed_alloc(Ctx* c) {
   for (int l = 0; l < c->nlev; ++l) {
     const size_t cells = c->lv[l].cells;
     LinLevel& L = m->lv[l];
-    float** bufs[] = {&L.e[0], &L.e[1], &L.rhs, &L.base, &L.sb};
-    for (float** b : bufs) {
-      hipError_t e = hipMalloc((void**)b, cells * sizeof(float));
+    void** bufs[] = {(void**)&L.e[0], (void**)&L.e[1], (void**)&L.rhs, (void**)&L.base, (void**)&L.sb};
+    for (void** b : bufs) {
+      hipError_t e = hipMalloc(b, cells * sizeof(float));
       if (e != hipSuccess) return fail(MR_ENOMEM, "mixed precision buffers: %s", hipGetErrorString(e));
       m->owned.push_back(*b);
     }
   }
   // linear sweep schedule per level, timed on the level's buffers
   for (int l = 0; l + 1 < c->nlev; ++l) {
-    int rc = tune_lin_sweep(c, l, &m->lv[l].sw);
+    LinSched ls;
+    int rc = tune_lin_sweep(c, l, &ls);
     if (rc != MR_OK) return rc;
+    m->lv[l].sw = ls.two;
+    m->lv[l].fused = ls.fused;
+    m->lv[l].fz = ls.fz;
   }
   return MR_OK;
 }
@@ -526,11 +636,35 @@ int Ctx::lin_sweep(int l) {
   LinLevel& L = mixed->lv[l];
   Level& F = lv[l];
   double* cs = linsum(l);
+  if (L.fused && !(opts.flags & MR_FLAG_TWO_PASS)) {
+    LinFusedArgs a{};
+    a.e_in = L.e[L.cur];
+    a.e_out = L.e[L.cur ^ 1];
+    a.base = L.base;
+    a.bq = scal + kSlotBase;
+    a.sb = L.sb;
+    a.rhs = L.rhs;
+    a.n = F.n;
+    a.h2 = (float)(F.h * F.h);
+    a.ih2 = (float)(1.0 / (F.h * F.h));
+    a.c_sum = cs;
+    a.c_scale = 1.0 / (double)F.cells;
+    a.sum_out = cs;   // (red sum, black sum): the shift of the next sweep
+    a.partials = partials;
+    a.counter = counter;
+    const int ev = (l == 0) ? timer.begin(stream) : -1;
+    hipError_t e = launch_lin_fused(a, L.fz, stream);
+    if (e != hipSuccess) return hip_fail(e, "linear fused sweep");
+    timer.end(1, ev, stream);
+    L.cur ^= 1;
+    return MR_OK;
+  }
   LinSweepArgs a{};
   a.e_in = L.e[L.cur];
   a.e_red_new = nullptr;
   a.e_out = L.e[L.cur ^ 1];
   a.base = L.base;
+  a.bq = scal + kSlotBase;
   a.sb = L.sb;
   a.rhs = L.rhs;
   a.n = F.n;
@@ -562,8 +696,8 @@ int Ctx::lin_vcycle(int l) {
   Level& F = lv[l];
   hipError_t e;
   if (l == nlev - 1) {
-    e = launch_lin_coarsest(L.e[L.cur], L.base, L.sb, L.rhs, F.n, opts.ncoarse, F.h, linsum(l), 1.0 / (double)F.cells,
-                            stream);
+    e = launch_lin_coarsest(L.e[L.cur], L.base, scal + kSlotBase, L.sb, L.rhs, F.n, opts.ncoarse, F.h, linsum(l),
+                            1.0 / (double)F.cells, stream);
     return e == hipSuccess ? MR_OK : hip_fail(e, "linear coarsest");
   }
   int rc;
@@ -571,8 +705,9 @@ int Ctx::lin_vcycle(int l) {
     if ((rc = lin_sweep(l)) != MR_OK) return rc;
   LinLevel& Lc = mixed->lv[l + 1];
   Level& Fc = lv[l + 1];
-  e = launch_lin_resid_restrict(L.e[L.cur], L.base, L.sb, L.rhs, F.n, F.h, ShiftRef{linsum(l), 1.0 / (double)F.cells, 0.0},
-                                Lc.rhs, Reduce{partials, counter, linsum(l + 1)}, stream);
+  e = launch_lin_resid_restrict(L.e[L.cur], L.base, scal + kSlotBase, L.sb, L.rhs, F.n, F.h,
+                                ShiftRef{linsum(l), 1.0 / (double)F.cells, 0.0}, Lc.rhs,
+                                Reduce{partials, counter, linsum(l + 1)}, stream);
   if (e == hipSuccess) e = launch_fill32(Lc.e[Lc.cur], 0.0f, Fc.cells, stream);
   if (e != hipSuccess) return hip_fail(e, "linear restriction");
   if ((rc = lin_vcycle(l + 1)) != MR_OK) return rc;
@@ -589,8 +724,9 @@ int Ctx::mixed_ready() { return mixed_alloc(this); }
 // finest level: base = R base (8-son mean), root from the coarse base and R delta at the level's h.
 int Ctx::lin_base_hierarchy() {
   for (int l = 1; l < nlev; ++l) {
-    hipError_t e = launch_restrict32(mixed->lv[l - 1].base, mixed->lv[l].base, lv[l - 1].n, stream);
-    if (e == hipSuccess) e = launch_base_root(mixed->lv[l].base, lv[l].delta, lv[l].n, lv[l].h, mixed->lv[l].sb, stream);
+    hipError_t e = launch_restrictq(mixed->lv[l - 1].base, mixed->lv[l].base, lv[l - 1].n, stream);
+    if (e == hipSuccess)
+      e = launch_base_root(mixed->lv[l].base, scal + kSlotBase, lv[l].delta, lv[l].n, lv[l].h, mixed->lv[l].sb, stream);
     if (e != hipSuccess) return hip_fail(e, "linear base hierarchy");
   }
   return MR_OK;
@@ -621,8 +757,12 @@ int Ctx::lin_vcycles_split(const double* theta_split, const double* rhs_split, i
   const double N3 = (double)L0.cells;
   if ((rc = write_scalar(kSlotRes, 0.0)) != MR_OK) return rc;
   if ((rc = write_scalar(kSlotRes + 1, 0.0)) != MR_OK) return rc;
-  hipError_t e = launch_mixed_resid64(theta_split, L0.delta, L0.n, ShiftRef{scal + kSlotRes, 1.0 / N3, 0.0}, M0.rhs,
-                                      M0.base, M0.sb, reducer(kSlotRes), stream);
+  if ((rc = write_scalar(kSlotTmax, 0.0)) != MR_OK) return rc;
+  hipError_t e = launch_absmax(theta_split, L0.cells, scal + kSlotTmax, stream);
+  if (e == hipSuccess) e = launch_base_scale(scal + kSlotTmax, scal + kSlotBase, stream);
+  if (e == hipSuccess)
+    e = launch_mixed_resid64(theta_split, L0.delta, L0.n, ShiftRef{scal + kSlotRes, 1.0 / N3, 0.0}, M0.rhs, M0.base,
+                             scal + kSlotBase, M0.sb, reducer(kSlotRes), stream);
   if (e == hipSuccess) e = launch_cast32(rhs_split, M0.rhs, L0.cells, stream);
   if (e == hipSuccess) e = launch_sum(rhs_split, L0.cells, reducer(kSlotAux), stream);
   if (e == hipSuccess) {
@@ -648,6 +788,9 @@ int Ctx::solve_mixed(const double* delta, double* theta, mr_info* info, int aa_d
   L0.cur = 0;
   hipError_t e = opts.warm_start ? launch_to_split(theta, L0.th[0], L0.n, stream)
                                  : hipMemsetAsync(L0.th[0], 0, L0.cells * sizeof(double), stream);
+  // max |theta| of the start, for the scale of the fixed-point base (kSlotTmax is zero between uses)
+  if (e == hipSuccess && (rc = write_scalar(kSlotTmax, 0.0)) != MR_OK) return rc;
+  if (e == hipSuccess && opts.warm_start) e = launch_absmax(L0.th[0], L0.cells, scal + kSlotTmax, stream);
   if (e != hipSuccess) return hip_fail(e, "initial theta");
   double r0, m0;
   if ((rc = finest_norm(nullptr, ShiftRef{nullptr, 0.0, 0.0}, &r0, &m0)) != MR_OK) return rc;
@@ -661,8 +804,10 @@ int Ctx::solve_mixed(const double* delta, double* theta, mr_info* info, int aa_d
   double rel = 1.0, best = 1e300, msig = m0;
   LinLevel& M0 = mixed->lv[0];
   for (;;) {
-    e = launch_mixed_resid64(L0.th[0], L0.delta, L0.n, ShiftRef{scal + kSlotRes, 1.0 / N3, 0.0}, M0.rhs, M0.base, M0.sb,
-                             reducer(kSlotRes), stream);
+    e = launch_base_scale(scal + kSlotTmax, scal + kSlotBase, stream);
+    if (e == hipSuccess)
+      e = launch_mixed_resid64(L0.th[0], L0.delta, L0.n, ShiftRef{scal + kSlotRes, 1.0 / N3, 0.0}, M0.rhs, M0.base,
+                               scal + kSlotBase, M0.sb, reducer(kSlotRes), stream);
     if (e != hipSuccess) return hip_fail(e, "mixed residual");
     double r[4];
     if ((rc = read_scalars(kSlotRes, 4, r)) != MR_OK) return rc;
@@ -685,7 +830,8 @@ int Ctx::solve_mixed(const double* delta, double* theta, mr_info* info, int aa_d
       // Anderson mixing of the outer iteration theta -> theta + e(theta): the step forms theta + e
       // itself and writes the mixed (or plain) new iterate
       if ((rc = aa_step(aa, L0.th[0], M0.e[M0.cur])) != MR_OK) return rc;
-    } else if ((e = launch_update64(L0.th[0], M0.e[M0.cur], L0.cells, stream)) != hipSuccess) {
+      if ((e = launch_absmax(L0.th[0], L0.cells, scal + kSlotTmax, stream)) != hipSuccess) return hip_fail(e, "max");
+    } else if ((e = launch_update64(L0.th[0], M0.e[M0.cur], L0.cells, scal + kSlotTmax, stream)) != hipSuccess) {
       return hip_fail(e, "update");
     }
     ++it;

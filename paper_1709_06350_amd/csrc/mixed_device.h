@@ -33,15 +33,49 @@ __device__ __forceinline__ void gather18_split_t(const T* __restrict__ a, int n,
   t.ypzm = a[split_idx(n, i, jp, km)]; t.ymzp = a[split_idx(n, i, jm, kp)];
 }
 
-// h^2 dSigma(e) for a cell with base neighbours b, base root s and perturbation neighbours e;
-// also returns the face-neighbour sum of e. FP32.
-__device__ __forceinline__ float lin_source(const Nb18f& b, float s, float ih2, const Nb18f& e, float& Se) {
-  const float bSx = b.xm + b.xp, bSy = b.ym + b.yp, bSz = b.zm + b.zp;
-  const float bS3 = (bSx + bSy + bSz) * (1.0f / 3.0f);
-  const float mx = (bSx - bS3) * ih2, my = (bSy - bS3) * ih2, mz = (bSz - bS3) * ih2;
-  const float mxy = 0.25f * ((b.xpyp + b.xmym) - (b.xpym + b.xmyp)) * ih2;
-  const float mxz = 0.25f * ((b.xpzp + b.xmzm) - (b.xpzm + b.xmzp)) * ih2;
-  const float myz = 0.25f * ((b.ypzp + b.ymzm) - (b.ypzm + b.ymzp)) * ih2;
+// The base potential of the linearisation is stored as 32-bit fixed point, q = round(theta 2^s)
+// with |q| < 2^29 (the scale chosen from max |theta|), so that second differences of the base are
+// exact integers: an FP32 copy of theta would round it to about 1e-7 of max |theta| (1.2e-4 for
+// |theta| ~ 1000 cells^2 on a 512^3 mesh) and the Hessian of a void cell, its eigenvalues near -1
+// and W = (9 s Mbar - 27 Mbar^2) / (3 s^2 + p) sensitive to them, would be wrong by several per
+// cent. With |q| < 2^29 every difference below fits int32: a neighbour minus the centre is below
+// 2^30 and the sum of two such, or the difference of two such, below 2^31. The fixed-point values
+// travel through the FP32 loaders and LDS slots as raw bits (qbits / qval).
+constexpr int kBaseBits = 29;
+__device__ __forceinline__ float qbits(int q) { return __builtin_bit_cast(float, q); }
+__device__ __forceinline__ int qval(float bits) { return __builtin_bit_cast(int, bits); }
+
+// Fixed-point base value of theta for the scale 2^s (s from base_scale_exp).
+__device__ __forceinline__ int base_quantise(double theta, double scale) { return __double2int_rn(theta * scale); }
+
+// Scale exponent for a potential with max |theta| = tmax: the largest s with tmax 2^s < 2^kBaseBits - 1
+// (at most 60, for theta = 0).
+__host__ __device__ inline int base_scale_exp(double tmax) {
+  int s = 60;
+  const double lim = (double)((1 << kBaseBits) - 1);
+  while (s > -60 && tmax * ldexp(1.0, s) >= lim) --s;
+  return s;
+}
+
+// h^2 dSigma(e) for a cell with base neighbours b and centre bc (fixed-point bits, scale bscl =
+// 2^-s), base root s and perturbation neighbours e; also returns the face-neighbour sum of e. FP32.
+__device__ __forceinline__ float lin_source(const Nb18f& b, float bc, float bscl, float s, float ih2, const Nb18f& e,
+                                            float& Se) {
+  const int c = qval(bc);
+  // exact integer second differences of the base (pair sums minus twice the centre) and cross differences
+  const int dx = (qval(b.xm) - c) + (qval(b.xp) - c);
+  const int dy = (qval(b.ym) - c) + (qval(b.yp) - c);
+  const int dz = (qval(b.zm) - c) + (qval(b.zp) - c);
+  const int cxy = (qval(b.xpyp) - qval(b.xpym)) - (qval(b.xmyp) - qval(b.xmym));
+  const int cxz = (qval(b.xpzp) - qval(b.xpzm)) - (qval(b.xmzp) - qval(b.xmzm));
+  const int cyz = (qval(b.ypzp) - qval(b.ypzm)) - (qval(b.ymzp) - qval(b.ymzm));
+  const float sc = bscl * ih2;
+  const float fx = (float)dx * sc, fy = (float)dy * sc, fz = (float)dz * sc;
+  const float f3 = (fx + fy + fz) * (1.0f / 3.0f);
+  const float mx = fx - f3, my = fy - f3, mz = fz - f3;
+  const float mxy = 0.25f * sc * (float)cxy;
+  const float mxz = 0.25f * sc * (float)cxz;
+  const float myz = 0.25f * sc * (float)cyz;
   const float xy2 = mxy * mxy, xz2 = mxz * mxz, yz2 = myz * myz;
   const float T2 = mx * mx + my * my + mz * mz + 2.0f * (xy2 + xz2 + yz2);
   // hardware reciprocal: the linearised operator only steers the defect correction
@@ -90,8 +124,8 @@ inline __device__ void lin_sweep_body(const LinSweepArgs& a, int logical, int bi
   const unsigned plane = (unsigned)n * (unsigned)nh;
   const float* __restrict__ f0 = a.e_red_new ? a.e_red_new : a.e_in;   // e red
   const float* __restrict__ f1 = a.e_in + half;                        // e black
-  const float* __restrict__ f2 = a.base;                               // base red
-  const float* __restrict__ f3 = a.base + half;                        // base black
+  const float* __restrict__ f2 = reinterpret_cast<const float*>(a.base);          // base red (fixed-point bits)
+  const float* __restrict__ f3 = reinterpret_cast<const float*>(a.base) + half;   // base black
 
   unsigned goff[NPF];
   int loff[NPF];
@@ -140,6 +174,7 @@ inline __device__ void lin_sweep_body(const LinSweepArgs& a, int logical, int bi
   const double Cd = (a.c_sum ? (a.c_sum[0] + a.c_sum[1]) * a.c_scale : 0.0) + a.c_add;
   const float C = (float)Cd;
   const float h2 = a.h2, ih2 = a.ih2;
+  const float bscl = (float)a.bq[0];
   const float* __restrict__ sbc = a.sb + c * half;
   const float* __restrict__ rc = a.rhs + c * half;
   float* __restrict__ out = a.e_out + c * half;
@@ -167,7 +202,7 @@ inline __device__ void lin_sweep_body(const LinSweepArgs& a, int logical, int bi
 #undef MR_LIN_GATHER
     const unsigned e = (unsigned)i * plane + (unsigned)j * nh + m;
     float Se;
-    const float g = lin_source(tb, sbc[e], ih2, te, Se) * ih2;
+    const float g = lin_source(tb, L(2 + c, i, R, S), bscl, sbc[e], ih2, te, Se) * ih2;
     const float rhs = rc[e];
     out[e] = (Se - h2 * (g + rhs - C)) * (1.0f / 6.0f);
     acc += (double)(g + rhs);
@@ -184,9 +219,11 @@ inline __device__ void lin_sweep_body(const LinSweepArgs& a, int logical, int bi
 // theta, sb32 = the physical root s. result = (sum Sigma, 0, sum b, sum b^2), so that the first two
 // entries serve as the running sum that sets C of the next pass.
 inline __device__ bool mixed_resid64_body(const double* __restrict__ theta, const double* __restrict__ delta, int n,
-                                   ShiftRef cref, float* __restrict__ rhs32, float* __restrict__ base32,
-                                   float* __restrict__ sb32, Reduce red, int bid, int nblocks) {
+                                   ShiftRef cref, float* __restrict__ rhs32, int* __restrict__ baseq,
+                                   const double* __restrict__ bq, float* __restrict__ sb32, Reduce red, int bid,
+                                   int nblocks) {
   const double C = (cref.c_sum ? (cref.c_sum[0] + cref.c_sum[1]) * cref.c_scale : 0.0) + cref.c_add;
+  const double qs = bq[1];
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
   const int rows = n * n;
   const int rpb = (rows + nblocks - 1) / nblocks;
@@ -203,7 +240,7 @@ inline __device__ bool mixed_resid64_body(const double* __restrict__ theta, cons
       const double th = theta[e];
       const double b = (S - 6.0 * th) - sig + C;
       rhs32[e] = (float)(-b);
-      base32[e] = (float)th;
+      baseq[e] = base_quantise(th, qs);
       sb32[e] = (float)(sig + 3.0);
       a0 += b;
       a1 += b * b;
@@ -213,42 +250,77 @@ inline __device__ bool mixed_resid64_body(const double* __restrict__ theta, cons
   double v[4] = {a2, 0.0, a0, a1};
   return grid_sum<4>(v, red.partials, red.counter, red.result, nblocks, bid);
 }
-// Base root on a coarse mesh (cell size h) from the restricted FP32 base potential; rows
-// bid, bid + nblocks, ... of the mesh.
-inline __device__ void base_root_body(const float* __restrict__ base32, const double* __restrict__ delta, int n, double ih2,
-                               float* __restrict__ sb32, int bid, int nblocks) {
+// Base root on a coarse mesh (cell size h) from the restricted fixed-point base potential (its
+// value bq[0] q, exact in FP64); rows bid, bid + nblocks, ... of the mesh.
+inline __device__ void base_root_body(const int* __restrict__ baseq, const double* __restrict__ bq,
+                               const double* __restrict__ delta, int n, double ih2, float* __restrict__ sb32, int bid,
+                               int nblocks) {
+  const double sc = bq[0];
   for (int row = xcd_remap(bid, nblocks); row < n * n; row += nblocks) {
     const int i = row / n, j = row - i * n;
     for (int k = threadIdx.x; k < n; k += blockDim.x) {
       const unsigned e = split_idx(n, i, j, k);
       Nb18f tf;
-      gather18_split_t(base32, n, i, j, k, tf);
-      Nb18 t{tf.xm, tf.xp, tf.ym, tf.yp, tf.zm, tf.zp, tf.xpyp, tf.xmym, tf.xpym, tf.xmyp,
-             tf.xpzp, tf.xmzm, tf.xpzm, tf.xmzp, tf.ypzp, tf.ymzm, tf.ypzm, tf.ymzp};
+      gather18_split_t(reinterpret_cast<const float*>(baseq), n, i, j, k, tf);
+      Nb18 t{sc * qval(tf.xm), sc * qval(tf.xp), sc * qval(tf.ym), sc * qval(tf.yp), sc * qval(tf.zm),
+             sc * qval(tf.zp), sc * qval(tf.xpyp), sc * qval(tf.xmym), sc * qval(tf.xpym), sc * qval(tf.xmyp),
+             sc * qval(tf.xpzp), sc * qval(tf.xmzm), sc * qval(tf.xpzm), sc * qval(tf.xmzp), sc * qval(tf.ypzp),
+             sc * qval(tf.ymzm), sc * qval(tf.ypzm), sc * qval(tf.ymzp)};
       double S;
       sb32[e] = (float)(sigma_cell(t, 1.0 + delta[e], ih2, S) + 3.0);
     }
   }
 }
-// 8-son mean, coarse rows bid, bid + nblocks, ...
-inline __device__ void restrict32_body(const float* __restrict__ fine, float* __restrict__ coarse, int n, int bid, int nblocks) {
+// 8-son mean of the fixed-point base (rounded to nearest; |q| < 2^kBaseBits keeps the sum in range
+// of int64 and the mean in range of int32), coarse rows bid, bid + nblocks, ...
+inline __device__ void restrictq_body(const int* __restrict__ fine, int* __restrict__ coarse, int n, int bid, int nblocks) {
   const int m = n >> 1;
   for (int row = xcd_remap(bid, nblocks); row < m * m; row += nblocks) {
     const int I = row / m, J = row - I * m;
     for (int K = threadIdx.x; K < m; K += blockDim.x) {
-      float s = 0.0f;
+      long long s = 0;
 #pragma unroll
       for (int q = 0; q < 8; ++q) s += fine[split_idx(n, 2 * I + (q >> 2), 2 * J + ((q >> 1) & 1), 2 * K + (q & 1))];
-      coarse[split_idx(m, I, J, K)] = 0.125f * s;
+      coarse[split_idx(m, I, J, K)] = (int)((s >= 0 ? s + 4 : s - 4) / 8);
     }
   }
 }
+// Block maximum of v over the calling block, then one atomic maximum on the bit pattern of a
+// non-negative double (whose order is that of unsigned integers) at *slot.
+inline __device__ void block_absmax_to(double v, double* slot) {
+  __shared__ double red[16];
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  const int tid = threadIdx.x, nw = (blockDim.x + 63) >> 6;
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  if (tid == 0) {
+    double m = 0.0;
+    for (int w = 0; w < nw; ++w) m = fmax(m, red[w]);
+    atomicMax(reinterpret_cast<unsigned long long*>(slot), (unsigned long long)__double_as_longlong(m));
+  }
+}
+// max |a| over cells into *slot (atomic maximum; the slot must hold a value <= the result).
+inline __device__ void absmax_body(const double* __restrict__ a, size_t cells, double* slot, int bid, int nblocks) {
+  double m = 0.0;
+  for (size_t x = bid * (size_t)blockDim.x + threadIdx.x; x < cells; x += (size_t)nblocks * blockDim.x) m = fmax(m, fabs(a[x]));
+  block_absmax_to(m, slot);
+}
+// Scale of the fixed-point base from max |theta| (*tmax): bq[0] = 2^-s, bq[1] = 2^s; *tmax is
+// returned to zero for the next maximum. One thread.
+inline __device__ void base_scale_body(double* tmax, double* bq) {
+  const int sx = base_scale_exp(*tmax);
+  bq[0] = ldexp(1.0, -sx);
+  bq[1] = ldexp(1.0, sx);
+  *tmax = 0.0;
+}
 // Residual of the linear level equation and its restriction: res = rhs + dSigma(e) - lap(e) - C,
 // rhs_c = R res (one thread per coarse cell). result[0..1] = (sum of rhs_c, 0).
-inline __device__ void lin_resid_restrict_body(const float* __restrict__ e, const float* __restrict__ base,
-    const float* __restrict__ sb, const float* __restrict__ rhs, int n, float ih2, ShiftRef cref,
-    float* __restrict__ rhs_c, Reduce red, int bid, int nblocks) {
+inline __device__ void lin_resid_restrict_body(const float* __restrict__ e, const int* __restrict__ baseq,
+    const double* __restrict__ bq, const float* __restrict__ sb, const float* __restrict__ rhs, int n, float ih2,
+    ShiftRef cref, float* __restrict__ rhs_c, Reduce red, int bid, int nblocks) {
   const int m = n >> 1;
+  const float* __restrict__ base = reinterpret_cast<const float*>(baseq);
+  const float bscl = (float)bq[0];
   const double Cd = (cref.c_sum ? (cref.c_sum[0] + cref.c_sum[1]) * cref.c_scale : 0.0) + cref.c_add;
   const float C = (float)Cd;
   double acc = 0.0;
@@ -268,7 +340,7 @@ inline __device__ void lin_resid_restrict_body(const float* __restrict__ e, cons
         gather18_split_t(e, n, i, j, k, te);
         gather18_split_t(base, n, i, j, k, tb);
         float Se;
-        const float src = lin_source(tb, sb[g], ih2, te, Se) * ih2;
+        const float src = lin_source(tb, base[g], bscl, sb[g], ih2, te, Se) * ih2;
         const float lap = (Se - 6.0f * e[g]) * ih2;
         sres += rhs[g] + src - lap - C;
       }
@@ -418,9 +490,11 @@ struct LinCoarsestShared {
   float cnew;
 };
 
-inline __device__ void lin_coarsest_body(float* __restrict__ e, const float* __restrict__ base, const float* __restrict__ sb,
-                                  const float* __restrict__ rhs, int n, int nsweeps, float h2, float ih2,
-                                  const double* c_sum, double c_scale, LinCoarsestShared& sh) {
+inline __device__ void lin_coarsest_body(float* __restrict__ e, const int* __restrict__ baseq, const double* __restrict__ bq,
+                                  const float* __restrict__ sb, const float* __restrict__ rhs, int n, int nsweeps,
+                                  float h2, float ih2, const double* c_sum, double c_scale, LinCoarsestShared& sh) {
+  const float* __restrict__ base = reinterpret_cast<const float*>(baseq);
+  const float bscl = (float)bq[0];
   float* te = sh.te;
   float* tb = sh.tb;
   float* ts = sh.ts;
@@ -457,7 +531,7 @@ inline __device__ void lin_coarsest_body(float* __restrict__ e, const float* __r
         nb(te, i, j, k, ve);
         nb(tb, i, j, k, vb);
         float Se;
-        const float g = lin_source(vb, ts[x], ih2, ve, Se) * ih2;
+        const float g = lin_source(vb, tb[x], bscl, ts[x], ih2, ve, Se) * ih2;
         tn[x] = (Se - h2 * (g + tr[x] - C)) * (1.0f / 6.0f);
         acc += (double)(g + tr[x]);
       }
@@ -480,9 +554,16 @@ inline __device__ void lin_coarsest_body(float* __restrict__ e, const float* __r
     e[split_idx(n, i, j, k)] = te[x];
   }
 }
-inline __device__ void update64_body(double* __restrict__ theta, const float* __restrict__ e, size_t cells, int bid, int nblocks) {
-  for (size_t x = bid * (size_t)blockDim.x + threadIdx.x; x < cells; x += (size_t)nblocks * blockDim.x)
-    theta[x] += (double)e[x];
+// theta += e; max |theta| of the result into *tmax (atomic maximum) when tmax is given.
+inline __device__ void update64_body(double* __restrict__ theta, const float* __restrict__ e, size_t cells, int bid,
+                                     int nblocks, double* tmax) {
+  double m = 0.0;
+  for (size_t x = bid * (size_t)blockDim.x + threadIdx.x; x < cells; x += (size_t)nblocks * blockDim.x) {
+    const double v = theta[x] + (double)e[x];
+    theta[x] = v;
+    m = fmax(m, fabs(v));
+  }
+  if (tmax) block_absmax_to(m, tmax);
 }
 
 inline __device__ void fill32_body(float* __restrict__ a, float v, size_t cells, int bid, int nblocks) {
@@ -512,8 +593,8 @@ __device__ void lin_sweep_pipe_body(const LinSweepArgs& a, int logical, int bid,
   const unsigned pbytes = (unsigned)plane * 4u;
   const float* __restrict__ f0 = COL == 1 ? a.e_red_new : a.e_in;   // e red
   const float* __restrict__ f1 = a.e_in + half;                      // e black
-  const float* __restrict__ f2 = a.base;                             // base red
-  const float* __restrict__ f3 = a.base + half;                      // base black
+  const float* __restrict__ f2 = reinterpret_cast<const float*>(a.base);          // base red (fixed-point bits)
+  const float* __restrict__ f3 = reinterpret_cast<const float*>(a.base) + half;   // base black
   // global accesses through a buffer resource of one plane (uniform) and a per-lane byte offset
   auto prs = [&](const float* arr, int p) { return plane_rsrc(arr + (size_t)p * plane, pbytes); };
 
@@ -557,6 +638,7 @@ __device__ void lin_sweep_pipe_body(const LinSweepArgs& a, int logical, int bid,
   const double Cd = (a.c_sum ? (a.c_sum[0] + a.c_sum[1]) * a.c_scale : 0.0) + a.c_add;
   const float C = (float)Cd;
   const float h2 = a.h2, ih2 = a.ih2;
+  const float bscl = (float)a.bq[0];
   const float* __restrict__ sbc = a.sb + COL * half;
   const float* __restrict__ rc = a.rhs + COL * half;
   float* __restrict__ out = a.e_out + COL * half;
@@ -608,7 +690,7 @@ __device__ void lin_sweep_pipe_body(const LinSweepArgs& a, int logical, int bid,
     MR_LP_GATHER(tb, 2 + O, 2 + COL)
 #undef MR_LP_GATHER
     float Se;
-    const float g = lin_source(tb, SB[K], ih2, te, Se) * ih2;
+    const float g = lin_source(tb, lds[(2 + COL) * 4 * SLOT + S0 * SLOT + ob], bscl, SB[K], ih2, te, Se) * ih2;
     const float rhs = RH[K];
     st_rs_f(prs(out, i0 + t), o_c, (Se - h2 * (g + rhs - C)) * (1.0f / 6.0f));
     acc += (double)(g + rhs);
@@ -635,7 +717,8 @@ __device__ void lin_sweep_pipe_body(const LinSweepArgs& a, int logical, int bid,
 // two steps ahead.
 struct LinRRArgs {
   const float* e;
-  const float* base;
+  const int* base;
+  const double* bq;
   const float* sb;
   const float* rhs;
   int n;
@@ -666,8 +749,9 @@ __device__ void lin_resid_restrict_tiled_body(const LinRRArgs& a, int logical, i
   const unsigned halfc = (unsigned)nc * (unsigned)nc * (unsigned)nch;
   const float* __restrict__ f0 = a.e;
   const float* __restrict__ f1 = a.e + half;
-  const float* __restrict__ f2 = a.base;
-  const float* __restrict__ f3 = a.base + half;
+  const float* __restrict__ f2 = reinterpret_cast<const float*>(a.base);          // fixed-point bits
+  const float* __restrict__ f3 = reinterpret_cast<const float*>(a.base) + half;
+  const float bscl = (float)a.bq[0];
 
   // loader: element k of field f is f * SLOT + (k % PER) * NT + tid (clamped inside the field), so
   // that the source field of every load is a compile-time constant
@@ -756,7 +840,7 @@ __device__ void lin_resid_restrict_tiled_body(const LinRRArgs& a, int logical, i
         MR_RR_GATHER(tb, 2 + O, 2 + c)
 #undef MR_RR_GATHER
         float Se;
-        const float src = lin_source(tb, sbv, ih2, te, Se) * ih2;
+        const float src = lin_source(tb, lds[((2 + c) * 4 + S0) * SLOT + ob], bscl, sbv, ih2, te, Se) * ih2;
         const float ec = lds[(c * 4 + S0) * SLOT + ob];
         const float lap = (Se - 6.0f * ec) * ih2;
         sres += rhv + src - lap - C;
@@ -796,7 +880,8 @@ struct ResidTiledArgs {
   int n;
   ShiftRef cref;
   float* rhs32;
-  float* base32;
+  int* baseq;
+  const double* bq;
   float* sb32;
   Reduce red;
   int tiles_j, tiles_m, nchunks;
@@ -854,6 +939,7 @@ __device__ bool mixed_resid64_tiled_body(const ResidTiledArgs& a, int logical, i
   const double C = (a.cref.c_sum ? (a.cref.c_sum[0] + a.cref.c_sum[1]) * a.cref.c_scale : 0.0) + a.cref.c_add;
   const double* __restrict__ dl = a.delta + own;
   const int last_plane = n - 1;
+  const double qs = a.bq[1];
   double a0 = 0.0, a1 = 0.0, a2 = 0.0;
 
   double V0[NPF], V1[NPF];
@@ -923,7 +1009,7 @@ __device__ bool mixed_resid64_tiled_body(const ResidTiledArgs& a, int logical, i
       const double b = (S[c] - 6.0 * thc) - sig + C;
       const unsigned e = (unsigned)c * half + e0;
       a.rhs32[e] = (float)(-b);
-      a.base32[e] = (float)thc;
+      a.baseq[e] = base_quantise(thc, qs);
       a.sb32[e] = (float)sr[c];
       a0 += b;
       a1 += b * b;
@@ -940,6 +1026,273 @@ __device__ bool mixed_resid64_tiled_body(const ResidTiledArgs& a, int logical, i
   }
   double v[4] = {a2, 0.0, a0, a1};
   return grid_sum<4>(v, a.red.partials, a.red.counter, a.red.result, nblocks, bid);
+}
+
+}  // namespace mr
+
+namespace mr {
+
+// ---- one-launch (fused) FP32 linear sweep -----------------------------------------------------
+// Both colours of a red-black sweep of the linear level equation in one pass over the mesh. A block
+// owns a TM x TJ tile of (m, j) and marches over a chunk of planes [i0, i1). At step t it updates the
+// red cells of plane t (its tile plus the one-cell ring around it that the black update of its tile
+// reads: the two halo rows and columns, no corners), then, after a barrier, the black cells of plane
+// t - 1 from the new red values of planes t - 2 .. t. A red cell's update reads only black values and
+// red values of the snapshot (never its own old value), so a ring cell recomputed here equals the
+// neighbouring block's result bit for bit: the blocks need no communication. Old e and the base
+// (both colours) of planes t - 2 .. t + 2 sit in 5-slot LDS rings with a two-cell halo, the new red
+// values in a 5-slot ring with a one-cell halo. Plane t + 3 is fetched into registers at step t and
+// stored into the ring's free slot at the end of step t + 1; the root and right-hand side of a step
+// are loaded one step ahead. The step loop is unrolled by 10 (the ring length times the two row
+// parities), so every LDS slot offset is a compile-time constant. Per cell update the kernel moves
+// 20 bytes (e read and written, base, root and right-hand side read once) against 28 for the two
+// one-colour launches, which each read both colours of e and of the base.
+template <int TM, int TJ>
+struct LinFusedTile {
+  static constexpr int NT = TM * TJ;
+  static constexpr int W2 = TM + 4, S2 = (TJ + 4) * W2;   // old e / base planes (halo 2)
+  static constexpr int W1 = TM + 2, S1 = (TJ + 2) * W1;   // new red planes (halo 1)
+  static constexpr int HC = 2 * TM + 2 * TJ;              // red ring cells per plane
+  static constexpr int PER = (S2 + NT - 1) / NT;          // loads per field and thread
+  static constexpr int NPF = 4 * PER;                     // e red, e black, base red, base black
+  static constexpr int OFF_B = 10 * S2, OFF_N = 20 * S2;
+  static constexpr int LDS = 20 * S2 + 5 * S1;            // floats
+};
+
+template <int TM, int TJ>
+__device__ void lin_fused_body(const LinFusedArgs& a, int logical, int bid, int nblocks, float* lds) {
+  using T = LinFusedTile<TM, TJ>;
+  constexpr int NT = T::NT, W2 = T::W2, S2 = T::S2, W1 = T::W1, S1 = T::S1, PER = T::PER, NPF = T::NPF;
+  constexpr int OB = T::OFF_B, ON = T::OFF_N;
+  const int n = a.n, nh = n >> 1;
+  const int tid = threadIdx.x;
+  const int ntile = a.tiles_m * a.tiles_j;
+  const int tile = logical % ntile, chunk = logical / ntile;
+  const int m0 = (tile % a.tiles_m) * TM, j0 = (tile / a.tiles_m) * TJ;
+  const int ci = n / a.nchunks, i0 = chunk * ci, i1 = i0 + ci;
+  const int U = ci + 2;   // steps: red planes i0 - 1 .. i1, black planes i0 .. i1 - 1
+  const size_t plane = (size_t)n * nh, half = plane * n;
+  const unsigned pbytes = (unsigned)plane * 4u;
+  const float* __restrict__ f0 = a.e_in;
+  const float* __restrict__ f1 = a.e_in + half;
+  const float* __restrict__ f2 = reinterpret_cast<const float*>(a.base);          // fixed-point bits
+  const float* __restrict__ f3 = reinterpret_cast<const float*>(a.base) + half;
+  auto prs = [&](const float* arr, int p) { return plane_rsrc(arr + (size_t)wrapi(p, n) * plane, pbytes); };
+
+  // loader: element k of each field is min(k NT + tid, S2 - 1) of its tile-plus-halo plane
+  unsigned goff[PER];
+  int loff[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    int e = k * NT + tid;
+    e = e < S2 ? e : S2 - 1;
+    const int rr = e / W2, cc = e - rr * W2;
+    goff[k] = ((unsigned)wrapi(j0 - 2 + rr, n) * nh + (unsigned)wrapi(m0 - 2 + cc, nh)) * 4u;
+    loff[k] = e;
+  }
+  auto fetch = [&](int p, float (&v)[NPF]) {
+    const auto r0 = prs(f0, p), r1 = prs(f1, p), r2 = prs(f2, p), r3 = prs(f3, p);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      v[k] = ld_rs_f(r0, goff[k]);
+      v[PER + k] = ld_rs_f(r1, goff[k]);
+      v[2 * PER + k] = ld_rs_f(r2, goff[k]);
+      v[3 * PER + k] = ld_rs_f(r3, goff[k]);
+    }
+  };
+  // plane with ring slot sl (compile-time): e red, e black, base red, base black
+  auto store = [&](int sl, const float (&v)[NPF]) {
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      lds[(sl * 2 + 0) * S2 + loff[k]] = v[k];
+      lds[(sl * 2 + 1) * S2 + loff[k]] = v[PER + k];
+      lds[OB + (sl * 2 + 0) * S2 + loff[k]] = v[2 * PER + k];
+      lds[OB + (sl * 2 + 1) * S2 + loff[k]] = v[3 * PER + k];
+    }
+  };
+
+  const int s = tid % TM, r = tid / TM;
+  const int j = j0 + r, m = m0 + s;
+  const unsigned o_c = ((unsigned)j * nh + m) * 4u;
+  // red ring cell of this thread (tid < HC): rows -1 and TJ, then columns -1 and TM
+  const bool has_halo = tid < T::HC;
+  int hr, hs;
+  if (tid < TM) {
+    hr = -1;
+    hs = tid;
+  } else if (tid < 2 * TM) {
+    hr = TJ;
+    hs = tid - TM;
+  } else if (tid < 2 * TM + TJ) {
+    hr = tid - 2 * TM;
+    hs = -1;
+  } else {
+    hr = has_halo ? tid - 2 * TM - TJ : 0;
+    hs = has_halo ? TM : 0;
+  }
+  const unsigned o_h = ((unsigned)wrapi(j0 + hr, n) * nh + (unsigned)wrapi(m0 + hs, nh)) * 4u;
+  // per-thread LDS offsets: cell (halo-2 and halo-1 planes) and its z neighbour k - 1 for the row
+  // parity of even (index 0) and odd (index 1) steps; the parity of a row at step u is p0 ^ (u & 1)
+  const int q0 = (i0 - 1 + j) & 1, qh0 = (i0 - 1 + j0 + hr) & 1;
+  const int ob2 = (r + 2) * W2 + (s + 2), ob1 = (r + 1) * W1 + (s + 1);
+  const int hb2 = (hr + 2) * W2 + (hs + 2), hb1 = (hr + 1) * W1 + (hs + 1);
+  const int oz2[2] = {ob2 + q0 - 1, ob2 + (q0 ^ 1) - 1};
+  const int oz1[2] = {ob1 + q0 - 1, ob1 + (q0 ^ 1) - 1};
+  const int hz2[2] = {hb2 + qh0 - 1, hb2 + (qh0 ^ 1) - 1};
+  const double Cd = (a.c_sum ? (a.c_sum[0] + a.c_sum[1]) * a.c_scale : 0.0) + a.c_add;
+  const float C = (float)Cd;
+  const float h2 = a.h2, ih2 = a.ih2, bscl = (float)a.bq[0];
+  const float* __restrict__ sbR = a.sb;
+  const float* __restrict__ sbB = a.sb + half;
+  const float* __restrict__ rhR = a.rhs;
+  const float* __restrict__ rhB = a.rhs + half;
+  float* __restrict__ outR = a.e_out;
+  float* __restrict__ outB = a.e_out + half;
+  double accR = 0.0, accB = 0.0;
+
+  // red update of the cell at LDS offsets (c2 in the halo-2 planes, z2 its k - 1 neighbour) with old
+  // slots SM, S0, SP of planes t - 1, t, t + 1
+  auto red_at = [&](auto smc, auto s0c, auto spc, int c2, int z2, float sbv, float rhv, float& g) -> float {
+    constexpr int SM = decltype(smc)::value, S0 = decltype(s0c)::value, SP = decltype(spc)::value;
+    const float* eR_m = lds + (SM * 2) * S2;
+    const float* eR_p = lds + (SP * 2) * S2;
+    const float* eR_0 = lds + (S0 * 2) * S2;
+    const float* eB_m = lds + (SM * 2 + 1) * S2;
+    const float* eB_p = lds + (SP * 2 + 1) * S2;
+    const float* eB_0 = lds + (S0 * 2 + 1) * S2;
+    Nb18f te, tb;
+#define MR_LF_RED(T_, O)                                                                             \
+    T_.xm = eB_m[O + c2];         T_.xp = eB_p[O + c2];                                              \
+    T_.ym = eB_0[O + c2 - W2];    T_.yp = eB_0[O + c2 + W2];                                         \
+    T_.zm = eB_0[O + z2];         T_.zp = eB_0[O + z2 + 1];                                          \
+    T_.xpyp = eR_p[O + c2 + W2];  T_.xmym = eR_m[O + c2 - W2];                                       \
+    T_.xpym = eR_p[O + c2 - W2];  T_.xmyp = eR_m[O + c2 + W2];                                       \
+    T_.xpzp = eR_p[O + z2 + 1];   T_.xmzm = eR_m[O + z2];                                            \
+    T_.xpzm = eR_p[O + z2];       T_.xmzp = eR_m[O + z2 + 1];                                        \
+    T_.ypzp = eR_0[O + z2 + 1 + W2]; T_.ymzm = eR_0[O + z2 - W2];                                    \
+    T_.ypzm = eR_0[O + z2 + W2];  T_.ymzp = eR_0[O + z2 + 1 - W2];
+    MR_LF_RED(te, 0)
+    MR_LF_RED(tb, OB)
+#undef MR_LF_RED
+    float Se;
+    g = lin_source(tb, eR_0[OB + c2], bscl, sbv, ih2, te, Se) * ih2;
+    return (Se - h2 * (g + rhv - C)) * (1.0f / 6.0f);
+  };
+
+  float X0[NPF], X1[NPF];
+  float SR[2], RR[2], SH[2], RH[2], SBk[2], RBk[2];
+  {
+    float va[NPF];
+    fetch(i0 - 2, va);
+    store(0, va);
+    fetch(i0 - 1, va);
+    store(1, va);
+    fetch(i0, va);
+    store(2, va);
+  }
+  fetch(i0 + 1, X1);   // stored at the end of step 0
+  SR[0] = ld_rs_f(prs(sbR, i0 - 1), o_c);
+  RR[0] = ld_rs_f(prs(rhR, i0 - 1), o_c);
+  SH[0] = has_halo ? ld_rs_f(prs(sbR, i0 - 1), o_h) : 0.0f;
+  RH[0] = has_halo ? ld_rs_f(prs(rhR, i0 - 1), o_h) : 0.0f;
+  SBk[0] = 0.0f;
+  RBk[0] = 0.0f;
+  __syncthreads();
+
+  auto step = [&](auto kc, int u) {
+    constexpr int K = decltype(kc)::value;
+    constexpr int P = K & 1;                                   // parity index of this step
+    constexpr int OM = (K + 0) % 5, O0 = (K + 1) % 5, OP = (K + 2) % 5, OQ = (K + 3) % 5;  // old planes t-1..t+2
+    constexpr int OMM = (K + 4) % 5;                           // old plane t - 2
+    constexpr int N0 = K % 5, NM = (K + 4) % 5, NMM = (K + 3) % 5;   // new red planes t, t - 1, t - 2
+    constexpr int CUR = K & 1, NXT = (K + 1) & 1;
+    if (u >= U) return;
+    const int t = i0 - 1 + u;
+    float(&xf)[NPF] = (K & 1) ? X1 : X0;   // fetched now (plane t + 3)
+    float(&xs)[NPF] = (K & 1) ? X0 : X1;   // fetched last step (plane t + 2), stored at the end
+    if (t + 3 <= i1 + 1) fetch(t + 3, xf);
+    // inputs of the next step: red of plane t + 1 (own, ring), black of plane t
+    if (u + 1 < U) {
+      SR[NXT] = ld_rs_f(prs(sbR, t + 1), o_c);
+      RR[NXT] = ld_rs_f(prs(rhR, t + 1), o_c);
+      if (has_halo) {
+        SH[NXT] = ld_rs_f(prs(sbR, t + 1), o_h);
+        RH[NXT] = ld_rs_f(prs(rhR, t + 1), o_h);
+      }
+      if (t >= i0) {
+        SBk[NXT] = ld_rs_f(prs(sbB, t), o_c);
+        RBk[NXT] = ld_rs_f(prs(rhB, t), o_c);
+      }
+    }
+    // phase A: red cells of plane t
+    {
+      float g;
+      const float v = red_at(std::integral_constant<int, OM>(), std::integral_constant<int, O0>(),
+                             std::integral_constant<int, OP>(), ob2, oz2[P], SR[CUR], RR[CUR], g);
+      lds[ON + N0 * S1 + ob1] = v;
+      if (t >= i0 && t < i1) {
+        st_rs_f(prs(outR, t), o_c, v);
+        accR += (double)(g + RR[CUR]);
+      }
+      if (has_halo) {
+        float gh;
+        lds[ON + N0 * S1 + hb1] = red_at(std::integral_constant<int, OM>(), std::integral_constant<int, O0>(),
+                                         std::integral_constant<int, OP>(), hb2, hz2[P], SH[CUR], RH[CUR], gh);
+      }
+    }
+    __syncthreads();
+    // phase B: black cells of plane t - 1 (own tile); the black row parity at plane t - 1 is that of
+    // the red cells of plane t
+    if (t - 1 >= i0) {
+      const float* nRm = lds + ON + NMM * S1;   // new red, plane t - 2
+      const float* nR0 = lds + ON + NM * S1;    // plane t - 1
+      const float* nRp = lds + ON + N0 * S1;    // plane t
+      const float* eBm = lds + (OMM * 2 + 1) * S2;   // old black, planes t - 2, t - 1, t
+      const float* eB0 = lds + (OM * 2 + 1) * S2;
+      const float* eBp = lds + (O0 * 2 + 1) * S2;
+      const float* bRm = lds + OB + (OMM * 2) * S2;  // base red, planes t - 2, t - 1, t
+      const float* bR0 = lds + OB + (OM * 2) * S2;
+      const float* bRp = lds + OB + (O0 * 2) * S2;
+      const int c2 = ob2, z2 = oz2[P], c1 = ob1, z1 = oz1[P];
+      Nb18f te, tb;
+      te.xm = nRm[c1];       te.xp = nRp[c1];
+      te.ym = nR0[c1 - W1];  te.yp = nR0[c1 + W1];
+      te.zm = nR0[z1];       te.zp = nR0[z1 + 1];
+      tb.xm = bRm[c2];       tb.xp = bRp[c2];
+      tb.ym = bR0[c2 - W2];  tb.yp = bR0[c2 + W2];
+      tb.zm = bR0[z2];       tb.zp = bR0[z2 + 1];
+#define MR_LF_EDGES(T_, O)                                                                           \
+      T_.xpyp = eBp[O + c2 + W2];  T_.xmym = eBm[O + c2 - W2];                                       \
+      T_.xpym = eBp[O + c2 - W2];  T_.xmyp = eBm[O + c2 + W2];                                       \
+      T_.xpzp = eBp[O + z2 + 1];   T_.xmzm = eBm[O + z2];                                            \
+      T_.xpzm = eBp[O + z2];       T_.xmzp = eBm[O + z2 + 1];                                        \
+      T_.ypzp = eB0[O + z2 + 1 + W2]; T_.ymzm = eB0[O + z2 - W2];                                    \
+      T_.ypzm = eB0[O + z2 + W2];  T_.ymzp = eB0[O + z2 + 1 - W2];
+      MR_LF_EDGES(te, 0)
+      MR_LF_EDGES(tb, OB)
+#undef MR_LF_EDGES
+      float Se;
+      const float g = lin_source(tb, eB0[OB + c2], bscl, SBk[CUR], ih2, te, Se) * ih2;
+      st_rs_f(prs(outB, t - 1), o_c, (Se - h2 * (g + RBk[CUR] - C)) * (1.0f / 6.0f));
+      accB += (double)(g + RBk[CUR]);
+    }
+    if (t + 2 <= i1 + 1) store(OQ, xs);
+    __syncthreads();
+  };
+  for (int u0 = 0; u0 < U; u0 += 10) {
+    step(std::integral_constant<int, 0>(), u0);
+    step(std::integral_constant<int, 1>(), u0 + 1);
+    step(std::integral_constant<int, 2>(), u0 + 2);
+    step(std::integral_constant<int, 3>(), u0 + 3);
+    step(std::integral_constant<int, 4>(), u0 + 4);
+    step(std::integral_constant<int, 5>(), u0 + 5);
+    step(std::integral_constant<int, 6>(), u0 + 6);
+    step(std::integral_constant<int, 7>(), u0 + 7);
+    step(std::integral_constant<int, 8>(), u0 + 8);
+    step(std::integral_constant<int, 9>(), u0 + 9);
+  }
+  double vv[2] = {accR, accB};
+  grid_sum<2>(vv, a.partials, a.counter, a.sum_out, nblocks, bid);
 }
 
 }  // namespace mr

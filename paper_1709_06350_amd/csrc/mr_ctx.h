@@ -22,6 +22,8 @@ constexpr int kSlotRes = 32;     // 4 values
 constexpr int kSlotGauge = 36;
 constexpr int kSlotAux = 40;     // 16 values
 constexpr int kSlotLin = 64;     // 3 per level: running sums of the linear (FP32 / adjoint) smoother
+constexpr int kSlotBase = 112;   // 2 values: 2^-s, 2^s of the fixed-point base of the mixed form
+constexpr int kSlotTmax = 114;   // max |theta| (as the bits of a non-negative double; zero between uses)
 constexpr int kSlotCount = 128;
 constexpr int kHostSlots = 80;
 

@@ -115,7 +115,8 @@ struct LinSweepArgs {
   const float* e_in;
   const float* e_red_new;
   float* e_out;
-  const float* base;
+  const int* base;      // fixed-point base potential (value bq[0] * q)
+  const double* bq;     // [0] 2^-s, [1] 2^s of the base's fixed-point scale
   const float* sb;
   const float* rhs;
   int n, colour;
@@ -242,23 +243,57 @@ hipError_t launch_validate(const double* delta, size_t cells, Reduce red, hipStr
 // result[0] = sum of a (size cells).
 hipError_t launch_sum(const double* a, size_t cells, Reduce red, hipStream_t s);
 hipError_t launch_cast32(const double* src, float* dst, size_t cells, hipStream_t s);
+// fixed-point copy q = round(src bq[1]) of an FP64 field (same layout)
+hipError_t launch_quantise(const double* src, int* dst, size_t cells, const double* bq, hipStream_t s);
 hipError_t launch_widen64(const float* src, double* dst, size_t cells, hipStream_t s);
-hipError_t launch_lin_residual(const float* e, const float* base, const float* sb, const float* rhs, int n, double h,
+hipError_t launch_lin_residual(const float* e, const int* baseq, const double* bq, const float* sb, const float* rhs,
+                               int n, double h,
                                double cshift, double* r_out, hipStream_t s);
 
 // ---- mixed precision (FP32 linearised multigrid) ----
+// One-launch FP32 sweep schedule: tile tm x tj of (m, j), nchunks equal chunks of planes.
+struct LinFusedCfg {
+  int tm = 0, tj = 0, nchunks = 0;
+};
+struct LinFusedArgs {
+  const float* e_in;     // both colours of the snapshot
+  float* e_out;          // both colours of the result (must not alias e_in)
+  const int* base;       // fixed-point base potential
+  const double* bq;      // its scale: [0] 2^-s
+  const float* sb;       // base root, both colours
+  const float* rhs;      // right-hand side, both colours
+  int n;
+  float h2, ih2;
+  const double* c_sum;   // running sums (red, black) of g + rhs of the previous sweep, or null
+  double c_scale, c_add;
+  double* sum_out;       // receives (red sum, black sum) of this sweep
+  double* partials;
+  unsigned int* counter;
+  int tiles_j, tiles_m, nchunks;
+};
+
+bool lin_fused_supported(int tm, int tj);
+hipError_t launch_lin_fused(const LinFusedArgs& a, const LinFusedCfg& t, hipStream_t s);
 bool lin_tile_supported(int tm, int tj);
 hipError_t launch_lin_half_sweep(const LinSweepArgs& a, const TileCfg& t, hipStream_t s);
-hipError_t launch_mixed_resid64(const double* theta, const double* delta, int n, ShiftRef C, float* rhs32, float* base32,
+hipError_t launch_mixed_resid64(const double* theta, const double* delta, int n, ShiftRef C, float* rhs32, int* baseq,
+                                const double* bq,
                                 float* sb32, Reduce red, hipStream_t s);
-hipError_t launch_base_root(const float* base32, const double* delta, int n, double h, float* sb32, hipStream_t s);
-hipError_t launch_restrict32(const float* fine, float* coarse, int n, hipStream_t s);
-hipError_t launch_lin_resid_restrict(const float* e, const float* base, const float* sb, const float* rhs, int n, double h,
+hipError_t launch_base_root(const int* baseq, const double* bq, const double* delta, int n, double h, float* sb32,
+                            hipStream_t s);
+hipError_t launch_restrictq(const int* fine, int* coarse, int n, hipStream_t s);
+// max |a| over cells into *tmax (atomic maximum on its bits; *tmax must start at or below it).
+hipError_t launch_absmax(const double* a, size_t cells, double* tmax, hipStream_t s);
+// bq[0] = 2^-s, bq[1] = 2^s for max |theta| = *tmax; returns *tmax to zero.
+hipError_t launch_base_scale(double* tmax, double* bq, hipStream_t s);
+hipError_t launch_lin_resid_restrict(const float* e, const int* baseq, const double* bq, const float* sb, const float* rhs,
+                                     int n, double h,
                                      ShiftRef c, float* rhs_c, Reduce red, hipStream_t s);
 hipError_t launch_prolong_add32(const float* ec, float* e, int n, hipStream_t s);
-hipError_t launch_lin_coarsest(float* e, const float* base, const float* sb, const float* rhs, int n, int nsweeps, double h,
+hipError_t launch_lin_coarsest(float* e, const int* baseq, const double* bq, const float* sb, const float* rhs, int n,
+                               int nsweeps, double h,
                                const double* c_sum, double c_scale, hipStream_t s);
-hipError_t launch_update64(double* theta, const float* e, size_t cells, hipStream_t s);
+hipError_t launch_update64(double* theta, const float* e, size_t cells, double* tmax, hipStream_t s);
 hipError_t launch_fill32(float* a, float v, size_t cells, hipStream_t s);
 
 }  // namespace mr

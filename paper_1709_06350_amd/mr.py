@@ -48,7 +48,7 @@ EXPORTED = [
     "mr_deposit", "mr_deposit_cic", "mr_lagrangian", "mr_residual", "mr_solve", "mr_solve_anderson", "mr_adjoint_solve", "mr_adjoint_solve_anderson", "mr_solve_batched",
     "mr_tune_lin_tiles",
     "mr_sweep", "mr_defect_restrict", "mr_tau_rhs", "mr_prolong_correct", "mr_restrict",
-    "mr_lin_residual", "mr_lin_defect_restrict", "mr_lin_vcycles",
+    "mr_lin_residual", "mr_lin_defect_restrict", "mr_lin_vcycles", "mr_lin_sweep",
     "mr_timing_enable", "mr_timing_read", "mr_hbm_stream", "mr_residual_noalloc", "mr_last_error",
 ]
 
@@ -141,6 +141,8 @@ def load(path: Optional[str] = None):
     lib.mr_lin_residual.argtypes = [vp, ip, ctypes.c_double, vp, vp, vp, vp, ctypes.c_double, vp]
     lib.mr_lin_defect_restrict.argtypes = [vp, ip, ctypes.c_double, vp, vp, vp, vp, ctypes.c_double, vp]
     lib.mr_lin_vcycles.argtypes = [vp, vp, vp, vp, ip, vp]
+    lib.mr_lin_sweep.argtypes = [vp, ip, ctypes.c_double, vp, vp, vp, vp, ctypes.c_double,
+                                 ctypes.POINTER(ctypes.c_int), vp]
     lib.mr_timing_enable.argtypes = [vp, ip]
     lib.mr_timing_read.argtypes = [vp, ctypes.POINTER(mr_timing)]
     lib.mr_hbm_stream.argtypes = [ip, ip, vp, vp, vp, ctypes.c_size_t, ip, vp, ctypes.POINTER(ctypes.c_float)]
@@ -400,6 +402,17 @@ class Context:
         out = self._empty(nl // 2)
         _check(self.lib.mr_lin_defect_restrict(self.h, nl, h, _ptr(delta), _ptr(theta_base), _ptr(e), _ptr(rhs),
                                                cshift, _ptr(out)))
+        return out
+
+    def lin_sweep(self, delta, theta_base, e_in, h=1.0, rhs=None, cshift=0.0, sched=None):
+        """mr_lin_sweep: one red-black sweep of the FP32 inner smoother; sched = (kind, tm, tj, nchunks)."""
+        nl = e_in.shape[0]
+        for t, what in ((delta, "delta"), (theta_base, "theta_base"), (e_in, "e_in"), (rhs, "rhs")):
+            _need(t, nl ** 3, what)
+        out = self._empty(nl)
+        sp = None if sched is None else (ctypes.c_int * 4)(*sched)
+        _check(self.lib.mr_lin_sweep(self.h, nl, h, _ptr(delta), _ptr(theta_base), _ptr(e_in), _ptr(rhs), cshift,
+                                     sp, _ptr(out)))
         return out
 
     def lin_vcycles(self, delta, theta_base, rhs, ncycles=1):

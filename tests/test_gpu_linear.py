@@ -60,14 +60,28 @@ def test_lin_residual_matches_oracle_jacobian(ctx, n, h):
     # with cshift = <dSigma(e)> and no rhs the building block returns -J_p e
     got = host(ctx.lin_residual(dev(delta), dev(theta), dev(e), h=h, cshift=float(dS.mean())))
     ref = -olin.jacobian_apply(theta, delta, e, h)
-    err = np.max(np.abs(got - ref))
-    assert err <= TOL32 * np.abs(ref).max(), f"max abs diff {err:.3e} (scale {np.abs(ref).max():.3e})"
+    err, scale = float(np.max(np.abs(got - ref))), float(np.abs(ref).max())
+    assert err <= TOL32 * scale, f"max abs diff {err:.3e} (scale {scale:.3e})"
     # with a right-hand side and an arbitrary shift
     C = 0.037
     got = host(ctx.lin_residual(dev(delta), dev(theta), dev(e), h=h, rhs=dev(rhs), cshift=C))
     ref = rhs + dS - oop.laplacian(e, h) - C
-    err = np.max(np.abs(got - ref))
-    assert err <= TOL32 * np.abs(ref).max(), f"max abs diff {err:.3e}"
+    err, scale = float(np.max(np.abs(got - ref))), float(np.abs(ref).max())
+    assert err <= TOL32 * scale, f"max abs diff {err:.3e} (scale {scale:.3e})"
+
+
+@pytest.mark.parametrize("offset", [1500.0, -4096.0])
+def test_lin_residual_with_a_large_base_potential(ctx, offset):
+    """The Jacobian ignores a constant in the base potential, and potentials of a 512^3 mesh reach
+    |theta| ~ 10^3 cells^2: the base must keep its second differences exact at that magnitude (an FP32
+    copy would round theta to ~1e-4 there and miss the oracle by ~1e-3)."""
+    n = 32
+    delta, theta, e, _ = _state(n, 650)
+    dS = _dsigma(theta, delta, e, 1.0)
+    got = host(ctx.lin_residual(dev(delta), dev(theta + offset), dev(e), h=1.0, cshift=float(dS.mean())))
+    ref = -olin.jacobian_apply(theta, delta, e, 1.0)
+    err, scale = float(np.max(np.abs(got - ref))), float(np.abs(ref).max())
+    assert err <= TOL32 * scale, f"max abs diff {err:.3e} (scale {scale:.3e})"
 
 
 def test_lin_residual_on_coarse_levels(ctx):
@@ -83,8 +97,8 @@ def test_lin_residual_on_coarse_levels(ctx):
         dS = _dsigma(th, de, e, h)
         got = host(ctx.lin_residual(dev(de), dev(th), dev(e), h=h, cshift=float(dS.mean())))
         ref = -olin.jacobian_apply(th, de, e, h)
-        err = np.max(np.abs(got - ref))
-        assert err <= TOL32 * np.abs(ref).max(), f"level {level}: max abs diff {err:.3e}"
+        err, scale = float(np.max(np.abs(got - ref))), float(np.abs(ref).max())
+        assert err <= TOL32 * scale, f"level {level}: max abs diff {err:.3e} (scale {scale:.3e})"
 
 
 @pytest.mark.parametrize("n,h", [(16, 1.0), (64, 1.0), (128, 1.0), (32, 2.0)])
@@ -95,8 +109,8 @@ def test_lin_defect_restrict_matches_oracle(ctx, n, h):
     C = float(dS.mean() + rhs.mean())
     got = host(ctx.lin_defect_restrict(dev(delta), dev(theta), dev(e), h=h, rhs=dev(rhs), cshift=C))
     ref = omg.restrict(rhs - rhs.mean() - olin.jacobian_apply(theta, delta, e, h))
-    err = np.max(np.abs(got - ref))
-    assert err <= TOL32 * np.abs(ref).max(), f"max abs diff {err:.3e} (scale {np.abs(ref).max():.3e})"
+    err, scale = float(np.max(np.abs(got - ref))), float(np.abs(ref).max())
+    assert err <= TOL32 * scale, f"max abs diff {err:.3e} (scale {scale:.3e})"
 
 
 def _bordered_solve(theta, delta, b):
@@ -129,3 +143,47 @@ def test_inner_vcycles_contract_to_the_oracle_solution():
     for a, z in zip(errs, errs[1:]):
         assert z < a or a < 1e-4, f"not contracting: {errs}"
     assert errs[-1] < 1e-4, errs
+    # the same solve with the base shifted by a constant (the Jacobian does not change)
+    with mr.Context(n, precision=mr.PREC_MIXED) as c:
+        e = host(c.lin_vcycles(dev(delta), dev(theta + 3000.0), dev(b), ncycles=8))
+    e -= e.mean()
+    assert np.linalg.norm(e - estar) / np.linalg.norm(estar) < 1e-4
+
+
+def _lin_sweep_ref(theta, delta, e, h, rhs, C):
+    """One red-black sweep of the linear level equation lap(e) - dSigma(e) = rhs - C with the oracle's
+    linearisation, snapshot semantics within a colour, red ((i + j + k) even) first."""
+    red = omg.red_mask(e.shape[0])
+    for mask in (red, ~red):
+        upd = e + (h * h / 6.0) * ((oop.laplacian(e, h) - _dsigma(theta, delta, e, h)) - (rhs - C))
+        e = np.where(mask, upd, e)
+    return e
+
+
+def _fused_schedules(n):
+    out = []
+    for tm, tj in ((32, 16), (64, 8), (64, 16), (16, 16), (32, 8), (16, 8), (8, 8), (4, 8)):
+        if (n // 2) % tm or n % tj:
+            continue
+        for ci in (2, 4, 8, 16, 32, 64, 128, 256):
+            if ci <= n and n % ci == 0 and (n // tj) * (n // 2 // tm) * (n // ci) <= 16384:
+                out.append((mr.MR_SCHED_FUSED, tm, tj, n // ci))
+    return out
+
+
+@pytest.mark.parametrize("n,h", [(32, 1.0), (64, 1.0), (64, 2.0)])
+def test_lin_sweep_all_schedules_match_oracle(ctx, n, h):
+    """Every one-launch tile and chunking the tuner may pick, and the two-launch kernels, against the
+    oracle's sweep of the linearised level equation (FP32 tolerance)."""
+    delta, theta, e, rhs = _state(n, 800 + n)
+    C = 0.021
+    ref = _lin_sweep_ref(theta, delta, e, h, rhs, C)
+    scale = float(np.abs(ref).max())
+    scheds = _fused_schedules(n) + [(mr.MR_SCHED_PIPELINED, 16, 16, n // 16), (mr.MR_SCHED_PIPELINED, 8, 16, n // 8),
+                                    (mr.MR_SCHED_TILED, 4, 8, n // 16)]
+    assert len(scheds) >= 10
+    for sc in scheds:
+        announce(f"lin_sweep n={n} h={h} schedule={sc}")
+        got = host(ctx.lin_sweep(dev(delta), dev(theta), dev(e), h=h, rhs=dev(rhs), cshift=C, sched=sc))
+        err = float(np.max(np.abs(got - ref)))
+        assert err <= TOL32 * scale, f"schedule {sc}: max abs diff {err:.3e} (scale {scale:.3e})"
