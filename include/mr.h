@@ -87,14 +87,18 @@ typedef struct {
  * fixed point is the same as with red-black.
  * MR_FLAG_ANDERSON (mr_solve_batched only): mix each box's outer iterations as mr_solve_anderson
  * does, with depth 2 (the state stays on the device, inside the replayed graph); not in the paper,
- * same solutions. */
+ * same solutions.
+ * MR_FLAG_PLAIN_INNER (mr_solve at MR_PREC_MIXED): the inner solve of each outer step is
+ * inner_cycles plain linear V-cycles instead of flexible GMRES with inner_cycles V-cycles as the
+ * preconditioner (the default; mr_solve_anderson at MR_PREC_MIXED always uses plain cycles). */
 enum {
   MR_FLAG_EAGER = 1,
   MR_FLAG_TWO_PASS = 2,
   MR_FLAG_ADJ_ROWS = 4,
   MR_FLAG_ADJ_TILED = 8,
   MR_FLAG_ORDER4 = 16,
-  MR_FLAG_ANDERSON = 32
+  MR_FLAG_ANDERSON = 32,
+  MR_FLAG_PLAIN_INNER = 64
 };
 
 /* Per-solve report. history[c] is the relative residual after cycle c (history[0] = start). */

@@ -100,6 +100,50 @@ __global__ void __launch_bounds__(TM * TJ) lin_sweep_pipe(LinSweepArgs a) {
   lin_sweep_pipe_body<TM, TJ, COL>(a, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x, gridDim.x, lds);
 }
 
+template <int TM, int TJ, int COL>
+__global__ void __launch_bounds__(TM * TJ) lin_apply_pipe(LinSweepArgs a) {
+  __shared__ float lds[LinTile<TM, TJ>::LDS];
+  lin_sweep_pipe_body<TM, TJ, COL, true>(a, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x, gridDim.x, lds);
+}
+
+// (J z)_c = nabla^2 z - dSigma(z) at every cell (rows of the mesh dealt to blocks), FP32.
+__global__ void __launch_bounds__(256) lin_apply_row_kernel(const float* __restrict__ z, const int* __restrict__ baseq,
+    const double* __restrict__ bq, const float* __restrict__ sb, int n, float ih2, float* __restrict__ w) {
+  const float* __restrict__ base = reinterpret_cast<const float*>(baseq);
+  const float bscl = (float)bq[0];
+  for (int row = blockIdx.x; row < n * n; row += gridDim.x) {
+    const int i = row / n, j = row - i * n;
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+      const unsigned g = split_idx(n, i, j, k);
+      Nb18f te, tb;
+      gather18_split_t(z, n, i, j, k, te);
+      gather18_split_t(base, n, i, j, k, tb);
+      float Se;
+      const float src = lin_source(tb, base[g], bscl, sb[g], ih2, te, Se) * ih2;
+      w[g] = (Se - 6.0f * z[g]) * ih2 - src;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) kry_dots_kernel(const float* __restrict__ w, KryPtrs v, int k, size_t cells,
+                                                       double* partials, unsigned* counter, double* result) {
+  kry_dots_body(w, v, k, cells, partials, counter, result, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(256) kry_orth_kernel(const float* __restrict__ w, KryPtrs v, KryCoef c, int k,
+                                                       size_t cells, float* __restrict__ out) {
+  kry_orth_body(w, v, c, k, cells, out, blockIdx.x, gridDim.x);
+}
+
+__global__ void __launch_bounds__(256) kry_update_kernel(double* __restrict__ theta, KryPtrs z, KryCoef y, int m,
+                                                         size_t cells, double* tmax) {
+  kry_update_body(theta, z, y, m, cells, tmax, blockIdx.x, gridDim.x);
+}
+
+__global__ void zero_scalars_kernel(double* p, int count) {
+  if ((int)threadIdx.x < count) p[threadIdx.x] = 0.0;
+}
+
 // Compiled tile shapes of the one-launch FP32 sweep.
 #define MR_LF_TILES(X) X(32, 16) X(64, 8) X(64, 16) X(16, 16) X(32, 8) X(16, 8) X(8, 8) X(4, 8)
 
@@ -316,6 +360,37 @@ hipError_t launch_lin_fused(const LinFusedArgs& a, const LinFusedCfg& t, hipStre
   return hipErrorInvalidValue;
 }
 
+// w = J z on an n^3 mesh (both colours): the pipelined kernel on tile t when it is pipelined and
+// compiled, otherwise the row kernel.
+hipError_t launch_lin_apply(const float* z, const int* baseq, const double* bq, const float* sb, int n, double h, float* w,
+                            const TileCfg& t, hipStream_t s) {
+  if (t.pipe && lin_tile_supported(t.tm, t.tj) && t.ci % 4 == 0 && t.tj * t.tiles_j == n && t.tm * t.tiles_m == n / 2) {
+    LinSweepArgs a{};
+    a.e_in = z;
+    a.e_out = w;
+    a.base = baseq;
+    a.bq = bq;
+    a.sb = sb;
+    a.n = n;
+    a.ih2 = (float)(1.0 / (h * h));
+    a.tiles_j = t.tiles_j;
+    a.tiles_m = t.tiles_m;
+    a.ci = t.ci;
+    const int blocks = t.tiles_j * t.tiles_m * (n / t.ci);
+#define MR_LA_LAUNCH(TM, TJ)                                                                             \
+    if (t.tm == TM && t.tj == TJ) {                                                                      \
+      hipLaunchKernelGGL((lin_apply_pipe<TM, TJ, 0>), dim3(blocks), dim3(TM * TJ), 0, s, a);            \
+      hipLaunchKernelGGL((lin_apply_pipe<TM, TJ, 1>), dim3(blocks), dim3(TM * TJ), 0, s, a);            \
+      return hipGetLastError();                                                                          \
+    }
+    MR_LIN_TILES(MR_LA_LAUNCH)
+#undef MR_LA_LAUNCH
+  }
+  hipLaunchKernelGGL(lin_apply_row_kernel, dim3(rows_blocks(n)), dim3(row_threads(n)), 0, s, z, baseq, bq, sb, n,
+                     (float)(1.0 / (h * h)), w);
+  return hipGetLastError();
+}
+
 hipError_t launch_mixed_resid64(const double* theta, const double* delta, int n, ShiftRef C, float* rhs32, int* baseq,
                                 const double* bq, float* sb32, Reduce red, hipStream_t s) {
   int tm = 0, tj = 0, nch = 0;
@@ -447,9 +522,22 @@ struct LinLevel {
   LinFusedCfg fz;
 };
 
+// Krylov space of the inner solve on the finest mesh: V[0..m] orthonormal mean-free vectors,
+// Z[0..m-1] their preconditioned images, W the operator's product, S a spare e buffer, and the
+// reduction buffers of the dot products.
+struct KryState {
+  int m = 0;
+  std::vector<float*> V, Z;
+  float *W = nullptr, *S = nullptr;
+  double *partials = nullptr, *result = nullptr;
+  unsigned* counter = nullptr;
+};
+
 struct MixedState {
   std::vector<LinLevel> lv;
   std::vector<void*> owned;
+  KryState kry;
+  std::vector<void*> kry_owned;
 };
 
 static TileCfg lin_tiles(int n) {
@@ -623,6 +711,7 @@ void Ctx::release_extra() {
   }
   if (mixed) {
     for (void* p : mixed->owned) (void)hipFree(p);
+    for (void* p : mixed->kry_owned) (void)hipFree(p);
     delete mixed;
     mixed = nullptr;
   }
@@ -776,6 +865,158 @@ int Ctx::lin_vcycles_split(const double* theta_split, const double* rhs_split, i
   return MR_OK;
 }
 
+// Krylov storage for a space of m vectors (kept with the context, grown on demand).
+static int kry_reserve(Ctx* c, int m) {
+  MixedState& ms = *c->mixed;
+  KryState& k = ms.kry;
+  if (k.m >= m) return MR_OK;
+  for (void* p : ms.kry_owned) (void)hipFree(p);
+  ms.kry_owned.clear();
+  k = KryState{};
+  const size_t bytes = c->lv[0].cells * sizeof(float);
+  auto get = [&](size_t b) -> void* {
+    void* p = nullptr;
+    if (hipMalloc(&p, b) != hipSuccess) return nullptr;
+    ms.kry_owned.push_back(p);
+    return p;
+  };
+  for (int i = 0; i <= m; ++i) k.V.push_back((float*)get(bytes));
+  for (int i = 0; i < m; ++i) k.Z.push_back((float*)get(bytes));
+  k.W = (float*)get(bytes);
+  k.S = (float*)get(bytes);
+  k.partials = (double*)get((size_t)kKryBlocks * kKryNV * sizeof(double));
+  k.result = (double*)get(kKryNV * sizeof(double));
+  k.counter = (unsigned*)get(64 * sizeof(unsigned));
+  bool ok = k.W && k.S && k.partials && k.result && k.counter;
+  for (float* p : k.V) ok = ok && p;
+  for (float* p : k.Z) ok = ok && p;
+  if (!ok || hipMemsetAsync(k.counter, 0, 64 * sizeof(unsigned), c->stream) != hipSuccess) {
+    for (void* p : ms.kry_owned) (void)hipFree(p);
+    ms.kry_owned.clear();
+    k = KryState{};
+    return fail(MR_ENOMEM, "Krylov space of %d vectors: allocation failed", m);
+  }
+  k.m = m;
+  return MR_OK;
+}
+
+// Least squares min |beta e_1 - H y| for the (k + 1) x k upper Hessenberg H (row-major, ld kKryMax + 1
+// columns... stored as h[row][col]) by Givens rotations; returns y.
+static void hessenberg_ls(std::vector<std::vector<double>> H, double beta, int k, std::vector<double>& y) {
+  std::vector<double> g(k + 1, 0.0);
+  g[0] = beta;
+  for (int i = 0; i < k; ++i) {
+    const double a = H[i][i], b = H[i + 1][i];
+    const double r = std::hypot(a, b);
+    const double cs = r > 0.0 ? a / r : 1.0, sn = r > 0.0 ? b / r : 0.0;
+    for (int j = i; j < k; ++j) {
+      const double u = H[i][j], v = H[i + 1][j];
+      H[i][j] = cs * u + sn * v;
+      H[i + 1][j] = -sn * u + cs * v;
+    }
+    const double u = g[i], v = g[i + 1];
+    g[i] = cs * u + sn * v;
+    g[i + 1] = -sn * u + cs * v;
+  }
+  y.assign(k, 0.0);
+  for (int i = k - 1; i >= 0; --i) {
+    double s = g[i];
+    for (int j = i + 1; j < k; ++j) s -= H[i][j] * y[j];
+    y[i] = H[i][i] != 0.0 ? s / H[i][i] : 0.0;
+  }
+}
+
+// One inner solve of the mixed outer step by flexible GMRES(m) on J_p e = rhs (rhs in the level-0
+// rhs buffer, FP32; rhs_sum and rhs_sq the sums of its FP64 values), preconditioned by one linear
+// V-cycle per iteration, from e = 0; then theta64 += e (and max |theta| into kSlotTmax). The
+// Krylov vectors are mean-free: J_p maps onto mean-free fields and annihilates constants, so the
+// mean of the right-hand side is removed and the Gram-Schmidt step removes the mean of J z.
+int Ctx::kry_step(double* theta64, int m, double rhs_sum, double rhs_sq) {
+  int rc = kry_reserve(this, m);
+  if (rc != MR_OK) return rc;
+  LinLevel& M0 = mixed->lv[0];
+  KryState& K = mixed->kry;
+  const size_t cells = lv[0].cells;
+  const double N = (double)cells;
+  const double mean_b = rhs_sum / N;
+  const double beta2 = rhs_sq - rhs_sum * rhs_sum / N;
+  const double beta = std::sqrt(beta2 > 0.0 ? beta2 : 0.0);
+  if (!(beta > 0.0)) return MR_OK;   // nothing to correct
+  const int nb = (int)std::min<size_t>((cells + 255) / 256, (size_t)kKryBlocks);
+  const int nbu = lin_blocks(cells);
+  KryPtrs vp{}, zp{};
+  KryCoef cf{};
+  cf.c[0] = mean_b;
+  cf.c[1] = 1.0 / beta;
+  hipLaunchKernelGGL(kry_orth_kernel, dim3(nbu), dim3(256), 0, stream, (const float*)M0.rhs, vp, cf, 0, cells, K.V[0]);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "Krylov start");
+  float* rhs_own = M0.rhs;
+  float* e_own[2] = {M0.e[0], M0.e[1]};
+  std::vector<std::vector<double>> H(m + 1, std::vector<double>(m, 0.0));
+  int k = 0;
+  for (int i = 0; i < m; ++i) {
+    // z_i = one V-cycle on J_p z = v_i from z = 0 (v_i is mean-free: the level-0 shift starts at 0)
+    M0.rhs = K.V[i];
+    M0.e[0] = K.Z[i];
+    M0.e[1] = K.S;
+    M0.cur = 0;
+    hipLaunchKernelGGL(zero_scalars_kernel, dim3(1), dim3(64), 0, stream, linsum(0), 2);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = launch_fill32(K.Z[i], 0.0f, cells, stream);
+    if (e != hipSuccess) rc = hip_fail(e, "Krylov cycle start");
+    if (rc == MR_OK) rc = lin_vcycle(0);
+    if (rc == MR_OK && M0.cur == 1) std::swap(K.Z[i], K.S);   // the result ended in the spare buffer
+    M0.rhs = rhs_own;
+    M0.e[0] = e_own[0];
+    M0.e[1] = e_own[1];
+    if (rc != MR_OK) return rc;
+    // w = J z_i, then its projections on v_0 .. v_i, its sum and its square
+    e = launch_lin_apply(K.Z[i], M0.base, scal + kSlotBase, M0.sb, lv[0].n, lv[0].h, K.W, M0.sw, stream);
+    for (int j = 0; j <= i; ++j) vp.p[j] = K.V[j];
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(kry_dots_kernel, dim3(nb), dim3(256), 0, stream, (const float*)K.W, vp, i + 1, cells, K.partials,
+                         K.counter, K.result);
+      e = hipGetLastError();
+    }
+    double d[kKryNV];
+    if (e == hipSuccess) e = hipMemcpyAsync(d, K.result, sizeof d, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "Krylov dot products");
+    const double mean_w = d[kKryMax] / N;
+    double hh = d[kKryMax + 1] - N * mean_w * mean_w;
+    for (int j = 0; j <= i; ++j) {
+      H[j][i] = d[j];
+      hh -= d[j] * d[j];
+    }
+    const double hn = std::sqrt(hh > 0.0 ? hh : 0.0);
+    H[i + 1][i] = hn;
+    k = i + 1;
+    // the space is exhausted (or the next vector would be rounding noise): stop here
+    if (hn <= 1e-6 * std::sqrt(d[kKryMax + 1] > 0.0 ? d[kKryMax + 1] : 0.0) || i + 1 == m) break;
+    for (int j = 0; j <= i; ++j) cf.c[j] = d[j];
+    cf.c[i + 1] = mean_w;
+    cf.c[i + 2] = 1.0 / hn;
+    hipLaunchKernelGGL(kry_orth_kernel, dim3(nbu), dim3(256), 0, stream, (const float*)K.W, vp, cf, i + 1, cells,
+                       K.V[i + 1]);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "Krylov orthogonalisation");
+  }
+  std::vector<double> y;
+  std::vector<std::vector<double>> Hk(k + 1, std::vector<double>(k, 0.0));
+  for (int r = 0; r <= k; ++r)
+    for (int c2 = 0; c2 < k; ++c2) Hk[r][c2] = H[r][c2];
+  hessenberg_ls(Hk, beta, k, y);
+  KryPtrs zz{};
+  KryCoef yy{};
+  for (int j = 0; j < k; ++j) {
+    zz.p[j] = K.Z[j];
+    yy.c[j] = y[j];
+  }
+  hipLaunchKernelGGL(kry_update_kernel, dim3(nbu), dim3(256), 0, stream, theta64, zz, yy, k, cells, scal + kSlotTmax);
+  e = hipGetLastError();
+  return e == hipSuccess ? MR_OK : hip_fail(e, "Krylov update");
+}
+
 int Ctx::solve_mixed(const double* delta, double* theta, mr_info* info, int aa_depth) {
   auto t0 = std::chrono::steady_clock::now();
   int rc = mixed_alloc(this);
@@ -822,6 +1063,12 @@ int Ctx::solve_mixed(const double* delta, double* theta, mr_info* info, int aa_d
     if (rel < best) best = rel;
     if (rel <= opts.tol || it >= opts.max_cycles) break;
     if ((rc = lin_base_hierarchy()) != MR_OK) return rc;
+    if (aa_depth == 0 && !(opts.flags & MR_FLAG_PLAIN_INNER)) {
+      // Krylov-accelerated inner solve; the rhs -b has sum -r[2] and square sum r[3]
+      if ((rc = kry_step(L0.th[0], opts.inner_cycles, -r[2], r[3])) != MR_OK) return rc;
+      ++it;
+      continue;
+    }
     // inner solve from e = 0; the shift starts at <rhs> = -<b>
     hipLaunchKernelGGL(inner_shift_kernel, dim3(1), dim3(64), 0, stream, (const double*)(scal + kSlotRes), linsum(0));
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "inner shift");

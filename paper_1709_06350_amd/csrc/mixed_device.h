@@ -574,7 +574,9 @@ inline __device__ void fill32_body(float* __restrict__ a, float v, size_t cells,
 // lin_sweep_body's decomposition and arithmetic with the colour compile-time and the plane loop
 // unrolled by the ring length (compile-time LDS slots); planes are fetched two steps before they
 // enter LDS and the base root / right-hand side two steps before use. Requires ci % 4 == 0.
-template <int TM, int TJ, int COL>
+// With APPLY the body instead writes the operator itself, (J e)_c = nabla^2 e - dSigma(e) at the
+// cells of colour COL (e_in holds both colours of e; rhs and the sums are not used).
+template <int TM, int TJ, int COL, bool APPLY = false>
 __device__ void lin_sweep_pipe_body(const LinSweepArgs& a, int logical, int bid, int nblocks, float* lds) {
   constexpr int NT = TM * TJ;
   constexpr int RW = TM + 2;
@@ -591,8 +593,8 @@ __device__ void lin_sweep_pipe_body(const LinSweepArgs& a, int logical, int bid,
   const size_t plane = (size_t)n * nh;
   const size_t half = plane * n;
   const unsigned pbytes = (unsigned)plane * 4u;
-  const float* __restrict__ f0 = COL == 1 ? a.e_red_new : a.e_in;   // e red
-  const float* __restrict__ f1 = a.e_in + half;                      // e black
+  const float* __restrict__ f0 = COL == 1 && !APPLY ? a.e_red_new : a.e_in;   // e red
+  const float* __restrict__ f1 = a.e_in + half;                                 // e black
   const float* __restrict__ f2 = reinterpret_cast<const float*>(a.base);          // base red (fixed-point bits)
   const float* __restrict__ f3 = reinterpret_cast<const float*>(a.base) + half;   // base black
   // global accesses through a buffer resource of one plane (uniform) and a per-lane byte offset
@@ -657,10 +659,12 @@ __device__ void lin_sweep_pipe_body(const LinSweepArgs& a, int logical, int bid,
     store(2, vc);
   }
   fetch(3, V0);
-  SB[0] = ld_rs_f(prs(sbc, i0), o_c);
-  RH[0] = ld_rs_f(prs(rc, i0), o_c);
-  SB[1] = ld_rs_f(prs(sbc, min(i0 + 1, last_plane)), o_c);
-  RH[1] = ld_rs_f(prs(rc, min(i0 + 1, last_plane)), o_c);
+  SB[0] = ld_rs_f_nt(prs(sbc, i0), o_c);
+  SB[1] = ld_rs_f_nt(prs(sbc, min(i0 + 1, last_plane)), o_c);
+  if (!APPLY) {
+    RH[0] = ld_rs_f_nt(prs(rc, i0), o_c);
+    RH[1] = ld_rs_f_nt(prs(rc, min(i0 + 1, last_plane)), o_c);
+  }
   __syncthreads();
 
   auto step = [&](auto kc, int t, float (&vst)[NPF], float (&vft)[NPF]) {
@@ -668,8 +672,8 @@ __device__ void lin_sweep_pipe_body(const LinSweepArgs& a, int logical, int bid,
     constexpr int SM = K & 3, S0 = (K + 1) & 3, SP = (K + 2) & 3, SN = (K + 3) & 3;
     fetch(t + 4, vft);
     const int pn = min(i0 + t + 2, last_plane);
-    SB[(K + 2) & 3] = ld_rs_f(prs(sbc, pn), o_c);
-    RH[(K + 2) & 3] = ld_rs_f(prs(rc, pn), o_c);
+    SB[(K + 2) & 3] = ld_rs_f_nt(prs(sbc, pn), o_c);
+    if (!APPLY) RH[(K + 2) & 3] = ld_rs_f_nt(prs(rc, pn), o_c);
     const int oq = (K & 1) ? oq1 : oq0;
     Nb18f te, tb;
 #define MR_LP_GATHER(T, LO, LC)                                                        \
@@ -691,9 +695,14 @@ __device__ void lin_sweep_pipe_body(const LinSweepArgs& a, int logical, int bid,
 #undef MR_LP_GATHER
     float Se;
     const float g = lin_source(tb, lds[(2 + COL) * 4 * SLOT + S0 * SLOT + ob], bscl, SB[K], ih2, te, Se) * ih2;
-    const float rhs = RH[K];
-    st_rs_f(prs(out, i0 + t), o_c, (Se - h2 * (g + rhs - C)) * (1.0f / 6.0f));
-    acc += (double)(g + rhs);
+    if (APPLY) {
+      const float ec = lds[COL * 4 * SLOT + S0 * SLOT + ob];
+      st_rs_f_nt(prs(out, i0 + t), o_c, (Se - 6.0f * ec) * ih2 - g);
+    } else {
+      const float rhs = RH[K];
+      st_rs_f_nt(prs(out, i0 + t), o_c, (Se - h2 * (g + rhs - C)) * (1.0f / 6.0f));
+      acc += (double)(g + rhs);
+    }
     store(SN, vst);
     __syncthreads();
   };
@@ -703,6 +712,7 @@ __device__ void lin_sweep_pipe_body(const LinSweepArgs& a, int logical, int bid,
     step(std::integral_constant<int, 2>(), t + 2, V0, V1);
     step(std::integral_constant<int, 3>(), t + 3, V1, V0);
   }
+  if (APPLY) return;
   double vv[1] = {acc};
   const bool last = grid_sum<1>(vv, a.partials, a.counter, a.sum_out, nblocks, bid);
   if (last && tid == 0 && a.copy_to) *a.copy_to = *a.copy_from;
@@ -1213,15 +1223,15 @@ __device__ void lin_fused_body(const LinFusedArgs& a, int logical, int bid, int 
     if (t + 3 <= i1 + 1) fetch(t + 3, xf);
     // inputs of the next step: red of plane t + 1 (own, ring), black of plane t
     if (u + 1 < U) {
-      SR[NXT] = ld_rs_f(prs(sbR, t + 1), o_c);
-      RR[NXT] = ld_rs_f(prs(rhR, t + 1), o_c);
+      SR[NXT] = ld_rs_f_nt(prs(sbR, t + 1), o_c);
+      RR[NXT] = ld_rs_f_nt(prs(rhR, t + 1), o_c);
       if (has_halo) {
         SH[NXT] = ld_rs_f(prs(sbR, t + 1), o_h);
         RH[NXT] = ld_rs_f(prs(rhR, t + 1), o_h);
       }
       if (t >= i0) {
-        SBk[NXT] = ld_rs_f(prs(sbB, t), o_c);
-        RBk[NXT] = ld_rs_f(prs(rhB, t), o_c);
+        SBk[NXT] = ld_rs_f_nt(prs(sbB, t), o_c);
+        RBk[NXT] = ld_rs_f_nt(prs(rhB, t), o_c);
       }
     }
     // phase A: red cells of plane t
@@ -1231,7 +1241,7 @@ __device__ void lin_fused_body(const LinFusedArgs& a, int logical, int bid, int 
                              std::integral_constant<int, OP>(), ob2, oz2[P], SR[CUR], RR[CUR], g);
       lds[ON + N0 * S1 + ob1] = v;
       if (t >= i0 && t < i1) {
-        st_rs_f(prs(outR, t), o_c, v);
+        st_rs_f_nt(prs(outR, t), o_c, v);
         accR += (double)(g + RR[CUR]);
       }
       if (has_halo) {
@@ -1273,7 +1283,7 @@ __device__ void lin_fused_body(const LinFusedArgs& a, int logical, int bid, int 
 #undef MR_LF_EDGES
       float Se;
       const float g = lin_source(tb, eB0[OB + c2], bscl, SBk[CUR], ih2, te, Se) * ih2;
-      st_rs_f(prs(outB, t - 1), o_c, (Se - h2 * (g + RBk[CUR] - C)) * (1.0f / 6.0f));
+      st_rs_f_nt(prs(outB, t - 1), o_c, (Se - h2 * (g + RBk[CUR] - C)) * (1.0f / 6.0f));
       accB += (double)(g + RBk[CUR]);
     }
     if (t + 2 <= i1 + 1) store(OQ, xs);
@@ -1293,6 +1303,63 @@ __device__ void lin_fused_body(const LinFusedArgs& a, int logical, int bid, int 
   }
   double vv[2] = {accR, accB};
   grid_sum<2>(vv, a.partials, a.counter, a.sum_out, nblocks, bid);
+}
+
+// ---- vector kernels of the Krylov-accelerated inner solve -------------------------------------
+constexpr int kKryMax = 8;          // longest Krylov space of the inner solve
+constexpr int kKryBlocks = 1024;    // blocks of the reducing vector kernels
+constexpr int kKryNV = kKryMax + 2; // values reduced per block
+struct KryPtrs {
+  const float* p[kKryMax + 1];
+};
+struct KryCoef {
+  double c[kKryMax + 1];
+};
+
+// Sums over all cells of w v_j (j < k) into result[j], of w into result[kKryMax] and of w^2 into
+// result[kKryMax + 1] (FP64 accumulation); blocks bid of nblocks, grid-stride.
+inline __device__ void kry_dots_body(const float* __restrict__ w, const KryPtrs& v, int k, size_t cells,
+                                     double* partials, unsigned* counter, double* result, int bid, int nblocks) {
+  double acc[kKryNV];
+#pragma unroll
+  for (int j = 0; j < kKryNV; ++j) acc[j] = 0.0;
+  for (size_t x = bid * (size_t)blockDim.x + threadIdx.x; x < cells; x += (size_t)nblocks * blockDim.x) {
+    const double wv = w[x];
+#pragma unroll
+    for (int j = 0; j < kKryMax; ++j)
+      if (j < k) acc[j] += wv * (double)v.p[j][x];
+    acc[kKryMax] += wv;
+    acc[kKryMax + 1] += wv * wv;
+  }
+  grid_sum<kKryNV>(acc, partials, counter, result, nblocks, bid);
+}
+
+// out = (w - sum_{j<k} c_j v_j - c_k) c_{k+1}: the next orthonormal Krylov vector (classical
+// Gram-Schmidt against mean-free orthonormal v_j, the mean c_k removed, scaled by c_{k+1}).
+inline __device__ void kry_orth_body(const float* __restrict__ w, const KryPtrs& v, KryCoef c, int k, size_t cells,
+                                     float* __restrict__ out, int bid, int nblocks) {
+  for (size_t x = bid * (size_t)blockDim.x + threadIdx.x; x < cells; x += (size_t)nblocks * blockDim.x) {
+    double s = (double)w[x] - c.c[k];
+#pragma unroll
+    for (int j = 0; j < kKryMax; ++j)
+      if (j < k) s -= c.c[j] * (double)v.p[j][x];
+    out[x] = (float)(s * c.c[k + 1]);
+  }
+}
+
+// theta += sum_{j<m} y_j z_j; max |theta| of the result into *tmax (atomic maximum) when given.
+inline __device__ void kry_update_body(double* __restrict__ theta, const KryPtrs& z, KryCoef y, int m, size_t cells,
+                                       double* tmax, int bid, int nblocks) {
+  double mx = 0.0;
+  for (size_t x = bid * (size_t)blockDim.x + threadIdx.x; x < cells; x += (size_t)nblocks * blockDim.x) {
+    double s = theta[x];
+#pragma unroll
+    for (int j = 0; j < kKryMax; ++j)
+      if (j < m) s += y.c[j] * (double)z.p[j][x];
+    theta[x] = s;
+    mx = fmax(mx, fabs(s));
+  }
+  if (tmax) block_absmax_to(mx, tmax);
 }
 
 }  // namespace mr

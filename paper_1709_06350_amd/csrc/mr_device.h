@@ -247,6 +247,17 @@ __device__ __forceinline__ void st_rs(__amdgpu_buffer_rsrc_t r, unsigned byte_of
                                        r, (int)byte_off, 0, 0);
 }
 
+// Non-temporal variants (cache policy NT): for data a kernel streams exactly once -- inputs read once
+// per pass and outputs not read again by the same launch -- so that they do not displace the reused
+// halo planes from the caches.
+__device__ __forceinline__ double ld_rs_nt(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, 2));
+}
+__device__ __forceinline__ void st_rs_nt(__amdgpu_buffer_rsrc_t r, unsigned byte_off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v),
+                                       r, (int)byte_off, 0, 2);
+}
+
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float* base, unsigned bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, (int)bytes, 0x00020000);
 }
@@ -255,6 +266,12 @@ __device__ __forceinline__ float ld_rs_f(__amdgpu_buffer_rsrc_t r, unsigned byte
 }
 __device__ __forceinline__ void st_rs_f(__amdgpu_buffer_rsrc_t r, unsigned byte_off, float v) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)byte_off, 0, 0);
+}
+__device__ __forceinline__ float ld_rs_f_nt(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 2));
+}
+__device__ __forceinline__ void st_rs_f_nt(__amdgpu_buffer_rsrc_t r, unsigned byte_off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, (int)byte_off, 0, 2);
 }
 
 // Map a launch-order block index to a logical tile index so that each of the 8 XCDs (which

@@ -342,8 +342,8 @@ __global__ void __launch_bounds__(TM * TJ) half_sweep_pipe(HalfSweepArgs a) {
     store(2, vc);
   }
   fetch(3, V0);
-  D[0] = ld_rs(prs(dl, i0), o_c);
-  D[1] = ld_rs(prs(dl, min(i0 + 1, last_plane)), o_c);
+  D[0] = ld_rs_nt(prs(dl, i0), o_c);
+  D[1] = ld_rs_nt(prs(dl, min(i0 + 1, last_plane)), o_c);
   if (HAS_F) {
     Fv[0] = ld_rs(prs(ff, i0), o_c);
     Fv[1] = ld_rs(prs(ff, min(i0 + 1, last_plane)), o_c);
@@ -356,7 +356,7 @@ __global__ void __launch_bounds__(TM * TJ) half_sweep_pipe(HalfSweepArgs a) {
     constexpr int SM = (K + 0) & 3, S0 = (K + 1) & 3, SP = (K + 2) & 3, SN = (K + 3) & 3;
     fetch(t + 4, vft);
     const int pn = min(i0 + t + 2, last_plane);
-    D[(K + 2) & 3] = ld_rs(prs(dl, pn), o_c);
+    D[(K + 2) & 3] = ld_rs_nt(prs(dl, pn), o_c);
     if (HAS_F) Fv[(K + 2) & 3] = ld_rs(prs(ff, pn), o_c);
     const int oq = (K & 1) ? oq1 : oq0;
     const double* __restrict__ lo = lds + O * 4 * SLOT;     // other colour
@@ -374,7 +374,7 @@ __global__ void __launch_bounds__(TM * TJ) half_sweep_pipe(HalfSweepArgs a) {
     const double fc = HAS_F ? Fv[K] : 0.0;
     double S;
     const double sig = sigma_cell(c, 1.0 + D[K], ih2, S);
-    st_rs(prs(out, i0 + t), o_c, (S - h2 * (sig + fc - C)) * (1.0 / 6.0));
+    st_rs_nt(prs(out, i0 + t), o_c, (S - h2 * (sig + fc - C)) * (1.0 / 6.0));
     acc += sig + fc;
     store(SN, vst);
     __syncthreads();
