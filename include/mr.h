@@ -101,7 +101,8 @@ enum {
   MR_FLAG_PLAIN_INNER = 64
 };
 
-/* Per-solve report. history[c] is the relative residual after cycle c (history[0] = start). */
+/* Per-solve report. history[c] is the relative residual after cycle c (history[0] = start).
+ * inner_cycles: total linear V-cycles of the inner solves of a mixed-precision solve (0 otherwise). */
 typedef struct {
   int status;
   int cycles;
@@ -110,6 +111,7 @@ typedef struct {
   double m_shift;
   double seconds;
   double history[128];
+  int inner_cycles;
 } mr_info;
 
 typedef struct mr_ctx mr_ctx;

@@ -125,9 +125,16 @@ __global__ void __launch_bounds__(256) lin_apply_row_kernel(const float* __restr
   }
 }
 
-__global__ void __launch_bounds__(256) kry_dots_kernel(const float* __restrict__ w, KryPtrs v, int k, size_t cells,
+template <int K>
+__global__ void __launch_bounds__(256) kry_dots_kernel(const float* __restrict__ w, KryPtrs v, size_t cells,
                                                        double* partials, unsigned* counter, double* result) {
-  kry_dots_body(w, v, k, cells, partials, counter, result, blockIdx.x, gridDim.x);
+  kry_dots_body<K>(w, v, cells, partials, counter, result, blockIdx.x, gridDim.x);
+}
+
+template <int TM, int TJ>
+__global__ void __launch_bounds__(TM * TJ) lin_apply_both(LinSweepArgs a) {
+  __shared__ float lds[LinTile<TM, TJ>::LDS];
+  lin_apply_both_body<TM, TJ>(a, xcd_remap(blockIdx.x, gridDim.x), lds);
 }
 
 __global__ void __launch_bounds__(256) kry_orth_kernel(const float* __restrict__ w, KryPtrs v, KryCoef c, int k,
@@ -379,8 +386,7 @@ hipError_t launch_lin_apply(const float* z, const int* baseq, const double* bq, 
     const int blocks = t.tiles_j * t.tiles_m * (n / t.ci);
 #define MR_LA_LAUNCH(TM, TJ)                                                                             \
     if (t.tm == TM && t.tj == TJ) {                                                                      \
-      hipLaunchKernelGGL((lin_apply_pipe<TM, TJ, 0>), dim3(blocks), dim3(TM * TJ), 0, s, a);            \
-      hipLaunchKernelGGL((lin_apply_pipe<TM, TJ, 1>), dim3(blocks), dim3(TM * TJ), 0, s, a);            \
+      hipLaunchKernelGGL((lin_apply_both<TM, TJ>), dim3(blocks), dim3(TM * TJ), 0, s, a);               \
       return hipGetLastError();                                                                          \
     }
     MR_LIN_TILES(MR_LA_LAUNCH)
@@ -931,7 +937,7 @@ static void hessenberg_ls(std::vector<std::vector<double>> H, double beta, int k
 // V-cycle per iteration, from e = 0; then theta64 += e (and max |theta| into kSlotTmax). The
 // Krylov vectors are mean-free: J_p maps onto mean-free fields and annihilates constants, so the
 // mean of the right-hand side is removed and the Gram-Schmidt step removes the mean of J z.
-int Ctx::kry_step(double* theta64, int m, double rhs_sum, double rhs_sq) {
+int Ctx::kry_step(double* theta64, int m, double rhs_sum, double rhs_sq, double eta, int* used) {
   int rc = kry_reserve(this, m);
   if (rc != MR_OK) return rc;
   LinLevel& M0 = mixed->lv[0];
@@ -954,6 +960,10 @@ int Ctx::kry_step(double* theta64, int m, double rhs_sum, double rhs_sq) {
   float* rhs_own = M0.rhs;
   float* e_own[2] = {M0.e[0], M0.e[1]};
   std::vector<std::vector<double>> H(m + 1, std::vector<double>(m, 0.0));
+  // Givens rotations applied so far and the rotated right-hand side: |g[i + 1]| is the residual norm
+  // of the least-squares solution after i + 1 iterations
+  std::vector<double> gcs(m, 1.0), gsn(m, 0.0), gg(m + 1, 0.0);
+  gg[0] = beta;
   int k = 0;
   for (int i = 0; i < m; ++i) {
     // z_i = one V-cycle on J_p z = v_i from z = 0 (v_i is mean-free: the level-0 shift starts at 0)
@@ -975,16 +985,25 @@ int Ctx::kry_step(double* theta64, int m, double rhs_sum, double rhs_sq) {
     e = launch_lin_apply(K.Z[i], M0.base, scal + kSlotBase, M0.sb, lv[0].n, lv[0].h, K.W, M0.sw, stream);
     for (int j = 0; j <= i; ++j) vp.p[j] = K.V[j];
     if (e == hipSuccess) {
-      hipLaunchKernelGGL(kry_dots_kernel, dim3(nb), dim3(256), 0, stream, (const float*)K.W, vp, i + 1, cells, K.partials,
-                         K.counter, K.result);
+      switch (i + 1) {
+#define MR_KD_CASE(KK)                                                                                          \
+        case KK:                                                                                                \
+          hipLaunchKernelGGL((kry_dots_kernel<KK>), dim3(nb), dim3(256), 0, stream, (const float*)K.W, vp, cells, \
+                             K.partials, K.counter, K.result);                                                  \
+          break;
+        MR_KD_CASE(1) MR_KD_CASE(2) MR_KD_CASE(3) MR_KD_CASE(4) MR_KD_CASE(5) MR_KD_CASE(6) MR_KD_CASE(7)
+        MR_KD_CASE(8)
+#undef MR_KD_CASE
+      }
       e = hipGetLastError();
     }
     double d[kKryNV];
-    if (e == hipSuccess) e = hipMemcpyAsync(d, K.result, sizeof d, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d, K.result, (i + 3) * sizeof(double), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return hip_fail(e, "Krylov dot products");
-    const double mean_w = d[kKryMax] / N;
-    double hh = d[kKryMax + 1] - N * mean_w * mean_w;
+    const double sum_w = d[i + 1], sq_w = d[i + 2];
+    const double mean_w = sum_w / N;
+    double hh = sq_w - N * mean_w * mean_w;
     for (int j = 0; j <= i; ++j) {
       H[j][i] = d[j];
       hh -= d[j] * d[j];
@@ -992,8 +1011,23 @@ int Ctx::kry_step(double* theta64, int m, double rhs_sum, double rhs_sq) {
     const double hn = std::sqrt(hh > 0.0 ? hh : 0.0);
     H[i + 1][i] = hn;
     k = i + 1;
-    // the space is exhausted (or the next vector would be rounding noise): stop here
-    if (hn <= 1e-6 * std::sqrt(d[kKryMax + 1] > 0.0 ? d[kKryMax + 1] : 0.0) || i + 1 == m) break;
+    {
+      std::vector<double> col(i + 2);
+      for (int r2 = 0; r2 <= i + 1; ++r2) col[r2] = H[r2][i];
+      for (int r2 = 0; r2 < i; ++r2) {
+        const double u = col[r2], v = col[r2 + 1];
+        col[r2] = gcs[r2] * u + gsn[r2] * v;
+        col[r2 + 1] = -gsn[r2] * u + gcs[r2] * v;
+      }
+      const double rr = std::hypot(col[i], col[i + 1]);
+      gcs[i] = rr > 0.0 ? col[i] / rr : 1.0;
+      gsn[i] = rr > 0.0 ? col[i + 1] / rr : 0.0;
+      gg[i + 1] = -gsn[i] * gg[i];
+      gg[i] = gcs[i] * gg[i];
+    }
+    // stop when the inner residual is below eta of the right-hand side, when the space is exhausted
+    // (the next vector would be rounding noise) or after m iterations
+    if (std::fabs(gg[i + 1]) <= eta * beta || hn <= 1e-6 * std::sqrt(sq_w > 0.0 ? sq_w : 0.0) || i + 1 == m) break;
     for (int j = 0; j <= i; ++j) cf.c[j] = d[j];
     cf.c[i + 1] = mean_w;
     cf.c[i + 2] = 1.0 / hn;
@@ -1014,6 +1048,7 @@ int Ctx::kry_step(double* theta64, int m, double rhs_sum, double rhs_sq) {
   }
   hipLaunchKernelGGL(kry_update_kernel, dim3(nbu), dim3(256), 0, stream, theta64, zz, yy, k, cells, scal + kSlotTmax);
   e = hipGetLastError();
+  if (used) *used = k;
   return e == hipSuccess ? MR_OK : hip_fail(e, "Krylov update");
 }
 
@@ -1042,7 +1077,7 @@ int Ctx::solve_mixed(const double* delta, double* theta, mr_info* info, int aa_d
   mr_info loc{};
   loc.r0_norm = r0;
   int it = 0, status = MR_OK;
-  double rel = 1.0, best = 1e300, msig = m0;
+  double rel = 1.0, best = 1e300, msig = m0, rel_prev = 0.0, eta_prev = 0.5;
   LinLevel& M0 = mixed->lv[0];
   for (;;) {
     e = launch_base_scale(scal + kSlotTmax, scal + kSlotBase, stream);
@@ -1064,8 +1099,24 @@ int Ctx::solve_mixed(const double* delta, double* theta, mr_info* info, int aa_d
     if (rel <= opts.tol || it >= opts.max_cycles) break;
     if ((rc = lin_base_hierarchy()) != MR_OK) return rc;
     if (aa_depth == 0 && !(opts.flags & MR_FLAG_PLAIN_INNER)) {
-      // Krylov-accelerated inner solve; the rhs -b has sum -r[2] and square sum r[3]
-      if ((rc = kry_step(L0.th[0], opts.inner_cycles, -r[2], r[3])) != MR_OK) return rc;
+      // Krylov-accelerated inner solve (inexact Newton): the inner residual is reduced to eta of the
+      // outer one, eta from the last outer reduction (Eisenstat and Walker's second choice,
+      // 0.9 (rel_k / rel_k-1)^2, safeguarded and at most 0.5) but not below what the tolerance
+      // needs (half of tol / rel); at most inner_cycles V-cycles. The rhs -b has sum -r[2] and
+      // square sum r[3].
+      double eta = 0.5;
+      if (it > 0 && rel_prev > 0.0) {
+        const double ratio = rel / rel_prev;
+        eta = 0.9 * ratio * ratio;
+        const double safe = 0.9 * eta_prev * eta_prev;
+        if (safe > 0.1) eta = std::max(eta, safe);
+      }
+      eta = std::min(0.5, std::max(eta, 0.5 * opts.tol / rel));
+      int used = 0;
+      if ((rc = kry_step(L0.th[0], opts.inner_cycles, -r[2], r[3], eta, &used)) != MR_OK) return rc;
+      loc.inner_cycles += used;
+      rel_prev = rel;
+      eta_prev = eta;
       ++it;
       continue;
     }
@@ -1073,6 +1124,7 @@ int Ctx::solve_mixed(const double* delta, double* theta, mr_info* info, int aa_d
     hipLaunchKernelGGL(inner_shift_kernel, dim3(1), dim3(64), 0, stream, (const double*)(scal + kSlotRes), linsum(0));
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "inner shift");
     if ((rc = lin_solve(opts.inner_cycles)) != MR_OK) return rc;
+    loc.inner_cycles += opts.inner_cycles;
     if (aa_depth > 0) {
       // Anderson mixing of the outer iteration theta -> theta + e(theta): the step forms theta + e
       // itself and writes the mixed (or plain) new iterate

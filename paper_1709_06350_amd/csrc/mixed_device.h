@@ -1305,6 +1305,136 @@ __device__ void lin_fused_body(const LinFusedArgs& a, int logical, int bid, int 
   grid_sum<2>(vv, a.partials, a.counter, a.sum_out, nblocks, bid);
 }
 
+// ---- the linear operator applied to both colours in one pass ----------------------------------
+// w = nabla^2 z - dSigma(z) at every cell: the pipelined sweep's tile decomposition and 4-slot plane
+// ring (z and the base, both colours, one-cell halo), with each thread evaluating the red and the
+// black cell of its (j, m) column per plane. No cell depends on another's result, so one launch
+// covers both colours (the two one-colour launches each read both colours of z and of the base).
+template <int TM, int TJ>
+__device__ void lin_apply_both_body(const LinSweepArgs& a, int logical, float* lds) {
+  constexpr int NT = TM * TJ;
+  constexpr int RW = TM + 2;
+  constexpr int SLOT = LinTile<TM, TJ>::SLOT;
+  constexpr int PER = (SLOT + NT - 1) / NT;
+  constexpr int NPF = 4 * PER;
+  const int n = a.n, nh = n >> 1;
+  const int tid = threadIdx.x;
+  const int tm_i = logical % a.tiles_m;
+  const int tj_i = (logical / a.tiles_m) % a.tiles_j;
+  const int chunk = logical / (a.tiles_m * a.tiles_j);
+  const int j0 = tj_i * TJ, m0 = tm_i * TM, i0 = chunk * a.ci, ci = a.ci;
+  const size_t plane = (size_t)n * nh;
+  const size_t half = plane * n;
+  const unsigned pbytes = (unsigned)plane * 4u;
+  const float* __restrict__ f0 = a.e_in;
+  const float* __restrict__ f1 = a.e_in + half;
+  const float* __restrict__ f2 = reinterpret_cast<const float*>(a.base);
+  const float* __restrict__ f3 = reinterpret_cast<const float*>(a.base) + half;
+  auto prs = [&](const float* arr, int p) { return plane_rsrc(arr + (size_t)p * plane, pbytes); };
+  unsigned goff[PER];
+  int loff[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    int e = tid + k * NT;
+    e = e < SLOT ? e : SLOT - 1;
+    const int r = e / RW;
+    const int c = e - r * RW;
+    goff[k] = ((unsigned)wrapi(j0 - 1 + r, n) * nh + (unsigned)wrapi(m0 - 1 + c, nh)) * 4u;
+    loff[k] = e;
+  }
+  auto fetch = [&](int rel, float (&v)[NPF]) {
+    const int p = wrapi(i0 - 1 + rel, n);
+    const auto b0 = prs(f0, p), b1 = prs(f1, p), b2 = prs(f2, p), b3 = prs(f3, p);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+      v[0 * PER + k] = ld_rs_f(b0, goff[k]);
+      v[1 * PER + k] = ld_rs_f(b1, goff[k]);
+      v[2 * PER + k] = ld_rs_f(b2, goff[k]);
+      v[3 * PER + k] = ld_rs_f(b3, goff[k]);
+    }
+  };
+  auto store = [&](int slot, const float (&v)[NPF]) {
+#pragma unroll
+    for (int f = 0; f < 4; ++f)
+#pragma unroll
+      for (int k = 0; k < PER; ++k) lds[(f * 4 + slot) * SLOT + loff[k]] = v[f * PER + k];
+  };
+  const int s = tid % TM, r = tid / TM;
+  const int j = j0 + r, m = m0 + s;
+  const unsigned o_c = ((unsigned)j * nh + m) * 4u;
+  const int ob = (r + 1) * RW + (s + 1);
+  const int qr = (i0 + j) & 1;   // z-parity of the red cell of this column at plane i0 (black: 1 - qr)
+  const float ih2 = a.ih2, bscl = (float)a.bq[0];
+  const float* __restrict__ sbR = a.sb;
+  const float* __restrict__ sbB = a.sb + half;
+  float* __restrict__ outR = a.e_out;
+  float* __restrict__ outB = a.e_out + half;
+  const int last_plane = n - 1;
+  float V0[NPF], V1[NPF];
+  float SR[4], SBv[4];
+  {
+    float va[NPF], vb[NPF], vc[NPF];
+    fetch(0, va);
+    fetch(1, vb);
+    fetch(2, vc);
+    store(0, va);
+    store(1, vb);
+    store(2, vc);
+  }
+  fetch(3, V0);
+  SR[0] = ld_rs_f_nt(prs(sbR, i0), o_c);
+  SBv[0] = ld_rs_f_nt(prs(sbB, i0), o_c);
+  SR[1] = ld_rs_f_nt(prs(sbR, min(i0 + 1, last_plane)), o_c);
+  SBv[1] = ld_rs_f_nt(prs(sbB, min(i0 + 1, last_plane)), o_c);
+  __syncthreads();
+  auto step = [&](auto kc, int t, float (&vst)[NPF], float (&vft)[NPF]) {
+    constexpr int K = decltype(kc)::value;
+    constexpr int SM = K & 3, S0 = (K + 1) & 3, SP = (K + 2) & 3, SN = (K + 3) & 3;
+    fetch(t + 4, vft);
+    const int pn = min(i0 + t + 2, last_plane);
+    SR[(K + 2) & 3] = ld_rs_f_nt(prs(sbR, pn), o_c);
+    SBv[(K + 2) & 3] = ld_rs_f_nt(prs(sbB, pn), o_c);
+    // z-parity at plane i0 + t: red (qr ^ (K & 1)), black the opposite
+    const int q_red = qr ^ (K & 1);
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int oq = ob + (c == 0 ? q_red : q_red ^ 1);
+      const int O = 1 - c;
+      Nb18f te, tb;
+#define MR_LA_GATHER(T, LO, LC)                                                        \
+      {                                                                                \
+        const float* lo = lds + (LO) * 4 * SLOT;                                        \
+        const float* lc = lds + (LC) * 4 * SLOT;                                        \
+        T.xm = lo[SM * SLOT + ob];         T.xp = lo[SP * SLOT + ob];                   \
+        T.ym = lo[S0 * SLOT + ob - RW];    T.yp = lo[S0 * SLOT + ob + RW];              \
+        T.zm = lo[S0 * SLOT + oq - 1];     T.zp = lo[S0 * SLOT + oq];                   \
+        T.xpyp = lc[SP * SLOT + ob + RW];  T.xmym = lc[SM * SLOT + ob - RW];            \
+        T.xpym = lc[SP * SLOT + ob - RW];  T.xmyp = lc[SM * SLOT + ob + RW];            \
+        T.xpzp = lc[SP * SLOT + oq];       T.xmzm = lc[SM * SLOT + oq - 1];             \
+        T.xpzm = lc[SP * SLOT + oq - 1];   T.xmzp = lc[SM * SLOT + oq];                 \
+        T.ypzp = lc[S0 * SLOT + oq + RW];  T.ymzm = lc[S0 * SLOT + oq - RW - 1];        \
+        T.ypzm = lc[S0 * SLOT + oq + RW - 1]; T.ymzp = lc[S0 * SLOT + oq - RW];         \
+      }
+      MR_LA_GATHER(te, O, c)
+      MR_LA_GATHER(tb, 2 + O, 2 + c)
+#undef MR_LA_GATHER
+      float Se;
+      const float g = lin_source(tb, lds[(2 + c) * 4 * SLOT + S0 * SLOT + ob], bscl, c == 0 ? SR[K] : SBv[K], ih2, te,
+                                 Se) * ih2;
+      const float zc = lds[c * 4 * SLOT + S0 * SLOT + ob];
+      st_rs_f_nt(prs(c == 0 ? outR : outB, i0 + t), o_c, (Se - 6.0f * zc) * ih2 - g);
+    }
+    store(SN, vst);
+    __syncthreads();
+  };
+  for (int t = 0; t < ci; t += 4) {
+    step(std::integral_constant<int, 0>(), t, V0, V1);
+    step(std::integral_constant<int, 1>(), t + 1, V1, V0);
+    step(std::integral_constant<int, 2>(), t + 2, V0, V1);
+    step(std::integral_constant<int, 3>(), t + 3, V1, V0);
+  }
+}
+
 // ---- vector kernels of the Krylov-accelerated inner solve -------------------------------------
 constexpr int kKryMax = 8;          // longest Krylov space of the inner solve
 constexpr int kKryBlocks = 1024;    // blocks of the reducing vector kernels
@@ -1316,22 +1446,27 @@ struct KryCoef {
   double c[kKryMax + 1];
 };
 
-// Sums over all cells of w v_j (j < k) into result[j], of w into result[kKryMax] and of w^2 into
-// result[kKryMax + 1] (FP64 accumulation); blocks bid of nblocks, grid-stride.
-inline __device__ void kry_dots_body(const float* __restrict__ w, const KryPtrs& v, int k, size_t cells,
-                                     double* partials, unsigned* counter, double* result, int bid, int nblocks) {
-  double acc[kKryNV];
+// Sums over all cells of w v_j (j < K) into result[j], of w into result[K] and of w^2 into
+// result[K + 1]: 16-byte loads, four FP32 products per lane and step added into FP64 accumulators.
+template <int K>
+__device__ void kry_dots_body(const float* __restrict__ w, const KryPtrs& v, size_t cells, double* partials,
+                              unsigned* counter, double* result, int bid, int nblocks) {
+  double acc[K + 2];
 #pragma unroll
-  for (int j = 0; j < kKryNV; ++j) acc[j] = 0.0;
-  for (size_t x = bid * (size_t)blockDim.x + threadIdx.x; x < cells; x += (size_t)nblocks * blockDim.x) {
-    const double wv = w[x];
+  for (int j = 0; j < K + 2; ++j) acc[j] = 0.0;
+  const float4* __restrict__ w4 = reinterpret_cast<const float4*>(w);
+  const size_t n4 = cells / 4;
+  for (size_t x = bid * (size_t)blockDim.x + threadIdx.x; x < n4; x += (size_t)nblocks * blockDim.x) {
+    const float4 a = w4[x];
 #pragma unroll
-    for (int j = 0; j < kKryMax; ++j)
-      if (j < k) acc[j] += wv * (double)v.p[j][x];
-    acc[kKryMax] += wv;
-    acc[kKryMax + 1] += wv * wv;
+    for (int j = 0; j < K; ++j) {
+      const float4 b = reinterpret_cast<const float4*>(v.p[j])[x];
+      acc[j] += (double)(a.x * b.x + a.y * b.y) + (double)(a.z * b.z + a.w * b.w);
+    }
+    acc[K] += (double)(a.x + a.y) + (double)(a.z + a.w);
+    acc[K + 1] += (double)(a.x * a.x + a.y * a.y) + (double)(a.z * a.z + a.w * a.w);
   }
-  grid_sum<kKryNV>(acc, partials, counter, result, nblocks, bid);
+  grid_sum<K + 2>(acc, partials, counter, result, nblocks, bid);
 }
 
 // out = (w - sum_{j<k} c_j v_j - c_k) c_{k+1}: the next orthonormal Krylov vector (classical

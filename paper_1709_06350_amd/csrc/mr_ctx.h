@@ -120,7 +120,7 @@ struct Ctx {
   int lin_base_hierarchy();
   int lin_solve(int ncycles);
   int lin_vcycles_split(const double* theta_split, const double* rhs_split, int ncycles, float** e_out);
-  int kry_step(double* theta64, int m, double rhs_sum, double rhs_sq);
+  int kry_step(double* theta64, int m, double rhs_sum, double rhs_sq, double eta, int* used);
   void release_extra();
   void release_adjoint();
 };

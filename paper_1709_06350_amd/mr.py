@@ -77,6 +77,7 @@ class mr_info(ctypes.Structure):
         ("m_shift", ctypes.c_double),
         ("seconds", ctypes.c_double),
         ("history", ctypes.c_double * 128),
+        ("inner_cycles", ctypes.c_int),
     ]
 
 
@@ -206,11 +207,12 @@ class Info:
     m_shift: float
     seconds: float
     history: List[float] = field(default_factory=list)
+    inner_cycles: int = 0
 
     @staticmethod
     def from_c(i: mr_info) -> "Info":
         return Info(i.status, i.cycles, i.rel_residual, i.r0_norm, i.m_shift, i.seconds,
-                    list(i.history[: min(i.cycles, 127) + 1]))
+                    list(i.history[: min(i.cycles, 127) + 1]), i.inner_cycles)
 
 
 class Context:
