@@ -353,6 +353,15 @@ int mr_lin_defect_restrict(mr_ctx* ctx, int nl, double h, const double* delta, c
 int mr_lin_sweep(mr_ctx* ctx, int nl, double h, const double* delta, const double* theta_base,
                  const double* e_in, const double* rhs, double cshift, const int* sched, double* e_out);
 
+/* The inner solve's coarse-to-fine correction (Sec. II.A.3, the prolongation P of the V-cycle, in
+ * FP32): e_out = e_in + P ec on the nl^3 mesh, ec on the (nl/2)^3 mesh, P the cell-centred
+ * trilinear interpolation (per axis, fine cell 2I takes 3/4 of coarse cell I and 1/4 of I-1, fine
+ * cell 2I+1 3/4 of I and 1/4 of I+1, periodic). Computed by the kernel the inner V-cycle runs at
+ * this size, with ec and e_in rounded to FP32; e_out receives the result widened to FP64. Arrays
+ * are natural-order doubles on the device; e_out may alias e_in. Returns MR_EINVAL for a NULL
+ * argument or nl not a multiple of 4 in 4..1024. */
+int mr_lin_prolong_add(mr_ctx* ctx, int nl, const double* ec, const double* e_in, double* e_out);
+
 /* ncycles (1..64) inner linear V-cycles of the mixed-precision solve on the context's mesh, from
  * e = 0, for J_p e = rhs at the base theta_base (the finest level's FP32 base and root come from
  * the same FP64 residual pass as in mr_solve; coarse levels restrict the base and take their own

@@ -1058,6 +1058,28 @@ int mr_lin_defect_restrict(mr_ctx* h, int nl, double hcell, const double* delta,
   return x == hipSuccess ? MR_OK : hip_fail(x, "mr_lin_defect_restrict");
 }
 
+int mr_lin_prolong_add(mr_ctx* h, int nl, const double* ec, const double* e_in, double* e_out) {
+  if (!h || !ec || !e_in || !e_out) return fail(MR_EINVAL, "mr_lin_prolong_add: null argument");
+  int rc = check_level(nl, true);
+  if (rc != MR_OK) return rc;
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  const size_t cells = (size_t)nl * nl * nl, cc = cells / 8;
+  Temps tmp(c->stream);
+  double* t64 = tmp.get(cells);
+  float* e32 = (float*)tmp.get((cells + 1) / 2);
+  float* ec32 = (float*)tmp.get((cc + 1) / 2);
+  if (!t64 || !e32 || !ec32) return fail(MR_ENOMEM, "mr_lin_prolong_add: temporaries");
+  hipError_t x = launch_to_split(ec, t64, nl / 2, c->stream);
+  if (x == hipSuccess) x = launch_cast32(t64, ec32, cc, c->stream);
+  if (x == hipSuccess) x = launch_to_split(e_in, t64, nl, c->stream);
+  if (x == hipSuccess) x = launch_cast32(t64, e32, cells, c->stream);
+  if (x == hipSuccess) x = launch_prolong_add32(ec32, e32, nl, c->stream);
+  if (x == hipSuccess) x = launch_widen64(e32, t64, cells, c->stream);
+  if (x == hipSuccess) x = launch_from_split(t64, e_out, nl, nullptr, 0.0, c->stream);
+  if (x == hipSuccess) x = hipStreamSynchronize(c->stream);
+  return x == hipSuccess ? MR_OK : hip_fail(x, "mr_lin_prolong_add");
+}
+
 int mr_lin_sweep(mr_ctx* h, int nl, double hcell, const double* delta, const double* theta_base, const double* e_in,
                  const double* rhs, double cshift, const int* sched, double* e_out) {
   if (!h || !delta || !theta_base || !e_in || !e_out || e_in == e_out) return fail(MR_EINVAL, "mr_lin_sweep: bad pointers");

@@ -94,16 +94,10 @@ __global__ void __launch_bounds__(256) fill32_kernel(float* __restrict__ a, floa
   fill32_body(a, v, cells, blockIdx.x, gridDim.x);
 }
 
-template <int TM, int TJ, int COL>
+template <int TM, int TJ, int COL, bool ZB = false>
 __global__ void __launch_bounds__(TM * TJ) lin_sweep_pipe(LinSweepArgs a) {
   __shared__ float lds[LinTile<TM, TJ>::LDS];
-  lin_sweep_pipe_body<TM, TJ, COL>(a, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x, gridDim.x, lds);
-}
-
-template <int TM, int TJ, int COL>
-__global__ void __launch_bounds__(TM * TJ) lin_apply_pipe(LinSweepArgs a) {
-  __shared__ float lds[LinTile<TM, TJ>::LDS];
-  lin_sweep_pipe_body<TM, TJ, COL, true>(a, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x, gridDim.x, lds);
+  lin_sweep_pipe_body<TM, TJ, COL, ZB>(a, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x, gridDim.x, lds);
 }
 
 // (J z)_c = nabla^2 z - dSigma(z) at every cell (rows of the mesh dealt to blocks), FP32.
@@ -131,10 +125,10 @@ __global__ void __launch_bounds__(256) kry_dots_kernel(const float* __restrict__
   kry_dots_body<K>(w, v, cells, partials, counter, result, blockIdx.x, gridDim.x);
 }
 
-template <int TM, int TJ>
-__global__ void __launch_bounds__(TM * TJ) lin_apply_both(LinSweepArgs a) {
+template <int TM, int TJ, int K>
+__global__ void __launch_bounds__(2 * TM * TJ) lin_apply_dots(LinApplyArgs a) {
   __shared__ float lds[LinTile<TM, TJ>::LDS];
-  lin_apply_both_body<TM, TJ>(a, xcd_remap(blockIdx.x, gridDim.x), lds);
+  lin_apply_dots_body<TM, TJ, K>(a, xcd_remap(blockIdx.x, gridDim.x), blockIdx.x, gridDim.x, lds);
 }
 
 __global__ void __launch_bounds__(256) kry_orth_kernel(const float* __restrict__ w, KryPtrs v, KryCoef c, int k,
@@ -145,6 +139,37 @@ __global__ void __launch_bounds__(256) kry_orth_kernel(const float* __restrict__
 __global__ void __launch_bounds__(256) kry_update_kernel(double* __restrict__ theta, KryPtrs z, KryCoef y, int m,
                                                          size_t cells, double* tmax) {
   kry_update_body(theta, z, y, m, cells, tmax, blockIdx.x, gridDim.x);
+}
+
+// Red half of a sweep from e = 0: with e = 0 the source dSigma(e) and the face sum vanish, so
+// e_red = -h^2 (rhs_red - C) / 6; also zeroes the black half of e_zero (the black snapshot of the
+// black half-sweep that follows) unless that pointer is null (a black half-sweep that does not
+// read the snapshot), and reduces sum rhs_red (the red sum of the sweep) into *sum_out.
+__global__ void __launch_bounds__(1024) lin_red_zero_kernel(const float* __restrict__ rhs, size_t half, float h2,
+    const double* c_sum, double c_scale, float* __restrict__ e_red, float* __restrict__ e_zero_black,
+    double* partials, unsigned* counter, double* sum_out) {
+  const float C = (float)(c_sum ? (c_sum[0] + c_sum[1]) * c_scale : 0.0);
+  const float g = -h2 * (1.0f / 6.0f);
+  double acc = 0.0;
+  // half is a multiple of 4 (n even): four cells per thread and pass
+  const size_t q = half >> 2;
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  const v4f* __restrict__ r4 = reinterpret_cast<const v4f*>(rhs);
+  v4f* __restrict__ e4 = reinterpret_cast<v4f*>(e_red);
+  v4f* __restrict__ z4 = reinterpret_cast<v4f*>(e_zero_black);
+  for (size_t x = blockIdx.x * (size_t)blockDim.x + threadIdx.x; x < q; x += (size_t)gridDim.x * blockDim.x) {
+    const v4f r = __builtin_nontemporal_load(r4 + x);
+    v4f o;
+    o.x = g * (r.x - C);
+    o.y = g * (r.y - C);
+    o.z = g * (r.z - C);
+    o.w = g * (r.w - C);
+    e4[x] = o;
+    if (z4) __builtin_nontemporal_store((v4f){0.0f, 0.0f, 0.0f, 0.0f}, z4 + x);
+    acc += ((double)r.x + (double)r.y) + ((double)r.z + (double)r.w);
+  }
+  double v[1] = {acc};
+  grid_sum<1>(v, partials, counter, sum_out, gridDim.x, blockIdx.x);
 }
 
 __global__ void zero_scalars_kernel(double* p, int count) {
@@ -323,6 +348,8 @@ hipError_t launch_lin_half_sweep(const LinSweepArgs& a, const TileCfg& t, hipStr
     if (t.tm == TM && t.tj == TJ) {                                                                   \
       if (a.colour == 0)                                                                              \
         hipLaunchKernelGGL((lin_sweep_pipe<TM, TJ, 0>), dim3(blocks), dim3(TM * TJ), 0, s, b);        \
+      else if (a.zero_black)                                                                          \
+        hipLaunchKernelGGL((lin_sweep_pipe<TM, TJ, 1, true>), dim3(blocks), dim3(TM * TJ), 0, s, b);  \
       else                                                                                            \
         hipLaunchKernelGGL((lin_sweep_pipe<TM, TJ, 1>), dim3(blocks), dim3(TM * TJ), 0, s, b);        \
       return hipGetLastError();                                                                       \
@@ -367,33 +394,62 @@ hipError_t launch_lin_fused(const LinFusedArgs& a, const LinFusedCfg& t, hipStre
   return hipErrorInvalidValue;
 }
 
-// w = J z on an n^3 mesh (both colours): the pipelined kernel on tile t when it is pipelined and
-// compiled, otherwise the row kernel.
-hipError_t launch_lin_apply(const float* z, const int* baseq, const double* bq, const float* sb, int n, double h, float* w,
-                            const TileCfg& t, hipStream_t s) {
-  if (t.pipe && lin_tile_supported(t.tm, t.tj) && t.ci % 4 == 0 && t.tj * t.tiles_j == n && t.tm * t.tiles_m == n / 2) {
-    LinSweepArgs a{};
-    a.e_in = z;
-    a.e_out = w;
-    a.base = baseq;
-    a.bq = bq;
-    a.sb = sb;
-    a.n = n;
-    a.ih2 = (float)(1.0 / (h * h));
-    a.tiles_j = t.tiles_j;
-    a.tiles_m = t.tiles_m;
-    a.ci = t.ci;
-    const int blocks = t.tiles_j * t.tiles_m * (n / t.ci);
-#define MR_LA_LAUNCH(TM, TJ)                                                                             \
-    if (t.tm == TM && t.tj == TJ) {                                                                      \
-      hipLaunchKernelGGL((lin_apply_both<TM, TJ>), dim3(blocks), dim3(TM * TJ), 0, s, a);               \
-      return hipGetLastError();                                                                          \
+// w = J z on an n^3 mesh (both colours) and the sums w v_j (j < k), w, w^2 into result[0 .. k + 1]:
+// one pipelined launch with the projections fused where a 64 x 8 tile fits (at most kKryBlocks
+// blocks), otherwise the row kernel followed by the dot-product kernel.
+hipError_t launch_lin_apply_dots(const float* z, const int* baseq, const double* bq, const float* sb, int n, double h,
+                                 float* w, const KryPtrs& v, int k, double* partials, unsigned* counter, double* result,
+                                 hipStream_t s) {
+  constexpr int TM = 64, TJ = 8;
+  if (k < 1 || k > kKryMax) return hipErrorInvalidValue;
+  if ((n / 2) % TM == 0 && n % TJ == 0 && n % 4 == 0) {
+    const int tiles = (n / TJ) * (n / 2 / TM);
+    // up to one block per CU: more blocks cost more in the per-block release of the reduction
+    // than they gain in occupancy (the blocks have 16 waves each)
+    int nch = 1;
+    while (tiles * nch * 2 <= kApplyBlocks && (n / (nch * 2)) % 4 == 0 && n / (nch * 2) >= 16) nch *= 2;
+    if (tiles * nch <= kKryBlocks && (n / nch) % 4 == 0) {
+      LinApplyArgs a{};
+      a.z = z;
+      a.base = baseq;
+      a.bq = bq;
+      a.sb = sb;
+      a.w = w;
+      a.n = n;
+      a.ih2 = (float)(1.0 / (h * h));
+      a.tiles_j = n / TJ;
+      a.tiles_m = n / 2 / TM;
+      a.ci = n / nch;
+      a.v = v;
+      a.partials = partials;
+      a.counter = counter;
+      a.result = result;
+      const unsigned blocks = (unsigned)(tiles * nch);
+      switch (k) {
+#define MR_AD_CASE(KK)                                                                                          \
+        case KK:                                                                                                \
+          hipLaunchKernelGGL((lin_apply_dots<TM, TJ, KK>), dim3(blocks), dim3(2 * TM * TJ), 0, s, a);          \
+          break;
+        MR_AD_CASE(1) MR_AD_CASE(2) MR_AD_CASE(3) MR_AD_CASE(4) MR_AD_CASE(5) MR_AD_CASE(6) MR_AD_CASE(7)
+        MR_AD_CASE(8)
+#undef MR_AD_CASE
+      }
+      return hipGetLastError();
     }
-    MR_LIN_TILES(MR_LA_LAUNCH)
-#undef MR_LA_LAUNCH
   }
   hipLaunchKernelGGL(lin_apply_row_kernel, dim3(rows_blocks(n)), dim3(row_threads(n)), 0, s, z, baseq, bq, sb, n,
                      (float)(1.0 / (h * h)), w);
+  const size_t cells = (size_t)n * n * n;
+  const int nb = (int)std::min<size_t>((cells / 4 + 255) / 256, (size_t)kKryBlocks);
+  switch (k) {
+#define MR_KD_CASE(KK)                                                                                            \
+    case KK:                                                                                                      \
+      hipLaunchKernelGGL((kry_dots_kernel<KK>), dim3(nb), dim3(256), 0, s, (const float*)w, v, cells, partials, counter, \
+                         result);                                                                                 \
+      break;
+    MR_KD_CASE(1) MR_KD_CASE(2) MR_KD_CASE(3) MR_KD_CASE(4) MR_KD_CASE(5) MR_KD_CASE(6) MR_KD_CASE(7) MR_KD_CASE(8)
+#undef MR_KD_CASE
+  }
   return hipGetLastError();
 }
 
@@ -469,8 +525,20 @@ __global__ void __launch_bounds__(256) prolong_rows32_kernel(const float* __rest
   prolong_rows32_body(ec, e, n, xcd_remap(blockIdx.x, gridDim.x), cl);
 }
 
+__global__ void __launch_bounds__(1024) prolong_pipe32_kernel(const float* __restrict__ ec, float* __restrict__ e, int n,
+                                                               int nchunks) {
+  __shared__ float cl[kProlongPipeLds];
+  prolong_pipe32_body(ec, e, n, xcd_remap(blockIdx.x, gridDim.x), nchunks, cl);
+}
+
 hipError_t launch_prolong_add32(const float* ec, float* e, int n, hipStream_t s) {
   const long cc = (long)(n / 2) * (n / 2) * (n / 2);   // one thread per coarse cell
+  if (prolong_pipe_ok(n)) {   // 1024-thread blocks of 1024 / nc coarse rows, about 512 blocks
+    const int nc = n / 2, tiles = nc * nc / 1024;
+    const int nchunks = std::min(nc / 8, std::max(1, 512 / tiles));
+    hipLaunchKernelGGL(prolong_pipe32_kernel, dim3((unsigned)(tiles * nchunks)), dim3(1024), 0, s, ec, e, n, nchunks);
+    return hipGetLastError();
+  }
   if (prolong_rows_ok(n)) {   // cc / 256 whole row groups
     hipLaunchKernelGGL(prolong_rows32_kernel, dim3((unsigned)(cc / 256)), dim3(256), 0, s, ec, e, n);
     return hipGetLastError();
@@ -539,11 +607,23 @@ struct KryState {
   unsigned* counter = nullptr;
 };
 
+// The coarse part of an inner V-cycle (levels 1 .. coarsest, from zero), captured once in a HIP graph
+// and replayed: its launches are short and latency-bound, and between V-cycles only buffer contents
+// change. cur_in / cur_out: the ping-pong state of the coarse levels before and after one cycle.
+struct CoarseGraph {
+  hipStream_t cs = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<int> cur_in, cur_out;
+  int npre = -1, npost = -1, ncoarse = -1;
+};
+
 struct MixedState {
   std::vector<LinLevel> lv;
   std::vector<void*> owned;
   KryState kry;
   std::vector<void*> kry_owned;
+  CoarseGraph cg;
 };
 
 static TileCfg lin_tiles(int n) {
@@ -718,6 +798,10 @@ void Ctx::release_extra() {
   if (mixed) {
     for (void* p : mixed->owned) (void)hipFree(p);
     for (void* p : mixed->kry_owned) (void)hipFree(p);
+    CoarseGraph& g = mixed->cg;
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    if (g.cs) (void)hipStreamDestroy(g.cs);
     delete mixed;
     mixed = nullptr;
   }
@@ -727,10 +811,56 @@ void Ctx::release_extra() {
 
 double* Ctx::linsum(int l) { return scal + kSlotLin + 3 * l; }
 
-int Ctx::lin_sweep(int l) {
+int Ctx::lin_sweep(int l, bool zero_start) {
   LinLevel& L = mixed->lv[l];
   Level& F = lv[l];
   double* cs = linsum(l);
+  if (zero_start && L.sw.tm == 0) {   // no two-launch tile on this mesh: clear e and sweep as usual
+    hipError_t e = launch_fill32(L.e[L.cur], 0.0f, F.cells, stream);
+    if (e != hipSuccess) return hip_fail(e, "fill");
+    zero_start = false;
+  }
+  if (zero_start) {
+    // e = 0 on entry: the red half needs no neighbours; the black half-sweep then runs as usual on
+    // the new red values and a zero black snapshot
+    const size_t half = F.cells / 2;
+    const int ev = (l == 0) ? timer.begin(stream) : -1;
+    // few large blocks: each block's counter release costs an L2 writeback, so the grid stays at
+    // one block per CU (16 waves each) however large the level
+    const int nbz = (int)std::min<size_t>(256, (half / 4 + 1023) / 1024);
+    // the pipelined black half-sweep takes the zero black snapshot as given; the others read it
+    const bool zb = L.sw.pipe;
+    hipLaunchKernelGGL(lin_red_zero_kernel, dim3(nbz), dim3(1024), 0, stream, (const float*)L.rhs, half,
+                       (float)(F.h * F.h), (const double*)cs, 1.0 / (double)F.cells, L.e[L.cur ^ 1],
+                       zb ? nullptr : L.e[L.cur] + half, partials, counter, cs + 2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "linear red half-sweep from zero");
+    LinSweepArgs a{};
+    a.e_in = L.e[L.cur];
+    a.e_red_new = L.e[L.cur ^ 1];
+    a.e_out = L.e[L.cur ^ 1];
+    a.base = L.base;
+    a.bq = scal + kSlotBase;
+    a.sb = L.sb;
+    a.rhs = L.rhs;
+    a.n = F.n;
+    a.colour = 1;
+    a.h2 = (float)(F.h * F.h);
+    a.ih2 = (float)(1.0 / (F.h * F.h));
+    a.c_sum = cs;
+    a.c_scale = 1.0 / (double)F.cells;
+    a.sum_out = cs + 1;
+    a.copy_from = cs + 2;
+    a.copy_to = cs + 0;
+    a.partials = partials;
+    a.counter = counter;
+    a.zero_black = zb ? 1 : 0;
+    e = launch_lin_half_sweep(a, L.sw, stream);
+    if (e != hipSuccess) return hip_fail(e, "linear black half-sweep");
+    timer.end(1, ev, stream);
+    L.cur ^= 1;
+    return MR_OK;
+  }
   if (L.fused && !(opts.flags & MR_FLAG_TWO_PASS)) {
     LinFusedArgs a{};
     a.e_in = L.e[L.cur];
@@ -786,30 +916,69 @@ int Ctx::lin_sweep(int l) {
   return MR_OK;
 }
 
-int Ctx::lin_vcycle(int l) {
+// Linear V-cycle on level l; zero: e of the level is zero on entry (it is then not read: the first
+// pre-smoothing sweep starts from zero, or the coarsest level is cleared first).
+int Ctx::lin_vcycle(int l, bool zero) {
   LinLevel& L = mixed->lv[l];
   Level& F = lv[l];
   hipError_t e;
   if (l == nlev - 1) {
-    e = launch_lin_coarsest(L.e[L.cur], L.base, scal + kSlotBase, L.sb, L.rhs, F.n, opts.ncoarse, F.h, linsum(l),
-                            1.0 / (double)F.cells, stream);
+    e = zero ? launch_fill32(L.e[L.cur], 0.0f, F.cells, stream) : hipSuccess;
+    if (e == hipSuccess)
+      e = launch_lin_coarsest(L.e[L.cur], L.base, scal + kSlotBase, L.sb, L.rhs, F.n, opts.ncoarse, F.h, linsum(l),
+                              1.0 / (double)F.cells, stream);
     return e == hipSuccess ? MR_OK : hip_fail(e, "linear coarsest");
   }
   int rc;
+  if (zero && opts.npre == 0 && (e = launch_fill32(L.e[L.cur], 0.0f, F.cells, stream)) != hipSuccess)
+    return hip_fail(e, "fill");
   for (int s = 0; s < opts.npre; ++s)
-    if ((rc = lin_sweep(l)) != MR_OK) return rc;
+    if ((rc = lin_sweep(l, zero && s == 0)) != MR_OK) return rc;
   LinLevel& Lc = mixed->lv[l + 1];
-  Level& Fc = lv[l + 1];
   e = launch_lin_resid_restrict(L.e[L.cur], L.base, scal + kSlotBase, L.sb, L.rhs, F.n, F.h,
                                 ShiftRef{linsum(l), 1.0 / (double)F.cells, 0.0}, Lc.rhs,
                                 Reduce{partials, counter, linsum(l + 1)}, stream);
-  if (e == hipSuccess) e = launch_fill32(Lc.e[Lc.cur], 0.0f, Fc.cells, stream);
   if (e != hipSuccess) return hip_fail(e, "linear restriction");
-  if ((rc = lin_vcycle(l + 1)) != MR_OK) return rc;
+  if ((rc = (l == 0 ? lin_coarse_cycle() : lin_vcycle(l + 1, true))) != MR_OK) return rc;
   e = launch_prolong_add32(Lc.e[Lc.cur], L.e[L.cur], F.n, stream);
   if (e != hipSuccess) return hip_fail(e, "linear prolongation");
   for (int s = 0; s < opts.npost; ++s)
     if ((rc = lin_sweep(l)) != MR_OK) return rc;
+  return MR_OK;
+}
+
+// lin_vcycle(1, true) through the captured graph (captured on first use, or again when the cycle
+// options change). The coarse levels start from zero, so their buffers' contents on entry do not
+// matter: each replay first puts the host-side ping-pong state back to the captured one.
+int Ctx::lin_coarse_cycle() {
+  CoarseGraph& g = mixed->cg;
+  hipError_t e = hipSuccess;
+  if (!g.exec || g.npre != opts.npre || g.npost != opts.npost || g.ncoarse != opts.ncoarse) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g.exec = nullptr;
+    g.graph = nullptr;
+    if (!g.cs && (e = hipStreamCreateWithFlags(&g.cs, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "stream");
+    g.cur_in.assign(nlev, 0);
+    for (int l = 1; l < nlev; ++l) g.cur_in[l] = mixed->lv[l].cur;
+    hipStream_t keep = stream;
+    stream = g.cs;
+    e = hipStreamBeginCapture(g.cs, hipStreamCaptureModeThreadLocal);
+    int rc = e == hipSuccess ? lin_vcycle(1, true) : hip_fail(e, "capture");
+    hipError_t e2 = hipStreamEndCapture(g.cs, &g.graph);
+    stream = keep;
+    if (rc != MR_OK) return rc;
+    if (e2 != hipSuccess) return hip_fail(e2, "capture");
+    if ((e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0)) != hipSuccess) return hip_fail(e, "graph");
+    g.cur_out.assign(nlev, 0);
+    for (int l = 1; l < nlev; ++l) g.cur_out[l] = mixed->lv[l].cur;
+    g.npre = opts.npre;
+    g.npost = opts.npost;
+    g.ncoarse = opts.ncoarse;
+  }
+  for (int l = 1; l < nlev; ++l) mixed->lv[l].cur = g.cur_in[l];
+  if ((e = hipGraphLaunch(g.exec, stream)) != hipSuccess) return hip_fail(e, "graph launch");
+  for (int l = 1; l < nlev; ++l) mixed->lv[l].cur = g.cur_out[l];
   return MR_OK;
 }
 
@@ -832,11 +1001,9 @@ int Ctx::lin_base_hierarchy() {
 int Ctx::lin_solve(int ncycles) {
   LinLevel& M0 = mixed->lv[0];
   M0.cur = 0;
-  hipError_t e = launch_fill32(M0.e[0], 0.0f, lv[0].cells, stream);
-  if (e != hipSuccess) return hip_fail(e, "fill");
   int rc;
   for (int k = 0; k < ncycles; ++k)
-    if ((rc = lin_vcycle(0)) != MR_OK) return rc;
+    if ((rc = lin_vcycle(0, k == 0)) != MR_OK) return rc;
   return MR_OK;
 }
 
@@ -948,7 +1115,6 @@ int Ctx::kry_step(double* theta64, int m, double rhs_sum, double rhs_sq, double 
   const double beta2 = rhs_sq - rhs_sum * rhs_sum / N;
   const double beta = std::sqrt(beta2 > 0.0 ? beta2 : 0.0);
   if (!(beta > 0.0)) return MR_OK;   // nothing to correct
-  const int nb = (int)std::min<size_t>((cells + 255) / 256, (size_t)kKryBlocks);
   const int nbu = lin_blocks(cells);
   KryPtrs vp{}, zp{};
   KryCoef cf{};
@@ -973,30 +1139,17 @@ int Ctx::kry_step(double* theta64, int m, double rhs_sum, double rhs_sq, double 
     M0.cur = 0;
     hipLaunchKernelGGL(zero_scalars_kernel, dim3(1), dim3(64), 0, stream, linsum(0), 2);
     e = hipGetLastError();
-    if (e == hipSuccess) e = launch_fill32(K.Z[i], 0.0f, cells, stream);
     if (e != hipSuccess) rc = hip_fail(e, "Krylov cycle start");
-    if (rc == MR_OK) rc = lin_vcycle(0);
+    if (rc == MR_OK) rc = lin_vcycle(0, true);
     if (rc == MR_OK && M0.cur == 1) std::swap(K.Z[i], K.S);   // the result ended in the spare buffer
     M0.rhs = rhs_own;
     M0.e[0] = e_own[0];
     M0.e[1] = e_own[1];
     if (rc != MR_OK) return rc;
-    // w = J z_i, then its projections on v_0 .. v_i, its sum and its square
-    e = launch_lin_apply(K.Z[i], M0.base, scal + kSlotBase, M0.sb, lv[0].n, lv[0].h, K.W, M0.sw, stream);
+    // w = J z_i, with its projections on v_0 .. v_i, its sum and its square
     for (int j = 0; j <= i; ++j) vp.p[j] = K.V[j];
-    if (e == hipSuccess) {
-      switch (i + 1) {
-#define MR_KD_CASE(KK)                                                                                          \
-        case KK:                                                                                                \
-          hipLaunchKernelGGL((kry_dots_kernel<KK>), dim3(nb), dim3(256), 0, stream, (const float*)K.W, vp, cells, \
-                             K.partials, K.counter, K.result);                                                  \
-          break;
-        MR_KD_CASE(1) MR_KD_CASE(2) MR_KD_CASE(3) MR_KD_CASE(4) MR_KD_CASE(5) MR_KD_CASE(6) MR_KD_CASE(7)
-        MR_KD_CASE(8)
-#undef MR_KD_CASE
-      }
-      e = hipGetLastError();
-    }
+    e = launch_lin_apply_dots(K.Z[i], M0.base, scal + kSlotBase, M0.sb, lv[0].n, lv[0].h, K.W, vp, i + 1, K.partials,
+                              K.counter, K.result, stream);
     double d[kKryNV];
     if (e == hipSuccess) e = hipMemcpyAsync(d, K.result, (i + 3) * sizeof(double), hipMemcpyDeviceToHost, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -1068,9 +1221,15 @@ int Ctx::solve_mixed(const double* delta, double* theta, mr_info* info, int aa_d
   if (e == hipSuccess && (rc = write_scalar(kSlotTmax, 0.0)) != MR_OK) return rc;
   if (e == hipSuccess && opts.warm_start) e = launch_absmax(L0.th[0], L0.cells, scal + kSlotTmax, stream);
   if (e != hipSuccess) return hip_fail(e, "initial theta");
-  double r0, m0;
-  if ((rc = finest_norm(nullptr, ShiftRef{nullptr, 0.0, 0.0}, &r0, &m0)) != MR_OK) return rc;
-  if (r0 == 0.0) r0 = 1.0;
+  // reference norm: the residual at theta = 0. From a cold start the first outer residual is that
+  // residual (its variance does not depend on the shift it is evaluated with), so it is not
+  // evaluated twice.
+  const bool cold = !opts.warm_start;
+  double r0 = 1.0, m0 = 0.0;
+  if (!cold) {
+    if ((rc = finest_norm(nullptr, ShiftRef{nullptr, 0.0, 0.0}, &r0, &m0)) != MR_OK) return rc;
+    if (r0 == 0.0) r0 = 1.0;
+  }
   // running sum of Sigma for the shift of the outer residual: (sum Sigma, 0) at theta = 0
   if ((rc = write_scalar(kSlotRes, m0 * N3)) != MR_OK) return rc;
   if ((rc = write_scalar(kSlotRes + 1, 0.0)) != MR_OK) return rc;
@@ -1088,6 +1247,11 @@ int Ctx::solve_mixed(const double* delta, double* theta, mr_info* info, int aa_d
     double r[4];
     if ((rc = read_scalars(kSlotRes, 4, r)) != MR_OK) return rc;
     const double var = r[3] - r[2] * r[2] / N3;
+    if (cold && it == 0) {
+      r0 = std::sqrt(var > 0.0 ? var : 0.0);
+      if (r0 == 0.0) r0 = 1.0;
+      loc.r0_norm = r0;
+    }
     rel = std::sqrt(var > 0.0 ? var : 0.0) / r0;
     msig = r[0] / N3;
     if (it < 128) loc.history[it] = rel;

@@ -426,28 +426,10 @@ inline __device__ void prolong_rows32_body(const float* __restrict__ ec, float* 
   const int I = blk / groups, J0 = (blk - I * groups) * R;
   const int tid = threadIdx.x;
   const unsigned halfc = (unsigned)nc * (unsigned)nc * (unsigned)nch;
-  const int rows = 3 * (R + 2);
-  for (int x = tid; x < rows * nc; x += 256) {
-    const int w = x / nc, pos = x - w * nc;
-    const int a = w / (R + 2), b = w - a * (R + 2);
-    const int c = pos / nch, m = pos - c * nch;
-    const int ii = wrapi(I - 1 + a, nc), jj = wrapi(J0 - 1 + b, nc);
-    cl[w * nc + 2 * m + ((ii + jj + c) & 1)] = ec[(unsigned)c * halfc + ((unsigned)ii * nc + jj) * (unsigned)nch + m];
-  }
-  __syncthreads();
   const int r = tid / nc, K = tid - r * nc;
   const int J = J0 + r;
-  const int km = K == 0 ? nc - 1 : K - 1, kp = K == nc - 1 ? 0 : K + 1;
-  float c3[3][3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      const float* row = cl + (a * (R + 2) + r + b) * nc;
-      c3[a][b][0] = row[km];
-      c3[a][b][1] = row[K];
-      c3[a][b][2] = row[kp];
-    }
+  // the fine values this thread corrects are loaded first, so that their latency overlaps the
+  // staging of the coarse rows
   const unsigned half = (unsigned)n * (unsigned)n * (unsigned)nh;
   unsigned off[2][2];
   int c0[2][2];
@@ -459,8 +441,28 @@ inline __device__ void prolong_rows32_body(const float* __restrict__ ec, float* 
       const int i = 2 * I + a, j = 2 * J + b;
       off[a][b] = ((unsigned)i * n + j) * (unsigned)nh + K;
       c0[a][b] = (i + j) & 1;
-      t[a][b][0] = e[c0[a][b] * half + off[a][b]];
-      t[a][b][1] = e[(1 - c0[a][b]) * half + off[a][b]];
+      t[a][b][0] = __builtin_nontemporal_load(e + c0[a][b] * half + off[a][b]);
+      t[a][b][1] = __builtin_nontemporal_load(e + (1 - c0[a][b]) * half + off[a][b]);
+    }
+  const int rows = 3 * (R + 2);
+  for (int x = tid; x < rows * nc; x += 256) {
+    const int w = x / nc, pos = x - w * nc;
+    const int a = w / (R + 2), b = w - a * (R + 2);
+    const int c = pos / nch, m = pos - c * nch;
+    const int ii = wrapi(I - 1 + a, nc), jj = wrapi(J0 - 1 + b, nc);
+    cl[w * nc + 2 * m + ((ii + jj + c) & 1)] = ec[(unsigned)c * halfc + ((unsigned)ii * nc + jj) * (unsigned)nch + m];
+  }
+  __syncthreads();
+  const int km = K == 0 ? nc - 1 : K - 1, kp = K == nc - 1 ? 0 : K + 1;
+  float c3[3][3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const float* row = cl + (a * (R + 2) + r + b) * nc;
+      c3[a][b][0] = row[km];
+      c3[a][b][1] = row[K];
+      c3[a][b][2] = row[kp];
     }
   const float wI[2] = {0.75f, 0.25f};
 #pragma unroll
@@ -477,11 +479,134 @@ inline __device__ void prolong_rows32_body(const float* __restrict__ ec, float* 
         lo += w * (0.75f * ek + 0.25f * c3[ia][jb][0]);
         hi += w * (0.75f * ek + 0.25f * c3[ia][jb][2]);
       }
-      e[c0[a][b] * half + off[a][b]] = t[a][b][0] + lo;
-      e[(1 - c0[a][b]) * half + off[a][b]] = t[a][b][1] + hi;
+      __builtin_nontemporal_store(t[a][b][0] + lo, e + c0[a][b] * half + off[a][b]);
+      __builtin_nontemporal_store(t[a][b][1] + hi, e + (1 - c0[a][b]) * half + off[a][b]);
     }
 }
 constexpr int kProlongRowsLds = 3 * (256 + 2 * 256);   // floats of cl
+
+// Pipelined form of the same prolongation for 128 <= nc <= 256: a block of 1024 threads owns
+// TJC = 1024 / nc coarse rows (all nc columns) and marches through a chunk of coarse planes. Each
+// coarse plane is staged once (rows J0-1 .. J0+TJC, natural k order) in a two-slot LDS ring, and
+// each thread keeps the in-plane (j, k) interpolation of planes I-1, I, I+1 at its four fine
+// (j, k) positions in registers, so a plane step reads one staged plane and interpolates in i
+// from registers. Coarse planes are fetched one step before they are staged.
+inline __host__ __device__ bool prolong_pipe_ok(int n) {
+  const int nc = n / 2;
+  return nc == 128 || nc == 256;
+}
+constexpr int kProlongPipeLds = 2 * 10 * 256;   // floats: 2 slots of (TJC + 2) rows x nc
+
+inline __device__ void prolong_pipe32_body(const float* __restrict__ ec, float* __restrict__ e, int n, int logical,
+                                           int nchunks, float* __restrict__ cl) {
+  const int nc = n >> 1, nh = nc, nch = nc >> 1;
+  const int tjc = 1024 / nc;
+  const int rows = tjc + 2;
+  const int slab = rows * nc;                  // floats of one staged plane
+  const int tiles = nc / tjc;
+  const int tile = logical % tiles, chunk = logical / tiles;
+  const int J0 = tile * tjc;
+  const int I0 = (int)(((long)chunk * nc) / nchunks), I1 = (int)(((long)(chunk + 1) * nc) / nchunks);
+  const int tid = threadIdx.x;
+  const unsigned halfc = (unsigned)nc * (unsigned)nc * (unsigned)nch;
+  const unsigned half = (unsigned)n * (unsigned)n * (unsigned)nh;
+  // staging: element x < slab of a plane is row w = x / nc, colour cc and column m of that row;
+  // two elements per thread (slab <= 2048)
+  float pf[2];
+  auto fetch = [&](int I) {
+    const int ii = wrapi(I, nc);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int x = tid + q * 1024;
+      if (x < slab) {
+        const int w = x / nc, pos = x - w * nc;
+        const int cc = pos / nch, m = pos - cc * nch;
+        const int jj = wrapi(J0 - 1 + w, nc);
+        pf[q] = ec[(unsigned)cc * halfc + ((unsigned)ii * nc + jj) * (unsigned)nch + m];
+      }
+    }
+  };
+  auto stage = [&](int I, int slot) {
+    const int ii = wrapi(I, nc);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int x = tid + q * 1024;
+      if (x < slab) {
+        const int w = x / nc, pos = x - w * nc;
+        const int cc = pos / nch, m = pos - cc * nch;
+        const int jj = wrapi(J0 - 1 + w, nc);
+        cl[slot * slab + w * nc + 2 * m + ((ii + jj + cc) & 1)] = pf[q];
+      }
+    }
+  };
+  const int r = tid / nc, K = tid - r * nc;
+  const int J = J0 + r;
+  const int km = K == 0 ? nc - 1 : K - 1, kp = K == nc - 1 ? 0 : K + 1;
+  // in-plane interpolation of a staged plane at fine rows 2J + b and columns 2K + kk:
+  // q[2 b + kk]; 3/4 of the own coarse row / column and 1/4 of the neighbour on that side
+  auto interp = [&](int slot, float (&q)[4]) {
+    const float* c = cl + slot * slab + r * nc;   // rows J-1, J, J+1 at c, c + nc, c + 2 nc
+    float lo[3], hi[3];
+    const int kk[3] = {km, K, kp};
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const float cm = c[kk[u]], c0 = c[nc + kk[u]], cp = c[2 * nc + kk[u]];
+      lo[u] = 0.75f * c0 + 0.25f * cm;
+      hi[u] = 0.75f * c0 + 0.25f * cp;
+    }
+    q[0] = 0.75f * lo[1] + 0.25f * lo[0];
+    q[1] = 0.75f * lo[1] + 0.25f * lo[2];
+    q[2] = 0.75f * hi[1] + 0.25f * hi[0];
+    q[3] = 0.75f * hi[1] + 0.25f * hi[2];
+  };
+  float Qm[4], Q0[4], Qp[4];
+  fetch(I0 - 1);
+  stage(I0 - 1, 0);
+  fetch(I0);
+  stage(I0, 1);
+  __syncthreads();
+  interp(0, Qm);
+  interp(1, Q0);
+  fetch(I0 + 1);
+  __syncthreads();   // slot 0 is read
+  stage(I0 + 1, 0);
+  __syncthreads();
+  for (int I = I0; I < I1; ++I) {
+    const int slot = (I - I0) & 1;               // plane I + 1 is staged here
+    fetch(I + 2);                                 // (one plane past the chunk on the last step: unused)
+    unsigned off[2][2];
+    int c0[2][2];
+    float t[2][2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int i = 2 * I + a, j = 2 * J + b;
+        off[a][b] = ((unsigned)i * n + j) * (unsigned)nh + K;
+        c0[a][b] = (i + j) & 1;
+        t[a][b][0] = __builtin_nontemporal_load(e + c0[a][b] * half + off[a][b]);
+        t[a][b][1] = __builtin_nontemporal_load(e + (1 - c0[a][b]) * half + off[a][b]);
+      }
+    interp(slot, Qp);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const float* nb = a ? Qp : Qm;
+        const float lo = 0.75f * Q0[2 * b] + 0.25f * nb[2 * b];
+        const float hi = 0.75f * Q0[2 * b + 1] + 0.25f * nb[2 * b + 1];
+        __builtin_nontemporal_store(t[a][b][0] + lo, e + c0[a][b] * half + off[a][b]);
+        __builtin_nontemporal_store(t[a][b][1] + hi, e + (1 - c0[a][b]) * half + off[a][b]);
+      }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      Qm[u] = Q0[u];
+      Q0[u] = Qp[u];
+    }
+    stage(I + 2, slot ^ 1);                       // the slot read in the previous step
+    __syncthreads();
+  }
+}
 
 // Linear coarsest solve: nsweeps red-black sweeps in one block (FP32, natural order in LDS).
 struct LinCoarsestShared {
@@ -574,9 +699,8 @@ inline __device__ void fill32_body(float* __restrict__ a, float v, size_t cells,
 // lin_sweep_body's decomposition and arithmetic with the colour compile-time and the plane loop
 // unrolled by the ring length (compile-time LDS slots); planes are fetched two steps before they
 // enter LDS and the base root / right-hand side two steps before use. Requires ci % 4 == 0.
-// With APPLY the body instead writes the operator itself, (J e)_c = nabla^2 e - dSigma(e) at the
-// cells of colour COL (e_in holds both colours of e; rhs and the sums are not used).
-template <int TM, int TJ, int COL, bool APPLY = false>
+// ZB (black half only): the old black values are zero, so they are not loaded.
+template <int TM, int TJ, int COL, bool ZB = false>
 __device__ void lin_sweep_pipe_body(const LinSweepArgs& a, int logical, int bid, int nblocks, float* lds) {
   constexpr int NT = TM * TJ;
   constexpr int RW = TM + 2;
@@ -593,8 +717,8 @@ __device__ void lin_sweep_pipe_body(const LinSweepArgs& a, int logical, int bid,
   const size_t plane = (size_t)n * nh;
   const size_t half = plane * n;
   const unsigned pbytes = (unsigned)plane * 4u;
-  const float* __restrict__ f0 = COL == 1 && !APPLY ? a.e_red_new : a.e_in;   // e red
-  const float* __restrict__ f1 = a.e_in + half;                                 // e black
+  const float* __restrict__ f0 = COL == 1 ? a.e_red_new : a.e_in;   // e red
+  const float* __restrict__ f1 = a.e_in + half;                      // e black
   const float* __restrict__ f2 = reinterpret_cast<const float*>(a.base);          // base red (fixed-point bits)
   const float* __restrict__ f3 = reinterpret_cast<const float*>(a.base) + half;   // base black
   // global accesses through a buffer resource of one plane (uniform) and a per-lane byte offset
@@ -615,13 +739,20 @@ __device__ void lin_sweep_pipe_body(const LinSweepArgs& a, int logical, int bid,
   }
   auto fetch = [&](int rel, float (&v)[NPF]) {
     const int p = wrapi(i0 - 1 + rel, n);
-    const auto b0 = prs(f0, p), b1 = prs(f1, p), b2 = prs(f2, p), b3 = prs(f3, p);
+    const auto b0 = prs(f0, p), b2 = prs(f2, p), b3 = prs(f3, p);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       v[0 * PER + k] = ld_rs_f(b0, goff[k]);
-      v[1 * PER + k] = ld_rs_f(b1, goff[k]);
       v[2 * PER + k] = ld_rs_f(b2, goff[k]);
       v[3 * PER + k] = ld_rs_f(b3, goff[k]);
+    }
+    if (!ZB) {
+      const auto b1 = prs(f1, p);
+#pragma unroll
+      for (int k = 0; k < PER; ++k) v[1 * PER + k] = ld_rs_f(b1, goff[k]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < PER; ++k) v[1 * PER + k] = 0.0f;
     }
   };
   auto store = [&](int slot, const float (&v)[NPF]) {
@@ -660,11 +791,9 @@ __device__ void lin_sweep_pipe_body(const LinSweepArgs& a, int logical, int bid,
   }
   fetch(3, V0);
   SB[0] = ld_rs_f_nt(prs(sbc, i0), o_c);
+  RH[0] = ld_rs_f_nt(prs(rc, i0), o_c);
   SB[1] = ld_rs_f_nt(prs(sbc, min(i0 + 1, last_plane)), o_c);
-  if (!APPLY) {
-    RH[0] = ld_rs_f_nt(prs(rc, i0), o_c);
-    RH[1] = ld_rs_f_nt(prs(rc, min(i0 + 1, last_plane)), o_c);
-  }
+  RH[1] = ld_rs_f_nt(prs(rc, min(i0 + 1, last_plane)), o_c);
   __syncthreads();
 
   auto step = [&](auto kc, int t, float (&vst)[NPF], float (&vft)[NPF]) {
@@ -673,7 +802,7 @@ __device__ void lin_sweep_pipe_body(const LinSweepArgs& a, int logical, int bid,
     fetch(t + 4, vft);
     const int pn = min(i0 + t + 2, last_plane);
     SB[(K + 2) & 3] = ld_rs_f_nt(prs(sbc, pn), o_c);
-    if (!APPLY) RH[(K + 2) & 3] = ld_rs_f_nt(prs(rc, pn), o_c);
+    RH[(K + 2) & 3] = ld_rs_f_nt(prs(rc, pn), o_c);
     const int oq = (K & 1) ? oq1 : oq0;
     Nb18f te, tb;
 #define MR_LP_GATHER(T, LO, LC)                                                        \
@@ -695,14 +824,9 @@ __device__ void lin_sweep_pipe_body(const LinSweepArgs& a, int logical, int bid,
 #undef MR_LP_GATHER
     float Se;
     const float g = lin_source(tb, lds[(2 + COL) * 4 * SLOT + S0 * SLOT + ob], bscl, SB[K], ih2, te, Se) * ih2;
-    if (APPLY) {
-      const float ec = lds[COL * 4 * SLOT + S0 * SLOT + ob];
-      st_rs_f_nt(prs(out, i0 + t), o_c, (Se - 6.0f * ec) * ih2 - g);
-    } else {
-      const float rhs = RH[K];
-      st_rs_f_nt(prs(out, i0 + t), o_c, (Se - h2 * (g + rhs - C)) * (1.0f / 6.0f));
-      acc += (double)(g + rhs);
-    }
+    const float rhs = RH[K];
+    st_rs_f_nt(prs(out, i0 + t), o_c, (Se - h2 * (g + rhs - C)) * (1.0f / 6.0f));
+    acc += (double)(g + rhs);
     store(SN, vst);
     __syncthreads();
   };
@@ -712,7 +836,6 @@ __device__ void lin_sweep_pipe_body(const LinSweepArgs& a, int logical, int bid,
     step(std::integral_constant<int, 2>(), t + 2, V0, V1);
     step(std::integral_constant<int, 3>(), t + 3, V1, V0);
   }
-  if (APPLY) return;
   double vv[1] = {acc};
   const bool last = grid_sum<1>(vv, a.partials, a.counter, a.sum_out, nblocks, bid);
   if (last && tid == 0 && a.copy_to) *a.copy_to = *a.copy_from;
@@ -811,13 +934,28 @@ __device__ void lin_resid_restrict_tiled_body(const LinRRArgs& a, int logical, i
     store(1, vb);
     store(2, vc);
   }
+  // root and right-hand side of the thread's 4 cells of a plane, fetched one plane step ahead
+  // (the last fetch of a chunk reads a clamped plane and is not used)
+  auto pre = [&](int t, float (&p)[8]) {
+    const int i = min(i0 + t, n - 1);
+#pragma unroll
+    for (int cell = 0; cell < 4; ++cell) {
+      const int j = j0 + 2 * rr + (cell >> 1);
+      const unsigned o = (unsigned)(cell & 1) * half + (unsigned)i * plane + (unsigned)j * nh + m;
+      p[cell] = __builtin_nontemporal_load(a.sb + o);
+      p[4 + cell] = __builtin_nontemporal_load(a.rhs + o);
+    }
+  };
+  float PA[8], PB[8];
+  pre(0, PA);
   fetch(3, V0);
   __syncthreads();
 
-  auto step = [&](auto kc, int t, float (&vst)[NPF], float (&vft)[NPF]) {
+  auto step = [&](auto kc, int t, float (&vst)[NPF], float (&vft)[NPF], const float (&pc)[8], float (&pn)[8]) {
     constexpr int K = decltype(kc)::value;
     constexpr int SM = K & 3, S0 = (K + 1) & 3, SP = (K + 2) & 3, SN = (K + 3) & 3;
     fetch(t + 4, vft);
+    pre(t + 1, pn);
     const int i = i0 + t;
 #pragma unroll 1
     for (int cell = 0; cell < 4; ++cell) {
@@ -825,8 +963,9 @@ __device__ void lin_resid_restrict_tiled_body(const LinRRArgs& a, int logical, i
       const int r = 2 * rr + dr;
       const int j = j0 + r;
       const int ob = (r + 1) * RW + (s + 1);
-      const unsigned o = (unsigned)c * half + (unsigned)i * plane + (unsigned)j * nh + m;
-      const float sbv = a.sb[o], rhv = a.rhs[o];
+      // register selects (a dynamic index would put the arrays in scratch memory)
+      const float sbv = cell == 0 ? pc[0] : cell == 1 ? pc[1] : cell == 2 ? pc[2] : pc[3];
+      const float rhv = cell == 0 ? pc[4] : cell == 1 ? pc[5] : cell == 2 ? pc[6] : pc[7];
       {
         const int q = (i + j + c) & 1;
         const int oq = ob + q;
@@ -868,10 +1007,10 @@ __device__ void lin_resid_restrict_tiled_body(const LinRRArgs& a, int logical, i
     __syncthreads();
   };
   for (int t = 0; t < i1 - i0; t += 4) {
-    step(std::integral_constant<int, 0>(), t, V0, V1);
-    step(std::integral_constant<int, 1>(), t + 1, V1, V0);
-    step(std::integral_constant<int, 2>(), t + 2, V0, V1);
-    step(std::integral_constant<int, 3>(), t + 3, V1, V0);
+    step(std::integral_constant<int, 0>(), t, V0, V1, PA, PB);
+    step(std::integral_constant<int, 1>(), t + 1, V1, V0, PB, PA);
+    step(std::integral_constant<int, 2>(), t + 2, V0, V1, PA, PB);
+    step(std::integral_constant<int, 3>(), t + 3, V1, V0, PB, PA);
   }
   double vv[2] = {acc, 0.0};
   grid_sum<2>(vv, a.red.partials, a.red.counter, a.red.result, nblocks, bid);
@@ -1305,14 +1444,43 @@ __device__ void lin_fused_body(const LinFusedArgs& a, int logical, int bid, int 
   grid_sum<2>(vv, a.partials, a.counter, a.sum_out, nblocks, bid);
 }
 
-// ---- the linear operator applied to both colours in one pass ----------------------------------
-// w = nabla^2 z - dSigma(z) at every cell: the pipelined sweep's tile decomposition and 4-slot plane
-// ring (z and the base, both colours, one-cell halo), with each thread evaluating the red and the
-// black cell of its (j, m) column per plane. No cell depends on another's result, so one launch
-// covers both colours (the two one-colour launches each read both colours of z and of the base).
-template <int TM, int TJ>
-__device__ void lin_apply_both_body(const LinSweepArgs& a, int logical, float* lds) {
-  constexpr int NT = TM * TJ;
+// ---- vector kernels of the Krylov-accelerated inner solve -------------------------------------
+constexpr int kKryMax = 8;          // longest Krylov space of the inner solve
+constexpr int kKryBlocks = 1024;    // blocks of the reducing vector kernels
+constexpr int kApplyBlocks = 256;   // preferred block count of the fused operator product
+constexpr int kKryNV = kKryMax + 2; // values reduced per block
+struct KryPtrs {
+  const float* p[kKryMax + 1];
+};
+struct KryCoef {
+  double c[kKryMax + 1];
+};
+
+// ---- the linear operator applied to both colours in one pass, with the Krylov projections ------
+// w = nabla^2 z - dSigma(z) at every cell, and the sums w v_j (j < K), w and w^2. The pipelined
+// sweep's tile decomposition and 4-slot plane ring (z and the base, both colours, one-cell halo);
+// the block has two threads per (j, m) column of its TM x TJ tile, the first half evaluating the red
+// cell of each plane and the second half the black one. No cell depends on another's result, so one
+// launch covers both colours, and the projections are accumulated where w is produced.
+struct LinApplyArgs {
+  const float* z;
+  const int* base;
+  const double* bq;
+  const float* sb;
+  float* w;
+  int n;
+  float ih2;
+  int tiles_j, tiles_m, ci;
+  KryPtrs v;
+  double* partials;
+  unsigned* counter;
+  double* result;
+};
+
+template <int TM, int TJ, int K>
+__device__ void lin_apply_dots_body(const LinApplyArgs& a, int logical, int bid, int nblocks, float* lds) {
+  constexpr int NC = TM * TJ;        // columns of the tile
+  constexpr int NT = 2 * NC;         // threads
   constexpr int RW = TM + 2;
   constexpr int SLOT = LinTile<TM, TJ>::SLOT;
   constexpr int PER = (SLOT + NT - 1) / NT;
@@ -1326,8 +1494,8 @@ __device__ void lin_apply_both_body(const LinSweepArgs& a, int logical, float* l
   const size_t plane = (size_t)n * nh;
   const size_t half = plane * n;
   const unsigned pbytes = (unsigned)plane * 4u;
-  const float* __restrict__ f0 = a.e_in;
-  const float* __restrict__ f1 = a.e_in + half;
+  const float* __restrict__ f0 = a.z;
+  const float* __restrict__ f1 = a.z + half;
   const float* __restrict__ f2 = reinterpret_cast<const float*>(a.base);
   const float* __restrict__ f3 = reinterpret_cast<const float*>(a.base) + half;
   auto prs = [&](const float* arr, int p) { return plane_rsrc(arr + (size_t)p * plane, pbytes); };
@@ -1359,19 +1527,27 @@ __device__ void lin_apply_both_body(const LinSweepArgs& a, int logical, float* l
 #pragma unroll
       for (int k = 0; k < PER; ++k) lds[(f * 4 + slot) * SLOT + loff[k]] = v[f * PER + k];
   };
-  const int s = tid % TM, r = tid / TM;
+  const int c = tid / NC;            // colour of this thread's cells (wave-uniform: NC is a multiple of 64)
+  const int col = tid - c * NC;
+  const int s = col % TM, r = col / TM;
   const int j = j0 + r, m = m0 + s;
   const unsigned o_c = ((unsigned)j * nh + m) * 4u;
   const int ob = (r + 1) * RW + (s + 1);
-  const int qr = (i0 + j) & 1;   // z-parity of the red cell of this column at plane i0 (black: 1 - qr)
+  const int q0 = (i0 + j + c) & 1;
+  const int oq0 = ob + q0, oq1 = ob + (q0 ^ 1);
   const float ih2 = a.ih2, bscl = (float)a.bq[0];
-  const float* __restrict__ sbR = a.sb;
-  const float* __restrict__ sbB = a.sb + half;
-  float* __restrict__ outR = a.e_out;
-  float* __restrict__ outB = a.e_out + half;
+  const float* __restrict__ sbc = a.sb + c * half;
+  float* __restrict__ out = a.w + c * half;
   const int last_plane = n - 1;
+  const float* lo = lds + (1 - c) * 4 * SLOT;       // z of the other colour
+  const float* lc = lds + c * 4 * SLOT;             // z of this colour
+  const float* bo = lds + (3 - c) * 4 * SLOT;       // base of the other colour
+  const float* bc = lds + (2 + c) * 4 * SLOT;       // base of this colour
+  double acc[K + 2];
+#pragma unroll
+  for (int q = 0; q < K + 2; ++q) acc[q] = 0.0;
   float V0[NPF], V1[NPF];
-  float SR[4], SBv[4];
+  float SB[4];
   {
     float va[NPF], vb[NPF], vc[NPF];
     fetch(0, va);
@@ -1382,48 +1558,45 @@ __device__ void lin_apply_both_body(const LinSweepArgs& a, int logical, float* l
     store(2, vc);
   }
   fetch(3, V0);
-  SR[0] = ld_rs_f_nt(prs(sbR, i0), o_c);
-  SBv[0] = ld_rs_f_nt(prs(sbB, i0), o_c);
-  SR[1] = ld_rs_f_nt(prs(sbR, min(i0 + 1, last_plane)), o_c);
-  SBv[1] = ld_rs_f_nt(prs(sbB, min(i0 + 1, last_plane)), o_c);
+  SB[0] = ld_rs_f_nt(prs(sbc, i0), o_c);
+  SB[1] = ld_rs_f_nt(prs(sbc, min(i0 + 1, last_plane)), o_c);
+  // the Krylov vectors at the thread's cell, one plane step ahead (two register sets)
+  constexpr int KV = K > 0 ? K : 1;
+  float VJ[2][KV];
+#pragma unroll
+  for (int q = 0; q < K; ++q) VJ[0][q] = ld_rs_f_nt(prs(a.v.p[q] + c * half, i0), o_c);
   __syncthreads();
   auto step = [&](auto kc, int t, float (&vst)[NPF], float (&vft)[NPF]) {
-    constexpr int K = decltype(kc)::value;
-    constexpr int SM = K & 3, S0 = (K + 1) & 3, SP = (K + 2) & 3, SN = (K + 3) & 3;
+    constexpr int KK = decltype(kc)::value;
+    constexpr int SM = KK & 3, S0 = (KK + 1) & 3, SP = (KK + 2) & 3, SN = (KK + 3) & 3;
     fetch(t + 4, vft);
-    const int pn = min(i0 + t + 2, last_plane);
-    SR[(K + 2) & 3] = ld_rs_f_nt(prs(sbR, pn), o_c);
-    SBv[(K + 2) & 3] = ld_rs_f_nt(prs(sbB, pn), o_c);
-    // z-parity at plane i0 + t: red (qr ^ (K & 1)), black the opposite
-    const int q_red = qr ^ (K & 1);
+    SB[(KK + 2) & 3] = ld_rs_f_nt(prs(sbc, min(i0 + t + 2, last_plane)), o_c);
+    const float (&vj)[KV] = VJ[KK & 1];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const int oq = ob + (c == 0 ? q_red : q_red ^ 1);
-      const int O = 1 - c;
-      Nb18f te, tb;
-#define MR_LA_GATHER(T, LO, LC)                                                        \
-      {                                                                                \
-        const float* lo = lds + (LO) * 4 * SLOT;                                        \
-        const float* lc = lds + (LC) * 4 * SLOT;                                        \
-        T.xm = lo[SM * SLOT + ob];         T.xp = lo[SP * SLOT + ob];                   \
-        T.ym = lo[S0 * SLOT + ob - RW];    T.yp = lo[S0 * SLOT + ob + RW];              \
-        T.zm = lo[S0 * SLOT + oq - 1];     T.zp = lo[S0 * SLOT + oq];                   \
-        T.xpyp = lc[SP * SLOT + ob + RW];  T.xmym = lc[SM * SLOT + ob - RW];            \
-        T.xpym = lc[SP * SLOT + ob - RW];  T.xmyp = lc[SM * SLOT + ob + RW];            \
-        T.xpzp = lc[SP * SLOT + oq];       T.xmzm = lc[SM * SLOT + oq - 1];             \
-        T.xpzm = lc[SP * SLOT + oq - 1];   T.xmzp = lc[SM * SLOT + oq];                 \
-        T.ypzp = lc[S0 * SLOT + oq + RW];  T.ymzm = lc[S0 * SLOT + oq - RW - 1];        \
-        T.ypzm = lc[S0 * SLOT + oq + RW - 1]; T.ymzp = lc[S0 * SLOT + oq - RW];         \
-      }
-      MR_LA_GATHER(te, O, c)
-      MR_LA_GATHER(tb, 2 + O, 2 + c)
-#undef MR_LA_GATHER
-      float Se;
-      const float g = lin_source(tb, lds[(2 + c) * 4 * SLOT + S0 * SLOT + ob], bscl, c == 0 ? SR[K] : SBv[K], ih2, te,
-                                 Se) * ih2;
-      const float zc = lds[c * 4 * SLOT + S0 * SLOT + ob];
-      st_rs_f_nt(prs(c == 0 ? outR : outB, i0 + t), o_c, (Se - 6.0f * zc) * ih2 - g);
-    }
+    for (int q = 0; q < K; ++q) VJ[(KK + 1) & 1][q] = ld_rs_f_nt(prs(a.v.p[q] + c * half, min(i0 + t + 1, last_plane)), o_c);
+    const int oq = (KK & 1) ? oq1 : oq0;
+    Nb18f te, tb;
+#define MR_AD_GATHER(T, LO, LC)                                                        \
+    T.xm = LO[SM * SLOT + ob];         T.xp = LO[SP * SLOT + ob];                       \
+    T.ym = LO[S0 * SLOT + ob - RW];    T.yp = LO[S0 * SLOT + ob + RW];                  \
+    T.zm = LO[S0 * SLOT + oq - 1];     T.zp = LO[S0 * SLOT + oq];                       \
+    T.xpyp = LC[SP * SLOT + ob + RW];  T.xmym = LC[SM * SLOT + ob - RW];                \
+    T.xpym = LC[SP * SLOT + ob - RW];  T.xmyp = LC[SM * SLOT + ob + RW];                \
+    T.xpzp = LC[SP * SLOT + oq];       T.xmzm = LC[SM * SLOT + oq - 1];                 \
+    T.xpzm = LC[SP * SLOT + oq - 1];   T.xmzp = LC[SM * SLOT + oq];                     \
+    T.ypzp = LC[S0 * SLOT + oq + RW];  T.ymzm = LC[S0 * SLOT + oq - RW - 1];            \
+    T.ypzm = LC[S0 * SLOT + oq + RW - 1]; T.ymzp = LC[S0 * SLOT + oq - RW];
+    MR_AD_GATHER(te, lo, lc)
+    MR_AD_GATHER(tb, bo, bc)
+#undef MR_AD_GATHER
+    float Se;
+    const float g = lin_source(tb, bc[S0 * SLOT + ob], bscl, SB[KK], ih2, te, Se) * ih2;
+    const float wv = (Se - 6.0f * lc[S0 * SLOT + ob]) * ih2 - g;
+    st_rs_f_nt(prs(out, i0 + t), o_c, wv);
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] += (double)(wv * vj[q]);
+    acc[K] += (double)wv;
+    acc[K + 1] += (double)(wv * wv);
     store(SN, vst);
     __syncthreads();
   };
@@ -1433,18 +1606,8 @@ __device__ void lin_apply_both_body(const LinSweepArgs& a, int logical, float* l
     step(std::integral_constant<int, 2>(), t + 2, V0, V1);
     step(std::integral_constant<int, 3>(), t + 3, V1, V0);
   }
+  grid_sum<K + 2>(acc, a.partials, a.counter, a.result, nblocks, bid);
 }
-
-// ---- vector kernels of the Krylov-accelerated inner solve -------------------------------------
-constexpr int kKryMax = 8;          // longest Krylov space of the inner solve
-constexpr int kKryBlocks = 1024;    // blocks of the reducing vector kernels
-constexpr int kKryNV = kKryMax + 2; // values reduced per block
-struct KryPtrs {
-  const float* p[kKryMax + 1];
-};
-struct KryCoef {
-  double c[kKryMax + 1];
-};
 
 // Sums over all cells of w v_j (j < K) into result[j], of w into result[K] and of w^2 into
 // result[K + 1]: 16-byte loads, four FP32 products per lane and step added into FP64 accumulators.

@@ -114,8 +114,9 @@ struct Ctx {
   int adj_vcycle(int l, double* norm2);
   double adj_last_norm = 0.0, adj_stop = 0.0;
   double* linsum(int l);
-  int lin_sweep(int l);
-  int lin_vcycle(int l);
+  int lin_sweep(int l, bool zero_start = false);
+  int lin_vcycle(int l, bool zero = false);
+  int lin_coarse_cycle();
   int mixed_ready();
   int lin_base_hierarchy();
   int lin_solve(int ncycles);

@@ -129,6 +129,7 @@ struct LinSweepArgs {
   double* partials;
   unsigned int* counter;
   int tiles_j, tiles_m, ci;
+  int zero_black;       // black half-sweep whose old black values are all zero (not read)
 };
 
 struct Reduce {

@@ -49,7 +49,7 @@ EXPORTED = [
     "mr_deposit", "mr_deposit_cic", "mr_lagrangian", "mr_residual", "mr_solve", "mr_solve_anderson", "mr_adjoint_solve", "mr_adjoint_solve_anderson", "mr_solve_batched",
     "mr_tune_lin_tiles",
     "mr_sweep", "mr_defect_restrict", "mr_tau_rhs", "mr_prolong_correct", "mr_restrict",
-    "mr_lin_residual", "mr_lin_defect_restrict", "mr_lin_vcycles", "mr_lin_sweep",
+    "mr_lin_residual", "mr_lin_defect_restrict", "mr_lin_vcycles", "mr_lin_sweep", "mr_lin_prolong_add",
     "mr_timing_enable", "mr_timing_read", "mr_hbm_stream", "mr_residual_noalloc", "mr_last_error",
 ]
 
@@ -145,6 +145,7 @@ def load(path: Optional[str] = None):
     lib.mr_lin_vcycles.argtypes = [vp, vp, vp, vp, ip, vp]
     lib.mr_lin_sweep.argtypes = [vp, ip, ctypes.c_double, vp, vp, vp, vp, ctypes.c_double,
                                  ctypes.POINTER(ctypes.c_int), vp]
+    lib.mr_lin_prolong_add.argtypes = [vp, ip, vp, vp, vp]
     lib.mr_timing_enable.argtypes = [vp, ip]
     lib.mr_timing_read.argtypes = [vp, ctypes.POINTER(mr_timing)]
     lib.mr_hbm_stream.argtypes = [ip, ip, vp, vp, vp, ctypes.c_size_t, ip, vp, ctypes.POINTER(ctypes.c_float)]
@@ -405,6 +406,15 @@ class Context:
         out = self._empty(nl // 2)
         _check(self.lib.mr_lin_defect_restrict(self.h, nl, h, _ptr(delta), _ptr(theta_base), _ptr(e), _ptr(rhs),
                                                cshift, _ptr(out)))
+        return out
+
+    def lin_prolong_add(self, ec, e_in):
+        """mr_lin_prolong_add: e_in + P ec (FP32 inner-solve prolongation) on the nl^3 mesh."""
+        nl = e_in.shape[0]
+        _need(e_in, nl ** 3, "e_in")
+        _need(ec, (nl // 2) ** 3, "ec")
+        out = self._empty(nl)
+        _check(self.lib.mr_lin_prolong_add(self.h, nl, _ptr(ec), _ptr(e_in), _ptr(out)))
         return out
 
     def lin_sweep(self, delta, theta_base, e_in, h=1.0, rhs=None, cshift=0.0, sched=None):

@@ -123,6 +123,21 @@ def _bordered_solve(theta, delta, b):
     return sol[:-1].reshape(theta.shape)
 
 
+@pytest.mark.parametrize("nl", [16, 64, 256, 512])
+def test_lin_prolong_add_matches_oracle(ctx, nl):
+    """The inner V-cycle's FP32 correction e + P ec against the oracle's prolongation: the plain
+    kernel (16), the staged-rows kernel (64) and the plane-pipelined kernel (256, 512; several
+    chunks of coarse planes per column of blocks, periodic wrap in every direction)."""
+    announce(f"lin_prolong_add nl={nl}")
+    rng = np.random.default_rng(900 + nl)
+    ec = rng.standard_normal((nl // 2,) * 3)
+    e = rng.standard_normal((nl,) * 3)
+    got = host(ctx.lin_prolong_add(dev(ec), dev(e)))
+    want = e + omg.prolong(ec)
+    err = np.abs(got - want).max()
+    assert err <= 2e-6 * (np.abs(e).max() + np.abs(ec).max()), err
+
+
 def test_inner_vcycles_contract_to_the_oracle_solution():
     require_gpu()
     n = 32
