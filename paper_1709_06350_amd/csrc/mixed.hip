@@ -85,6 +85,11 @@ __global__ void __launch_bounds__(256) lin_coarsest_kernel(float* __restrict__ e
   lin_coarsest_body(e, baseq, bq, sb, rhs, n, nsweeps, h2, ih2, c_sum, c_scale, sh);
 }
 
+__global__ void __launch_bounds__(kTailThreads) lin_tail_kernel(LinTailArgs a) {
+  __shared__ LinTailShared sh;
+  lin_tail_body(a, sh);
+}
+
 __global__ void __launch_bounds__(256) update64_kernel(double* __restrict__ theta, const float* __restrict__ e, size_t cells,
                                                        double* tmax) {
   update64_body(theta, e, cells, blockIdx.x, gridDim.x, tmax);
@@ -922,6 +927,27 @@ int Ctx::lin_vcycle(int l, bool zero) {
   LinLevel& L = mixed->lv[l];
   Level& F = lv[l];
   hipError_t e;
+  if (l > 0 && zero && F.n <= kTailMaxN && nlev - l <= kTailMaxLev) {
+    // this level and all coarser ones in one workgroup
+    LinTailArgs a{};
+    a.e_out = L.e[L.cur];
+    a.rhs = L.rhs;
+    for (int t = 0; t < nlev - l; ++t) {
+      a.base[t] = mixed->lv[l + t].base;
+      a.sb[t] = mixed->lv[l + t].sb;
+    }
+    a.bq = scal + kSlotBase;
+    a.c_sum = linsum(l);
+    a.n0 = F.n;
+    a.levels = nlev - l;
+    a.npre = opts.npre;
+    a.npost = opts.npost;
+    a.ncoarse = opts.ncoarse;
+    a.h0 = (float)F.h;
+    hipLaunchKernelGGL(lin_tail_kernel, dim3(1), dim3(kTailThreads), 0, stream, a);
+    e = hipGetLastError();
+    return e == hipSuccess ? MR_OK : hip_fail(e, "linear V-cycle tail");
+  }
   if (l == nlev - 1) {
     e = zero ? launch_fill32(L.e[L.cur], 0.0f, F.cells, stream) : hipSuccess;
     if (e == hipSuccess)

@@ -608,6 +608,197 @@ inline __device__ void prolong_pipe32_body(const float* __restrict__ ec, float* 
   }
 }
 
+// ---- the small levels of an inner V-cycle in one workgroup -----------------------------------
+// Every level with n <= kTailMaxN (down to the coarsest) of a zero-start inner V-cycle, in one
+// block of kTailThreads threads with all fields in LDS (natural order): on each level e = 0,
+// npre sweeps, the defect rhs + dSigma(e) - lap(e) - C restricted to the next level (8-son mean,
+// whose mean starts that level's shift), the coarsest level ncoarse sweeps, then on the way up
+// e += P e_coarse and npost sweeps. A sweep is the red then the black half with snapshot
+// semantics within a colour; its shift C is the mean of dSigma(e) + rhs over the previous sweep
+// (the first from the level's right-hand side), as on the larger levels. The launch overhead of
+// these levels' kernels, not their arithmetic, is what they cost when launched one by one.
+constexpr int kTailMaxN = 16;
+constexpr int kTailMaxLev = 3;                       // 16, 8, 4 (or 12, 6)
+constexpr int kTailCells = 4096 + 512 + 64 + 8;      // sum of n^3 over the levels, rounded up
+constexpr int kTailThreads = 1024;
+struct LinTailArgs {
+  float* e_out;                      // split e of the first tail level
+  const float* rhs;                  // split rhs of the first tail level
+  const int* base[kTailMaxLev];      // split fixed-point base of each tail level
+  const float* sb[kTailMaxLev];      // split root of each tail level
+  const double* bq;
+  const double* c_sum;               // (sum rhs, 0) of the first tail level
+  int n0, levels, npre, npost, ncoarse;
+  float h0;
+};
+struct LinTailShared {
+  float e[kTailCells], b[kTailCells], s[kTailCells], r[kTailCells];
+  float t[4096];
+  float C[kTailMaxLev];
+  double red[16][1];   // (a half level, at most 2048 cells, is 2 cells per thread)
+};
+
+inline __device__ void tail_gather(const float* __restrict__ a, int n, int i, int j, int k, Nb18f& t) {
+  const int im = i == 0 ? n - 1 : i - 1, ip = i == n - 1 ? 0 : i + 1;
+  const int jm = j == 0 ? n - 1 : j - 1, jp = j == n - 1 ? 0 : j + 1;
+  const int km = k == 0 ? n - 1 : k - 1, kp = k == n - 1 ? 0 : k + 1;
+  auto at = [&](int ii, int jj, int kk) { return a[(ii * n + jj) * n + kk]; };
+  t.xm = at(im, j, k); t.xp = at(ip, j, k); t.ym = at(i, jm, k); t.yp = at(i, jp, k);
+  t.zm = at(i, j, km); t.zp = at(i, j, kp);
+  t.xpyp = at(ip, jp, k); t.xmym = at(im, jm, k); t.xpym = at(ip, jm, k); t.xmyp = at(im, jp, k);
+  t.xpzp = at(ip, j, kp); t.xmzm = at(im, j, km); t.xpzm = at(ip, j, km); t.xmzp = at(im, j, kp);
+  t.ypzp = at(i, jp, kp); t.ymzm = at(i, jm, km); t.ypzm = at(i, jp, km); t.ymzp = at(i, jm, kp);
+}
+
+inline __device__ void lin_tail_body(const LinTailArgs& a, LinTailShared& sh) {
+  const int tid = threadIdx.x;
+  const float bscl = (float)a.bq[0];
+  // level l: n0 >> l cells a side, cell size h0 2^l, fields at offset sum_{t<l} (n0 >> t)^3
+  // (computed, not indexed, so that nothing is kept in per-lane scratch memory)
+  auto nn = [&](int l) { return a.n0 >> l; };
+  auto hh = [&](int l) { return a.h0 * (float)(1 << l); };
+  auto off = [&](int l) {
+    int o = 0;
+    for (int t = 0; t < l; ++t) o += (a.n0 >> t) * (a.n0 >> t) * (a.n0 >> t);
+    return o;
+  };
+  // fields of every level, and the first level's right-hand side, into natural order
+  for (int l = 0; l < a.levels; ++l) {
+    const int n = nn(l), n3 = n * n * n;
+    // (selects, not a dynamic index into the argument block)
+    const float* bsrc = reinterpret_cast<const float*>(l == 0 ? a.base[0] : l == 1 ? a.base[1] : a.base[2]);
+    const float* ssrc = l == 0 ? a.sb[0] : l == 1 ? a.sb[1] : a.sb[2];
+    for (int x = tid; x < n3; x += kTailThreads) {
+      const int i = x / (n * n), j = (x / n) % n, k = x % n;
+      const unsigned g = split_idx(n, i, j, k);
+      sh.b[off(l) + x] = bsrc[g];
+      sh.s[off(l) + x] = ssrc[g];
+      if (l == 0) sh.r[x] = a.rhs[g];
+    }
+  }
+  __syncthreads();
+
+  // one sweep of level l (shift C in, next shift out)
+  auto sweep = [&](int l) {
+    const float C = sh.C[l];
+    const int n = nn(l), nh = n >> 1, n3 = n * n * n, half = n3 >> 1;
+    float* e = sh.e + off(l);
+    const float* b = sh.b + off(l);
+    const float* sv = sh.s + off(l);
+    const float* r = sh.r + off(l);
+    const float h2 = hh(l) * hh(l), ih2 = 1.0f / h2;
+    double acc = 0.0;
+    for (int c = 0; c < 2; ++c) {
+      float nv[2];
+      int nx[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int y = tid + q * kTailThreads;
+        nx[q] = -1;
+        if (y < half) {
+          const int i = y / (n * nh), j = (y / nh) % n, m = y % nh;
+          const int k = 2 * m + ((i + j + c) & 1);
+          const int x = (i * n + j) * n + k;
+          Nb18f te, tb;
+          tail_gather(e, n, i, j, k, te);
+          tail_gather(b, n, i, j, k, tb);
+          float Se;
+          const float g = lin_source(tb, b[x], bscl, sv[x], ih2, te, Se) * ih2;
+          nv[q] = (Se - h2 * (g + r[x] - C)) * (1.0f / 6.0f);
+          nx[q] = x;
+          acc += (double)(g + r[x]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        if (nx[q] >= 0) e[nx[q]] = nv[q];
+      __syncthreads();
+    }
+    double v[1] = {acc};
+    block_sum<1>(v, sh.red, tid, kTailThreads);
+    if (tid == 0) sh.C[l] = (float)(v[0] / (double)n3);
+    __syncthreads();
+  };
+
+  float* Cl = sh.C;   // shift of each level (uniform values, kept in LDS)
+  if (tid == 0) Cl[0] = (float)((a.c_sum[0] + a.c_sum[1]) / (double)(a.n0 * a.n0 * a.n0));
+  __syncthreads();
+  const int last = a.levels - 1;
+  // down: smooth from zero, restrict the defect
+  for (int l = 0; l <= last; ++l) {
+    const int n = nn(l), n3 = n * n * n;
+    for (int x = tid; x < n3; x += kTailThreads) sh.e[off(l) + x] = 0.0f;
+    __syncthreads();
+    const int ns = l == last ? a.ncoarse : a.npre;
+    for (int sw = 0; sw < ns; ++sw) sweep(l);
+    if (l == last) break;
+    // defect at every cell into t, then its 8-son means into the next level's rhs
+    {
+      const float* e = sh.e + off(l);
+      const float* b = sh.b + off(l);
+      const float* sv = sh.s + off(l);
+      const float* r = sh.r + off(l);
+      const float ih2 = 1.0f / (hh(l) * hh(l));
+      for (int x = tid; x < n3; x += kTailThreads) {
+        const int i = x / (n * n), j = (x / n) % n, k = x % n;
+        Nb18f te, tb;
+        tail_gather(e, n, i, j, k, te);
+        tail_gather(b, n, i, j, k, tb);
+        float Se;
+        const float g = lin_source(tb, b[x], bscl, sv[x], ih2, te, Se) * ih2;
+        sh.t[x] = r[x] + g - (Se - 6.0f * e[x]) * ih2 - Cl[l];
+      }
+      __syncthreads();
+      const int nc = n >> 1, nc3 = nc * nc * nc;
+      float* rc = sh.r + off(l + 1);
+      double acc = 0.0;
+      for (int X = tid; X < nc3; X += kTailThreads) {
+        const int I = X / (nc * nc), J = (X / nc) % nc, K = X % nc;
+        float sum = 0.0f;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          sum += sh.t[((2 * I + (q >> 2)) * n + 2 * J + ((q >> 1) & 1)) * n + 2 * K + (q & 1)];
+        rc[X] = 0.125f * sum;
+        acc += (double)(0.125f * sum);
+      }
+      double v[1] = {acc};
+      block_sum<1>(v, sh.red, tid, kTailThreads);
+      if (tid == 0) Cl[l + 1] = (float)(v[0] / (double)nc3);
+      __syncthreads();
+    }
+  }
+  // up: correct from the coarser level, smooth
+  for (int l = last - 1; l >= 0; --l) {
+    const int n = nn(l), n3 = n * n * n, nc = n >> 1;
+    float* e = sh.e + off(l);
+    const float* ec = sh.e + off(l + 1);
+    for (int x = tid; x < n3; x += kTailThreads) {
+      const int i = x / (n * n), j = (x / n) % n, k = x % n;
+      const int I = i >> 1, J = j >> 1, K = k >> 1;
+      const int I2 = (i & 1) ? (I + 1 == nc ? 0 : I + 1) : (I == 0 ? nc - 1 : I - 1);
+      const int J2 = (j & 1) ? (J + 1 == nc ? 0 : J + 1) : (J == 0 ? nc - 1 : J - 1);
+      const int K2 = (k & 1) ? (K + 1 == nc ? 0 : K + 1) : (K == 0 ? nc - 1 : K - 1);
+      auto at = [&](int ii, int jj, int kk) { return ec[(ii * nc + jj) * nc + kk]; };
+      const float z0 = 0.75f * at(I, J, K) + 0.25f * at(I, J, K2);
+      const float z1 = 0.75f * at(I, J2, K) + 0.25f * at(I, J2, K2);
+      const float z2 = 0.75f * at(I2, J, K) + 0.25f * at(I2, J, K2);
+      const float z3 = 0.75f * at(I2, J2, K) + 0.25f * at(I2, J2, K2);
+      e[x] += 0.75f * (0.75f * z0 + 0.25f * z1) + 0.25f * (0.75f * z2 + 0.25f * z3);
+    }
+    __syncthreads();
+    for (int sw = 0; sw < a.npost; ++sw) sweep(l);
+  }
+  // the first level's e back to the split layout
+  {
+    const int n = nn(0), n3 = n * n * n;
+    for (int x = tid; x < n3; x += kTailThreads) {
+      const int i = x / (n * n), j = (x / n) % n, k = x % n;
+      a.e_out[split_idx(n, i, j, k)] = sh.e[x];
+    }
+  }
+}
+
 // Linear coarsest solve: nsweeps red-black sweeps in one block (FP32, natural order in LDS).
 struct LinCoarsestShared {
   float te[kMaxCoarsest], tb[kMaxCoarsest], ts[kMaxCoarsest], tr[kMaxCoarsest], tn[kMaxCoarsest];
