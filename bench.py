@@ -13,9 +13,11 @@ algorithmic 24 bytes per cell update (theta read + write, delta read) against th
 peak; "traffic" is the HBM traffic per sweep measured with rocprofv3 counters (committed
 summary), over the same sweep time.
 
-Also reported: time to solution of both 512^3 solves; one adjoint solve at 512^3; the CIC
-deposit of 256^3 particles onto a 256^3 mesh; and the batched form on 64 boxes of
-{64, 96, 128}^3 (mixed precision to 1e-8), each timed after an untimed run.
+Also reported: time to solution of both 512^3 solves (medians over the timed steps; the mixed
+solve with npre = npost = 2 and at most 4 FP32 V-cycles per outer step) and the largest difference
+of the two solutions relative to max |theta|; one adjoint solve at 512^3; the CIC deposit of 256^3
+particles onto a 256^3 mesh; and the batched form on 64 boxes of {64, 96, 128}^3 (mixed precision
+to 1e-8), each timed after an untimed run. The CPU baseline times the oracle on bounded samples.
 
 Prints ONE JSON line. --gpus N > 1 is refused: this path runs on one GPU.
 """
@@ -26,6 +28,7 @@ import hashlib
 import json
 import os
 import re
+import statistics
 import sys
 import time
 
@@ -61,32 +64,80 @@ def measured_traffic(schedule: str):
 
 
 SCHED_KERNEL = {0: "half_sweep_tiled", 1: "half_sweep_pipe", 2: "sweep_fused"}
+# options of the mixed-precision solve
+MIXED_OPTS = {"npre": 2, "npost": 2, "inner_cycles": 4}
 
 
-def cpu_baseline(delta_np, seconds_target=12.0):
-    """The oracle's red-black sweep timed on host cores on a bounded 128^3 periodic sample."""
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(full: bool = False, reps: int = 5):
+    """The oracle (numpy, FP64, one thread) on the host cores, on bounded samples of the workload:
+    the red-black sweep at 32^3 and 128^3 and the whole solve to 1e-10 at 32^3, medians of `reps`
+    runs each, inputs of the same recipe (lognormal, sigma_g = 1.0, R_c = 2 cells, seed 1002) at the
+    sample size. The 128^3 and 512^3 times to solution are extrapolated from the 32^3 solve's
+    sweep-equivalents (solve time / sweep time) and the sweep time at the target size (scaled by
+    the cell count from 128^3 for 512^3), and labelled so; with full=True the 128^3 solve is run
+    once and reported as measured."""
+    import statistics
+
     import numpy as np
 
+    import inputs
     from oracle import multigrid as omg
 
-    s = 128
-    d = np.ascontiguousarray(delta_np[:s, :s, :s])
-    th = np.zeros_like(d)
-    sweeps = 0
-    t0 = time.perf_counter()
-    while True:
-        th = omg.rb_sweep(th, d, None, 1.0)
-        sweeps += 1
-        if time.perf_counter() - t0 > seconds_target or sweeps >= 32:
-            break
-    dt = time.perf_counter() - t0
+    def med(fn, k):
+        ts = []
+        out = None
+        for _ in range(k):
+            t0 = time.perf_counter()
+            out = fn()
+            ts.append(time.perf_counter() - t0)
+        return statistics.median(ts), out
+
+    sweep_s, solve = {}, {}
+    for s in (32, 128):
+        d = inputs.lognormal(s, 1.0, 2.0, 1002)
+        th = np.zeros_like(d)
+        omg.rb_sweep(th, d, None, 1.0)
+        sweep_s[s], _ = med(lambda: omg.rb_sweep(th, d, None, 1.0), reps)
+    d32 = inputs.lognormal(32, 1.0, 2.0, 1002)
+    t32, (_, info32) = med(lambda: omg.solve(d32, tol=1e-10), reps)
+    solve["32"] = {"seconds": round(t32, 3), "cycles": info32["cycles"], "kind": "measured", "runs": reps}
+    equiv = t32 / sweep_s[32]
+    solve["128"] = {"seconds": round(equiv * sweep_s[128], 1), "kind": "extrapolated",
+                    "how": "32^3 solve in sweep-equivalents x 128^3 sweep time"}
+    if full:
+        d128 = inputs.lognormal(128, 1.0, 2.0, 1002)
+        t0 = time.perf_counter()
+        _, info128 = omg.solve(d128, tol=1e-10)
+        solve["128"] = {"seconds": round(time.perf_counter() - t0, 1), "cycles": info128["cycles"],
+                        "kind": "measured", "runs": 1}
+    solve["512"] = {"seconds": round(equiv * sweep_s[128] * 64, 0), "kind": "extrapolated",
+                    "how": "32^3 solve in sweep-equivalents x 128^3 sweep time x 64 (cells)"}
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
     return {
-        "value": s ** 3 * sweeps / dt / 1e9,
+        "value": round(128 ** 3 / sweep_s[128] / 1e9, 5),
         "unit": "Gcell-updates/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"{sweeps} red-black sweeps of the oracle on a 128^3 periodic sub-box of the "
-                  f"512^3 input ({dt:.1f} s, numpy, single thread)",
+        "sample": f"oracle red-black sweep at 128^3 (median of {reps}: {sweep_s[128]:.3f} s) and at 32^3 "
+                  f"({sweep_s[32]:.4f} s); oracle solve to 1e-10 at 32^3 (median of {reps}); numpy, one thread; "
+                  "128^3 and 512^3 times to solution extrapolated unless marked measured",
+        "sweep_seconds": {"32": round(sweep_s[32], 5), "128": round(sweep_s[128], 4)},
+        "time_to_1e-10_s": solve,
+        "host": {"cpu_model": _cpu_model(), "os_cpu_count": os.cpu_count(), "affinity_cpus": affinity},
     }
 
 
@@ -286,7 +337,7 @@ def anderson_run(ctx, delta, theta, rb_cycles, depth=2):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -300,6 +351,10 @@ def main():
                     help="pin the finest-level FP64 relaxation schedule (mr_set_schedule) instead of the timed one")
     ap.add_argument("--stream-probe", action="store_true",
                     help="only measure the achievable HBM bandwidth with the library's streaming kernels")
+    ap.add_argument("--mixed-only", action="store_true",
+                    help="only run the mixed-precision solve (steps times, untimed; for counter runs)")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also run the oracle's 128^3 solve to 1e-10 once for the CPU baseline (minutes)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a device copy of BYTES bytes (counter calibration)")
     args = ap.parse_args()
@@ -334,15 +389,18 @@ def main():
         ctx.set_schedule(0, tuple(int(x) for x in args.schedule.split(",")))
     sched = ctx.get_schedule(0)
     sched_str = ",".join(str(x) for x in sched)
-    run_mixed = not args.no_mixed
+    run_mixed = not args.no_mixed or args.mixed_only
     ctxm = None
     if run_mixed:
-        try:
-            ctxm = mr.Context(n, tol=1e-10, max_cycles=100, precision=mr.PREC_MIXED)
+        ctxm = mr.Context(n, tol=1e-10, max_cycles=100, precision=mr.PREC_MIXED, **MIXED_OPTS)
+        ctxm.solve(delta, theta_m)
+    if args.mixed_only:
+        # the mixed-precision solve alone (for counter runs of its kernels)
+        for _ in range(args.steps):
             ctxm.solve(delta, theta_m)
-        except mr.MRError:
-            run_mixed = False
-            ctxm = None
+        torch.cuda.synchronize()
+        print(json.dumps({"mixed_only": True, "n": n, "steps": args.steps}), flush=True)
+        return
 
     def step():
         _, i64 = ctx.solve(delta, theta)
@@ -355,7 +413,7 @@ def main():
         step()
     torch.cuda.synchronize()
     ctx.timing_enable(True)
-    t64 = tm = 0.0
+    ts64, tsm = [], []
     info64 = infom = None
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -364,15 +422,21 @@ def main():
         _, info64 = ctx.solve(delta, theta)
         torch.cuda.synchronize()
         b = time.perf_counter()
-        t64 += b - a
+        ts64.append(b - a)
         if run_mixed:
             _, infom = ctxm.solve(delta, theta_m)
             torch.cuda.synchronize()
-            tm += time.perf_counter() - b
+            tsm.append(time.perf_counter() - b)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t_start
     tim = ctx.timing_read()
     ctx.timing_enable(False)
+    t64 = statistics.median(ts64)
+    tm = statistics.median(tsm) if run_mixed else 0.0
+    theta_err = None
+    if run_mixed:
+        # both solutions carry the zero-mean gauge
+        theta_err = float((theta_m - theta).abs().max() / theta.abs().max())
 
     avg_sweep_s = tim["sweep64_ms"] / max(1, tim["sweep64_launches"]) * 1e-3
     cells = float(n) ** 3
@@ -417,9 +481,15 @@ def main():
             "sweeps_timed": tim["sweep64_launches"],
         },
         "time_to_solution_s": {
-            "fp64": round(t64 / args.steps, 4),
-            "mixed": round(tm / args.steps, 4) if run_mixed else None,
+            "fp64": round(t64, 4),
+            "mixed": round(tm, 4) if run_mixed else None,
             "ratio_mixed_over_fp64": round(tm / t64, 4) if run_mixed and t64 > 0 else None,
+            "statistic": f"median of {args.steps} timed solves each (after {args.warmup} untimed)",
+            "fp64_all": [round(x, 4) for x in ts64],
+            "mixed_all": [round(x, 4) for x in tsm],
+            "mixed_opts": dict(MIXED_OPTS, note="flexible GMRES inner solve of at most inner_cycles FP32 "
+                                                 "V-cycles per outer FP64 step; FP64 solve at npre = npost = 2"),
+            "theta_max_rel_diff_mixed_vs_fp64": theta_err,
         },
         "cycles": {"fp64": info64.cycles if info64 else None,
                    "mixed": infom.cycles if infom else None},
@@ -438,11 +508,11 @@ def main():
             out["anderson"]["mixed"] = anderson_run(ctxm, delta, theta_m, infom.cycles if infom else None)
             if t64 > 0:
                 out["anderson"]["mixed_over_plain_fp64"] = round(
-                    out["anderson"]["mixed"]["seconds"] / (t64 / args.steps), 4)
+                    out["anderson"]["mixed"]["seconds"] / t64, 4)
     if not args.no_batched:
         out["batched"] = batched_run()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(delta_np)
+        out["cpu_baseline"] = cpu_baseline(full=args.cpu_full)
     print(json.dumps(out), flush=True)
 
 
