@@ -162,6 +162,13 @@ int mr_set_schedule(mr_ctx* ctx, int level, const int sched[4]);
  * max_count < 0, or sched = NULL with max_count > 0. */
 int mr_schedule_candidates(const mr_ctx* ctx, int level, int* sched, int max_count);
 
+/* The FP32 sweep schedule of the mixed-precision form on a level (the tuner's choice, see the
+ * persistent record of tuner choices below), in the (kind, tm, tj, nchunks) form of
+ * mr_get_schedule; the first call allocates the context's mixed-precision buffers (and times the
+ * candidates unless a recorded choice applies). Returns MR_EINVAL for a NULL argument or a level
+ * without a sweep (the coarsest), MR_ENOMEM if the buffers cannot be allocated. */
+int mr_get_lin_schedule(mr_ctx* ctx, int level, int sched[4]);
+
 /* Density assignment (the paper's footnote on density assignment, Sec. I, allows NGP, CIC or TSC).
  * pos: device, np x 3 doubles (x, y, z) in cell units, any finite real value (wrapped
  * periodically); mesh points sit at integer coordinates. Per axis, with b = floor(x) and
@@ -276,6 +283,30 @@ int mr_solve_batched(int nbox, const int* n, const double* const* delta, double*
  * block, ms the time of one red+black sweep per box. Any output pointer may be NULL.
  * n: multiple of 4, 8..1024. */
 int mr_tune_lin_tiles(int n, void* hip_stream, int* tm, int* tj, int* ci, float* ms);
+
+/* Persistent tuner choices. Every tuner of the library (FP64 sweep and defect schedules, the FP32
+ * sweep of the mixed form, the batched FP32 sweep tiles, the adjoint sweep) times its candidates
+ * once per device and mesh size; the choice is kept for the process and recorded in a text file
+ * so that later processes on the same kind of device make the same choice without timing. A
+ * record is a list of integers under (tuner kind with a format version, architecture name,
+ * device (its memory size, "<GiB>GiB"), compute-unit count, n). A tuner uses a recorded choice only if it is among its
+ * current candidates, and times again otherwise. The file is $MR_TUNING_FILE if that variable is
+ * set (an empty value: no file), else $XDG_CACHE_HOME/paper_1709_06350_amd/tuning.txt, else
+ * $HOME/.cache/paper_1709_06350_amd/tuning.txt; it is read on first use and rewritten (through a
+ * temporary file and a rename) when a choice is recorded. A file that cannot be written is not an
+ * error for the tuners. Host code only; no device is needed for these four calls.
+ *
+ * mr_tuning_file: use path from now on (NULL: back to the default above; "": no file) and forget
+ * the choices read so far. mr_tuning_file_path: the file in use ("" if none; the pointer is valid
+ * until the next mr_tuning_file). mr_tuning_store: record count (1..64) values under the key and
+ * write the file (MR_EINVAL if it cannot be written). mr_tuning_lookup: the values recorded under
+ * the key into vals (at most max_count), their number into *count (0 if none). */
+int mr_tuning_file(const char* path);
+const char* mr_tuning_file_path(void);
+int mr_tuning_store(const char* kind, const char* arch, const char* device, int cus, int n, const int* vals,
+                    int count);
+int mr_tuning_lookup(const char* kind, const char* arch, const char* device, int cus, int n, int* vals, int max_count,
+                     int* count);
 
 /* ---- Building blocks of the cycle, exported so that each can be checked in isolation. ----
  * All act on one mesh of size nl (any level of a hierarchy) with cell size h, on the context's

@@ -26,6 +26,7 @@
 #include "mr_ctx.h"
 #include "mr_device.h"
 #include "mr_kernels.h"
+#include "tuning.h"
 
 namespace mr {
 
@@ -567,6 +568,8 @@ static int tune_adj_sweep(const AdjSweepArgs& base, hipStream_t s, AdjCfg* out) 
   if (hipGetDevice(&dev) != hipSuccess) return hip_fail(hipErrorInvalidDevice, "adjoint tuner");
   {
     std::lock_guard<std::mutex> lk(g_adj_tune_mu);
+    static int gen = -1;
+    tuning_sync(gen, g_adj_tuned);
     auto it = g_adj_tuned.find({dev, n});
     if (it != g_adj_tuned.end()) {
       *out = it->second;
@@ -604,14 +607,26 @@ static int tune_adj_sweep(const AdjSweepArgs& base, hipStream_t s, AdjCfg* out) 
     hipError_t r = launch_adj_half(base, 0, c, s);
     return r == hipSuccess ? launch_adj_half(base, 1, c, s) : r;
   };
+  auto code = [](const AdjCfg& c) { return std::vector<int>{c.tm, c.tj, c.ci, c.pfc ? 1 : 0}; };
   size_t bi = 0;
-  hipError_t e = pick_fastest(cand.size(), reps, s, [&](size_t i) { return run(cand[i]); }, &bi);
+  bool recorded = false;
+  {
+    std::vector<int> rec;
+    if (tuning_lookup("adj64.v1", dev, n, rec))
+      for (size_t i = 0; i < cand.size() && !recorded; ++i)
+        if (code(cand[i]) == rec) {
+          bi = i;
+          recorded = true;
+        }
+  }
+  hipError_t e = recorded ? hipSuccess : pick_fastest(cand.size(), reps, s, [&](size_t i) { return run(cand[i]); }, &bi);
   const AdjCfg best_c = cand[bi];
   if (e != hipSuccess) return hip_fail(e, "adjoint tuner");
   {
     std::lock_guard<std::mutex> lk(g_adj_tune_mu);
     g_adj_tuned[{dev, n}] = best_c;
   }
+  if (!recorded) tuning_record("adj64.v1", dev, n, code(best_c));
   *out = best_c;
   return MR_OK;
 }

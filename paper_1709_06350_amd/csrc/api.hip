@@ -655,6 +655,14 @@ int mr_get_schedule(const mr_ctx* h, int level, int sched[4]) {
   return MR_OK;
 }
 
+int mr_get_lin_schedule(mr_ctx* h, int level, int sched[4]) {
+  if (!h || !sched) return fail(MR_EINVAL, "mr_get_lin_schedule: null argument");
+  Ctx* c = reinterpret_cast<Ctx*>(h);
+  if (level < 0 || level >= c->nlev - 1)
+    return fail(MR_EINVAL, "mr_get_lin_schedule: level %d has no sweep schedule", level);
+  return c->lin_schedule(level, sched);
+}
+
 int mr_set_schedule(mr_ctx* h, int level, const int sched[4]) {
   if (!h || !sched) return fail(MR_EINVAL, "mr_set_schedule: null argument");
   Ctx* c = reinterpret_cast<Ctx*>(h);

@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -23,6 +24,7 @@
 #include "mr_device.h"
 #include "mr_kernels.h"
 #include "mixed_device.h"
+#include "tuning.h"
 
 namespace mr {
 
@@ -447,12 +449,32 @@ int tune_lin_tiles(int n, hipStream_t s, TileCfg* out, float* ms_out) {
   const int nb = (int)std::max<size_t>(1, std::min<size_t>(64, ((size_t)1 << 25) / cells));
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    static int gen = -1;
+    tuning_sync(gen, g_tuned);
     auto it = g_tuned.find({dev, n});
     if (it != g_tuned.end()) {
       *out = it->second.first;
       if (ms_out) *ms_out = it->second.second;
       return MR_OK;
     }
+  }
+  // a recorded choice that is still a candidate: the tile and the time of one sweep (float bits)
+  {
+    std::vector<int> rec;
+    if (tuning_lookup("blin32.v1", dev, n, rec) && rec.size() == 8)
+      for (const TileCfg& t : lin_candidates(n)) {
+        std::vector<int> code = tile_code(t);
+        if (!std::equal(code.begin(), code.end(), rec.begin())) continue;
+        float ms = 0.0f;
+        std::memcpy(&ms, &rec[7], sizeof ms);
+        {
+          std::lock_guard<std::mutex> lk(g_tune_mu);
+          g_tuned[{dev, n}] = {t, ms};
+        }
+        *out = t;
+        if (ms_out) *ms_out = ms;
+        return MR_OK;
+      }
   }
   std::vector<void*> mem;
   auto get = [&](size_t bytes) -> void* {
@@ -536,6 +558,13 @@ int tune_lin_tiles(int n, hipStream_t s, TileCfg* out, float* ms_out) {
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tuned[{dev, n}] = {cand[bi], best_ms};
+  }
+  {
+    std::vector<int> code = tile_code(cand[bi]);
+    int bits = 0;
+    std::memcpy(&bits, &best_ms, sizeof bits);
+    code.push_back(bits);
+    tuning_record("blin32.v1", dev, n, code);
   }
   *out = cand[bi];
   if (ms_out) *ms_out = best_ms;

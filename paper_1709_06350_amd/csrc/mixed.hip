@@ -26,6 +26,7 @@
 #include "mr_device.h"
 #include "mr_kernels.h"
 #include "mixed_device.h"
+#include "tuning.h"
 
 namespace mr {
 
@@ -673,6 +674,8 @@ static int tune_lin_sweep(Ctx* c, int l, LinSched* out) {
   if (hipGetDevice(&dev) != hipSuccess) return hip_fail(hipErrorInvalidDevice, "linear sweep tuner");
   {
     std::lock_guard<std::mutex> lk(g_lin_tune_mu);
+    static int gen = -1;
+    tuning_sync(gen, g_lin_tuned);
     auto it = g_lin_tuned.find({dev, n});
     if (it != g_lin_tuned.end()) {
       *out = it->second;
@@ -754,8 +757,24 @@ static int tune_lin_sweep(Ctx* c, int l, LinSched* out) {
   auto run_any = [&](size_t i) {
     return ok[i].fused ? launch_lin_fused(fa, ok[i].fz, c->stream) : run(ok[i].two);
   };
+  auto code = [](const LinSched& t) {
+    std::vector<int> v{t.fused ? 1 : 0};
+    for (int x : tile_code(t.two)) v.push_back(x);
+    for (int x : {t.fz.tm, t.fz.tj, t.fz.nchunks}) v.push_back(x);
+    return v;
+  };
   size_t bi = 0;
-  if (e == hipSuccess && !ok.empty()) e = pick_fastest(ok.size(), reps, c->stream, run_any, &bi);
+  bool recorded = false;
+  {
+    std::vector<int> rec;
+    if (tuning_lookup("lin32.v1", dev, n, rec))
+      for (size_t i = 0; i < ok.size() && !recorded; ++i)
+        if (code(ok[i]) == rec) {
+          bi = i;
+          recorded = true;
+        }
+  }
+  if (e == hipSuccess && !ok.empty() && !recorded) e = pick_fastest(ok.size(), reps, c->stream, run_any, &bi);
   LinSched best_t;
   if (!ok.empty()) best_t = ok[bi];
   else best_t.two = cand[0];
@@ -764,6 +783,7 @@ static int tune_lin_sweep(Ctx* c, int l, LinSched* out) {
     std::lock_guard<std::mutex> lk(g_lin_tune_mu);
     g_lin_tuned[{dev, n}] = best_t;
   }
+  if (!ok.empty() && !recorded) tuning_record("lin32.v1", dev, n, code(best_t));
   *out = best_t;
   return MR_OK;
 }
@@ -1005,6 +1025,24 @@ int Ctx::lin_coarse_cycle() {
   for (int l = 1; l < nlev; ++l) mixed->lv[l].cur = g.cur_in[l];
   if ((e = hipGraphLaunch(g.exec, stream)) != hipSuccess) return hip_fail(e, "graph launch");
   for (int l = 1; l < nlev; ++l) mixed->lv[l].cur = g.cur_out[l];
+  return MR_OK;
+}
+
+int Ctx::lin_schedule(int l, int sched[4]) {
+  int rc = mixed_alloc(this);
+  if (rc != MR_OK) return rc;
+  const LinLevel& L = mixed->lv[l];
+  if (L.fused && !(opts.flags & MR_FLAG_TWO_PASS)) {
+    sched[0] = MR_SCHED_FUSED;
+    sched[1] = L.fz.tm;
+    sched[2] = L.fz.tj;
+    sched[3] = L.fz.nchunks;
+  } else {
+    sched[0] = L.sw.pipe ? MR_SCHED_PIPELINED : MR_SCHED_TILED;
+    sched[1] = L.sw.tm;
+    sched[2] = L.sw.tj;
+    sched[3] = L.sw.ci > 0 ? lv[l].n / L.sw.ci : 0;
+  }
   return MR_OK;
 }
 

@@ -118,6 +118,7 @@ struct Ctx {
   int lin_vcycle(int l, bool zero = false);
   int lin_coarse_cycle();
   int mixed_ready();
+  int lin_schedule(int l, int sched[4]);
   int lin_base_hierarchy();
   int lin_solve(int ncycles);
   int lin_vcycles_split(const double* theta_split, const double* rhs_split, int ncycles, float** e_out);

@@ -26,6 +26,7 @@
 #include "mr_ctx.h"
 #include "mr_device.h"
 #include "mr_kernels.h"
+#include "tuning.h"
 
 namespace mr {
 
@@ -1384,6 +1385,8 @@ int tune_defect(const DefectArgs& a, hipStream_t s) {
   if (hipGetDevice(&dev) != hipSuccess) return hip_fail(hipErrorInvalidDevice, "defect tuner");
   {
     std::lock_guard<std::mutex> lk(g_defect_tune_mu);
+    static int gen = -1;
+    tuning_sync(gen, g_defect_tuned);
     if (g_defect_tuned.count(std::make_tuple(dev, n, has_f))) return MR_OK;
   }
   std::vector<DefectCfg> cand;
@@ -1398,6 +1401,17 @@ int tune_defect(const DefectArgs& a, hipStream_t s) {
   MR_DR_TILES(MR_DR_ADD)
 #undef MR_DR_ADD
   if (cand.empty()) return MR_OK;
+  const char* kind = has_f ? "defect64f.v1" : "defect64.v1";
+  {
+    std::vector<int> rec;
+    if (tuning_lookup(kind, dev, n, rec))
+      for (const DefectCfg& c : cand)
+        if (rec == std::vector<int>{c.tm, c.tj, c.nchunks}) {
+          std::lock_guard<std::mutex> lk(g_defect_tune_mu);
+          g_defect_tuned[std::make_tuple(dev, n, has_f)] = c;
+          return MR_OK;
+        }
+  }
   const size_t cells = (size_t)n * n * n;
   const int reps = cells >= ((size_t)1 << 24) ? 2 : 4;
   size_t bi = 0;
@@ -1405,8 +1419,11 @@ int tune_defect(const DefectArgs& a, hipStream_t s) {
                                     [&](size_t i) { return launch_defect_pipe(a, cand[i].tm, cand[i].tj, cand[i].nchunks, s); },
                                     &bi);
   if (e != hipSuccess) return hip_fail(e, "defect tuner");
-  std::lock_guard<std::mutex> lk(g_defect_tune_mu);
-  g_defect_tuned[std::make_tuple(dev, n, has_f)] = cand[bi];
+  {
+    std::lock_guard<std::mutex> lk(g_defect_tune_mu);
+    g_defect_tuned[std::make_tuple(dev, n, has_f)] = cand[bi];
+  }
+  tuning_record(kind, dev, n, {cand[bi].tm, cand[bi].tj, cand[bi].nchunks});
   return MR_OK;
 }
 
@@ -1597,6 +1614,9 @@ int tune_sweep(int n, double* th_a, double* th_b, double* delta, double* partial
   if (hipGetDevice(&dev) != hipSuccess) return hip_fail(hipErrorInvalidDevice, "sweep tuner");
   {
     std::lock_guard<std::mutex> lk(g_sweep_tune_mu);
+    static int gen = -1, gen_half = -1;
+    tuning_sync(gen, g_sweep_tuned);
+    tuning_sync(gen_half, g_half_tuned);
     auto it = g_sweep_tuned.find({dev, n});
     if (it != g_sweep_tuned.end()) {
       *use_fused = it->second.first;
@@ -1613,6 +1633,29 @@ int tune_sweep(int n, double* th_a, double* th_b, double* delta, double* partial
   FusedCfg best_cfg;
   bool best_fused = false;
   const std::vector<SweepCand> all = sweep_candidates(n, *two);
+  // a recorded choice (this or an earlier process) that is still a candidate
+  const TileCfg def_two = *two;
+  auto code = [&](const SweepCand& c) {
+    std::vector<int> v{c.fused ? 1 : 0};
+    for (int x : tile_code(c.fused ? def_two : c.two)) v.push_back(x);
+    const FusedCfg f = c.fused ? c.fz : FusedCfg{};
+    for (int x : {f.tm, f.tj, f.tiles_j, f.tiles_m, f.nchunks}) v.push_back(x);
+    return v;
+  };
+  {
+    std::vector<int> rec;
+    if (tuning_lookup("sweep64.v1", dev, n, rec))
+      for (const SweepCand& c : all)
+        if (code(c) == rec) {
+          *use_fused = c.fused;
+          *cfg = c.fused ? c.fz : FusedCfg{};
+          if (!c.fused) *two = c.two;
+          std::lock_guard<std::mutex> lk(g_sweep_tune_mu);
+          g_sweep_tuned[{dev, n}] = {*use_fused, *cfg};
+          g_half_tuned[{dev, n}] = *two;
+          return MR_OK;
+        }
+  }
   using Cand = SweepCand;
   auto run = [&](const Cand& c) -> hipError_t {
     if (c.fused) {
@@ -1664,6 +1707,7 @@ int tune_sweep(int n, double* th_a, double* th_b, double* delta, double* partial
     g_sweep_tuned[{dev, n}] = {best_fused, best_cfg};
     g_half_tuned[{dev, n}] = best_two;
   }
+  if (!all.empty()) tuning_record("sweep64.v1", dev, n, code(all[bk]));
   *use_fused = best_fused;
   *cfg = best_cfg;
   *two = best_two;

@@ -45,12 +45,13 @@ DEPOSIT_SCHEMES = {"ngp": MR_DEPOSIT_NGP, "cic": MR_DEPOSIT_CIC, "tsc": MR_DEPOS
 
 EXPORTED = [
     "mr_default_opts", "mr_create", "mr_destroy", "mr_set_opts", "mr_size", "mr_levels",
-    "mr_get_schedule", "mr_set_schedule", "mr_schedule_candidates",
+    "mr_get_schedule", "mr_set_schedule", "mr_schedule_candidates", "mr_get_lin_schedule",
     "mr_deposit", "mr_deposit_cic", "mr_lagrangian", "mr_residual", "mr_solve", "mr_solve_anderson", "mr_adjoint_solve", "mr_adjoint_solve_anderson", "mr_solve_batched",
     "mr_tune_lin_tiles",
     "mr_sweep", "mr_defect_restrict", "mr_tau_rhs", "mr_prolong_correct", "mr_restrict",
     "mr_lin_residual", "mr_lin_defect_restrict", "mr_lin_vcycles", "mr_lin_sweep", "mr_lin_prolong_add",
-    "mr_timing_enable", "mr_timing_read", "mr_hbm_stream", "mr_residual_noalloc", "mr_last_error",
+    "mr_timing_enable", "mr_timing_read", "mr_hbm_stream", "mr_residual_noalloc",
+    "mr_tuning_file", "mr_tuning_file_path", "mr_tuning_store", "mr_tuning_lookup", "mr_last_error",
 ]
 
 
@@ -150,10 +151,18 @@ def load(path: Optional[str] = None):
     lib.mr_timing_read.argtypes = [vp, ctypes.POINTER(mr_timing)]
     lib.mr_hbm_stream.argtypes = [ip, ip, vp, vp, vp, ctypes.c_size_t, ip, vp, ctypes.POINTER(ctypes.c_float)]
     lib.mr_residual_noalloc.argtypes = [ip, vp, vp, vp, dp, dp, vp]
+    lib.mr_get_lin_schedule.argtypes = [vp, ip, ctypes.POINTER(ctypes.c_int)]
+    lib.mr_tuning_file.argtypes = [ctypes.c_char_p]
+    lib.mr_tuning_file_path.argtypes = []
+    lib.mr_tuning_file_path.restype = ctypes.c_char_p
+    cp = ctypes.c_char_p
+    lib.mr_tuning_store.argtypes = [cp, cp, cp, ip, ip, ctypes.POINTER(ctypes.c_int), ip]
+    lib.mr_tuning_lookup.argtypes = [cp, cp, cp, ip, ip, ctypes.POINTER(ctypes.c_int), ip,
+                                     ctypes.POINTER(ctypes.c_int)]
     lib.mr_last_error.argtypes = []
     lib.mr_last_error.restype = ctypes.c_char_p
     for name in EXPORTED:
-        if name not in ("mr_default_opts", "mr_destroy", "mr_last_error"):
+        if name not in ("mr_default_opts", "mr_destroy", "mr_last_error", "mr_tuning_file_path"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -258,6 +267,12 @@ class Context:
         """Pin a level's FP64 relaxation schedule (mr_set_schedule); sched = (kind, tm, tj, nchunks)."""
         a = (ctypes.c_int * 4)(*sched)
         _check(self.lib.mr_set_schedule(self.h, level, a))
+
+    def get_lin_schedule(self, level: int = 0):
+        """FP32 sweep schedule of the mixed form on a level (mr_get_lin_schedule): (kind, tm, tj, nchunks)."""
+        a = (ctypes.c_int * 4)()
+        _check(self.lib.mr_get_lin_schedule(self.h, level, a))
+        return tuple(a)
 
     def schedule_candidates(self, level: int = 0):
         """Every schedule the tuner times for a level (mr_schedule_candidates), as (kind, tm, tj, nchunks)."""
@@ -520,3 +535,29 @@ def residual_noalloc(delta: torch.Tensor, theta: torch.Tensor, r_out: Optional[t
     _check(load().mr_residual_noalloc(n, _ptr(delta), _ptr(theta), _ptr(r_out), ctypes.byref(rel), ctypes.byref(ms),
                                       _stream()))
     return r_out, rel.value, ms.value
+
+
+def tuning_file(path: Optional[str]):
+    """mr_tuning_file: record tuner choices in `path` from now on (None: the default location,
+    "": no file)."""
+    _check(load().mr_tuning_file(None if path is None else path.encode()))
+
+
+def tuning_file_path() -> str:
+    """mr_tuning_file_path: the file of recorded tuner choices in use ("" if none)."""
+    return load().mr_tuning_file_path().decode()
+
+
+def tuning_store(kind: str, arch: str, device: str, cus: int, n: int, values):
+    """mr_tuning_store: record integer values under (kind, arch, device, cus, n)."""
+    vals = (ctypes.c_int * len(values))(*values)
+    _check(load().mr_tuning_store(kind.encode(), arch.encode(), device.encode(), cus, n, vals, len(values)))
+
+
+def tuning_lookup(kind: str, arch: str, device: str, cus: int, n: int, max_count: int = 64):
+    """mr_tuning_lookup: the values recorded under the key, or None."""
+    vals = (ctypes.c_int * max_count)()
+    cnt = ctypes.c_int()
+    _check(load().mr_tuning_lookup(kind.encode(), arch.encode(), device.encode(), cus, n, vals, max_count,
+                                   ctypes.byref(cnt)))
+    return list(vals[: cnt.value]) if cnt.value else None
