@@ -276,6 +276,23 @@ int mr_adjoint_solve_anderson(mr_ctx* ctx, const double* delta, const double* th
 int mr_solve_batched(int nbox, const int* n, const double* const* delta, double* const* theta,
                      const mr_opts* opts, mr_info* infos, void* hip_stream);
 
+/* Reusable batch: the work of mr_solve_batched split into a set-up that is done once and solves
+ * that repeat it on new inputs. mr_batch_create groups the nbox sizes n[] into size classes, picks
+ * the tiles, allocates one device block for every box's working set (all levels, the descriptors,
+ * the status array) and captures one outer iteration in a HIP graph, on hip_stream; opts as for
+ * mr_solve_batched. mr_batch_solve solves the boxes for delta[b] into theta[b] (host arrays of
+ * nbox device pointers to n[b]^3 doubles, natural order) exactly as mr_solve_batched does, with
+ * no device allocation and no graph capture; it synchronises the batch's stream and returns as
+ * mr_solve_batched. mr_batch_destroy frees the batch (NULL is a no-op). A batch is not thread
+ * safe: calls on one batch must not overlap. Device memory per box: 28 bytes per cell on every
+ * level (two FP32 corrections, the FP32 right-hand side, the fixed-point base and its root, FP64
+ * delta), about 1.15 x that over the hierarchy, plus the FP64 potential (8 bytes per finest cell);
+ * with MR_FLAG_ANDERSON, 12 bytes more per finest cell and history slot. */
+typedef struct mr_batch mr_batch;
+int mr_batch_create(mr_batch** out, int nbox, const int* n, const mr_opts* opts, void* hip_stream);
+int mr_batch_solve(mr_batch* batch, const double* const* delta, double* const* theta, mr_info* infos);
+int mr_batch_destroy(mr_batch* batch);
+
 /* Tile tuner of the FP32 linear sweep used by mr_solve_batched: times every compiled tile shape
  * and plane-chunk length on a launch over several synthetic n^3 boxes (as many as fill 2^25 cells,
  * 1 to 64: the batched solve launches all boxes of a size together) on the current device, and

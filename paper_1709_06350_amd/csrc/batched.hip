@@ -17,6 +17,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "mr.h"
@@ -785,13 +786,44 @@ static int record_iteration(std::vector<SizeClass>& cls, BBox* dboxes, const mr_
   return MR_OK;
 }
 
-int solve_batched(int nbox, const int* n, const double* const* delta, double* const* theta, const mr_opts& o,
-                  mr_info* infos, hipStream_t s) {
-  auto t0 = std::chrono::steady_clock::now();
+// A batch: the size classes of its boxes, their tiles, one device allocation for every box's
+// working set, the descriptors, and the captured outer iteration. Everything a solve needs is made
+// once here; a solve then allocates no device memory and captures nothing.
+struct Batch {
+  int nbox = 0;
+  std::vector<int> n;
+  mr_opts o{};
+  hipStream_t s = nullptr;   // the caller's stream: set-up, inputs and outputs
   BatchMem mem;
-  std::vector<BBox> hb(nbox);
+  std::vector<BBox> hb;
   std::map<int, int> cls_of_n;
   std::vector<SizeClass> cls;
+  BStat* dstat = nullptr;
+  BBox* dboxes = nullptr;
+  double* scratch = nullptr;
+  unsigned* scounter = nullptr;
+  double* resall = nullptr;   // 8 doubles per box: the residual sums of its outer iteration
+  double* rbuf = nullptr;     // 8 doubles per box: results of the set-up and final reductions
+  hipStream_t cs = nullptr;   // the replay stream
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~Batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cs) (void)hipStreamDestroy(cs);
+  }
+};
+
+static int batch_create(Batch& B) {
+  const int nbox = B.nbox;
+  const int* n = B.n.data();
+  const mr_opts& o = B.o;
+  hipStream_t s = B.s;
+  BatchMem& mem = B.mem;
+  std::vector<BBox>& hb = B.hb;
+  std::map<int, int>& cls_of_n = B.cls_of_n;
+  std::vector<SizeClass>& cls = B.cls;
+  hb.resize(nbox);
   for (int b = 0; b < nbox; ++b) {
     if (cls_of_n.find(n[b]) == cls_of_n.end()) {
       cls_of_n[n[b]] = (int)cls.size();
@@ -821,12 +853,12 @@ int solve_batched(int nbox, const int* n, const double* const* delta, double* co
     for (int l = 0; l + 1 < c.nlev; ++l) c.rr[l] = pick_btile(c.ns[l]);
   }
   // per-box memory and descriptors, carved from one allocation (measured first)
-  BStat* dstat = nullptr;
-  BBox* dboxes = nullptr;
-  double* scratch = nullptr;
-  unsigned* scounter = nullptr;
-  double* resall = nullptr;   // 8 doubles per box: the residual sums of its outer iteration
-  double* rbuf = nullptr;     // 8 doubles per box: results of the set-up and final reductions
+  BStat*& dstat = B.dstat;
+  BBox*& dboxes = B.dboxes;
+  double*& scratch = B.scratch;
+  unsigned*& scounter = B.scounter;
+  double*& resall = B.resall;
+  double*& rbuf = B.rbuf;
   auto carve = [&]() -> int {
   dstat = mem.get<BStat>(nbox);
   resall = mem.get<double>(8 * (size_t)nbox);
@@ -883,6 +915,42 @@ int solve_batched(int nbox, const int* n, const double* const* delta, double* co
   for (auto& c : cls)
     if (e == hipSuccess) e = hipMemcpy(c.d_boxes, c.boxes.data(), c.boxes.size() * sizeof(int), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemsetAsync(scounter, 0, 16 * sizeof(unsigned), s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dboxes, hb.data(), nbox * sizeof(BBox), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "batched setup");
+  // capture one outer iteration (the kernels read the descriptors and per-box state from device
+  // memory, so the graph stays valid for every solve of the batch)
+  const bool eager = (o.flags & MR_FLAG_EAGER) != 0;
+  e = hipStreamCreateWithFlags(&B.cs, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "stream");
+  if (eager) return MR_OK;
+  e = hipStreamBeginCapture(B.cs, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e, "graph capture");
+  int rc = record_iteration(cls, dboxes, o, B.cs);
+  hipError_t e2 = hipStreamEndCapture(B.cs, &B.graph);
+  if (rc != MR_OK) return rc;
+  if (e2 != hipSuccess) return hip_fail(e2, "graph capture");
+  e = hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+  return MR_OK;
+}
+
+static int batch_solve(Batch& B, const double* const* delta, double* const* theta, mr_info* infos) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int nbox = B.nbox;
+  const int* n = B.n.data();
+  const mr_opts& o = B.o;
+  hipStream_t s = B.s;
+  std::vector<BBox>& hb = B.hb;
+  std::map<int, int>& cls_of_n = B.cls_of_n;
+  std::vector<SizeClass>& cls = B.cls;
+  BStat* dstat = B.dstat;
+  double* scratch = B.scratch;
+  unsigned* scounter = B.scounter;
+  double* resall = B.resall;
+  double* rbuf = B.rbuf;
+  hipStream_t cs = B.cs;
+  hipError_t e = hipSuccess;
   // Inputs: validate, convert, delta hierarchy, theta = 0. The residual at theta = 0 gives the
   // normalisation r0 and the running sum of Sigma that sets the shift of the first outer residual.
   // Every box reduces into its own result slots, so each phase needs one synchronisation.
@@ -932,42 +1000,22 @@ int solve_batched(int nbox, const int* n, const double* const* delta, double* co
     resinit[8 * (size_t)b] = -s0;   // b = -Sigma at theta = 0: running sum of Sigma
   }
   e = hipMemcpy(resall, resinit.data(), resinit.size() * sizeof(double), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(dboxes, hb.data(), nbox * sizeof(BBox), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(dstat, hs.data(), nbox * sizeof(BStat), hipMemcpyHostToDevice);
   if (o.flags & MR_FLAG_ANDERSON) {
     const BAAState zero{};
     for (int b = 0; b < nbox && e == hipSuccess; ++b) e = hipMemcpy(hb[b].aa, &zero, sizeof(BAAState), hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) return hip_fail(e, "batched setup");
-  // capture one outer iteration
   const bool eager = (o.flags & MR_FLAG_EAGER) != 0;
-  hipStream_t cs = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-  if (e == hipSuccess && !eager) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   int rc = MR_OK;
-  if (eager) {
-    if (e != hipSuccess) rc = hip_fail(e, "stream");
-  } else if (e == hipSuccess) {
-    rc = record_iteration(cls, dboxes, o, cs);
-    hipError_t e2 = hipStreamEndCapture(cs, &graph);
-    if (rc == MR_OK && e2 != hipSuccess) rc = hip_fail(e2, "graph capture");
-  } else {
-    rc = hip_fail(e, "graph capture");
-  }
-  if (rc == MR_OK && !eager) {
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) rc = hip_fail(e, "graph instantiate");
-  }
   // Replay until no box is active; each replay measures every active box once, so max_cycles + 1
   // replays always suffice.
   for (int rep = 0; rc == MR_OK && rep <= o.max_cycles; ++rep) {
     if (eager) {
-      rc = record_iteration(cls, dboxes, o, cs);
+      rc = record_iteration(cls, B.dboxes, o, cs);
       if (rc != MR_OK) break;
     } else {
-      e = hipGraphLaunch(exec, cs);
+      e = hipGraphLaunch(B.exec, cs);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(cs);
     if (e == hipSuccess) e = hipMemcpy(hs.data(), dstat, nbox * sizeof(BStat), hipMemcpyDeviceToHost);
@@ -979,9 +1027,6 @@ int solve_batched(int nbox, const int* n, const double* const* delta, double* co
     for (int b = 0; b < nbox; ++b) any = any || hs[b].active;
     if (!any) break;
   }
-  if (exec) (void)hipGraphExecDestroy(exec);
-  if (graph) (void)hipGraphDestroy(graph);
-  if (cs) (void)hipStreamDestroy(cs);
   if (rc != MR_OK) return rc;
   // final residual of the returned potentials, gauge, output (one synchronisation)
   for (int b = 0; b < nbox && e == hipSuccess; ++b) {
@@ -1027,22 +1072,82 @@ int solve_batched(int nbox, const int* n, const double* const* delta, double* co
 
 }  // namespace mr
 
-extern "C" int mr_solve_batched(int nbox, const int* n, const double* const* delta, double* const* theta,
-                                const mr_opts* opts, mr_info* infos, void* hip_stream) {
-  if (nbox < 1 || !n || !delta || !theta) return mr::fail(MR_EINVAL, "mr_solve_batched: bad arguments");
-  mr_opts o;
+static int batch_check(int nbox, const int* n, const mr_opts* opts, mr_opts& o) {
+  if (nbox < 1 || !n) return mr::fail(MR_EINVAL, "batched: bad arguments");
   mr_default_opts(&o);
   if (opts) o = *opts;
   int rc = mr::check_opts(o);
   if (rc != MR_OK) return rc;
   for (int b = 0; b < nbox; ++b) {
-    if (!delta[b] || !theta[b]) return mr::fail(MR_EINVAL, "mr_solve_batched: null box pointer");
-    if (n[b] < 8 || n[b] % 2 || n[b] > 1024) return mr::fail(MR_EINVAL, "mr_solve_batched: box size %d not supported", n[b]);
+    if (n[b] < 8 || n[b] % 2 || n[b] > 1024) return mr::fail(MR_EINVAL, "batched: box size %d not supported", n[b]);
     const auto s = mr::level_sizes(n[b]);
     if ((long)s.back() * s.back() * s.back() > mr::kMaxCoarsest || (int)s.size() > mr::kMaxLevels)
-      return mr::fail(MR_EINVAL, "mr_solve_batched: box size %d not supported", n[b]);
+      return mr::fail(MR_EINVAL, "batched: box size %d not supported", n[b]);
   }
-  return mr::solve_batched(nbox, n, delta, theta, o, infos, (hipStream_t)hip_stream);
+  return MR_OK;
+}
+
+static int batch_check_io(int nbox, const double* const* delta, double* const* theta) {
+  if (!delta || !theta) return mr::fail(MR_EINVAL, "batched: null pointer array");
+  for (int b = 0; b < nbox; ++b)
+    if (!delta[b] || !theta[b]) return mr::fail(MR_EINVAL, "batched: null box pointer");
+  return MR_OK;
+}
+
+extern "C" int mr_solve_batched(int nbox, const int* n, const double* const* delta, double* const* theta,
+                                const mr_opts* opts, mr_info* infos, void* hip_stream) {
+  mr_opts o;
+  int rc = batch_check(nbox, n, opts, o);
+  if (rc == MR_OK) rc = batch_check_io(nbox, delta, theta);
+  if (rc != MR_OK) return rc;
+  mr::Batch B;
+  B.nbox = nbox;
+  B.n.assign(n, n + nbox);
+  B.o = o;
+  B.s = (hipStream_t)hip_stream;
+  rc = mr::batch_create(B);
+  if (rc != MR_OK) return rc;
+  return mr::batch_solve(B, delta, theta, infos);
+}
+
+struct mr_batch {
+  mr::Batch b;
+};
+
+extern "C" int mr_batch_create(mr_batch** out, int nbox, const int* n, const mr_opts* opts, void* hip_stream) {
+  if (!out) return mr::fail(MR_EINVAL, "mr_batch_create: null out");
+  *out = nullptr;
+  mr_opts o;
+  int rc = batch_check(nbox, n, opts, o);
+  if (rc != MR_OK) return rc;
+  mr_batch* h = new (std::nothrow) mr_batch();
+  if (!h) return mr::fail(MR_ENOMEM, "mr_batch_create: host memory");
+  h->b.nbox = nbox;
+  h->b.n.assign(n, n + nbox);
+  h->b.o = o;
+  h->b.s = (hipStream_t)hip_stream;
+  rc = mr::batch_create(h->b);
+  if (rc != MR_OK) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return MR_OK;
+}
+
+extern "C" int mr_batch_solve(mr_batch* h, const double* const* delta, double* const* theta, mr_info* infos) {
+  if (!h) return mr::fail(MR_EINVAL, "mr_batch_solve: null batch");
+  int rc = batch_check_io(h->b.nbox, delta, theta);
+  if (rc != MR_OK) return rc;
+  return mr::batch_solve(h->b, delta, theta, infos);
+}
+
+extern "C" int mr_batch_destroy(mr_batch* h) {
+  if (!h) return MR_OK;
+  if (h->b.s) (void)hipStreamSynchronize(h->b.s);
+  if (h->b.cs) (void)hipStreamSynchronize(h->b.cs);
+  delete h;
+  return MR_OK;
 }
 
 extern "C" int mr_tune_lin_tiles(int n, void* hip_stream, int* tm, int* tj, int* ci, float* ms) {

@@ -47,6 +47,7 @@ EXPORTED = [
     "mr_default_opts", "mr_create", "mr_destroy", "mr_set_opts", "mr_size", "mr_levels",
     "mr_get_schedule", "mr_set_schedule", "mr_schedule_candidates", "mr_get_lin_schedule",
     "mr_deposit", "mr_deposit_cic", "mr_lagrangian", "mr_residual", "mr_solve", "mr_solve_anderson", "mr_adjoint_solve", "mr_adjoint_solve_anderson", "mr_solve_batched",
+    "mr_batch_create", "mr_batch_solve", "mr_batch_destroy",
     "mr_tune_lin_tiles",
     "mr_sweep", "mr_defect_restrict", "mr_tau_rhs", "mr_prolong_correct", "mr_restrict",
     "mr_lin_residual", "mr_lin_defect_restrict", "mr_lin_vcycles", "mr_lin_sweep", "mr_lin_prolong_add",
@@ -134,6 +135,9 @@ def load(path: Optional[str] = None):
     lib.mr_solve_batched.argtypes = [ip, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(vp),
                                      ctypes.POINTER(vp), ctypes.POINTER(mr_opts),
                                      ctypes.POINTER(mr_info), vp]
+    lib.mr_batch_create.argtypes = [ctypes.POINTER(vp), ip, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(mr_opts), vp]
+    lib.mr_batch_solve.argtypes = [vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(mr_info)]
+    lib.mr_batch_destroy.argtypes = [vp]
     lib.mr_tune_lin_tiles.argtypes = [ip, vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_float)]
     lib.mr_sweep.argtypes = [vp, ip, ctypes.c_double, vp, vp, ctypes.c_double, vp, vp, dp]
@@ -504,6 +508,62 @@ def solve_batched(deltas: Sequence[torch.Tensor], thetas: Optional[Sequence[torc
     if check:
         _check(code)
     return thetas, [Info.from_c(i) for i in infos]
+
+
+class Batch:
+    """A reusable batch (mr_batch_create / mr_batch_solve / mr_batch_destroy): the working set of
+    boxes of sizes `ns` is allocated and one outer iteration captured once; each solve() then runs
+    the batched mixed-precision solve on new inputs without device allocation."""
+
+    def __init__(self, ns: Sequence[int], eager: bool = False, anderson: bool = False, **opts):
+        self.lib = load()
+        self.ns = [int(x) for x in ns]
+        o = default_opts(**opts)
+        if eager:
+            o.flags |= MR_FLAG_EAGER
+        if anderson:
+            o.flags |= MR_FLAG_ANDERSON
+        h = ctypes.c_void_p()
+        arr = (ctypes.c_int * len(self.ns))(*self.ns)
+        _check(self.lib.mr_batch_create(ctypes.byref(h), len(self.ns), arr, ctypes.byref(o), _stream()))
+        self.h = h
+
+    def solve(self, deltas: Sequence[torch.Tensor], thetas: Optional[Sequence[torch.Tensor]] = None,
+              check: bool = True):
+        """Solve the boxes (shapes (n_b,)*3 in the batch's order); returns (thetas, infos)."""
+        if len(deltas) != len(self.ns):
+            raise ValueError(f"expected {len(self.ns)} boxes, got {len(deltas)}")
+        thetas = [torch.zeros_like(d) for d in deltas] if thetas is None else list(thetas)
+        for d, t, n in zip(deltas, thetas, self.ns):
+            _need(d, n ** 3, "delta")
+            _need(t, n ** 3, "theta")
+            _ptr(d)
+            _ptr(t)
+        nbox = len(self.ns)
+        dp = (ctypes.c_void_p * nbox)(*[d.data_ptr() for d in deltas])
+        tp = (ctypes.c_void_p * nbox)(*[t.data_ptr() for t in thetas])
+        infos = (mr_info * nbox)()
+        code = self.lib.mr_batch_solve(self.h, dp, tp, infos)
+        if check:
+            _check(code)
+        return thetas, [Info.from_c(i) for i in infos]
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mr_batch_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def tune_lin_tiles(n: int):

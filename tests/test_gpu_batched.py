@@ -104,6 +104,35 @@ def test_batched_replays_stop_per_box():
         assert b.cycles < a.cycles and b.rel_residual <= 1e-4
 
 
+def test_reusable_batch_equals_one_shot_calls():
+    """mr_batch_create once, mr_batch_solve on two different inputs (and again on the first):
+    every solve equals the one-shot mr_solve_batched bitwise, iterations and history included;
+    an invalid input is rejected without spoiling the batch (graph and eager forms)."""
+    require_gpu()
+    announce("reusable batch")
+    first = [dev(d) for d in _fields(SMALL)]
+    second = [dev(d) for d in _fields([(n, s * 0.8, rc, seed + 50) for n, s, rc, seed in SMALL])]
+    for eager in (False, True):
+        with mr.Batch([d.shape[0] for d in first], eager=eager, tol=TOL) as b:
+            for deltas in (first, second, first):
+                tb, ib = b.solve(deltas)
+                to, io = mr.solve_batched(deltas, tol=TOL, eager=eager)
+                for x, y, p, q in zip(tb, to, ib, io):
+                    assert torch.equal(x, y)
+                    assert p.cycles == q.cycles and p.history[: p.cycles + 1] == q.history[: q.cycles + 1]
+            bad = [d.clone() for d in first]
+            bad[2][1, 2, 3] = -2.0
+            with pytest.raises(mr.MRError) as ei:
+                b.solve(bad)
+            assert ei.value.code == mr.MR_EDOMAIN
+            tb, ib = b.solve(first)
+            to, io = mr.solve_batched(first, tol=TOL, eager=eager)
+            assert all(torch.equal(x, y) for x, y in zip(tb, to))
+    with pytest.raises(ValueError):
+        with mr.Batch([16, 24]) as b:
+            b.solve(first)
+
+
 def test_batched_rejects_bad_input():
     require_gpu()
     d = dev(inputs.lognormal(16, 0.5, 3.0, 7))
