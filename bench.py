@@ -235,28 +235,48 @@ def batched_run():
 
 
 def cic_run():
-    """CIC deposit of 256^3 Zel'dovich-displaced particles onto a 256^3 mesh (particles resident)."""
+    """Deposits of 256^3 Zel'dovich-displaced particles onto a 256^3 mesh (particles resident): NGP,
+    CIC and TSC for the catalogue in lattice order and randomly permuted, by the default path (tile
+    sort for CIC and TSC) and by the atomic scatter kernels (MR_FLAG_DEPOSIT_SCATTER); medians of 5
+    launches after one untimed. Then the Lagrangian mapping of the same particles."""
+    import numpy as np
     import torch
 
     import inputs
     from paper_1709_06350_amd import mr
 
     n = 256
-    pos = torch.from_numpy(inputs.zeldovich_particles(n, 4.0, 1001)).cuda()
+    pos_np = inputs.zeldovich_particles(n, 4.0, 1001)
+    pos = torch.from_numpy(pos_np).cuda()
+    perm = np.random.default_rng(1002).permutation(pos_np.shape[0])
+    shuf = torch.from_numpy(np.ascontiguousarray(pos_np[perm])).cuda()
     theta = torch.from_numpy(40.0 * inputs.grf(n, 4.0, 1006)).cuda()   # a smooth synthetic potential
     npart = pos.shape[0]
     reps = 5
-    with mr.Context(n) as c:
-        schemes = {}
-        for scheme in ("ngp", "cic", "tsc"):
-            out = c.deposit(pos, 1.0, scheme)
-            torch.cuda.synchronize()
+
+    def timed(c, p, scheme, out):
+        c.deposit(p, 1.0, scheme, out=out)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
             t0 = time.perf_counter()
-            for _ in range(reps):
-                c.deposit(pos, 1.0, scheme, out=out)
+            c.deposit(p, 1.0, scheme, out=out)
             torch.cuda.synchronize()
-            schemes[scheme] = (time.perf_counter() - t0) / reps
-        dt = schemes["cic"]
+            ts.append(time.perf_counter() - t0)
+        return statistics.median(ts)
+
+    with mr.Context(n) as c:
+        out = c.deposit(pos, 1.0, "cic")
+        ref = out.clone()
+        res = {}
+        for flags, tag in ((0, ""), (mr.MR_FLAG_DEPOSIT_SCATTER, "scatter_")):
+            c.set_opts(flags=flags)
+            for scheme in ("ngp", "cic", "tsc"):
+                res[f"{tag}{scheme}"] = timed(c, pos, scheme, out)
+                res[f"{tag}{scheme}_shuffled"] = timed(c, shuf, scheme, out)
+        c.set_opts(flags=0)
+        c.deposit(shuf, 1.0, "cic", out=out)
+        same = bool(torch.equal(out, ref))
         # Lagrangian mapping of the same particles (mesh displacement + CIC gather), and without the
         # mesh field (the differences formed at the particles from theta)
         disp, psi = c.lagrangian(theta, pos, want_psi=True)
@@ -273,8 +293,15 @@ def cic_run():
             c.lagrangian(theta, pos, out=disp)
         torch.cuda.synchronize()
         dn = (time.perf_counter() - t0) / reps
+    dt = res["cic"]
     cic = {"particles": npart, "mesh": n, "seconds": round(dt, 5), "gparticles_per_s": round(npart / dt / 1e9, 3),
-           "ngp_seconds": round(schemes["ngp"], 5), "tsc_seconds": round(schemes["tsc"], 5)}
+           "ngp_seconds": round(res["ngp"], 5), "tsc_seconds": round(res["tsc"], 5),
+           "shuffled_seconds": {k: round(res[f"{k}_shuffled"], 5) for k in ("ngp", "cic", "tsc")},
+           "scatter_kernels_seconds": {k: round(res[f"scatter_{k}"], 5) for k in ("ngp", "cic", "tsc")},
+           "scatter_kernels_shuffled_seconds": {k: round(res[f"scatter_{k}_shuffled"], 5) for k in ("ngp", "cic", "tsc")},
+           "shuffled_equals_lattice_bitwise": same,
+           "note": "CIC and TSC sort the particles by 16 x 16 x 32 mesh tile (no global atomics); NGP and the "
+                   "scatter_kernels entries use 64-bit atomics; medians of 5"}
     lag = {"particles": npart, "mesh": n, "seconds": round(dl, 5), "gparticles_per_s": round(npart / dl / 1e9, 3),
            "note": "mesh displacement grad(theta) into a caller buffer + CIC gather to the particles",
            "without_mesh_field_seconds": round(dn, 5)}

@@ -88,6 +88,9 @@ typedef struct {
  * MR_FLAG_ANDERSON (mr_solve_batched only): mix each box's outer iterations as mr_solve_anderson
  * does, with depth 2 (the state stays on the device, inside the replayed graph); not in the paper,
  * same solutions.
+ * MR_FLAG_DEPOSIT_SCATTER (mr_deposit): deposit CIC and TSC with the atomic scatter kernels instead
+ * of sorting the particles by mesh tile; both give the same result bit for bit (the same rounded
+ * contribution per particle and mesh point, summed exactly in 64-bit fixed point).
  * MR_FLAG_PLAIN_INNER (mr_solve at MR_PREC_MIXED): the inner solve of each outer step is
  * inner_cycles plain linear V-cycles instead of flexible GMRES with inner_cycles V-cycles as the
  * preconditioner (the default; mr_solve_anderson at MR_PREC_MIXED always uses plain cycles). */
@@ -98,7 +101,8 @@ enum {
   MR_FLAG_ADJ_TILED = 8,
   MR_FLAG_ORDER4 = 16,
   MR_FLAG_ANDERSON = 32,
-  MR_FLAG_PLAIN_INNER = 64
+  MR_FLAG_PLAIN_INNER = 64,
+  MR_FLAG_DEPOSIT_SCATTER = 128
 };
 
 /* Per-solve report. history[c] is the relative residual after cycle c (history[0] = start).
@@ -178,7 +182,12 @@ int mr_get_lin_schedule(mr_ctx* ctx, int level, int sched[4]);
  * deposits mass times the product of its three axis weights on each point. delta_out: device
  * n^3, receives rho / <rho> - 1 with <rho> = np * mass / n^3 (mass > 0). Accumulation is in
  * unsigned 64-bit fixed point (each weight rounded to a multiple of 2^-40 of a particle's mass
- * before the sum), so the result is bitwise reproducible. Returns MR_EINVAL for a NULL argument,
+ * before the sum), so the result is bitwise reproducible and independent of the particles' order.
+ * CIC and TSC on meshes with n a multiple of 32 up to 512 first sort the particles by mesh tile
+ * (16 x 16 x 32 points; counting sort on the device) and accumulate each tile in LDS, without global
+ * atomics; this needs 24 bytes per particle and about 11 bytes per mesh point of device memory,
+ * kept with the context. NGP, other meshes and MR_FLAG_DEPOSIT_SCATTER use atomic scatter kernels
+ * into a 64-bit grid; both ways give the same result bit for bit. Returns MR_EINVAL for a NULL argument,
  * np < 1, a mass that is not positive and finite, an unknown scheme, or particles with a
  * non-finite coordinate (then delta_out is left unchanged); a cell can hold at most 2^24
  * particles' worth of weight, and an overflow (detected from the total) returns MR_EINVAL. */

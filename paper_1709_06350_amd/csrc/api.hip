@@ -54,7 +54,7 @@ int check_opts(const mr_opts& o) {
       (o.precision != MR_PREC_FP64 && o.precision != MR_PREC_MIXED) || o.inner_cycles < 1 ||
       o.inner_cycles > 8 ||
       (o.flags & ~(MR_FLAG_EAGER | MR_FLAG_TWO_PASS | MR_FLAG_ADJ_ROWS | MR_FLAG_ADJ_TILED | MR_FLAG_ORDER4 |
-                   MR_FLAG_ANDERSON | MR_FLAG_PLAIN_INNER)) != 0 ||
+                   MR_FLAG_ANDERSON | MR_FLAG_PLAIN_INNER | MR_FLAG_DEPOSIT_SCATTER)) != 0 ||
       (o.flags & MR_FLAG_ADJ_ROWS && o.flags & MR_FLAG_ADJ_TILED))
     return fail(MR_EINVAL, "invalid options");
   return MR_OK;

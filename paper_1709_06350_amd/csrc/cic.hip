@@ -216,6 +216,215 @@ __global__ void __launch_bounds__(256) deposit_scatter_binned_kernel(const doubl
   }
 }
 
+// ---- deposit through particles sorted by mesh tile (any particle order) ------------------------
+// The mesh is cut into tiles of 16 x 16 x 32 points. A particle belongs to the tile of the lowest
+// mesh point it reaches (the first of its S points per axis, wrapped); its S^3 points then lie in
+// the tile's box of (16 + S - 1) x (16 + S - 1) x (32 + S - 1) points. Counting sort of the
+// particles by tile: count per (block of particles, tile), exclusive scan, scatter of the
+// positions into tile order. One block per tile then accumulates its particles' contributions in
+// its box in LDS (64-bit fixed point, the same rounded contribution per particle and point as the
+// scatter kernels above, so the integer sums and the result are bitwise those of the scatter) and
+// writes the whole box out; a last pass adds to every point of a tile the boxes of the (up to 7)
+// lower neighbour tiles that reach it and writes delta. No global atomics: the result does not
+// depend on particle order, and the traffic is that of reading the catalogue three times.
+constexpr int kDepTX = 16, kDepTY = 16, kDepTZ = 32;
+
+struct DepGeom {
+  int n, tnx, tny, tnz, ntiles;
+};
+
+template <int S>
+struct DepBox {
+  static constexpr int BX = kDepTX + S - 1, BY = kDepTY + S - 1, BZ = kDepTZ + S - 1;
+  static constexpr int CELLS = BX * BY * BZ;
+};
+
+// The particle's tile and its first mesh point inside the tile (false for a non-finite position).
+template <int S>
+__device__ __forceinline__ bool dep_place(const double* __restrict__ pos, long long p, const DepGeom& g, int& tile,
+                                          int (&ix)[S], int (&iy)[S], int (&iz)[S], double (&wx)[S], double (&wy)[S],
+                                          double (&wz)[S]) {
+  const double x = pos[3 * p], y = pos[3 * p + 1], z = pos[3 * p + 2];
+  if (!__builtin_isfinite(x) || !__builtin_isfinite(y) || !__builtin_isfinite(z)) return false;
+  axis_assign<S>(x, g.n, ix, wx);
+  axis_assign<S>(y, g.n, iy, wy);
+  axis_assign<S>(z, g.n, iz, wz);
+  tile = ((ix[0] / kDepTX) * g.tny + iy[0] / kDepTY) * g.tnz + iz[0] / kDepTZ;
+  return true;
+}
+
+// hist[b][t]: particles of block b's range [b per, (b + 1) per) in tile t.
+template <int S>
+__global__ void __launch_bounds__(256) dep_count_kernel(const double* __restrict__ pos, long long np, DepGeom g,
+                                                        long long per, unsigned* __restrict__ hist,
+                                                        double* __restrict__ bad_count) {
+  extern __shared__ unsigned dep_lds[];
+  for (int t = threadIdx.x; t < g.ntiles; t += blockDim.x) dep_lds[t] = 0u;
+  __syncthreads();
+  const long long p0 = (long long)blockIdx.x * per, p1 = min(np, p0 + per);
+  for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    int tile, ix[S], iy[S], iz[S];
+    double wx[S], wy[S], wz[S];
+    if (dep_place<S>(pos, p, g, tile, ix, iy, iz, wx, wy, wz))
+      atomicAdd(&dep_lds[tile], 1u);
+    else
+      __hip_atomic_fetch_add(bad_count, 1.0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  unsigned* row = hist + (size_t)blockIdx.x * g.ntiles;
+  for (int t = threadIdx.x; t < g.ntiles; t += blockDim.x) row[t] = dep_lds[t];
+}
+
+// hist[b][t] <- particles of tile t in blocks before b; total[t]. A block takes 64 consecutive tiles
+// (one per lane, coalesced rows) and splits the blocks into 16 segments, one per wave: each wave
+// sums its segment, the segment sums are scanned in LDS, then each wave writes its prefixes.
+constexpr int kDepScanSeg = 16;
+__global__ void __launch_bounds__(64 * kDepScanSeg) dep_scan_blocks_kernel(unsigned* __restrict__ hist, int nblocks,
+                                                                           int ntiles, unsigned* __restrict__ total) {
+  __shared__ unsigned seg[kDepScanSeg][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int t = blockIdx.x * 64 + lane;
+  const int b0 = (int)(((long)w * nblocks) / kDepScanSeg), b1 = (int)(((long)(w + 1) * nblocks) / kDepScanSeg);
+  unsigned s = 0u;
+  if (t < ntiles)
+    for (int b = b0; b < b1; ++b) s += hist[(size_t)b * ntiles + t];
+  seg[w][lane] = s;
+  __syncthreads();
+  unsigned run = 0u;
+  for (int k = 0; k < w; ++k) run += seg[k][lane];
+  if (t < ntiles) {
+    for (int b = b0; b < b1; ++b) {
+      unsigned* c = hist + (size_t)b * ntiles + t;
+      const unsigned v = *c;
+      *c = run;
+      run += v;
+    }
+    if (w == kDepScanSeg - 1) total[t] = run;
+  }
+}
+
+// One block of 1024 threads: start[t] = particles of tiles before t, start[ntiles] = all of them.
+__global__ void __launch_bounds__(1024) dep_scan_tiles_kernel(const unsigned* __restrict__ total, int ntiles,
+                                                              unsigned* __restrict__ start) {
+  __shared__ unsigned part[1024];
+  const int tid = threadIdx.x;
+  const int per = (ntiles + 1023) / 1024;
+  const int t0 = tid * per, t1 = min(ntiles, t0 + per);
+  unsigned s = 0u;
+  for (int t = t0; t < t1; ++t) s += total[t];
+  part[tid] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {   // inclusive scan of the per-thread sums
+    const unsigned v = tid >= off ? part[tid - off] : 0u;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  unsigned run = tid == 0 ? 0u : part[tid - 1];
+  for (int t = t0; t < t1; ++t) {
+    start[t] = run;
+    run += total[t];
+  }
+  if (tid == 1023) start[ntiles] = part[1023];
+}
+
+// The positions of block b's particles into tile order (the order inside a tile is immaterial).
+template <int S>
+__global__ void __launch_bounds__(256) dep_scatter_kernel(const double* __restrict__ pos, long long np, DepGeom g,
+                                                          long long per, const unsigned* __restrict__ hist,
+                                                          const unsigned* __restrict__ start,
+                                                          double* __restrict__ sorted) {
+  extern __shared__ unsigned dep_lds[];
+  const unsigned* row = hist + (size_t)blockIdx.x * g.ntiles;
+  for (int t = threadIdx.x; t < g.ntiles; t += blockDim.x) dep_lds[t] = start[t] + row[t];
+  __syncthreads();
+  const long long p0 = (long long)blockIdx.x * per, p1 = min(np, p0 + per);
+  for (long long p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+    int tile, ix[S], iy[S], iz[S];
+    double wx[S], wy[S], wz[S];
+    if (!dep_place<S>(pos, p, g, tile, ix, iy, iz, wx, wy, wz)) continue;
+    const unsigned slot = atomicAdd(&dep_lds[tile], 1u);
+    double* r = sorted + 3 * (size_t)slot;
+    r[0] = pos[3 * p];
+    r[1] = pos[3 * p + 1];
+    r[2] = pos[3 * p + 2];
+  }
+}
+
+// One block per tile: the tile's particles into its box (LDS), the box out to boxes[tile].
+template <int S>
+__global__ void __launch_bounds__(256) dep_tile_kernel(const double* __restrict__ sorted,
+                                                       const unsigned* __restrict__ start, DepGeom g,
+                                                       unsigned long long* __restrict__ boxes) {
+  using B = DepBox<S>;
+  __shared__ unsigned long long box[B::CELLS];
+  const int t = blockIdx.x;
+  for (int c = threadIdx.x; c < B::CELLS; c += blockDim.x) box[c] = 0ull;
+  __syncthreads();
+  const int tz = t % g.tnz, ty = (t / g.tnz) % g.tny, tx = t / (g.tnz * g.tny);
+  const unsigned q0 = start[t], q1 = start[t + 1];
+  for (unsigned q = q0 + threadIdx.x; q < q1; q += blockDim.x) {
+    int tile, ix[S], iy[S], iz[S];
+    double wx[S], wy[S], wz[S];
+    (void)dep_place<S>(sorted, (long long)q, g, tile, ix, iy, iz, wx, wy, wz);   // finite by construction
+    const int lx = ix[0] - tx * kDepTX, ly = iy[0] - ty * kDepTY, lz = iz[0] - tz * kDepTZ;
+#pragma unroll
+    for (int a = 0; a < S; ++a)
+#pragma unroll
+      for (int b = 0; b < S; ++b)
+#pragma unroll
+        for (int d = 0; d < S; ++d) {
+          const double w = wx[a] * wy[b] * wz[d];
+          const unsigned long long v = (unsigned long long)__double2ull_rn(w * kFixScale);
+          if (v) atomicAdd(&box[((lx + a) * B::BY + (ly + b)) * B::BZ + (lz + d)], v);
+        }
+  }
+  __syncthreads();
+  unsigned long long* out = boxes + (size_t)t * B::CELLS;
+  for (int c = threadIdx.x; c < B::CELLS; c += blockDim.x) out[c] = box[c];
+}
+
+// One block per tile: every point of the tile sums its own box and the lower neighbours' boxes that
+// reach it; delta = count n^3 / (np 2^40) - 1; partials[tile] = the tile's sum of counts / 2^40.
+// Writes nothing when a particle had a non-finite position (*bad_count != 0, complete since the
+// counting launch): the call then fails and leaves delta unchanged.
+template <int S>
+__global__ void __launch_bounds__(256) dep_combine_kernel(const unsigned long long* __restrict__ boxes, DepGeom g,
+                                                          double scale, double* __restrict__ delta,
+                                                          double* __restrict__ partials, const double* bad_count) {
+  using B = DepBox<S>;
+  __shared__ double red[16][1];
+  const int t = blockIdx.x;
+  if (*bad_count != 0.0) {
+    if (threadIdx.x == 0) partials[t] = 0.0;
+    return;
+  }
+  const int tz = t % g.tnz, ty = (t / g.tnz) % g.tny, tx = t / (g.tnz * g.tny);
+  const int n = g.n;
+  double acc = 0.0;
+  for (int c = threadIdx.x; c < kDepTX * kDepTY * kDepTZ; c += blockDim.x) {
+    const int lz = c % kDepTZ, ly = (c / kDepTZ) % kDepTY, lx = c / (kDepTZ * kDepTY);
+    unsigned long long v = 0ull;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int dx = k >> 2, dy = (k >> 1) & 1, dz = k & 1;
+      if ((dx && lx >= S - 1) || (dy && ly >= S - 1) || (dz && lz >= S - 1)) continue;
+      const int nx = tx - dx < 0 ? g.tnx - 1 : tx - dx;
+      const int ny = ty - dy < 0 ? g.tny - 1 : ty - dy;
+      const int nz = tz - dz < 0 ? g.tnz - 1 : tz - dz;
+      const int nt = (nx * g.tny + ny) * g.tnz + nz;
+      v += boxes[(size_t)nt * B::CELLS + ((lx + dx * kDepTX) * B::BY + (ly + dy * kDepTY)) * B::BZ + (lz + dz * kDepTZ)];
+    }
+    const size_t cell = ((size_t)(tx * kDepTX + lx) * n + (ty * kDepTY + ly)) * n + (tz * kDepTZ + lz);
+    const double cnt = (double)v;
+    delta[cell] = cnt * scale - 1.0;
+    acc += cnt * (1.0 / kFixScale);
+  }
+  double vv[1] = {acc};
+  block_sum<1>(vv, red, threadIdx.x, blockDim.x);
+  if (threadIdx.x == 0) partials[t] = vv[0];
+}
+
 // delta = count * n^3 / (np * 2^40) - 1; partials[block] = the block's sum of counts / 2^40. The
 // partials are added by sum_partials_kernel in the next launch (fixed order, no per-block fences).
 __global__ void __launch_bounds__(256) cic_normalise_kernel(const unsigned long long* __restrict__ grid, size_t cells,
@@ -256,8 +465,73 @@ static int blocks_for(size_t work, int cap) {
   return (int)(b < 1 ? 1 : (b > (size_t)cap ? cap : b));
 }
 
+// The tile-sorted deposit (CIC, TSC) on meshes with n a multiple of 32 up to 512.
+template <int S>
+static int deposit_sorted(Ctx* c, const double* pos, long long np, double* delta_out) {
+  const int n = c->n;
+  DepGeom g{n, n / kDepTX, n / kDepTY, n / kDepTZ, 0};
+  g.ntiles = g.tnx * g.tny * g.tnz;
+  const size_t cells = (size_t)n * n * n;
+  // particle ranges: at most 1024 blocks and 4M (block, tile) counters
+  int nb = (int)std::min<long long>(1024, std::max<long long>(1, (4 << 20) / g.ntiles));
+  nb = (int)std::min<long long>(nb, (np + 255) / 256);
+  const long long per = (np + nb - 1) / nb;
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t b_hist = al((size_t)nb * g.ntiles * 4), b_tot = al((size_t)g.ntiles * 4),
+               b_start = al(((size_t)g.ntiles + 1) * 4), b_sorted = al((size_t)np * 24),
+               b_boxes = al((size_t)g.ntiles * DepBox<3>::CELLS * 8);
+  const size_t need = b_hist + b_tot + b_start + b_sorted + b_boxes;
+  if (c->dep_bytes < need) {
+    if (c->dep_mem) (void)hipFree(c->dep_mem);
+    c->dep_mem = nullptr;
+    c->dep_bytes = 0;
+    hipError_t e = hipMalloc(&c->dep_mem, need);
+    if (e != hipSuccess) return fail(MR_ENOMEM, "density assignment: %.1f MiB of sort buffers", need / 1048576.0);
+    c->dep_bytes = need;
+  }
+  char* m = (char*)c->dep_mem;
+  unsigned* hist = (unsigned*)m;
+  unsigned* total = (unsigned*)(m + b_hist);
+  unsigned* start = (unsigned*)(m + b_hist + b_tot);
+  double* sorted = (double*)(m + b_hist + b_tot + b_start);
+  unsigned long long* boxes = (unsigned long long*)(m + b_hist + b_tot + b_start + b_sorted);
+  double* bad_count = c->scal + kSlotRes;
+  const size_t lds = (size_t)g.ntiles * 4;
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, c->stream, (unsigned long long*)nullptr, (size_t)0, bad_count);
+  hipLaunchKernelGGL(dep_count_kernel<S>, dim3(nb), dim3(256), lds, c->stream, pos, np, g, per, hist, bad_count);
+  hipLaunchKernelGGL(dep_scan_blocks_kernel, dim3((g.ntiles + 63) / 64), dim3(64 * kDepScanSeg), 0, c->stream, hist, nb,
+                     g.ntiles, total);
+  hipLaunchKernelGGL(dep_scan_tiles_kernel, dim3(1), dim3(1024), 0, c->stream, (const unsigned*)total, g.ntiles, start);
+  hipLaunchKernelGGL(dep_scatter_kernel<S>, dim3(nb), dim3(256), lds, c->stream, pos, np, g, per, (const unsigned*)hist,
+                     (const unsigned*)start, sorted);
+  hipLaunchKernelGGL(dep_tile_kernel<S>, dim3(g.ntiles), dim3(256), 0, c->stream, (const double*)sorted,
+                     (const unsigned*)start, g, boxes);
+  const double scale = (double)cells / ((double)np * kFixScale);
+  hipLaunchKernelGGL(dep_combine_kernel<S>, dim3(g.ntiles), dim3(256), 0, c->stream, (const unsigned long long*)boxes, g,
+                     scale, delta_out, c->partials, (const double*)bad_count);
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, c->stream, (const double*)c->partials, g.ntiles,
+                     c->scal + kSlotRes + 1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "mr_deposit");
+  double r[2];
+  int rc = c->read_scalars(kSlotRes, 2, r);
+  if (rc != MR_OK) return rc;
+  if (r[0] != 0.0) return fail(MR_EINVAL, "mr_deposit: %.0f particles with non-finite coordinates", r[0]);
+  if (!(std::fabs(r[1] - (double)np) <= 0.5 + 1e-9 * (double)np))
+    return fail(MR_EINVAL, "mr_deposit: fixed-point overflow (deposited %.6g of %lld particles)", r[1], np);
+  return MR_OK;
+}
+
+static bool deposit_sorted_applies(int n, long long np) {
+  return n % 32 == 0 && n >= 32 && n <= 512 && np < ((long long)1 << 31);
+}
+
 int Ctx::deposit(const double* pos, long long np, double mass, int scheme, double* delta_out) {
   const size_t cells = lv[0].cells;
+  (void)mass;
+  if (!(opts.flags & MR_FLAG_DEPOSIT_SCATTER) && scheme != MR_DEPOSIT_NGP && deposit_sorted_applies(n, np))
+    return scheme == MR_DEPOSIT_CIC ? deposit_sorted<2>(this, pos, np, delta_out)
+                                    : deposit_sorted<3>(this, pos, np, delta_out);
   if (!cic_grid) {
     hipError_t e = hipMalloc((void**)&cic_grid, cells * sizeof(unsigned long long));
     if (e != hipSuccess) return fail(MR_ENOMEM, "density assignment grid: %s", hipGetErrorString(e));

@@ -816,6 +816,11 @@ static int mixed_alloc(Ctx* c) {
 }
 
 void Ctx::release_extra() {
+  if (dep_mem) {
+    (void)hipFree(dep_mem);
+    dep_mem = nullptr;
+    dep_bytes = 0;
+  }
   if (cic_grid) {
     (void)hipFree(cic_grid);
     cic_grid = nullptr;

@@ -85,6 +85,8 @@ struct Ctx {
   std::vector<void*> owned;
   EventTimer timer;
   unsigned long long* cic_grid = nullptr;   // fixed-point CIC accumulation grid (allocated on first use)
+  void* dep_mem = nullptr;                   // tile-sorted deposit: counts, offsets, sorted particles, boxes
+  size_t dep_bytes = 0;
   MixedState* mixed = nullptr;
   AdjointState* adj = nullptr;
   double* aa_mem = nullptr;   // Anderson history (x save, f and y rings, partials), on first use

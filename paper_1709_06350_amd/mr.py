@@ -30,6 +30,7 @@ MR_FLAG_ADJ_TILED = 8
 MR_FLAG_ORDER4 = 16
 MR_FLAG_ANDERSON = 32
 MR_FLAG_PLAIN_INNER = 64
+MR_FLAG_DEPOSIT_SCATTER = 128
 PREC_FP64 = 0
 PREC_MIXED = 1
 MR_SCHED_TILED = 0

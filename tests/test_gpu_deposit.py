@@ -196,3 +196,53 @@ def test_displaced_lattice_catalogues(scheme, m, n):
     assert np.array_equal(a, b)
     ref = odep.overdensity(odep.deposit(pos, n, 1.5, scheme))
     np.testing.assert_allclose(a, ref, rtol=0, atol=_tol(n, m ** 3) + 1e-13 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("scheme", ["cic", "tsc"])
+@pytest.mark.parametrize("n", [32, 128, 256])
+def test_tile_sorted_deposit_equals_scatter_bitwise(scheme, n):
+    """The tile-sorted deposit (counting sort by 16 x 16 x 32 mesh tile, LDS accumulation, no global
+    atomics) against the atomic scatter kernels (MR_FLAG_DEPOSIT_SCATTER): the same rounded
+    contribution per particle and point, summed exactly, so the same delta bit for bit; for a
+    Zel'dovich catalogue in lattice order and shuffled, with particles on the seam and far outside."""
+    require_gpu()
+    announce(f"tile-sorted deposit {scheme} n={n}")
+    m = n if n <= 128 else n // 2
+    pos = inputs.zeldovich_particles(m, 2.0, 1300 + n, rms_disp=1.5) * (n / m)
+    rng = np.random.default_rng(1400 + n)
+    pos[::4999] = rng.uniform(-2 * n, 3 * n, pos[::4999].shape)
+    pos[1:5, 0] = [n - 1e-9, 0.0, -1e-12, n - 0.5]
+    shuffled = np.ascontiguousarray(pos[rng.permutation(pos.shape[0])])
+    with mr.Context(n) as c:
+        a = host(c.deposit(dev(pos), 1.0, scheme))
+        b = host(c.deposit(dev(shuffled), 1.0, scheme))
+        c.set_opts(flags=mr.MR_FLAG_DEPOSIT_SCATTER)
+        s = host(c.deposit(dev(shuffled), 1.0, scheme))
+    assert np.array_equal(a, b)
+    assert np.array_equal(a, s)
+    if n <= 128:
+        ref = odep.overdensity(odep.deposit(pos, n, 1.0, scheme))
+        np.testing.assert_allclose(a, ref, rtol=0, atol=_tol(n, pos.shape[0]) * 8 + 1e-13 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("scheme", ["cic", "tsc"])
+def test_tile_sorted_deposit_clustered_and_empty_tiles(scheme):
+    """Most particles in one tile (a tight clump across the seam of x), the rest in a few cells:
+    one tile block takes a large share, most tiles are empty; against the scatter kernels and the
+    oracle."""
+    require_gpu()
+    n = 64
+    announce(f"tile-sorted deposit clustered {scheme}")
+    rng = np.random.default_rng(77)
+    clump = rng.normal(0.0, 1.2, (200000, 3)) + np.array([0.3, 20.0, 40.0])
+    few = rng.uniform(0, n, (40, 3))
+    pos = np.ascontiguousarray(np.concatenate([clump, few]))
+    with mr.Context(n) as c:
+        a = host(c.deposit(dev(pos), 2.0, scheme))
+        c.set_opts(flags=mr.MR_FLAG_DEPOSIT_SCATTER)
+        s = host(c.deposit(dev(pos), 2.0, scheme))
+    assert np.array_equal(a, s)
+    ref = odep.overdensity(odep.deposit(pos, n, 2.0, scheme))
+    # every contribution is rounded by at most 2^-41 particle masses; at most all np particles
+    # with 27 points each reach one cell
+    np.testing.assert_allclose(a, ref, rtol=0, atol=27 * 2.0 ** -41 * pos.shape[0] * n ** 3 / pos.shape[0])
