@@ -56,5 +56,35 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     return LIB
 
 
+# The host half of every source instrumented by AddressSanitizer and UndefinedBehaviorSanitizer
+# (the device code is not instrumented: each flag is for the host compilation only).
+SANITIZE_HOST = [
+    "-Xarch_host", "-fsanitize=address",
+    "-Xarch_host", "-fsanitize=undefined",
+    "-Xarch_host", "-fno-sanitize-recover=undefined",
+    "-Xarch_host", "-fno-omit-frame-pointer",
+]
+
+
+def build_host_check(outdir: str, verbose: bool = False, jobs: int | None = None) -> str:
+    """Build tests/host_check.cpp against every HIP source with the host sanitizers into outdir;
+    returns the executable's path (run it with ASAN_OPTIONS=detect_leaks=0: the HIP runtime keeps
+    allocations until exit)."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(outdir, exist_ok=True)
+    flags = ["--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC",
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", *SANITIZE_HOST, "-I", INCLUDE, "-I", CSRC]
+    srcs = sources() + [os.path.join(ROOT, "tests", "host_check.cpp")]
+    objs = [os.path.join(outdir, os.path.basename(s).rsplit(".", 1)[0] + ".o") for s in srcs]
+    cmds = [[hipcc, *flags, "-x", "hip", "-c", s, "-o", o] for s, o in zip(srcs, objs)]
+    jobs = jobs or max(1, min(len(cmds), os.cpu_count() or 1, 8))
+    with ThreadPoolExecutor(jobs) as ex:
+        for f in [ex.submit(_run, c, verbose) for c in cmds]:
+            f.result()
+    exe = os.path.join(outdir, "host_check")
+    _run([hipcc, "--offload-arch=gfx950", *SANITIZE_HOST, *objs, "-o", exe], verbose)
+    return exe
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
