@@ -14,7 +14,8 @@ peak; "traffic" is the HBM traffic per sweep measured with rocprofv3 counters (c
 summary), over the same sweep time.
 
 Also reported: time to solution of both 512^3 solves (medians over the timed steps; the mixed
-solve with npre = npost = 2 and at most 4 FP32 V-cycles per outer step) and the largest difference
+solve with npre = npost = 2, at most 4 FP32 V-cycles per outer step and 8 sweeps on the inner
+coarsest mesh) and the largest difference
 of the two solutions relative to max |theta|; one adjoint solve at 512^3; the CIC deposit of 256^3
 particles onto a 256^3 mesh; and the batched form on 64 boxes of {64, 96, 128}^3 (mixed precision
 to 1e-8), each timed after an untimed run. The CPU baseline times the oracle on bounded samples.
@@ -65,7 +66,7 @@ def measured_traffic(schedule: str):
 
 SCHED_KERNEL = {0: "half_sweep_tiled", 1: "half_sweep_pipe", 2: "sweep_fused"}
 # options of the mixed-precision solve
-MIXED_OPTS = {"npre": 2, "npost": 2, "inner_cycles": 4}
+MIXED_OPTS = {"npre": 2, "npost": 2, "inner_cycles": 4, "ncoarse": 8}
 
 
 def _cpu_model() -> str:
@@ -528,7 +529,8 @@ def main():
             "fp64_all": [round(x, 4) for x in ts64],
             "mixed_all": [round(x, 4) for x in tsm],
             "mixed_opts": dict(MIXED_OPTS, note="flexible GMRES inner solve of at most inner_cycles FP32 "
-                                                 "V-cycles per outer FP64 step; FP64 solve at npre = npost = 2"),
+                                                 "V-cycles per outer FP64 step, ncoarse sweeps on the inner "
+                                                 "coarsest mesh; FP64 solve at npre = npost = 2, ncoarse = 20"),
             "theta_max_rel_diff_mixed_vs_fp64": theta_err,
         },
         "cycles": {"fp64": info64.cycles if info64 else None,

@@ -506,10 +506,22 @@ hipError_t launch_quantise(const double* src, int* dst, size_t cells, const doub
   return hipGetLastError();
 }
 
-hipError_t launch_lin_resid_restrict(const float* e, const int* baseq, const double* bq, const float* sb, const float* rhs,
-                                     int n, double h, ShiftRef c, float* rhs_c, Reduce red, hipStream_t s) {
+// With tm0 > 0 the tile (tm0, tj0) and nch0 chunks (a timed choice); otherwise the largest tile that
+// fits with chunks from the occupancy model.
+static hipError_t launch_lin_rr(const float* e, const int* baseq, const double* bq, const float* sb, const float* rhs,
+                                int n, double h, ShiftRef c, float* rhs_c, Reduce red, hipStream_t s, int tm0, int tj0,
+                                int nch0) {
   int tm = 0, tj = 0, nch = 0;
-  if (tiled_cfg(n, rr_tiled_kernel, 2, tm, tj, nch, kPref8)) {
+  bool tiled = false;
+  if (tm0 > 0) {
+    tm = tm0;
+    tj = tj0;
+    nch = nch0;
+    tiled = (n / 2) % tm == 0 && n % tj == 0 && nch >= 1 && nch <= n / 4;
+  } else {
+    tiled = tiled_cfg(n, rr_tiled_kernel, 2, tm, tj, nch, kPref8);
+  }
+  if (tiled) {
     LinRRArgs a{e, baseq, bq, sb, rhs, n, (float)(1.0 / (h * h)), c, rhs_c, red, n / tj, n / 2 / tm, nch};
     const unsigned blocks = (unsigned)(a.tiles_j * a.tiles_m * nch);
 #define MR_RR_LAUNCH(TM, TJ)                                                                           \
@@ -524,6 +536,11 @@ hipError_t launch_lin_resid_restrict(const float* e, const int* baseq, const dou
   hipLaunchKernelGGL(lin_resid_restrict_kernel, dim3(rows_blocks(m)), dim3(row_threads(m)), 0, s, e, baseq, bq, sb, rhs,
                      n, (float)(1.0 / (h * h)), c, rhs_c, red);
   return hipGetLastError();
+}
+
+hipError_t launch_lin_resid_restrict(const float* e, const int* baseq, const double* bq, const float* sb, const float* rhs,
+                                     int n, double h, ShiftRef c, float* rhs_c, Reduce red, hipStream_t s) {
+  return launch_lin_rr(e, baseq, bq, sb, rhs, n, h, c, rhs_c, red, s, 0, 0, 0);
 }
 
 __global__ void __launch_bounds__(256) prolong_rows32_kernel(const float* __restrict__ ec, float* __restrict__ e, int n) {
@@ -600,6 +617,7 @@ struct LinLevel {
   TileCfg sw;            // two-launch schedule
   bool fused = false;    // the one-launch sweep (schedule fz) won the tuner
   LinFusedCfg fz;
+  int rr_tm = 0, rr_tj = 0, rr_nch = 0;   // timed defect + restriction tile (rr_tm == 0: default)
 };
 
 // Krylov space of the inner solve on the finest mesh: V[0..m] orthonormal mean-free vectors,
@@ -788,6 +806,72 @@ static int tune_lin_sweep(Ctx* c, int l, LinSched* out) {
   return MR_OK;
 }
 
+static std::mutex g_rr_tune_mu;
+static std::map<std::pair<int, int>, std::vector<int>> g_rr_tuned;   // (device, n) -> (tm, tj, nchunks)
+
+// Times the FP32 defect + restriction of level l (< coarsest) on every compiled tile with 1 to n/4
+// chunks (powers of two) and the occupancy-model default, on the level's zeroed buffers (the kernel
+// only reads them and writes the coarse right-hand side); keeps and records the fastest.
+static int tune_lin_rr(Ctx* c, int l, int* tm, int* tj, int* nch) {
+  const int n = c->lv[l].n, nh = n / 2;
+  *tm = *tj = *nch = 0;
+  if (n % 8 != 0) return MR_OK;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return hip_fail(hipErrorInvalidDevice, "defect tuner");
+  {
+    std::lock_guard<std::mutex> lk(g_rr_tune_mu);
+    static int gen = -1;
+    tuning_sync(gen, g_rr_tuned);
+    auto it = g_rr_tuned.find({dev, n});
+    if (it != g_rr_tuned.end()) {
+      *tm = it->second[0];
+      *tj = it->second[1];
+      *nch = it->second[2];
+      return MR_OK;
+    }
+  }
+  std::vector<std::vector<int>> cand{{0, 0, 0}};
+  auto add = [&](int TM, int TJ) {
+    if (nh % TM != 0 || n % TJ != 0) return;
+    for (int k = 1; k <= n / 4; k *= 2)
+      if ((long)(n / TJ) * (nh / TM) * k <= kMaxReduceBlocks) cand.push_back({TM, TJ, k});
+  };
+#define MR_RR_ADD(TM, TJ) add(TM, TJ);
+  MR_RR_TILES(MR_RR_ADD)
+#undef MR_RR_ADD
+  size_t bi = 0;
+  bool recorded = false;
+  {
+    std::vector<int> rec;
+    if (tuning_lookup("linrr32.v1", dev, n, rec))
+      for (size_t i = 0; i < cand.size() && !recorded; ++i)
+        if (cand[i] == rec) {
+          bi = i;
+          recorded = true;
+        }
+  }
+  LinLevel& L = c->mixed->lv[l];
+  LinLevel& Lc = c->mixed->lv[l + 1];
+  const Level& F = c->lv[l];
+  const int reps = F.cells >= ((size_t)1 << 24) ? 2 : 4;
+  hipError_t e = hipSuccess;
+  if (!recorded)
+    e = pick_fastest(cand.size(), reps, c->stream, [&](size_t i) {
+      return launch_lin_rr(L.e[0], L.base, c->scal + kSlotBase, L.sb, L.rhs, F.n, F.h, ShiftRef{nullptr, 0.0, 0.0}, Lc.rhs,
+                           c->reducer(kSlotAux), c->stream, cand[i][0], cand[i][1], cand[i][2]);
+    }, &bi);
+  if (e != hipSuccess) return hip_fail(e, "defect tuner");
+  {
+    std::lock_guard<std::mutex> lk(g_rr_tune_mu);
+    g_rr_tuned[{dev, n}] = cand[bi];
+  }
+  if (!recorded) tuning_record("linrr32.v1", dev, n, cand[bi]);
+  *tm = cand[bi][0];
+  *tj = cand[bi][1];
+  *nch = cand[bi][2];
+  return MR_OK;
+}
+
 static int mixed_alloc(Ctx* c) {
   if (c->mixed) return MR_OK;
   MixedState* m = new MixedState();
@@ -811,6 +895,7 @@ static int mixed_alloc(Ctx* c) {
     m->lv[l].sw = ls.two;
     m->lv[l].fused = ls.fused;
     m->lv[l].fz = ls.fz;
+    if ((rc = tune_lin_rr(c, l, &m->lv[l].rr_tm, &m->lv[l].rr_tj, &m->lv[l].rr_nch)) != MR_OK) return rc;
   }
   return MR_OK;
 }
@@ -986,9 +1071,9 @@ int Ctx::lin_vcycle(int l, bool zero) {
   for (int s = 0; s < opts.npre; ++s)
     if ((rc = lin_sweep(l, zero && s == 0)) != MR_OK) return rc;
   LinLevel& Lc = mixed->lv[l + 1];
-  e = launch_lin_resid_restrict(L.e[L.cur], L.base, scal + kSlotBase, L.sb, L.rhs, F.n, F.h,
-                                ShiftRef{linsum(l), 1.0 / (double)F.cells, 0.0}, Lc.rhs,
-                                Reduce{partials, counter, linsum(l + 1)}, stream);
+  e = launch_lin_rr(L.e[L.cur], L.base, scal + kSlotBase, L.sb, L.rhs, F.n, F.h,
+                    ShiftRef{linsum(l), 1.0 / (double)F.cells, 0.0}, Lc.rhs, Reduce{partials, counter, linsum(l + 1)},
+                    stream, L.rr_tm, L.rr_tj, L.rr_nch);
   if (e != hipSuccess) return hip_fail(e, "linear restriction");
   if ((rc = (l == 0 ? lin_coarse_cycle() : lin_vcycle(l + 1, true))) != MR_OK) return rc;
   e = launch_prolong_add32(Lc.e[Lc.cur], L.e[L.cur], F.n, stream);
