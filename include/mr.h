@@ -320,13 +320,17 @@ int mr_tune_lin_tiles(int n, void* hip_stream, int* tm, int* tj, int* ci, float*
  * set (an empty value: no file), else $XDG_CACHE_HOME/paper_1709_06350_amd/tuning.txt, else
  * $HOME/.cache/paper_1709_06350_amd/tuning.txt; it is read on first use and rewritten (through a
  * temporary file and a rename) when a choice is recorded. A file that cannot be written is not an
- * error for the tuners. Host code only; no device is needed for these four calls.
+ * error for the tuners. A key the file does not hold is looked up in the choices shipped with the
+ * library, tuning_defaults.txt in the directory of libmr.so (or $MR_TUNING_DEFAULTS; an empty value:
+ * none), which is read but never written (a choice taken from it is copied into the record file).
+ * Host code only; no device is needed for these four calls.
  *
  * mr_tuning_file: use path from now on (NULL: back to the default above; "": no file) and forget
- * the choices read so far. mr_tuning_file_path: the file in use ("" if none; the pointer is valid
- * until the next mr_tuning_file). mr_tuning_store: record count (1..64) values under the key and
- * write the file (MR_EINVAL if it cannot be written). mr_tuning_lookup: the values recorded under
- * the key into vals (at most max_count), their number into *count (0 if none). */
+ * the choices read so far (the shipped ones are read again too). mr_tuning_file_path: the file in
+ * use ("" if none; the pointer is valid until the next mr_tuning_file). mr_tuning_store: record count
+ * (1..64) values under the key and write the file (MR_EINVAL if it cannot be written).
+ * mr_tuning_lookup: the values recorded under the key (else the shipped ones) into vals (at most
+ * max_count), their number into *count (0 if none). */
 int mr_tuning_file(const char* path);
 const char* mr_tuning_file_path(void);
 int mr_tuning_store(const char* kind, const char* arch, const char* device, int cus, int n, const int* vals,

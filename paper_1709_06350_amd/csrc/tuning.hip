@@ -5,6 +5,7 @@
 // through a temporary file and a rename, whenever a choice is recorded.
 #include <hip/hip_runtime.h>
 
+#include <dlfcn.h>
 #include <sys/stat.h>
 #include <unistd.h>
 
@@ -28,6 +29,10 @@ namespace {
 std::mutex g_mu;
 std::map<std::string, std::vector<int>> g_store;
 bool g_loaded = false;
+// choices shipped beside the library (tuning_defaults.txt next to libmr.so, or $MR_TUNING_DEFAULTS):
+// consulted when the record file has no entry for a key; never written
+std::map<std::string, std::vector<int>> g_defaults;
+bool g_defaults_loaded = false;
 bool g_path_set = false;   // mr_tuning_file was called
 int g_generation = 0;
 std::string g_path;        // the file in use when g_path_set ("" = none)
@@ -68,11 +73,32 @@ std::string make_key(const std::string& kind, const std::string& arch, const std
   return clean(kind) + "|" + clean(arch) + "|" + clean(dev) + "|" + std::to_string(cus) + "|" + std::to_string(n);
 }
 
+void parse_file(const std::string& p, std::map<std::string, std::vector<int>>& store);
+
+std::string defaults_path() {
+  const char* env = std::getenv("MR_TUNING_DEFAULTS");
+  if (env) return std::string(env);   // "" turns the defaults off
+  Dl_info info;
+  if (dladdr(reinterpret_cast<void*>(&default_path), &info) == 0 || !info.dli_fname) return std::string();
+  std::string lib = info.dli_fname;
+  const size_t slash = lib.rfind('/');
+  return (slash == std::string::npos ? std::string(".") : lib.substr(0, slash)) + "/tuning_defaults.txt";
+}
+
 void load_locked() {
+  if (!g_defaults_loaded) {
+    g_defaults_loaded = true;
+    const std::string d = defaults_path();
+    if (!d.empty()) parse_file(d, g_defaults);
+  }
   if (g_loaded) return;
   g_loaded = true;
   const std::string& p = path_locked();
   if (p.empty()) return;
+  parse_file(p, g_store);
+}
+
+void parse_file(const std::string& p, std::map<std::string, std::vector<int>>& store) {
   std::ifstream f(p);
   std::string line;
   while (std::getline(f, line)) {
@@ -96,7 +122,7 @@ void load_locked() {
       }
       vals.push_back((int)v);
     }
-    if (ok && !vals.empty()) g_store[line.substr(0, bar)] = vals;
+    if (ok && !vals.empty()) store[line.substr(0, bar)] = vals;
   }
 }
 
@@ -149,8 +175,16 @@ bool lookup_key(const std::string& key, std::vector<int>& vals) {
   std::lock_guard<std::mutex> lk(g_mu);
   load_locked();
   auto it = g_store.find(key);
-  if (it == g_store.end()) return false;
+  if (it != g_store.end()) {
+    vals = it->second;
+    return true;
+  }
+  it = g_defaults.find(key);
+  if (it == g_defaults.end()) return false;
   vals = it->second;
+  // the record file lists every choice in use, shipped ones included
+  g_store[key] = vals;
+  (void)save_locked();
   return true;
 }
 
@@ -188,6 +222,8 @@ int mr_tuning_file(const char* path) {
   std::lock_guard<std::mutex> lk(mr::g_mu);
   mr::g_store.clear();
   mr::g_loaded = false;
+  mr::g_defaults.clear();
+  mr::g_defaults_loaded = false;
   ++mr::g_generation;
   if (path) {
     mr::g_path = path;

@@ -102,3 +102,44 @@ def test_bad_arguments_are_errors(tfile):
     mr.tuning_store("k", ARCH, DEV, 256, 8, [1, 2, 3])
     with pytest.raises(mr.MRError):
         mr.tuning_lookup("k", ARCH, DEV, 256, 8, max_count=2)
+
+
+def test_shipped_defaults_are_consulted_after_the_record_file(tmp_path, monkeypatch):
+    """A key missing from the record file is taken from the shipped choices ($MR_TUNING_DEFAULTS
+    here, tuning_defaults.txt beside the library otherwise); a record in the file wins; the shipped
+    file is never written."""
+    shipped = tmp_path / "defaults.txt"
+    shipped.write_text(f"# shipped\nsweep64.v1|{ARCH}|288GiB|256|512|0,64,16,256,32,4,1,1,0,0,0,0,0\n")
+    before = shipped.read_text()
+    monkeypatch.setenv("MR_TUNING_DEFAULTS", str(shipped))
+    user = tmp_path / "user.txt"
+    mr.tuning_file(str(user))
+    try:
+        assert mr.tuning_lookup("sweep64.v1", ARCH, "288GiB", 256, 512) == [0, 64, 16, 256, 32, 4, 1, 1, 0, 0, 0, 0, 0]
+        mr.tuning_store("sweep64.v1", ARCH, "288GiB", 256, 512, [1, 2, 3])
+        assert mr.tuning_lookup("sweep64.v1", ARCH, "288GiB", 256, 512) == [1, 2, 3]
+        assert shipped.read_text() == before
+        assert "sweep64.v1" in user.read_text()
+        monkeypatch.setenv("MR_TUNING_DEFAULTS", "")
+        mr.tuning_file(str(tmp_path / "other.txt"))
+        assert mr.tuning_lookup("sweep64.v1", ARCH, "288GiB", 256, 512) is None
+    finally:
+        monkeypatch.delenv("MR_TUNING_DEFAULTS", raising=False)
+        mr.tuning_file(None)
+
+
+def test_shipped_defaults_file_parses_and_names_this_device_kind():
+    """The committed defaults are records of the library's tuner kinds for gfx950 devices."""
+    path = os.path.join(os.path.dirname(mr.__file__), "tuning_defaults.txt")
+    if not os.path.exists(path):
+        pytest.skip("no shipped defaults")
+    kinds = set()
+    for ln in open(path):
+        if ln.startswith("#") or not ln.strip():
+            continue
+        parts = ln.strip().split("|")
+        assert len(parts) == 6, ln
+        kinds.add(parts[0])
+        assert parts[1].startswith("gfx950")
+        assert all(v.lstrip("-").isdigit() for v in parts[5].split(","))
+    assert {"sweep64.v1", "lin32.v1"} <= kinds
