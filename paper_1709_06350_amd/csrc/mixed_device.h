@@ -59,41 +59,46 @@ __host__ __device__ inline int base_scale_exp(double tmax) {
 
 // h^2 dSigma(e) for a cell with base neighbours b and centre bc (fixed-point bits, scale bscl =
 // 2^-s), base root s and perturbation neighbours e; also returns the face-neighbour sum of e. FP32.
+// With Mbar the traceless (scaled) Hessian of the base and W = (9 s Mbar - 27 Mbar^2 + 9 T2 I) /
+// (3 s^2 - 4.5 T2) the result is sum_a W_aa eS_a + (1/2) sum_{a<b} W_ab eD_ab, evaluated as
+// (9 s A - 27 B + 9 T2 Se) / (3 s^2 - 4.5 T2) with A and B the same contractions of Mbar and Mbar^2;
+// the off-diagonal entries of Mbar^2 use the zero trace (Mbar_xx + Mbar_yy = -Mbar_zz, ...).
 __device__ __forceinline__ float lin_source(const Nb18f& b, float bc, float bscl, float s, float ih2, const Nb18f& e,
                                             float& Se) {
   const int c = qval(bc);
-  // exact integer second differences of the base (pair sums minus twice the centre) and cross differences
-  const int dx = (qval(b.xm) - c) + (qval(b.xp) - c);
-  const int dy = (qval(b.ym) - c) + (qval(b.yp) - c);
-  const int dz = (qval(b.zm) - c) + (qval(b.zp) - c);
+  // exact integer second differences of the base (pair sums minus twice the centre: with |q| < 2^29
+  // a pair sum and twice the centre are below 2^30, their difference below 2^31) and cross differences
+  const int c2 = c + c;
+  const int dx = (qval(b.xm) + qval(b.xp)) - c2;
+  const int dy = (qval(b.ym) + qval(b.yp)) - c2;
+  const int dz = (qval(b.zm) + qval(b.zp)) - c2;
   const int cxy = (qval(b.xpyp) - qval(b.xpym)) - (qval(b.xmyp) - qval(b.xmym));
   const int cxz = (qval(b.xpzp) - qval(b.xpzm)) - (qval(b.xmzp) - qval(b.xmzm));
   const int cyz = (qval(b.ypzp) - qval(b.ypzm)) - (qval(b.ymzp) - qval(b.ymzm));
   const float sc = bscl * ih2;
+  const float sc4 = 0.25f * sc;
   const float fx = (float)dx * sc, fy = (float)dy * sc, fz = (float)dz * sc;
   const float f3 = (fx + fy + fz) * (1.0f / 3.0f);
   const float mx = fx - f3, my = fy - f3, mz = fz - f3;
-  const float mxy = 0.25f * sc * (float)cxy;
-  const float mxz = 0.25f * sc * (float)cxz;
-  const float myz = 0.25f * sc * (float)cyz;
+  const float mxy = sc4 * (float)cxy;
+  const float mxz = sc4 * (float)cxz;
+  const float myz = sc4 * (float)cyz;
+  const float mx2 = mx * mx, my2 = my * my, mz2 = mz * mz;
   const float xy2 = mxy * mxy, xz2 = mxz * mxz, yz2 = myz * myz;
-  const float T2 = mx * mx + my * my + mz * mz + 2.0f * (xy2 + xz2 + yz2);
+  const float T2 = (mx2 + my2 + mz2) + 2.0f * (xy2 + xz2 + yz2);
   // hardware reciprocal: the linearised operator only steers the defect correction
   const float inv = __builtin_amdgcn_rcpf(3.0f * s * s - 4.5f * T2);
-  const float s9 = 9.0f * s;
-  const float q9 = 9.0f * T2;
-  const float Wxx = (s9 * mx - 27.0f * (mx * mx + xy2 + xz2) + q9) * inv;
-  const float Wyy = (s9 * my - 27.0f * (xy2 + my * my + yz2) + q9) * inv;
-  const float Wzz = (s9 * mz - 27.0f * (xz2 + yz2 + mz * mz) + q9) * inv;
-  const float Wxy = (s9 * mxy - 27.0f * (mx * mxy + mxy * my + mxz * myz)) * inv;
-  const float Wxz = (s9 * mxz - 27.0f * (mx * mxz + mxy * myz + mxz * mz)) * inv;
-  const float Wyz = (s9 * myz - 27.0f * (mxy * mxz + my * myz + myz * mz)) * inv;
   const float eSx = e.xm + e.xp, eSy = e.ym + e.yp, eSz = e.zm + e.zp;
   Se = eSx + eSy + eSz;
   const float eDxy = (e.xpyp + e.xmym) - (e.xpym + e.xmyp);
   const float eDxz = (e.xpzp + e.xmzm) - (e.xpzm + e.xmzp);
   const float eDyz = (e.ypzp + e.ymzm) - (e.ypzm + e.ymzp);
-  return Wxx * eSx + Wyy * eSy + Wzz * eSz + 0.5f * (Wxy * eDxy + Wxz * eDxz + Wyz * eDyz);
+  // Mbar^2
+  const float Nxx = mx2 + xy2 + xz2, Nyy = xy2 + my2 + yz2, Nzz = xz2 + yz2 + mz2;
+  const float Nxy = mxz * myz - mxy * mz, Nxz = mxy * myz - mxz * my, Nyz = mxy * mxz - myz * mx;
+  const float A = (mx * eSx + my * eSy + mz * eSz) + 0.5f * (mxy * eDxy + mxz * eDxz + myz * eDyz);
+  const float B = (Nxx * eSx + Nyy * eSy + Nzz * eSz) + 0.5f * (Nxy * eDxy + Nxz * eDxz + Nyz * eDyz);
+  return ((9.0f * s) * A - 27.0f * B + (9.0f * T2) * Se) * inv;
 }
 
 // ---- FP32 linear half-sweep (compile-time tile, same decomposition as the FP64 sweep) -------
@@ -1718,7 +1723,10 @@ __device__ void lin_apply_dots_body(const LinApplyArgs& a, int logical, int bid,
 #pragma unroll
       for (int k = 0; k < PER; ++k) lds[(f * 4 + slot) * SLOT + loff[k]] = v[f * PER + k];
   };
-  const int c = tid / NC;            // colour of this thread's cells (wave-uniform: NC is a multiple of 64)
+  // colour of this thread's cells: the same on every lane of a wave (NC is a multiple of 64), taken
+  // from the wave's first lane so that the compiler keeps the colour's pointers in scalar registers
+  static_assert(NC % 64 == 0, "whole waves per colour");
+  const int c = __builtin_amdgcn_readfirstlane(tid) / NC;
   const int col = tid - c * NC;
   const int s = col % TM, r = col / TM;
   const int j = j0 + r, m = m0 + s;

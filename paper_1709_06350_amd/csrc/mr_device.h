@@ -47,13 +47,16 @@ __device__ __forceinline__ void largest_roots(const double (&p)[N], const double
   for (int u = 0; u < N; ++u) s[u] = (double)root_seed(p[u], q[u]);
   // Four steps for every root: from the upper-bound seed (typically ~1e-4 away) this reaches the
   // stopping test for nearly every cell, with no per-lane control in the common path.
+  // One step: with s2 = s^2 and t = s2 + p, the cubic is s t + q and its derivative 3 s2 + p is
+  // 2 s2 + t (a multiply-add by 2, which the hardware takes as an inline constant).
 #pragma unroll
   for (int it = 0; it < 4; ++it) {
 #pragma unroll
     for (int u = 0; u < N; ++u) {
       const double s2 = s[u] * s[u];
-      const double g = __builtin_fma(s[u], s2 + p[u], q[u]);
-      const double gp = __builtin_fma(3.0, s2, p[u]);
+      const double t = s2 + p[u];
+      const double g = __builtin_fma(s[u], t, q[u]);
+      const double gp = __builtin_fma(2.0, s2, t);
       ds[u] = g * __builtin_amdgcn_rcp(gp);
       s[u] -= ds[u];
     }
@@ -73,8 +76,9 @@ __device__ __forceinline__ void largest_roots(const double (&p)[N], const double
 #pragma unroll
     for (int u = 0; u < N; ++u) {
       const double s2 = s[u] * s[u];
-      const double g = __builtin_fma(s[u], s2 + p[u], q[u]);
-      const double gp = __builtin_fma(3.0, s2, p[u]);
+      const double t = s2 + p[u];
+      const double g = __builtin_fma(s[u], t, q[u]);
+      const double gp = __builtin_fma(2.0, s2, t);
       const double d = g * __builtin_amdgcn_rcp(gp);
       const double sn = s[u] - d;
       s[u] = done[u] ? s[u] : sn;
@@ -92,23 +96,27 @@ __device__ __forceinline__ double largest_root(double p, double q) {
 }
 
 // Cubic coefficients p, q of one cell and S = sum of the 6 face neighbours (see sigma_cell).
+// Evaluated on U_a = 4 u_a and D_ab = 4 w_ab, so that no quarter is applied per term: every
+// factor 4 is exact in binary, h^4 T2 = (sum U_a^2 + 2 sum D_ab^2) / 16 and h^6 T3 = (3 U_x U_y U_z
+// - 3 (U_z D_xy^2 + U_y D_xz^2 + U_x D_yz^2) + 6 D_xy D_xz D_yz) / 64, and the powers of two
+// 1/16 and 1/64 go into the constants -9/2 and 9, so p and q round exactly as with u and w.
 __device__ __forceinline__ void cell_pq(const Nb18& t, double opd, double ih2, double& S, double& p, double& q) {
   const double Sx = t.xm + t.xp;
   const double Sy = t.ym + t.yp;
   const double Sz = t.zm + t.zp;
   S = Sx + Sy + Sz;
-  const double s3 = S * (1.0 / 3.0);
-  const double ux = Sx - s3, uy = Sy - s3, uz = Sz - s3;
-  const double wxy = 0.25 * ((t.xpyp + t.xmym) - (t.xpym + t.xmyp));
-  const double wxz = 0.25 * ((t.xpzp + t.xmzm) - (t.xpzm + t.xmzp));
-  const double wyz = 0.25 * ((t.ypzp + t.ymzm) - (t.ypzm + t.ymzp));
+  const double s3 = S * (4.0 / 3.0);
+  const double ux = __builtin_fma(4.0, Sx, -s3), uy = __builtin_fma(4.0, Sy, -s3), uz = __builtin_fma(4.0, Sz, -s3);
+  const double wxy = (t.xpyp + t.xmym) - (t.xpym + t.xmyp);
+  const double wxz = (t.xpzp + t.xmzm) - (t.xpzm + t.xmzp);
+  const double wyz = (t.ypzp + t.ymzm) - (t.ypzm + t.ymzp);
   const double wxy2 = wxy * wxy, wxz2 = wxz * wxz, wyz2 = wyz * wyz;
   const double P = __builtin_fma(ux, ux, __builtin_fma(uy, uy, uz * uz)) + 2.0 * (wxy2 + wxz2 + wyz2);
   const double Q = 3.0 * (ux * uy * uz - (__builtin_fma(uz, wxy2, __builtin_fma(uy, wxz2, ux * wyz2))))
                    + 6.0 * wxy * wxz * wyz;
   const double ih4 = ih2 * ih2;
-  p = -4.5 * P * ih4;
-  q = __builtin_fma(9.0 * Q, ih4 * ih2, -27.0 * opd);
+  p = (-4.5 / 16.0) * P * ih4;
+  q = __builtin_fma((9.0 / 64.0) * Q, ih4 * ih2, -27.0 * opd);
 }
 
 // Sigma = s* - 3 of one cell and S = sum of the 6 face neighbours.

@@ -252,8 +252,6 @@ __global__ void __launch_bounds__(TM * TJ) half_sweep_pipe(HalfSweepArgs a) {
   constexpr int NT = TM * TJ;
   constexpr int RW = TM + 2, RH = TJ + 2;
   constexpr int SLOT = RH * RW;
-  constexpr int TOTAL = 2 * SLOT;
-  constexpr int NPF = (TOTAL + NT - 1) / NT;
   constexpr int O = 1 - COL;
   __shared__ double lds[2 * 4 * SLOT];
   const int n = a.n, nh = n >> 1;
@@ -270,47 +268,34 @@ __global__ void __launch_bounds__(TM * TJ) half_sweep_pipe(HalfSweepArgs a) {
   // byte offset inside it
   auto prs = [&](const double* arr, int p) { return plane_rsrc(arr + (size_t)p * plane, pbytes); };
 
-  // loader. SPLIT (when it costs no extra elements): elements 0 .. NPC-1 of a thread cover colour 0,
-  // NPC .. 2 NPC-1 colour 1, each over the slot's SLOT cells. Otherwise element t covers
-  // e = tid + t NT of the two slots together (colour e / SLOT), whose colour is per lane only
-  // where the block's range of t straddles the colour boundary. Out-of-range elements are clamped
-  // onto the last one (duplicate stores of the same value).
-  constexpr int NPC = (SLOT + NT - 1) / NT;
-  constexpr bool SPLIT = 2 * NPC == NPF;
+  // loader: element t of a thread is e = tid + t NT of the two slots laid end to end, colour 0
+  // over e < SLOTP and colour 1 from SLOTP on, where SLOTP is SLOT rounded up to whole waves, so
+  // that the colour of an element is the same on every lane of a wave and the buffer resource is
+  // chosen in scalar registers (a per-lane choice of resource makes the compiler loop over the
+  // distinct resources, one load at a time). Out-of-range elements are clamped onto the last one
+  // of their colour (duplicate stores of the same value).
+  static_assert(NT % 64 == 0, "whole waves per block");
+  constexpr int SLOTP = (SLOT + 63) / 64 * 64;
+  constexpr int NPF = (SLOTP + SLOT + NT - 1) / NT;
+  const int wave0 = __builtin_amdgcn_readfirstlane(tid) & ~63;   // first thread of this wave
   unsigned gb[NPF];
   int le[NPF];
-  bool col1[NPF];
 #pragma unroll
   for (int t = 0; t < NPF; ++t) {
-    int cc, rem;
-    if (SPLIT) {
-      cc = t / NPC;
-      const int e = tid + (t - cc * NPC) * NT;
-      rem = e < SLOT ? e : SLOT - 1;
-    } else {
-      int e = tid + t * NT;
-      e = e < TOTAL ? e : TOTAL - 1;
-      cc = e / SLOT;
-      rem = e - cc * SLOT;
-    }
+    const int cc = wave0 + t * NT >= SLOTP ? 1 : 0;
+    int rem = tid + t * NT - cc * SLOTP;
+    rem = rem < SLOT ? rem : SLOT - 1;
     const int r = rem / RW;
     const int c = rem - r * RW;
     gb[t] = ((unsigned)wrapi(j0 - 1 + r, n) * nh + (unsigned)wrapi(m0 - 1 + c, nh)) * 8u;
     le[t] = cc * 4 * SLOT + rem;
-    col1[t] = cc != 0;
   }
   // plane i0 - 1 + rel sits in slot rel & 3
   auto fetch = [&](int rel, double (&v)[NPF]) {
     const int p = wrapi(i0 - 1 + rel, n);
     const auto b0 = prs(src0, p), b1 = prs(src1, p);
 #pragma unroll
-    for (int t = 0; t < NPF; ++t) {
-      if (SPLIT) v[t] = ld_rs(t < NPC ? b0 : b1, gb[t]);
-      else if ((t + 1) * NT <= SLOT) v[t] = ld_rs(b0, gb[t]);
-      else if (t * NT >= SLOT) v[t] = ld_rs(b1, gb[t]);
-      else if (col1[t]) v[t] = ld_rs(b1, gb[t]);
-      else v[t] = ld_rs(b0, gb[t]);
-    }
+    for (int t = 0; t < NPF; ++t) v[t] = ld_rs(wave0 + t * NT >= SLOTP ? b1 : b0, gb[t]);
   };
   auto store = [&](int slot, const double (&v)[NPF]) {
 #pragma unroll
