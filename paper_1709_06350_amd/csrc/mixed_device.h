@@ -257,22 +257,60 @@ inline __device__ bool mixed_resid64_body(const double* __restrict__ theta, cons
 }
 // Base root on a coarse mesh (cell size h) from the restricted fixed-point base potential (its
 // value bq[0] q, exact in FP64); rows bid, bid + nblocks, ... of the mesh.
+// Largest real root of s^3 + p s + q = 0 in FP32 (the root of the linearisation's base, which
+// only weights the FP32 operator): the upper-bound seed of the FP64 iteration, then Newton steps in
+// FP32 until every lane of the wave has a step below 1e-6 of its root (at most 12).
+__device__ __forceinline__ float largest_root_f32(float p, float q) {
+  const float mq = fmaxf(-q, 0.0f);
+  const float c = mq > 0.0f ? __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(mq) * (1.0f / 3.0f)) : 0.0f;
+  const float b1 = __builtin_amdgcn_sqrtf(fmaxf(-p, 0.0f)) + c;
+  const float b2 = c > 0.0f ? c - p * __builtin_amdgcn_rcpf(3.0f * c) : b1;
+  float s = fminf(b1, b2);
+  bool done = false;
+#pragma unroll 1
+  for (int it = 0; it < 12; ++it) {
+    const float s2 = s * s;
+    const float t = s2 + p;
+    const float g = __builtin_fmaf(s, t, q);
+    const float gp = __builtin_fmaf(2.0f, s2, t);
+    const float d = g * __builtin_amdgcn_rcpf(gp);
+    const float sn = s - d;
+    s = done ? s : sn;
+    done = done || !(__builtin_fabsf(d) > 1e-6f * sn);
+    if (it >= 3 && __ballot(!done) == 0) break;
+  }
+  return s;
+}
+
+// Root of the linearisation at every cell of a coarse level from its fixed-point base, FP32: the
+// traceless Hessian from exact integer differences (as in lin_source), T2 and T3 of it, and
+// p = -(9/2) T2, q = 9 T3 - 27 (1 + delta).
 inline __device__ void base_root_body(const int* __restrict__ baseq, const double* __restrict__ bq,
                                const double* __restrict__ delta, int n, double ih2, float* __restrict__ sb32, int bid,
                                int nblocks) {
-  const double sc = bq[0];
+  const float sc = (float)bq[0] * (float)ih2;
+  const float sc4 = 0.25f * sc;
   for (int row = xcd_remap(bid, nblocks); row < n * n; row += nblocks) {
     const int i = row / n, j = row - i * n;
     for (int k = threadIdx.x; k < n; k += blockDim.x) {
       const unsigned e = split_idx(n, i, j, k);
-      Nb18f tf;
-      gather18_split_t(reinterpret_cast<const float*>(baseq), n, i, j, k, tf);
-      Nb18 t{sc * qval(tf.xm), sc * qval(tf.xp), sc * qval(tf.ym), sc * qval(tf.yp), sc * qval(tf.zm),
-             sc * qval(tf.zp), sc * qval(tf.xpyp), sc * qval(tf.xmym), sc * qval(tf.xpym), sc * qval(tf.xmyp),
-             sc * qval(tf.xpzp), sc * qval(tf.xmzm), sc * qval(tf.xpzm), sc * qval(tf.xmzp), sc * qval(tf.ypzp),
-             sc * qval(tf.ymzm), sc * qval(tf.ypzm), sc * qval(tf.ymzp)};
-      double S;
-      sb32[e] = (float)(sigma_cell(t, 1.0 + delta[e], ih2, S) + 3.0);
+      Nb18f b;
+      gather18_split_t(reinterpret_cast<const float*>(baseq), n, i, j, k, b);
+      const int c2 = 2 * baseq[e];
+      const int dx = (qval(b.xm) + qval(b.xp)) - c2;
+      const int dy = (qval(b.ym) + qval(b.yp)) - c2;
+      const int dz = (qval(b.zm) + qval(b.zp)) - c2;
+      const int cxy = (qval(b.xpyp) - qval(b.xpym)) - (qval(b.xmyp) - qval(b.xmym));
+      const int cxz = (qval(b.xpzp) - qval(b.xpzm)) - (qval(b.xmzp) - qval(b.xmzm));
+      const int cyz = (qval(b.ypzp) - qval(b.ypzm)) - (qval(b.ymzp) - qval(b.ymzm));
+      const float fx = (float)dx * sc, fy = (float)dy * sc, fz = (float)dz * sc;
+      const float f3 = (fx + fy + fz) * (1.0f / 3.0f);
+      const float mx = fx - f3, my = fy - f3, mz = fz - f3;
+      const float mxy = sc4 * (float)cxy, mxz = sc4 * (float)cxz, myz = sc4 * (float)cyz;
+      const float xy2 = mxy * mxy, xz2 = mxz * mxz, yz2 = myz * myz;
+      const float T2 = (mx * mx + my * my + mz * mz) + 2.0f * (xy2 + xz2 + yz2);
+      const float T3 = 3.0f * (mx * my * mz - (mz * xy2 + my * xz2 + mx * yz2)) + 6.0f * mxy * mxz * myz;
+      sb32[e] = largest_root_f32(-4.5f * T2, 9.0f * T3 - 27.0f * (float)(1.0 + delta[e]));
     }
   }
 }
@@ -1742,9 +1780,15 @@ __device__ void lin_apply_dots_body(const LinApplyArgs& a, int logical, int bid,
   const float* lc = lds + c * 4 * SLOT;             // z of this colour
   const float* bo = lds + (3 - c) * 4 * SLOT;       // base of the other colour
   const float* bc = lds + (2 + c) * 4 * SLOT;       // base of this colour
+  // projections: FP32 partial sums over the four plane steps of a ring cycle, added into FP64
+  // accumulators at its end
   double acc[K + 2];
+  float accf[K + 2];
 #pragma unroll
-  for (int q = 0; q < K + 2; ++q) acc[q] = 0.0;
+  for (int q = 0; q < K + 2; ++q) {
+    acc[q] = 0.0;
+    accf[q] = 0.0f;
+  }
   float V0[NPF], V1[NPF];
   float SB[4];
   {
@@ -1793,9 +1837,16 @@ __device__ void lin_apply_dots_body(const LinApplyArgs& a, int logical, int bid,
     const float wv = (Se - 6.0f * lc[S0 * SLOT + ob]) * ih2 - g;
     st_rs_f_nt(prs(out, i0 + t), o_c, wv);
 #pragma unroll
-    for (int q = 0; q < K; ++q) acc[q] += (double)(wv * vj[q]);
-    acc[K] += (double)wv;
-    acc[K + 1] += (double)(wv * wv);
+    for (int q = 0; q < K; ++q) accf[q] = __builtin_fmaf(wv, vj[q], accf[q]);
+    accf[K] += wv;
+    accf[K + 1] = __builtin_fmaf(wv, wv, accf[K + 1]);
+    if (KK == 3) {
+#pragma unroll
+      for (int q = 0; q < K + 2; ++q) {
+        acc[q] += (double)accf[q];
+        accf[q] = 0.0f;
+      }
+    }
     store(SN, vst);
     __syncthreads();
   };
