@@ -82,12 +82,12 @@ def _cpu_model() -> str:
 
 def cpu_baseline(full: bool = False, reps: int = 5):
     """The oracle (numpy, FP64, one thread) on the host cores, on bounded samples of the workload:
-    the red-black sweep at 32^3 and 128^3 and the whole solve to 1e-10 at 32^3, medians of `reps`
-    runs each, inputs of the same recipe (lognormal, sigma_g = 1.0, R_c = 2 cells, seed 1002) at the
-    sample size. The 128^3 and 512^3 times to solution are extrapolated from the 32^3 solve's
-    sweep-equivalents (solve time / sweep time) and the sweep time at the target size (scaled by
-    the cell count from 128^3 for 512^3), and labelled so; with full=True the 128^3 solve is run
-    once and reported as measured."""
+    the red-black sweep at 32^3 and 128^3 (medians of `reps` runs) and at 256^3 (median of 3), and
+    the whole solve to 1e-10 at 32^3 (median of `reps`), inputs of the same recipe (lognormal,
+    sigma_g = 1.0, R_c = 2 cells, seed 1002) at the sample size. Times to solution at 128^3, 256^3 and
+    512^3 are extrapolated from the 32^3 solve's sweep-equivalents (solve time / sweep time) and the
+    measured sweep time at that size (512^3: the 256^3 sweep time scaled by the cell count), and
+    labelled so; with full=True the 128^3 solve is run once and reported as measured."""
     import statistics
 
     import numpy as np
@@ -105,38 +105,41 @@ def cpu_baseline(full: bool = False, reps: int = 5):
         return statistics.median(ts), out
 
     sweep_s, solve = {}, {}
-    for s in (32, 128):
+    for s, k in ((32, reps), (128, reps), (256, 3)):
         d = inputs.lognormal(s, 1.0, 2.0, 1002)
         th = np.zeros_like(d)
-        omg.rb_sweep(th, d, None, 1.0)
-        sweep_s[s], _ = med(lambda: omg.rb_sweep(th, d, None, 1.0), reps)
+        if s < 256:   # one untimed sweep first (the 256^3 median of 3 absorbs a slow first run)
+            omg.rb_sweep(th, d, None, 1.0)
+        sweep_s[s], _ = med(lambda: omg.rb_sweep(th, d, None, 1.0), k)
+        del d, th
     d32 = inputs.lognormal(32, 1.0, 2.0, 1002)
     t32, (_, info32) = med(lambda: omg.solve(d32, tol=1e-10), reps)
     solve["32"] = {"seconds": round(t32, 3), "cycles": info32["cycles"], "kind": "measured", "runs": reps}
     equiv = t32 / sweep_s[32]
-    solve["128"] = {"seconds": round(equiv * sweep_s[128], 1), "kind": "extrapolated",
-                    "how": "32^3 solve in sweep-equivalents x 128^3 sweep time"}
+    for s in (128, 256):
+        solve[str(s)] = {"seconds": round(equiv * sweep_s[s], 1), "kind": "extrapolated",
+                         "how": f"32^3 solve in sweep-equivalents x {s}^3 sweep time"}
     if full:
         d128 = inputs.lognormal(128, 1.0, 2.0, 1002)
         t0 = time.perf_counter()
         _, info128 = omg.solve(d128, tol=1e-10)
         solve["128"] = {"seconds": round(time.perf_counter() - t0, 1), "cycles": info128["cycles"],
                         "kind": "measured", "runs": 1}
-    solve["512"] = {"seconds": round(equiv * sweep_s[128] * 64, 0), "kind": "extrapolated",
-                    "how": "32^3 solve in sweep-equivalents x 128^3 sweep time x 64 (cells)"}
+    solve["512"] = {"seconds": round(equiv * sweep_s[256] * 8, 0), "kind": "extrapolated",
+                    "how": "32^3 solve in sweep-equivalents x 256^3 sweep time x 8 (cells)"}
     try:
         affinity = len(os.sched_getaffinity(0))
     except AttributeError:
         affinity = None
     return {
-        "value": round(128 ** 3 / sweep_s[128] / 1e9, 5),
+        "value": round(256 ** 3 / sweep_s[256] / 1e9, 5),
         "unit": "Gcell-updates/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"oracle red-black sweep at 128^3 (median of {reps}: {sweep_s[128]:.3f} s) and at 32^3 "
-                  f"({sweep_s[32]:.4f} s); oracle solve to 1e-10 at 32^3 (median of {reps}); numpy, one thread; "
-                  "128^3 and 512^3 times to solution extrapolated unless marked measured",
-        "sweep_seconds": {"32": round(sweep_s[32], 5), "128": round(sweep_s[128], 4)},
+        "sample": f"oracle red-black sweep at 256^3 (median of 3: {sweep_s[256]:.2f} s), 128^3 (median of {reps}: "
+                  f"{sweep_s[128]:.3f} s) and 32^3 ({sweep_s[32]:.4f} s); oracle solve to 1e-10 at 32^3 (median of "
+                  f"{reps}); numpy, one thread; times to solution above 32^3 extrapolated unless marked measured",
+        "sweep_seconds": {"32": round(sweep_s[32], 5), "128": round(sweep_s[128], 4), "256": round(sweep_s[256], 3)},
         "time_to_1e-10_s": solve,
         "host": {"cpu_model": _cpu_model(), "os_cpu_count": os.cpu_count(), "affinity_cpus": affinity},
     }
