@@ -27,12 +27,20 @@ def _tol(n, npart):
     return 64 * 2.0 ** -41 * n ** 3 / npart
 
 
+def _report(name, got, ref, n, npart):
+    """Print the achieved error in delta units and in particle masses per cell (n^3 / np delta units)."""
+    err = float(np.max(np.abs(got - ref)))
+    announce(f"{name}: max |delta_gpu - delta_oracle| = {err:.3e} = {err * npart / n ** 3:.3e} particle masses "
+             f"(tolerance {_tol(n, npart):.3e}; 1e-12 max rho would be {1e-12 * float(np.max(ref + 1.0)):.3e})")
+
+
 def test_random_particles_match_oracle_loop():
     rng = np.random.default_rng(0)
     pos = rng.uniform(-5.0, 21.0, size=(500, 3))
     n = 16
     got = _gpu_cic(pos, n, mass=0.7)
     ref = odep.overdensity(odep.deposit_cic_loop(pos, n, 0.7))
+    _report("cic random n=16", got, ref, n, 500)
     np.testing.assert_allclose(got, ref, atol=_tol(n, 500) + 1e-13)
 
 
@@ -53,6 +61,7 @@ def test_zeldovich_matches_oracle_and_conserves_mass():
     pos = inputs.zeldovich_particles(n, 2.0, 1001, rms_disp=2.0)
     got = _gpu_cic(pos, n)
     ref = odep.overdensity(odep.deposit_cic(pos, n))
+    _report("cic zeldovich n=64", got, ref, n, n ** 3)
     np.testing.assert_allclose(got, ref, atol=_tol(n, n ** 3) + 1e-13)
     assert abs(got.sum()) < 1e-9 * n ** 3
 
