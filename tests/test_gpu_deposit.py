@@ -126,8 +126,10 @@ def test_particles_per_cell_convergence(scheme):
 
 
 @pytest.mark.parametrize("scheme", SCHEMES)
-@pytest.mark.parametrize("n,count", [(48, 2000), (8, 1), (96, 1)])
+@pytest.mark.parametrize("n,count", [(48, 2000), (8, 1), (96, 1), (32, 1), (64, 5), (256, 1)])
 def test_ragged_meshes_and_single_particle(scheme, n, count):
+    """Ragged meshes (scatter kernels) and a handful of particles, also on meshes of the tile-sorted
+    form (n a multiple of 32: one block of the sort, almost every tile empty)."""
     require_gpu()
     announce(f"deposit {scheme} n={n} particles={count}")
     pos = np.random.default_rng(700 + n + count).uniform(-n, 2 * n, (count, 3))
